@@ -1,0 +1,203 @@
+"""Throughput benchmark of the fused D2Q9 TRT-RLB sweep on one MI355X.
+
+Workload (one "step" = one time step of the whole lattice): Taylor-Green
+vortex 4096 x 4096, periodic, u0 = 0.01, tau_s = 0.6, Lambda_s = 1/4
+(tau_s2 = 3), populations stored as f - w in FP32, FP32 arithmetic.  The
+lattices are resident in HBM before timing starts; K steps are timed with HIP
+events on the stream the sweeps are launched on.
+
+The JSON line reports MLUPS (lattice updates per second / 1e6), the roofline
+of the sweep kernel (algorithmic bytes per lattice update x updates per
+launch / average launch time, against the 8 TB/s HBM peak), and the FP64 CPU
+oracle timed on a bounded sample of the same workload on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
+                      [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}  # 9 reads + 9 writes per node
+SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_tg4096_f32_hbm_counters.json")
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(lat, steps, warmup):
+    """Average time per step (ms) over `steps` steps after `warmup` steps."""
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(lat.stream):
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(lat.stream)
+        lat.step(steps)
+        end.record(lat.stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def tg_lattice(n, storage, tau1=0.6, lam=0.25, tuning=None):
+    from paper_2312_10318_amd import inputs, params
+    from paper_2312_10318_amd.lattice import Lattice
+    tau2 = params.tau2_from_magic(tau1, lam)
+    rho, ux, uy = inputs.taylor_green(n, 0.01, seed=0)
+    lat = Lattice(n, n, tau1, tau2, storage=storage)
+    if tuning:
+        lat.set_tuning(*tuning)
+    lat.init_equilibrium(rho, ux, uy)
+    return lat
+
+
+def cpu_baseline(n=4096, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample: the same
+    4096^2 Taylor-Green lattice, as many whole steps as fit in ~budget_s."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_2312_10318_amd import inputs, params
+    tau1 = 0.6
+    tau2 = params.tau2_from_magic(tau1, 0.25)
+    rho, ux, uy = inputs.taylor_green(n, 0.01, seed=0)
+    f = oracle.init_equilibrium(rho, ux, uy)
+    t0 = time.perf_counter()
+    f = oracle.step(f, tau1, tau2)
+    t1 = time.perf_counter() - t0
+    extra = max(0, int(budget_s / max(t1, 1e-9)) - 1)
+    t0 = time.perf_counter()
+    if extra:
+        f = oracle.run(f, extra, tau1, tau2)
+    t2 = time.perf_counter() - t0
+    steps = 1 + extra
+    total = t1 + t2
+    return {"value": round(n * n * steps / total / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total)}
+
+
+def traffic_from_counters(n, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current sweep source; else None."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != sweep_source_hash() or c.get("nodes") != n * n or \
+            c.get("storage") != storage:
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def run_extra(steps):
+    """Companion measurements: the same lattice in FP16 and FP64 storage."""
+    out = {}
+    for storage in ("f16", "f64"):
+        lat = tg_lattice(4096, storage)
+        ms = time_steps(lat, steps, 20)
+        lat.close()
+        mlups = 4096 * 4096 / (ms * 1e-3) / 1e6
+        out["tg4096_" + storage] = {
+            "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5),
+            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / (HBM_PEAK_GBS * 1e9), 4)}
+        log("extra %s: %.1f MLUPS" % (storage, mlups))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", default="", help="rows_per_wave,waves_per_block,xcd_remap")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the TRT-RLB sweep is built and measured on a "
+              "single MI355X; multi-GPU slab decomposition is a design note, not a run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+
+    n, storage = args.n, args.storage
+    tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    log("bench: TG %dx%d %s, warmup %d, steps %d" % (n, n, storage, args.warmup, args.steps))
+    lat = tg_lattice(n, storage, tuning=tuning)
+    ms = time_steps(lat, args.steps, args.warmup)
+    stable = lat.check()
+    rows, waves, remap = lat.tuning()
+    lat.close()
+    lups = n * n / (ms * 1e-3)
+    mlups = lups / 1e6
+    bytes_launch = BYTES_PER_LU[storage] * n * n
+    achieved = bytes_launch / (ms * 1e-3) / 1e9
+    traffic = traffic_from_counters(n, storage)
+    log("bench: %.4f ms/step, %.1f MLUPS, %.1f GB/s algorithmic (%.1f%% of peak)" %
+        (ms, mlups, achieved, 100 * achieved / HBM_PEAK_GBS))
+
+    rec = {
+        "metric": "D2Q9 TRT-RLB MLUPS (% HBM roofline)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": storage,
+        "data": "synthetic",
+        "config": {"workload": "taylor_green_%dx%d" % (n, n), "storage": storage + "_shifted"
+                   if storage != "f64" else "f64", "tau_s": 0.6, "tau_s2": 3.0, "u0": 0.01,
+                   "nodes": n * n, "launch": {"rows_per_wave": rows, "waves_per_block": waves,
+                                              "xcd_remap": remap},
+                   "stable": bool(stable)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_lu": BYTES_PER_LU[storage],
+                     "kernel": "sweep_single_kernel<%s,nomask>" % storage,
+                     "source_hash": sweep_source_hash()},
+    }
+    if not args.no_extra:
+        rec["extra"] = run_extra(max(200, args.steps // 4))
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle on a bounded sample")
+        rec["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * trtlbm.h -- C ABI of the MI355X (gfx950) D2Q9 TRT-RLB lattice Boltzmann
+ * library.
+ *
+ * The library advances the two-relaxation-time regularized lattice Boltzmann
+ * (TRT-RLB) model of Yu, Qin, Chen, Shu and Yuan, "Two-relaxation-time
+ * regularized lattice Boltzmann model for Navier-Stokes equations"
+ * (arXiv:2312.10318) on the GPU.  One time step is the evolution equation of
+ * Sec. II.B (Eq. 2): density and He-shifted velocity (Eqs. 12-13), the
+ * third-order Hermite equilibrium (Eq. 5), the regularized projections of the
+ * non-equilibrium part (Eq. 6), relaxation of orders 1-2 at tau_s and of
+ * order 3 at the free rate tau_s2, the cubic-error compensation G_i
+ * (Eqs. 8-10) and the forcing term F_i (Eq. 11); then streaming with periodic
+ * wrap and half-way bounce-back at solid nodes (Sec. II.D).  Lattice units
+ * throughout: dx = dt = c = 1, c_s^2 = 1/3.
+ *
+ * Conventions shared by every call:
+ *  - All calls return a trt_status; no C++ exception crosses the ABI.  On an
+ *    error, trt_last_error() (thread-local, never NULL) holds a message.
+ *  - Work is enqueued asynchronously on the HIP stream given at creation
+ *    (a hipStream_t passed as void*; NULL is the legacy default stream).
+ *    Results in device memory are ready once that stream reaches them.
+ *  - The caller owns and frees every lattice-sized buffer (population
+ *    lattices, mask, field arrays).  The library owns only small scratch
+ *    memory (reduction partials, batch tables) and HIP graphs, freed by the
+ *    matching destroy call.
+ *  - Population lattices are device buffers of trt_lattice_bytes() bytes,
+ *    256-byte aligned, laid out as 9 planes [i][y][x] with row pitch
+ *    trt_pitch(nx, storage) elements and plane stride
+ *    trt_plane_stride(nx, ny, storage) elements.  Storage TRT_F64 holds f_i;
+ *    TRT_F32_SHIFTED / TRT_F16_SHIFTED hold f_i - w_i (the population minus
+ *    its rest-state weight) rounded to nearest even.  The stored values are
+ *    post-collision populations of the previous step (pull streaming); use
+ *    trt_get_populations / trt_set_populations to read or write the
+ *    pre-collision state f(x, t) in a storage-independent form.
+ *  - Field arrays exchanged with the caller (rho, ux, uy, f) are dense FP64
+ *    device arrays [ny][nx] (populations: [9][ny][nx]), x fastest.
+ *  - The mask, when present, is a device uint8 array [ny][nx]; nonzero marks
+ *    a solid node.  Solid nodes are never collided; their rho, u and f read
+ *    back as 0 and they contribute nothing to diagnostics.
+ */
+#ifndef TRTLBM_H
+#define TRTLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TRT_OK = 0,
+    TRT_EINVAL = 1,    /* invalid argument; nothing was enqueued */
+    TRT_ENOMEM = 2,    /* library scratch allocation failed */
+    TRT_EDEVICE = 3,   /* a HIP call failed; message in trt_last_error() */
+    TRT_EUNSTABLE = 4, /* divergence detected (non-finite, rho <= 0 or |u| >= 1) */
+    TRT_ESTATE = 5     /* call not valid in the object's current state */
+} trt_status;
+
+typedef enum {
+    TRT_F64 = 0,         /* FP64 storage, FP64 arithmetic */
+    TRT_F32_SHIFTED = 1, /* FP32 storage of f - w, FP32 arithmetic */
+    TRT_F16_SHIFTED = 2  /* IEEE half storage of f - w, FP32 arithmetic */
+} trt_storage;
+
+/* One simulation: the problem statement of the paper (Sec. II.B-II.D). */
+typedef struct {
+    int32_t nx, ny;        /* lattice size, 1..46340 each; periodic in x and y */
+    double tau_s;          /* tau_s1 > 1/2: viscosity nu = (tau_s - 1/2)/3 (Sec. II.C) */
+    double tau_s2;         /* tau_s2 >= 1/2: free third-order rate (Sec. II.B) */
+    double gx, gy;         /* body acceleration g; the force is F = rho g (Sec. II.D) */
+    const uint8_t *mask;   /* device [ny][nx], nonzero = solid (half-way bounce-back); NULL = none */
+    int32_t storage;       /* trt_storage */
+} trt_problem;
+
+/* Launch shape of the fused sweep.  Zero fields take the built-in default. */
+typedef struct {
+    int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 */
+    int32_t waves_per_block; /* wavefronts per workgroup, 1..16 */
+    int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default */
+} trt_tuning;
+
+typedef struct trt_sim trt_sim;
+typedef struct trt_batch trt_batch;
+
+/* Number of FP64 values written by trt_diagnostics, and their order:
+ *   [0] sum of rho over fluid nodes (mass)
+ *   [1] sum of rho u_x, [2] sum of rho u_y (He-shifted velocity, Eq. 13)
+ *   [3] max |u| over fluid nodes with finite values
+ *   [4] number of divergent fluid nodes (non-finite rho or u, rho <= 0, or
+ *       |u| >= 1 = c)
+ *   [5] number of fluid nodes
+ *   [6] min rho over fluid nodes with finite values
+ *   [7] time steps taken since creation or the last trt_set_populations */
+#define TRT_NDIAG 8
+
+/* Row pitch in elements: nx rounded up so each row is a multiple of 256 B.
+ * Returns -1 for an invalid size or storage. */
+int32_t trt_pitch(int32_t nx, int32_t storage);
+
+/* Elements between population planes i and i+1 (ny * pitch).  -1 if invalid. */
+int64_t trt_plane_stride(int32_t nx, int32_t ny, int32_t storage);
+
+/* Bytes of one population lattice (9 planes).  0 if the problem is invalid. */
+size_t trt_lattice_bytes(const trt_problem *p);
+
+/* Device bytes one simulation needs: two lattices, the mask, and the
+ * library's scratch.  Used for admission by memory budget.  0 if invalid. */
+size_t trt_footprint_bytes(const trt_problem *p);
+
+/* Create a simulation over two caller-owned lattices f_a and f_b (ping-pong:
+ * each step reads one and writes the other; they must not overlap).  The
+ * state starts undefined: call trt_init_equilibrium or trt_set_populations
+ * next.  The problem (including the mask pointer) is copied; the mask memory
+ * must stay valid while the simulation exists.  EINVAL on a NULL or
+ * misaligned pointer, a size out of range, tau_s <= 1/2, tau_s2 < 1/2 or a
+ * non-finite parameter. */
+trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stream,
+                      trt_sim **out);
+
+/* Replace the sweep's launch shape (re-captures the step graph). */
+trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t);
+trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t);
+
+/* f(x, 0) = f^eq(rho, u), the third-order Hermite equilibrium of Eq. 5, at
+ * every fluid node (no non-equilibrium part).  rho, ux, uy: device FP64
+ * [ny][nx]; ux, uy are the velocities that enter f^eq.  Resets time to 0. */
+trt_status trt_init_equilibrium(trt_sim *s, const double *rho, const double *ux,
+                                const double *uy);
+
+/* Set the pre-collision state f(x, t) from a device FP64 array [9][ny][nx]
+ * (unshifted populations; entries at solid nodes are ignored).  Resets
+ * time to 0. */
+trt_status trt_set_populations(trt_sim *s, const double *f);
+
+/* Read the pre-collision state f(x, t) into a device FP64 array
+ * [9][ny][nx] (unshifted; 0 at solid nodes). */
+trt_status trt_get_populations(trt_sim *s, double *f);
+
+/* Advance nsteps >= 0 time steps (Eq. 2 followed by streaming), enqueued on
+ * the stream as a captured HIP graph of two sweeps plus at most one plain
+ * launch. */
+trt_status trt_step(trt_sim *s, int64_t nsteps);
+
+/* rho and He-shifted u (Eq. 13) at time t into device FP64 [ny][nx];
+ * 0 at solid nodes.  Any of the three pointers may be NULL. */
+trt_status trt_macros(trt_sim *s, double *rho, double *ux, double *uy);
+
+/* FP64 diagnostics (see TRT_NDIAG) into device memory out[TRT_NDIAG],
+ * reduced in a fixed order (bitwise reproducible). */
+trt_status trt_diagnostics(trt_sim *s, double *out);
+
+/* Mean of u_x over the fluid nodes of each row, FP64, into device
+ * out[ny] (0 for a row without fluid) -- the slip measurement of Sec. III.C. */
+trt_status trt_row_mean_ux(trt_sim *s, double *out);
+
+/* Synchronous check: runs trt_diagnostics into library scratch, waits for
+ * the stream, and returns TRT_EUNSTABLE if any fluid node diverged. */
+trt_status trt_check(trt_sim *s);
+
+/* Which caller lattice holds the current state (0 = f_a, 1 = f_b), and the
+ * steps taken. */
+trt_status trt_state(const trt_sim *s, int32_t *current, int64_t *time);
+
+void trt_destroy(trt_sim *s);
+
+/* ---- batching: many independent simulations advanced by one launch per
+ * step.  All members must share one storage type and stream; each keeps its
+ * own lattices, parameters and time.  The member objects must outlive the
+ * batch and must not be stepped on their own while it exists. ---- */
+
+/* Build the tile work list over n >= 1 simulations. */
+trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out);
+
+/* Advance every member nsteps steps (graph-captured pairs of launches). */
+trt_status trt_batch_step(trt_batch *b, int64_t nsteps);
+
+/* Diagnostics of every member into device out[n][TRT_NDIAG]. */
+trt_status trt_batch_diagnostics(trt_batch *b, double *out);
+
+/* Launch shape used for the whole batch. */
+trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t);
+
+void trt_batch_destroy(trt_batch *b);
+
+/* Thread-local description of the last error; never NULL. */
+const char *trt_last_error(void);
+
+/* Library version string. */
+const char *trt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRTLBM_H */

@@ -63,6 +63,7 @@ def _bind(lib):
     lib.orc_step.restype = i
     lib.orc_run.argtypes = [i, i, P, P, L, d, d, d, d]
     lib.orc_run.restype = i
+    lib.orc_num_threads.restype = i
     return lib
 
 
@@ -223,6 +224,11 @@ def step(*a, **k):
 
 def run(*a, **k):
     return _inst().run(*a, **k)
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_inst().lib.orc_num_threads())
 
 
 def build_variant(source_text: str, out_path: str) -> str:

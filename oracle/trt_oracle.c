@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 9
 #define DIM 2
@@ -324,4 +327,13 @@ int orc_run(int nx, int ny, const uint8_t *solid, double *f, long nsteps, double
     if (a != f) memcpy(f, a, sizeof(double) * len);
     free(tmp);
     return 0;
+}
+
+/* Threads the OpenMP loops above use (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,519 @@
+// api.hip -- the C ABI of include/trtlbm.h: argument validation, the
+// simulation and batch objects, step-graph capture and error reporting.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/trtlbm.h"
+#include "kernels.hpp"
+
+using trt::InstDesc;
+using trt::Launch;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+trt_status fail(trt_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+trt_status fail_hip(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TRT_EDEVICE;
+}
+
+#define TRT_HIP(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return fail_hip(e_, #expr); \
+    } while (0)
+
+constexpr Launch kDefaultLaunch = {32, 4, 1};
+constexpr int kMaxSide = 46340;
+
+int elem_size(int storage) {
+    switch (storage) {
+        case TRT_F64: return 8;
+        case TRT_F32_SHIFTED: return 4;
+        case TRT_F16_SHIFTED: return 2;
+        default: return 0;
+    }
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+trt_status check_problem(const trt_problem *p) {
+    if (!p) return fail(TRT_EINVAL, "problem is NULL");
+    if (elem_size(p->storage) == 0) return fail(TRT_EINVAL, "unknown storage type");
+    if (p->nx < 1 || p->ny < 1 || p->nx > kMaxSide || p->ny > kMaxSide)
+        return fail(TRT_EINVAL, "nx and ny must lie in [1, 46340]");
+    if (!isfinite(p->tau_s) || !(p->tau_s > 0.5))
+        return fail(TRT_EINVAL, "tau_s must be finite and > 1/2");
+    if (!isfinite(p->tau_s2) || !(p->tau_s2 >= 0.5))
+        return fail(TRT_EINVAL, "tau_s2 must be finite and >= 1/2");
+    if (!isfinite(p->gx) || !isfinite(p->gy)) return fail(TRT_EINVAL, "g must be finite");
+    return TRT_OK;
+}
+
+trt_status check_launch(const trt_tuning *t, Launch &l) {
+    l = kDefaultLaunch;
+    if (!t) return TRT_OK;
+    if (t->rows_per_wave != 0) {
+        if (t->rows_per_wave < 1 || t->rows_per_wave > 4096)
+            return fail(TRT_EINVAL, "rows_per_wave must lie in [1, 4096]");
+        l.rows_per_wave = t->rows_per_wave;
+    }
+    if (t->waves_per_block != 0) {
+        if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
+            return fail(TRT_EINVAL, "waves_per_block must be 1, 2 or 4");
+        l.waves_per_block = t->waves_per_block;
+    }
+    if (t->xcd_remap != -1) {
+        if (t->xcd_remap != 0 && t->xcd_remap != 1)
+            return fail(TRT_EINVAL, "xcd_remap must be -1, 0 or 1");
+        l.xcd_remap = t->xcd_remap;
+    }
+    return TRT_OK;
+}
+
+}  // namespace
+
+struct trt_sim {
+    trt_problem prob;
+    hipStream_t stream;
+    InstDesc desc;  // desc.cur stays 0: the lattice read is passed per launch
+    Launch launch;
+    int cur;        // lattice holding the current state
+    int64_t time;
+    double *scratch;  // diagnostics partials + one TRT_NDIAG result
+    hipStream_t cap_stream;
+    hipGraphExec_t pair;  // captured sweeps 0 -> 1 -> 0
+    bool in_batch;
+};
+
+struct trt_batch {
+    std::vector<trt_sim *> sims;
+    int storage;
+    bool mask;
+    hipStream_t stream;
+    Launch launch;
+    InstDesc *d_descs;
+    int4 *d_items;
+    int nitems;
+    int parity;  // steps taken by the batch, mod 2
+    hipStream_t cap_stream;
+    hipGraphExec_t pair;
+};
+
+namespace {
+
+void release_graph(hipGraphExec_t &g) {
+    if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Capture `body` (which enqueues work on the given stream) into an
+// executable graph.
+template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F body) {
+    hipGraph_t g = nullptr;
+    TRT_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = body(cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail_hip(e, "kernel launch during capture");
+    }
+    if (e2 != hipSuccess) return fail_hip(e2, "hipStreamEndCapture");
+    hipError_t e3 = hipGraphInstantiate(&out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        out = nullptr;
+        return fail_hip(e3, "hipGraphInstantiate");
+    }
+    return TRT_OK;
+}
+
+trt_status sim_capture(trt_sim *s) {
+    release_graph(s->pair);
+    const int st = s->prob.storage;
+    const bool m = s->prob.mask != nullptr;
+    return capture(s->cap_stream, s->pair, [&](hipStream_t cs) {
+        hipError_t e = trt::launch_sweep(s->desc, st, m, 0, s->launch, cs);
+        if (e != hipSuccess) return e;
+        return trt::launch_sweep(s->desc, st, m, 1, s->launch, cs);
+    });
+}
+
+trt_status check_sim(const trt_sim *s) {
+    if (!s) return fail(TRT_EINVAL, "simulation handle is NULL");
+    return TRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t trt_pitch(int32_t nx, int32_t storage) {
+    const int es = elem_size(storage);
+    if (es == 0 || nx < 1 || nx > kMaxSide) return -1;
+    const int per = 256 / es;
+    return (nx + per - 1) / per * per;
+}
+
+int64_t trt_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
+    const int32_t p = trt_pitch(nx, storage);
+    if (p < 0 || ny < 1 || ny > kMaxSide) return -1;
+    return (int64_t)p * ny;
+}
+
+size_t trt_lattice_bytes(const trt_problem *p) {
+    if (check_problem(p) != TRT_OK) return 0;
+    return (size_t)9 * (size_t)trt_plane_stride(p->nx, p->ny, p->storage) *
+           (size_t)elem_size(p->storage);
+}
+
+size_t trt_footprint_bytes(const trt_problem *p) {
+    const size_t lat = trt_lattice_bytes(p);
+    if (lat == 0) return 0;
+    const size_t mask = p->mask ? (size_t)p->nx * p->ny : 0;
+    const size_t scratch = (size_t)(trt::diag_partial_count() + 1) * TRT_NDIAG * sizeof(double);
+    return 2 * lat + mask + scratch;
+}
+
+trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stream,
+                      trt_sim **out) {
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    *out = nullptr;
+    trt_status st = check_problem(p);
+    if (st != TRT_OK) return st;
+    if (!f_a || !f_b) return fail(TRT_EINVAL, "both lattices f_a and f_b are required");
+    if (!aligned(f_a, 256) || !aligned(f_b, 256))
+        return fail(TRT_EINVAL, "lattices must be 256-byte aligned");
+    const size_t bytes = trt_lattice_bytes(p);
+    const char *a = (const char *)f_a, *b = (const char *)f_b;
+    if (a < b + bytes && b < a + bytes) return fail(TRT_EINVAL, "lattices overlap");
+
+    trt_sim *s = new (std::nothrow) trt_sim();
+    if (!s) return fail(TRT_ENOMEM, "out of host memory");
+    s->prob = *p;
+    s->stream = (hipStream_t)hip_stream;
+    s->launch = kDefaultLaunch;
+    s->cur = 0;
+    s->time = 0;
+    InstDesc &d = s->desc;
+    d.buf[0] = f_a;
+    d.buf[1] = f_b;
+    d.mask = p->mask;
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.pitch = trt_pitch(p->nx, p->storage);
+    d.plane = trt_plane_stride(p->nx, p->ny, p->storage);
+    d.cur = 0;
+    d.pad_ = 0;
+    d.omega1 = 1.0 - 1.0 / p->tau_s;
+    d.omega2 = 1.0 - 1.0 / p->tau_s2;
+    d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
+    d.gx = p->gx;
+    d.gy = p->gy;
+    trt::tile(d, s->launch);
+
+    hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
+                                                      TRT_NDIAG * sizeof(double));
+    if (e != hipSuccess) {
+        delete s;
+        return fail_hip(e, "hipMalloc(scratch)");
+    }
+    e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(s->scratch);
+        delete s;
+        return fail_hip(e, "hipStreamCreateWithFlags");
+    }
+    *out = s;
+    return TRT_OK;
+}
+
+trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    Launch l;
+    trt_status st = check_launch(t, l);
+    if (st != TRT_OK) return st;
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    s->launch = l;
+    trt::tile(s->desc, l);
+    release_graph(s->pair);
+    return TRT_OK;
+}
+
+trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!t) return fail(TRT_EINVAL, "out is NULL");
+    t->rows_per_wave = s->launch.rows_per_wave;
+    t->waves_per_block = s->launch.waves_per_block;
+    t->xcd_remap = s->launch.xcd_remap;
+    return TRT_OK;
+}
+
+trt_status trt_init_equilibrium(trt_sim *s, const double *rho, const double *ux,
+                                const double *uy) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!rho || !ux || !uy) return fail(TRT_EINVAL, "rho, ux and uy are required");
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    TRT_HIP(trt::launch_init_equilibrium(s->desc, s->prob.storage, s->cur, rho, ux, uy, s->stream));
+    s->time = 0;
+    return TRT_OK;
+}
+
+trt_status trt_set_populations(trt_sim *s, const double *f) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!f) return fail(TRT_EINVAL, "f is NULL");
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    TRT_HIP(trt::launch_set_populations(s->desc, s->prob.storage, s->cur, f, s->stream));
+    s->time = 0;
+    return TRT_OK;
+}
+
+trt_status trt_get_populations(trt_sim *s, double *f) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!f) return fail(TRT_EINVAL, "f is NULL");
+    TRT_HIP(trt::launch_get_populations(s->desc, s->prob.storage, s->cur, f, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_step(trt_sim *s, int64_t nsteps) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (nsteps < 0) return fail(TRT_EINVAL, "nsteps must be >= 0");
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    if (nsteps == 0) return TRT_OK;
+    const int st = s->prob.storage;
+    const bool m = s->prob.mask != nullptr;
+    if (s->cur == 1) {
+        TRT_HIP(trt::launch_sweep(s->desc, st, m, 1, s->launch, s->stream));
+        s->cur = 0;
+        ++s->time;
+        --nsteps;
+    }
+    if (nsteps >= 2) {
+        if (!s->pair) {
+            trt_status cs = sim_capture(s);
+            if (cs != TRT_OK) return cs;
+        }
+        for (int64_t k = 0; k < nsteps / 2; ++k) TRT_HIP(hipGraphLaunch(s->pair, s->stream));
+        s->time += nsteps / 2 * 2;
+    }
+    if (nsteps % 2) {
+        TRT_HIP(trt::launch_sweep(s->desc, st, m, 0, s->launch, s->stream));
+        s->cur = 1;
+        ++s->time;
+    }
+    return TRT_OK;
+}
+
+trt_status trt_macros(trt_sim *s, double *rho, double *ux, double *uy) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!rho && !ux && !uy) return TRT_OK;
+    TRT_HIP(trt::launch_macros(s->desc, s->prob.storage, s->cur, rho, ux, uy, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_diagnostics(trt_sim *s, double *out) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    TRT_HIP(trt::launch_diagnostics(s->desc, s->prob.storage, s->cur, s->scratch, out,
+                                    (double)s->time, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_row_mean_ux(trt_sim *s, double *out) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    TRT_HIP(trt::launch_row_mean_ux(s->desc, s->prob.storage, s->cur, out, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_check(trt_sim *s) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    double *res = s->scratch + (size_t)trt::diag_partial_count() * TRT_NDIAG;
+    trt_status st = trt_diagnostics(s, res);
+    if (st != TRT_OK) return st;
+    double h[TRT_NDIAG];
+    TRT_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    TRT_HIP(hipStreamSynchronize(s->stream));
+    if (h[4] > 0.0) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "%.0f of %.0f fluid nodes diverged at step %lld", h[4], h[5],
+                 (long long)s->time);
+        return fail(TRT_EUNSTABLE, buf);
+    }
+    return TRT_OK;
+}
+
+trt_status trt_state(const trt_sim *s, int32_t *current, int64_t *time) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (current) *current = s->cur;
+    if (time) *time = s->time;
+    return TRT_OK;
+}
+
+void trt_destroy(trt_sim *s) {
+    if (!s) return;
+    release_graph(s->pair);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->scratch) (void)hipFree(s->scratch);
+    delete s;
+}
+
+// ---------------------------------------------------------------- batches
+
+static trt_status batch_build(trt_batch *b) {
+    std::vector<InstDesc> descs(b->sims.size());
+    std::vector<int4> items;
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        InstDesc d = b->sims[k]->desc;
+        d.cur = b->sims[k]->cur;
+        trt::tile(d, b->launch);
+        descs[k] = d;
+        for (int r = 0; r < d.rowblocks; ++r)
+            for (int c = 0; c < d.strips; ++c) items.push_back(make_int4((int)k, c, r, 0));
+    }
+    if (b->d_descs) (void)hipFree(b->d_descs);
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_descs = nullptr;
+    b->d_items = nullptr;
+    TRT_HIP(hipMalloc((void **)&b->d_descs, descs.size() * sizeof(InstDesc)));
+    TRT_HIP(hipMalloc((void **)&b->d_items, items.size() * sizeof(int4)));
+    TRT_HIP(hipMemcpyAsync(b->d_descs, descs.data(), descs.size() * sizeof(InstDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    TRT_HIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, b->stream));
+    TRT_HIP(hipStreamSynchronize(b->stream));
+    b->nitems = (int)items.size();
+    b->parity = 0;
+    release_graph(b->pair);
+    return TRT_OK;
+}
+
+trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !sims) return fail(TRT_EINVAL, "a batch needs n >= 1 simulations");
+    for (int k = 0; k < n; ++k) {
+        if (!sims[k]) return fail(TRT_EINVAL, "NULL batch member");
+        if (sims[k]->in_batch) return fail(TRT_ESTATE, "simulation already in a batch");
+        if (sims[k]->prob.storage != sims[0]->prob.storage)
+            return fail(TRT_EINVAL, "batch members must share one storage type");
+        if (sims[k]->stream != sims[0]->stream)
+            return fail(TRT_EINVAL, "batch members must share one stream");
+        for (int j = 0; j < k; ++j)
+            if (sims[j] == sims[k]) return fail(TRT_EINVAL, "duplicate batch member");
+    }
+    trt_batch *b = new (std::nothrow) trt_batch();
+    if (!b) return fail(TRT_ENOMEM, "out of host memory");
+    b->sims.assign(sims, sims + n);
+    b->storage = sims[0]->prob.storage;
+    b->mask = false;
+    for (int k = 0; k < n; ++k) b->mask = b->mask || sims[k]->prob.mask != nullptr;
+    b->stream = sims[0]->stream;
+    b->launch = kDefaultLaunch;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return fail_hip(e, "hipStreamCreateWithFlags");
+    }
+    trt_status st = batch_build(b);
+    if (st != TRT_OK) {
+        trt_batch_destroy(b);
+        return st;
+    }
+    for (int k = 0; k < n; ++k) sims[k]->in_batch = true;
+    *out = b;
+    return TRT_OK;
+}
+
+trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+    Launch l;
+    trt_status st = check_launch(t, l);
+    if (st != TRT_OK) return st;
+    // members' cur already reflects every step taken; rebuilding restarts
+    // the batch parity from there
+    b->launch = l;
+    st = batch_build(b);
+    return st;
+}
+
+static void batch_sync_members(trt_batch *b, int64_t n) {
+    for (trt_sim *s : b->sims) {
+        s->time += n;
+        if (n & 1) s->cur ^= 1;
+    }
+}
+
+trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+    if (nsteps < 0) return fail(TRT_EINVAL, "nsteps must be >= 0");
+    int64_t n = nsteps;
+    if (n == 0) return TRT_OK;
+    if (b->parity == 1) {
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, 1,
+                                        b->launch, b->stream));
+        b->parity = 0;
+        batch_sync_members(b, 1);
+        --n;
+    }
+    if (n >= 2) {
+        if (!b->pair) {
+            trt_status cs = capture(b->cap_stream, b->pair, [&](hipStream_t cs2) {
+                hipError_t e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems,
+                                                       b->storage, b->mask, 0, b->launch, cs2);
+                if (e != hipSuccess) return e;
+                return trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage,
+                                               b->mask, 1, b->launch, cs2);
+            });
+            if (cs != TRT_OK) return cs;
+        }
+        for (int64_t k = 0; k < n / 2; ++k) TRT_HIP(hipGraphLaunch(b->pair, b->stream));
+        batch_sync_members(b, n / 2 * 2);
+    }
+    if (n % 2) {
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, 0,
+                                        b->launch, b->stream));
+        b->parity = 1;
+        batch_sync_members(b, 1);
+    }
+    return TRT_OK;
+}
+
+trt_status trt_batch_diagnostics(trt_batch *b, double *out) {
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        trt_status st = trt_diagnostics(b->sims[k], out + k * TRT_NDIAG);
+        if (st != TRT_OK) return st;
+    }
+    return TRT_OK;
+}
+
+void trt_batch_destroy(trt_batch *b) {
+    if (!b) return;
+    for (trt_sim *s : b->sims) s->in_batch = false;
+    release_graph(b->pair);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_descs) (void)hipFree(b->d_descs);
+    if (b->d_items) (void)hipFree(b->d_items);
+    delete b;
+}
+
+const char *trt_last_error(void) { return g_err.c_str(); }
+
+const char *trt_version(void) { return "trtlbm 0.1 (gfx950)"; }
+
+}  // extern "C"

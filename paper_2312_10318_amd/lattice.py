@@ -1,0 +1,198 @@
+"""Python front end of the TRT-RLB library: device memory and streams come
+from PyTorch (ROCm); every step of the method runs in libtrtlbm.so."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import capi
+
+STORAGES = {"f64": capi.TRT_F64, "f32": capi.TRT_F32_SHIFTED, "f16": capi.TRT_F16_SHIFTED}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+DIAG_NAMES = ("mass", "mom_x", "mom_y", "max_speed", "n_diverged", "n_fluid", "min_rho", "time")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the TRT-RLB library needs a ROCm GPU (torch.cuda is unavailable)")
+    return torch
+
+
+def problem(nx, ny, tau_s, tau_s2, g=(0.0, 0.0), storage="f32", mask_ptr=None):
+    """The C problem struct (no device memory touched)."""
+    return capi.trt_problem(int(nx), int(ny), float(tau_s), float(tau_s2), float(g[0]),
+                            float(g[1]), mask_ptr, STORAGES[storage])
+
+
+def footprint_bytes(nx, ny, storage="f32", has_mask=False) -> int:
+    """Device bytes a simulation needs (two lattices, mask, scratch)."""
+    p = problem(nx, ny, 0.6, 0.6, storage=storage, mask_ptr=1 if has_mask else None)
+    return capi.trt_footprint_bytes(p)
+
+
+class Lattice:
+    """One D2Q9 TRT-RLB simulation on the GPU.
+
+    nx, ny      lattice size (periodic in x and y; walls are mask rows)
+    tau_s       tau_s1 > 1/2 (viscosity nu = (tau_s - 1/2) / 3)
+    tau_s2      free third-order relaxation time >= 1/2
+    g           body acceleration (F = rho g)
+    mask        optional [ny, nx] array, nonzero = solid (half-way bounce-back)
+    storage     "f64", "f32" (f - w) or "f16" (f - w)
+    stream      torch.cuda.Stream to enqueue on (default: the current stream)
+    """
+
+    def __init__(self, nx, ny, tau_s, tau_s2, g=(0.0, 0.0), mask=None, storage="f32",
+                 stream=None, device="cuda"):
+        torch = _torch()
+        self.nx, self.ny = int(nx), int(ny)
+        self.tau_s, self.tau_s2 = float(tau_s), float(tau_s2)
+        self.g = (float(g[0]), float(g[1]))
+        self.storage = storage
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.mask = None
+        if mask is not None:
+            m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+            if m.shape != (self.ny, self.nx):
+                raise ValueError("mask must have shape [ny, nx]")
+            self.mask = torch.from_numpy(m).to(self.device)
+        prob = problem(self.nx, self.ny, self.tau_s, self.tau_s2, self.g, storage,
+                       self.mask.data_ptr() if self.mask is not None else None)
+        nbytes = capi.trt_lattice_bytes(prob)
+        if nbytes == 0:
+            capi.trt_create(prob, 0, 0, 0)  # raises with the validation message
+        self.lattice_bytes = nbytes
+        self.fa = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.fb = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = capi.trt_create(prob, self.fa.data_ptr(), self.fb.data_ptr(),
+                                      self.stream.cuda_stream)
+        self._diag = torch.empty(capi.TRT_NDIAG, dtype=torch.float64, device=self.device)
+
+    # ---------------------------------------------------------------- helpers
+    def _dev64(self, a, shape):
+        torch = _torch()
+        t = torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
+        return t
+
+    def _sync(self):
+        self.stream.synchronize()
+
+    # ------------------------------------------------------------------- API
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1):
+        capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap)
+
+    def tuning(self):
+        return capi.trt_get_tuning(self.handle)
+
+    def init_equilibrium(self, rho, ux, uy):
+        shape = (self.ny, self.nx)
+        r, u, v = self._dev64(rho, shape), self._dev64(ux, shape), self._dev64(uy, shape)
+        capi.trt_init_equilibrium(self.handle, r.data_ptr(), u.data_ptr(), v.data_ptr())
+        self._sync()
+        return self
+
+    def set_populations(self, f):
+        t = self._dev64(f, (9, self.ny, self.nx))
+        capi.trt_set_populations(self.handle, t.data_ptr())
+        self._sync()
+        return self
+
+    def get_populations(self):
+        torch = _torch()
+        out = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        capi.trt_get_populations(self.handle, out.data_ptr())
+        self._sync()
+        return out
+
+    def step(self, nsteps=1):
+        capi.trt_step(self.handle, int(nsteps))
+        return self
+
+    def macros(self):
+        """(rho, ux, uy) as float64 device tensors [ny, nx]."""
+        torch = _torch()
+        out = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        n = self.nx * self.ny * 8
+        base = out.data_ptr()
+        capi.trt_macros(self.handle, base, base + n, base + 2 * n)
+        self._sync()
+        return out[0], out[1], out[2]
+
+    def diagnostics(self) -> dict:
+        capi.trt_diagnostics(self.handle, self._diag.data_ptr())
+        self._sync()
+        vals = self._diag.cpu().numpy()
+        return dict(zip(DIAG_NAMES, (float(v) for v in vals)))
+
+    def row_mean_ux(self):
+        torch = _torch()
+        out = torch.empty(self.ny, dtype=torch.float64, device=self.device)
+        capi.trt_row_mean_ux(self.handle, out.data_ptr())
+        self._sync()
+        return out
+
+    def check(self) -> bool:
+        """True while no fluid node has diverged (synchronous)."""
+        return capi.trt_check(self.handle) == capi.TRT_OK
+
+    def state(self):
+        """(index of the lattice holding the state, steps taken)."""
+        return capi.trt_state(self.handle)
+
+    def raw_state(self):
+        """The storage bytes of the current lattice (exact checkpoint)."""
+        cur, t = self.state()
+        return (self.fb if cur else self.fa).clone(), cur, t
+
+    def close(self):
+        if getattr(self, "handle", None):
+            capi.trt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent lattices advanced together, one launch per step."""
+
+    def __init__(self, lattices):
+        if not lattices:
+            raise ValueError("empty batch")
+        self.lattices = list(lattices)
+        self.stream = self.lattices[0].stream
+        self.handle = capi.trt_batch_create([l.handle for l in self.lattices])
+        torch = _torch()
+        self._diag = torch.empty((len(self.lattices), capi.TRT_NDIAG), dtype=torch.float64,
+                                 device=self.lattices[0].device)
+
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1):
+        capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap)
+
+    def step(self, nsteps=1):
+        capi.trt_batch_step(self.handle, int(nsteps))
+        return self
+
+    def diagnostics(self):
+        """[n, TRT_NDIAG] numpy array (synchronous)."""
+        capi.trt_batch_diagnostics(self.handle, self._diag.data_ptr())
+        self.stream.synchronize()
+        return self._diag.cpu().numpy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            capi.trt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

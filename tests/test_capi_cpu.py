@@ -1,0 +1,91 @@
+"""The C ABI library loads without a GPU, exports every symbol its header
+declares, and validates arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_10318_amd import capi, lattice
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "trtlbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trt_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_2312_10318_amd import build
+        build.build()
+    return capi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(capi.EXPORTED) == declared
+
+
+def test_pitch_and_sizes(lib):
+    assert capi.trt_pitch(4096, capi.TRT_F32_SHIFTED) == 4096
+    assert capi.trt_pitch(400, capi.TRT_F32_SHIFTED) == 448
+    assert capi.trt_pitch(400, capi.TRT_F64) == 416
+    assert capi.trt_pitch(400, capi.TRT_F16_SHIFTED) == 512
+    assert capi.trt_pitch(0, capi.TRT_F64) == -1
+    assert capi.trt_pitch(5, 7) == -1
+    assert capi.trt_plane_stride(64, 10, capi.TRT_F64) == 640
+    p = lattice.problem(4096, 4096, 0.6, 3.0, storage="f32")
+    assert capi.trt_lattice_bytes(p) == 9 * 4096 * 4096 * 4
+    assert capi.trt_footprint_bytes(p) >= 2 * 9 * 4096 * 4096 * 4
+    assert lattice.footprint_bytes(400, 200, "f16", has_mask=True) >= 2 * 9 * 512 * 200 * 2 + 80000
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=0), "nx and ny"),
+    (dict(ny=50000), "nx and ny"),
+    (dict(tau_s=0.5), "tau_s"),
+    (dict(tau_s=float("nan")), "tau_s"),
+    (dict(tau_s2=0.49), "tau_s2"),
+    (dict(gx=float("inf")), "g must be finite"),
+    (dict(storage=9), "storage"),
+])
+def test_create_rejects_invalid_problems(lib, kw, msg):
+    args = dict(nx=16, ny=16, tau_s=0.6, tau_s2=1.0, gx=0.0, gy=0.0, storage=1)
+    args.update(kw)
+    p = capi.trt_problem(args["nx"], args["ny"], args["tau_s"], args["tau_s2"], args["gx"],
+                         args["gy"], None, args["storage"])
+    with pytest.raises(capi.TrtError) as e:
+        capi.trt_create(p, 4096, 8192, 0)
+    assert e.value.status == capi.TRT_EINVAL
+    assert msg in str(e.value)
+    assert capi.trt_lattice_bytes(p) == 0
+
+
+def test_create_rejects_bad_buffers(lib):
+    p = capi.trt_problem(16, 16, 0.6, 1.0, 0.0, 0.0, None, 1)
+    for a, b, msg in [(0, 1 << 20, "required"), (256 + 4, 1 << 20, "aligned"),
+                      (1 << 20, (1 << 20) + 256, "overlap")]:
+        with pytest.raises(capi.TrtError) as e:
+            capi.trt_create(p, a, b, 0)
+        assert e.value.status == capi.TRT_EINVAL and msg in str(e.value)
+
+
+def test_null_handles_are_rejected(lib):
+    for fn, args in [(lib.trt_step, (None, 1)), (lib.trt_macros, (None, None, None, None)),
+                     (lib.trt_diagnostics, (None, None)), (lib.trt_batch_step, (None, 1)),
+                     (lib.trt_check, (None,))]:
+        assert fn(*args) == capi.TRT_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.trt_batch_create(0, None, ctypes.byref(out)) == capi.TRT_EINVAL
+    lib.trt_destroy(None)
+    lib.trt_batch_destroy(None)
+    assert "batch" in capi.trt_last_error()
+    assert "gfx950" in capi.trt_version()

@@ -128,6 +128,23 @@ def run_extra(steps):
     return out
 
 
+def profile_run(n, storage, steps, warmup, tuning):
+    """Kernels for rocprofv3: `steps` sweeps of the benchmark lattice, then a
+    plain copy of 1 GiB (known bytes) to scale the HBM counters."""
+    import torch
+    lat = tg_lattice(n, storage, tuning=tuning)
+    lat.step(warmup + steps)
+    torch.cuda.synchronize()
+    lat.close()
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "done", "sweeps": warmup + steps, "copy_bytes": 1 << 30,
+                      "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +155,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default="", help="rows_per_wave,waves_per_block,xcd_remap")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiler driver: run warmup + steps sweeps untimed, then a plain "
+                         "1 GiB device copy (the counter calibration kernel), and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -153,6 +173,9 @@ def main():
 
     n, storage = args.n, args.storage
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    if args.profile:
+        profile_run(n, storage, args.steps, args.warmup, tuning)
+        return
     log("bench: TG %dx%d %s, warmup %d, steps %d" % (n, n, storage, args.warmup, args.steps))
     lat = tg_lattice(n, storage, tuning=tuning)
     ms = time_steps(lat, args.steps, args.warmup)

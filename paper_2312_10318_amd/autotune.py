@@ -1,0 +1,120 @@
+"""Launch-shape autotuner for the fused sweep.
+
+For a lattice shape, storage type and mask presence it times the fused sweep
+over a grid of launch shapes (rows a wavefront marches, wavefronts per
+workgroup, XCD remap on/off) on a scratch lattice of that shape, and keeps
+the fastest.  Results persist in a JSON cache keyed by GPU architecture,
+storage, mask presence and size bucket; the cache path is
+$TRTLBM_TUNE_CACHE, else ~/.cache/trtlbm/tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+ROWS = (4, 8, 16, 32, 64, 128)
+WAVES = (1, 2, 4)
+REMAP = (1, 0)
+
+
+def cache_path() -> str:
+    return os.environ.get("TRTLBM_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "trtlbm", "tune.json"))
+
+
+def _bucket(v: int) -> int:
+    """Power-of-two size bucket (64, 128, ..., 32768)."""
+    return 1 << max(6, min(15, int(round(math.log2(max(1, v))))))
+
+
+def key(nx: int, ny: int, storage: str, has_mask: bool, arch: str = "gfx950") -> str:
+    return "%s|%s|%s|%d|%d" % (arch, storage, "mask" if has_mask else "open", _bucket(nx),
+                               _bucket(ny))
+
+
+def load_cache(path: str | None = None) -> dict:
+    try:
+        with open(path or cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(ny: int):
+    out = []
+    for r in ROWS:
+        if r > max(4, ny):
+            continue
+        for w in WAVES:
+            for x in REMAP:
+                out.append((r, w, x))
+    return out
+
+
+def time_shape(lat, shape, steps: int, warmup: int) -> float:
+    """Milliseconds per sweep for one launch shape on lattice `lat`."""
+    import torch
+    lat.set_tuning(*shape)
+    lat.step(warmup)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(steps)
+    end.record(lat.stream)
+    end.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def tune(nx: int, ny: int, storage: str = "f32", mask=None, steps: int | None = None,
+         shapes=None, log=None) -> dict:
+    """Time every candidate launch shape; returns {"best": shape, "ms": ...,
+    "table": [(shape, ms), ...]}.  The scratch lattice starts at rest."""
+    import numpy as np
+
+    from .lattice import Lattice
+    lat = Lattice(nx, ny, 0.6, 1.0, storage=storage, mask=mask)
+    lat.init_equilibrium(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+    if steps is None:
+        steps = max(10, min(400, int(2e9 / max(1, nx * ny))))
+    table = []
+    for shape in shapes or candidates(ny):
+        ms = time_shape(lat, shape, steps, max(2, steps // 10))
+        table.append((list(shape), ms))
+        if log:
+            log("tune %dx%d %s %s: %.4f ms" % (nx, ny, storage, shape, ms))
+    lat.close()
+    table.sort(key=lambda t: t[1])
+    return {"best": table[0][0], "ms": table[0][1], "table": table,
+            "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+
+
+def best_shape(nx: int, ny: int, storage: str = "f32", has_mask: bool = False,
+               autotune: bool = False, log=None):
+    """Cached best launch shape, tuning (and caching) on a miss when
+    `autotune` is set; None when unknown (the library default applies)."""
+    cache = load_cache()
+    k = key(nx, ny, storage, has_mask)
+    if k in cache:
+        return tuple(cache[k]["best"])
+    if not autotune:
+        return None
+    mask = None
+    if has_mask:
+        import numpy as np
+        mask = np.zeros((ny, nx), np.uint8)
+        mask[0] = mask[-1] = 1
+    res = tune(nx, ny, storage, mask=mask, log=log)
+    cache[k] = {"best": res["best"], "ms": res["ms"], "when": res["when"]}
+    save_cache(cache)
+    return tuple(res["best"])

@@ -11,7 +11,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtrtlbm.so")
+# TRTLBM_LIB selects another build of the same library (e.g. an instrumented
+# or differently compiled copy); the default is the in-tree build.
+LIB_PATH = os.environ.get("TRTLBM_LIB") or os.path.join(HERE, "libtrtlbm.so")
 
 TRT_OK, TRT_EINVAL, TRT_ENOMEM, TRT_EDEVICE, TRT_EUNSTABLE, TRT_ESTATE = range(6)
 TRT_F64, TRT_F32_SHIFTED, TRT_F16_SHIFTED = 0, 1, 2

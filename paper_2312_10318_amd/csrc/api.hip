@@ -101,6 +101,7 @@ struct trt_batch {
     std::vector<trt_sim *> sims;
     int storage;
     bool mask;
+    bool buf;  // every member fits one buffer resource
     hipStream_t stream;
     Launch launch;
     InstDesc *d_descs;
@@ -420,7 +421,11 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     b->sims.assign(sims, sims + n);
     b->storage = sims[0]->prob.storage;
     b->mask = false;
-    for (int k = 0; k < n; ++k) b->mask = b->mask || sims[k]->prob.mask != nullptr;
+    b->buf = true;
+    for (int k = 0; k < n; ++k) {
+        b->mask = b->mask || sims[k]->prob.mask != nullptr;
+        b->buf = b->buf && trt::buffer_addressable(sims[k]->desc, sims[k]->prob.storage);
+    }
     b->stream = sims[0]->stream;
     b->launch = kDefaultLaunch;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -463,7 +468,7 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
     int64_t n = nsteps;
     if (n == 0) return TRT_OK;
     if (b->parity == 1) {
-        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, 1,
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf, 1,
                                         b->launch, b->stream));
         b->parity = 0;
         batch_sync_members(b, 1);
@@ -473,10 +478,11 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
         if (!b->pair) {
             trt_status cs = capture(b->cap_stream, b->pair, [&](hipStream_t cs2) {
                 hipError_t e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems,
-                                                       b->storage, b->mask, 0, b->launch, cs2);
+                                                       b->storage, b->mask, b->buf, 0, b->launch,
+                                                       cs2);
                 if (e != hipSuccess) return e;
                 return trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage,
-                                               b->mask, 1, b->launch, cs2);
+                                               b->mask, b->buf, 1, b->launch, cs2);
             });
             if (cs != TRT_OK) return cs;
         }
@@ -484,7 +490,7 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
         batch_sync_members(b, n / 2 * 2);
     }
     if (n % 2) {
-        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, 0,
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf, 0,
                                         b->launch, b->stream));
         b->parity = 1;
         batch_sync_members(b, 1);

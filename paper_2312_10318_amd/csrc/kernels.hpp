@@ -26,11 +26,17 @@ inline void tile(InstDesc &d, const Launch &l) {
 hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, const Launch &l,
                         hipStream_t stream);
 
+// Whether a lattice of this instance fits one buffer resource (<= 4 GiB),
+// which selects the buffer-instruction variant of the sweep.
+bool buffer_addressable(const InstDesc &d, int storage);
+
 // One fused sweep of every instance of a batch.  descs: device InstDesc[n];
 // items: device int4[nitems] of (instance, strip, rowblock, 0); the lattice
-// read by instance k is buf[descs[k].cur ^ flip].
+// read by instance k is buf[descs[k].cur ^ flip].  `buf` may be true only if
+// every instance is buffer_addressable.
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
-                              bool mask, int flip, const Launch &l, hipStream_t stream);
+                              bool mask, bool buf, int flip, const Launch &l,
+                              hipStream_t stream);
 
 // Pre-collision state <-> device FP64 [9][ny][nx]; f^eq initialisation.
 hipError_t launch_set_populations(const InstDesc &d, int storage, int src, const double *f,

@@ -57,9 +57,8 @@ template <> struct Store<ST_F16> {
     static constexpr bool shifted = true;
 };
 
-// Columns one wavefront produces: lanes 1..62 write, lanes 0 and 63 supply
-// the x-neighbours' Phi_x at the strip edges.
-constexpr int kStripWidth = 62;
+// Columns one wavefront produces (one per lane).
+constexpr int kStripWidth = 64;
 
 // Everything one instance's sweep needs.  buf[0], buf[1] are the caller's
 // two lattices; the step reading buf[s] writes buf[1 - s].
@@ -103,10 +102,17 @@ __device__ __forceinline__ float to_c(_Float16 v) { return (float)v; }
 
 template <class T, class C> __device__ __forceinline__ T from_c(C v) { return (T)v; }
 
-// Correctly rounded reciprocal (the hardware approximation's error is
-// systematic for rho close to 1 and would bias the velocity).
+// Reciprocal of the density.  FP32: the hardware estimate refined by one
+// Newton step (error ~1e-14 before the final rounding), which removes the
+// estimate's systematic error for rho close to 1 -- that error would bias
+// the velocity coherently from step to step -- at a third of the cost of a
+// correctly rounded division.  FP64: correctly rounded division.
 __device__ __forceinline__ double recip(double r) { return 1.0 / r; }
-__device__ __forceinline__ float recip(float r) { return 1.0f / r; }
+__device__ __forceinline__ float recip(float r) {
+    const float y = __builtin_amdgcn_rcpf(r);
+    const float e = __builtin_fmaf(-r, y, 1.0f);
+    return __builtin_fmaf(e, y, y);
+}
 
 // Moments of one node (Eqs. 12-13): base = sum_i f_i (shifted: delta rho),
 // rho, j = sum_i e_i f_i, and the He-shifted velocity u = j / rho + g / 2
@@ -157,10 +163,16 @@ __device__ __forceinline__ void equilibrium(C f[9], C base, C rho, C ux, C uy) {
     reconstruct<C>(f, base, rux, ruy, rux * ux, ruy * uy, exy, exy * ux, exy * uy);
 }
 
-// Collision of one node, Eq. 2 (post-collision state overwrites f).
+// Hermite coefficients of the post-collision state of one node (Eq. 2),
+// except for the y-gradient of Phi, which the sweep adds to b_yy once the
+// row above has been gathered (-phi * dPhi_y).
+template <class C> struct Coeffs {
+    C base, bx, by, bxx, byy, bxy, bxxy, bxyy;
+};
+
 template <class C, bool SHIFTED>
-__device__ __forceinline__ void collide(C f[9], const Moments<C, SHIFTED> &m, C dphix, C dphiy,
-                                        C w1, C w2, C phi, C gx, C gy) {
+__device__ __forceinline__ Coeffs<C> collide_coeffs(const C f[9], const Moments<C, SHIFTED> &m,
+                                                    C dphix, C w1, C w2, C phi, C gx, C gy) {
     const C third = C(1) / C(3);
     const C Fx = m.rho * gx, Fy = m.rho * gy;
     // raw moments of the (possibly shifted) populations
@@ -180,13 +192,152 @@ __device__ __forceinline__ void collide(C f[9], const Moments<C, SHIFTED> &m, C 
     const C axxy = qxxy - m.jy * third - exxy;
     const C axyy = qxyy - m.jx * third - exyy;
     // collected Hermite coefficients of f* (relaxation + G_i + F_i)
-    const C bx = m.jx + Fx, by = m.jy + Fy;
-    const C bxx = exx + w1 * axx + phi * (C(2) * Fx * m.ux - dphix);
-    const C byy = eyy + w1 * ayy + phi * (C(2) * Fy * m.uy - dphiy);
-    const C bxy = exy + w1 * axy + phi * (Fx * m.uy + m.ux * Fy);
-    const C bxxy = exxy + w2 * axxy;
-    const C bxyy = exyy + w2 * axyy;
-    reconstruct<C>(f, m.base, bx, by, bxx, byy, bxy, bxxy, bxyy);
+    Coeffs<C> c;
+    c.base = m.base;
+    c.bx = m.jx + Fx;
+    c.by = m.jy + Fy;
+    c.bxx = exx + w1 * axx + phi * (C(2) * Fx * m.ux - dphix);
+    c.byy = eyy + w1 * ayy + phi * (C(2) * Fy * m.uy);
+    c.bxy = exy + w1 * axy + phi * (Fx * m.uy + m.ux * Fy);
+    c.bxxy = exxy + w2 * axxy;
+    c.bxyy = exyy + w2 * axyy;
+    return c;
+}
+
+// Collision of one node, Eq. 2 (post-collision state overwrites f).
+template <class C, bool SHIFTED>
+__device__ __forceinline__ void collide(C f[9], const Moments<C, SHIFTED> &m, C dphix, C dphiy,
+                                        C w1, C w2, C phi, C gx, C gy) {
+    Coeffs<C> c = collide_coeffs<C, SHIFTED>(f, m, dphix, w1, w2, phi, gx, gy);
+    reconstruct<C>(f, c.base, c.bx, c.by, c.bxx, c.byy - phi * dphiy, c.bxy, c.bxxy, c.bxyy);
+}
+
+// Load of one element at a wave-uniform base plus a per-lane byte offset
+// below 4 GiB: this form maps onto the scalar-base + 32-bit vector-offset
+// global load, so a lane keeps three column offsets instead of nine 64-bit
+// addresses.
+// The base goes through readfirstlane so that loop strength reduction cannot
+// fold it into per-lane 64-bit induction pointers, and is re-typed as a
+// global (address space 1) pointer so that the access stays a global (not a
+// flat) memory instruction.
+template <class T> using gptr = __attribute__((address_space(1))) T *;
+
+template <class T> __device__ __forceinline__ uint64_t wave_uniform_addr(const T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_at(const T *__restrict__ base, uint32_t off) {
+    const uint64_t b = wave_uniform_addr(base);
+    return *(gptr<const T>)(b + off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T *__restrict__ base, uint32_t off, T v) {
+    const uint64_t b = wave_uniform_addr(base);
+    *(gptr<T>)(b + off) = v;
+}
+
+// Buffer-instruction access to a lattice of at most 4 GiB: a 128-bit buffer
+// resource (base, byte range) in scalar registers, a wave-uniform byte
+// offset (population plane and row) in a scalar register and the lane's
+// column byte offset in one vector register.  Every access is range-checked
+// by the hardware against the lattice size.  The third descriptor word is
+// the gfx9-family raw-buffer format (32-bit data format, as used by the ROCm
+// composable-kernel library for these targets).
+constexpr uint32_t kRawBufferWord3 = 0x00020000u;
+// Cache-policy bits of the sweep's population stores.
+#ifndef TRT_STORE_CPOL
+#define TRT_STORE_CPOL 2  // nt: streaming stores (measured +1.5-2% on the sweep)
+#endif
+
+template <class T> struct BufAccess {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BufAccess(const void *base, uint64_t bytes) {
+        r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
+                                              (int)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes),
+                                              (int)kRawBufferWord3);
+    }
+    __device__ __forceinline__ T ld(int64_t elem, uint32_t voff) const;
+    __device__ __forceinline__ void st(int64_t elem, uint32_t voff, T v) const;
+};
+template <> __device__ __forceinline__ float BufAccess<float>::ld(int64_t e, uint32_t v) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, (uint32_t)(e * 4), 0));
+}
+template <> __device__ __forceinline__ void BufAccess<float>::st(int64_t e, uint32_t v, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, (uint32_t)(e * 4), TRT_STORE_CPOL);
+}
+template <> __device__ __forceinline__ _Float16 BufAccess<_Float16>::ld(int64_t e, uint32_t v) const {
+    return __builtin_bit_cast(_Float16,
+                              (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, v, (uint32_t)(e * 2), 0));
+}
+template <> __device__ __forceinline__ void BufAccess<_Float16>::st(int64_t e, uint32_t v, _Float16 x) const {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, (uint32_t)(e * 2), TRT_STORE_CPOL);
+}
+template <> __device__ __forceinline__ double BufAccess<double>::ld(int64_t e, uint32_t v) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, (uint32_t)(e * 8), 0));
+}
+template <> __device__ __forceinline__ void BufAccess<double>::st(int64_t e, uint32_t v, double x) const {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, (uint32_t)(e * 8), TRT_STORE_CPOL);
+}
+
+// Pointer access (any lattice size): wave-uniform element offset + lane
+// byte offset through the global-address-space helpers above.
+template <class T> struct PtrAccess {
+    T *p;
+    __device__ __forceinline__ PtrAccess(const void *base, uint64_t) : p((T *)base) {}
+    __device__ __forceinline__ T ld(int64_t e, uint32_t v) const { return ld_at<T>(p + e, v); }
+    __device__ __forceinline__ void st(int64_t e, uint32_t v, T x) const { st_at<T>(p + e, v, x); }
+};
+
+// Pull-gather for a lattice without solid nodes.  ym, y, yp are the wrapped
+// rows, om, oc, op the byte offsets of the wrapped columns x-1, x, x+1.
+template <class T, class C>
+__device__ __forceinline__ void gather_open(const T *__restrict__ src, int64_t plane, int pitch,
+                                            int ym, int y, int yp, uint32_t om, uint32_t oc,
+                                            uint32_t op, C f[9]) {
+    const T *r0 = src + (int64_t)y * pitch;
+    const T *rm = src + (int64_t)ym * pitch;
+    const T *rp = src + (int64_t)yp * pitch;
+    f[0] = to_c(ld_at(r0, oc));
+    f[1] = to_c(ld_at(r0 + plane, om));
+    f[2] = to_c(ld_at(rm + 2 * plane, oc));
+    f[3] = to_c(ld_at(r0 + 3 * plane, op));
+    f[4] = to_c(ld_at(rp + 4 * plane, oc));
+    f[5] = to_c(ld_at(rm + 5 * plane, om));
+    f[6] = to_c(ld_at(rm + 6 * plane, op));
+    f[7] = to_c(ld_at(rp + 7 * plane, op));
+    f[8] = to_c(ld_at(rp + 8 * plane, om));
+}
+
+// Raw pull-gather with walls: like gather() below but without widening;
+// returns whether the node itself is solid.
+template <class T>
+__device__ __forceinline__ bool gather_masked_raw(const T *__restrict__ src, int64_t plane,
+                                                  int pitch, const uint8_t *__restrict__ mask,
+                                                  int nx, int ym, int y, int yp, int xm, int xc,
+                                                  int xp, T v[9]) {
+    const T *r0 = src + (int64_t)y * pitch;
+    const T *rm = src + (int64_t)ym * pitch;
+    const T *rp = src + (int64_t)yp * pitch;
+    const uint8_t *mm = mask + (int64_t)ym * nx;
+    const uint8_t *m0 = mask + (int64_t)y * nx;
+    const uint8_t *mp = mask + (int64_t)yp * nx;
+    const T *a[9] = {r0 + xc,
+                     m0[xm] ? r0 + 3 * plane + xc : r0 + plane + xm,
+                     mm[xc] ? r0 + 4 * plane + xc : rm + 2 * plane + xc,
+                     m0[xp] ? r0 + 1 * plane + xc : r0 + 3 * plane + xp,
+                     mp[xc] ? r0 + 2 * plane + xc : rp + 4 * plane + xc,
+                     mm[xm] ? r0 + 7 * plane + xc : rm + 5 * plane + xm,
+                     mm[xp] ? r0 + 8 * plane + xc : rm + 6 * plane + xp,
+                     mp[xp] ? r0 + 5 * plane + xc : rp + 7 * plane + xp,
+                     mp[xm] ? r0 + 6 * plane + xc : rp + 8 * plane + xm};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = a[i][0];
+    return m0[xc] != 0;
 }
 
 // Pull-gather of the pre-collision populations f_i(x, t) of node (xc, y)

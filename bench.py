@@ -17,7 +17,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -30,16 +29,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}  # 9 reads + 9 writes per node
-SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp"]
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_tg4096_f32_hbm_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_tg%d_%s_hbm_counters.json")
 
 
 def sweep_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2312_10318_amd.profiling import sweep_source_hash as h
+    return h()
 
 
 def log(msg):
@@ -103,7 +98,7 @@ def traffic_from_counters(n, storage):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current sweep source; else None."""
     try:
-        with open(COUNTERS_FILE) as fh:
+        with open(COUNTERS_FILE % (n, storage)) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -113,8 +108,63 @@ def traffic_from_counters(n, storage):
     return c.get("hbm_bytes_per_launch")
 
 
+def run_batch(count=256, steps=5000, storage="f32", seed=0):
+    """The batched workload: `count` independent periodic lattices (sides
+    log-uniform in [64, 1024], half Taylor-Green and half double shear layer,
+    Re log-uniform in [1e2, 1e7], tau_s2 uniform in [0.5, 2]) advanced by one
+    batched launch per step (graph-captured pairs)."""
+    import torch
+    from paper_2312_10318_amd import inputs
+    from paper_2312_10318_amd.lattice import Batch, Lattice
+    members = inputs.batch_workload(count, seed=seed)
+    lats = []
+    for k, m in enumerate(members):
+        rho, ux, uy = inputs.member_fields(m, seed=k)
+        lats.append(Lattice(m.n, m.n, m.tau1, m.tau2, storage=storage).init_equilibrium(rho, ux, uy))
+    b = Batch(lats)
+    b.step(20)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    b.step(steps)
+    end.record(b.stream)
+    end.synchronize()
+    sec = start.elapsed_time(end) * 1e-3
+    diag = b.diagnostics()
+    nodes = sum(m.n * m.n for m in members)
+    b.close()
+    for l in lats:
+        l.close()
+    bad = [k for k in range(count) if diag[k, 4] > 0]
+    return {"instances": count, "steps": steps, "storage": storage, "nodes": nodes,
+            "seconds": round(sec, 4), "solves_per_s": round(count / sec, 3),
+            "aggregate_MLUPS": round(nodes * steps / sec / 1e6, 1),
+            "diverged_instances": len(bad),
+            "diverged": ["%s n=%d Re=%.3g 1/tau2=%.3f" % (members[k].kind, members[k].n,
+                                                         members[k].re, 1 / members[k].tau2)
+                         for k in bad[:40]]}
+
+
+def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
+    """Poisson solve stream through the continuous-batching server."""
+    from paper_2312_10318_amd import serving
+    reqs = serving.serving_workload(rate=rate, duration=duration, seed=seed)
+    ex = serving.GpuExecutor(storage)
+    sched = serving.Scheduler(ex, budget_bytes=int(budget_gb * (1 << 30)), quantum=100)
+    t0 = time.perf_counter()
+    res = sched.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.shutdown()
+    out = serving.summarize(res, wall)
+    out.update({"storage": storage, "offered_rate_per_s": rate, "arrival_window_s": duration,
+                "peak_active": sched.peak_active, "peak_bytes": sched.peak_used,
+                "quanta": sched.quanta})
+    return out
+
+
 def run_extra(steps):
-    """Companion measurements: the same lattice in FP16 and FP64 storage."""
+    """Companion measurements: the same lattice in FP16 and FP64 storage,
+    the batched workload, and the serving stream (FP16 and FP32)."""
     out = {}
     for storage in ("f16", "f64"):
         lat = tg_lattice(4096, storage)
@@ -125,6 +175,11 @@ def run_extra(steps):
             "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5),
             "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / (HBM_PEAK_GBS * 1e9), 4)}
         log("extra %s: %.1f MLUPS" % (storage, mlups))
+    out["batch256_f32"] = run_batch()
+    log("extra batch: %s" % out["batch256_f32"])
+    for storage in ("f16", "f32"):
+        out["serving_" + storage] = run_serving(storage)
+        log("extra serving %s: %s" % (storage, out["serving_" + storage]))
     return out
 
 
@@ -142,7 +197,8 @@ def profile_run(n, storage, steps, warmup, tuning):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"profile": "done", "sweeps": warmup + steps, "copy_bytes": 1 << 30,
-                      "copies": 3}), flush=True)
+                      "copies": 3, "storage": storage, "n": n,
+                      "source_hash": sweep_source_hash()}), flush=True)
 
 
 def main():

@@ -74,10 +74,12 @@ typedef struct {
     int32_t storage;       /* trt_storage */
 } trt_problem;
 
-/* Launch shape of the fused sweep.  Zero fields take the built-in default. */
+/* Launch shape of the fused sweep.  Zero fields take the built-in default
+ * (rows per wavefront chosen from the lattice size, 4 wavefronts per
+ * workgroup, XCD remap on).  trt_get_tuning reports the rows in effect. */
 typedef struct {
-    int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 */
-    int32_t waves_per_block; /* wavefronts per workgroup, 1..16 */
+    int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 (0: automatic) */
+    int32_t waves_per_block; /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default */
 } trt_tuning;
 

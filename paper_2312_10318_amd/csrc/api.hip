@@ -34,7 +34,9 @@ trt_status fail_hip(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return fail_hip(e_, #expr); \
     } while (0)
 
-constexpr Launch kDefaultLaunch = {32, 4, 1};
+// Default launch shape: rows per wave chosen per lattice (auto_rows), four
+// wavefronts per workgroup, XCD-contiguous workgroup order.
+constexpr Launch kDefaultLaunch = {0, 4, 1};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -66,7 +68,7 @@ trt_status check_launch(const trt_tuning *t, Launch &l) {
     if (!t) return TRT_OK;
     if (t->rows_per_wave != 0) {
         if (t->rows_per_wave < 1 || t->rows_per_wave > 4096)
-            return fail(TRT_EINVAL, "rows_per_wave must lie in [1, 4096]");
+            return fail(TRT_EINVAL, "rows_per_wave must be 0 (automatic) or lie in [1, 4096]");
         l.rows_per_wave = t->rows_per_wave;
     }
     if (t->waves_per_block != 0) {
@@ -224,7 +226,7 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
     d.gx = p->gx;
     d.gy = p->gy;
-    trt::tile(d, s->launch);
+    trt::tile(d, s->launch, p->storage);
 
     hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
                                                       TRT_NDIAG * sizeof(double));
@@ -249,7 +251,7 @@ trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
     if (st != TRT_OK) return st;
     if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
     s->launch = l;
-    trt::tile(s->desc, l);
+    trt::tile(s->desc, l, s->prob.storage);
     release_graph(s->pair);
     return TRT_OK;
 }
@@ -257,7 +259,7 @@ trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
 trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!t) return fail(TRT_EINVAL, "out is NULL");
-    t->rows_per_wave = s->launch.rows_per_wave;
+    t->rows_per_wave = s->desc.rows;
     t->waves_per_block = s->launch.waves_per_block;
     t->xcd_remap = s->launch.xcd_remap;
     return TRT_OK;
@@ -380,7 +382,7 @@ static trt_status batch_build(trt_batch *b) {
     for (size_t k = 0; k < b->sims.size(); ++k) {
         InstDesc d = b->sims[k]->desc;
         d.cur = b->sims[k]->cur;
-        trt::tile(d, b->launch);
+        trt::tile(d, b->launch, b->sims[k]->prob.storage);
         descs[k] = d;
         for (int r = 0; r < d.rowblocks; ++r)
             for (int c = 0; c < d.strips; ++c) items.push_back(make_int4((int)k, c, r, 0));

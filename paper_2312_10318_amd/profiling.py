@@ -1,0 +1,179 @@
+"""Turn rocprofv3 output for the benchmark workload into the short summaries
+kept under profiles/.
+
+Three profiler runs of `python3 bench.py --profile ...` (sweeps of the
+benchmark lattice followed by a plain 1 GiB device copy):
+
+  rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- python3 bench.py --profile ...
+  rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- python3 bench.py --profile ...
+  rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- python3 bench.py --profile ...
+
+FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Each is scaled
+by the ratio of the copy kernel's known bytes (1 GiB read, 1 GiB written) to
+what the same counter reads for that copy, so the sweep's HBM traffic is in
+bytes of the same kind as the algorithmic figure.
+
+  python -m paper_2312_10318_amd.profiling <T> <F> <W> --storage f32 --n 4096 \
+      --steps 10 --warmup 2 --out profiles/sweep_tg4096_f32 --run-log <stdout of a run>
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp"]
+COPY_BYTES = 1 << 30
+BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _csv(d, suffix):
+    fs = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not fs:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    with open(fs[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _is_sweep(name):
+    return "sweep_single_kernel" in name
+
+
+def _is_copy(name):
+    return "copyBuffer" in name
+
+
+def kernel_durations(trace_dir):
+    rows = _csv(trace_dir, "kernel_trace.csv")
+    sweep, copy = [], []
+    name = None
+    for r in rows:
+        dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        if _is_sweep(r["Kernel_Name"]):
+            sweep.append(dt)
+            name = r["Kernel_Name"]
+        elif _is_copy(r["Kernel_Name"]):
+            copy.append(dt)
+    return sweep, copy, name
+
+
+def counter_values(pmc_dir, counter):
+    rows = _csv(pmc_dir, "counter_collection.csv")
+    sweep, copy = [], []
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if _is_sweep(r["Kernel_Name"]):
+            sweep.append(v)
+        elif _is_copy(r["Kernel_Name"]):
+            copy.append(v)
+    return sweep, copy
+
+
+def _run_hash(log_path):
+    """The sweep source hash that `bench.py --profile` printed at run time."""
+    with open(log_path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"profile"' in line:
+                return json.loads(line).get("source_hash")
+    raise ValueError("no profile record in " + log_path)
+
+
+def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_prefix,
+              skip_first=2, run_log=None):
+    sweep_ns, copy_ns, kname = kernel_durations(trace_dir)
+    fs, fc = counter_values(fetch_dir, "FETCH_SIZE")
+    ws, wc = counter_values(write_dir, "WRITE_SIZE")
+    # the first dispatches include cold-cache and launch warm-up effects
+    sweep_ns, fs, ws = sweep_ns[skip_first:], fs[skip_first:], ws[skip_first:]
+    avg = lambda v: sum(v) / len(v)
+    fetch_scale = COPY_BYTES / (avg(fc) * 1024.0)
+    write_scale = COPY_BYTES / (avg(wc) * 1024.0)
+    fetch_b = avg(fs) * 1024.0 * fetch_scale
+    write_b = avg(ws) * 1024.0 * write_scale
+    nodes = n * n
+    alg = BYTES_PER_LU[storage] * nodes
+    dur = avg(sweep_ns) * 1e-9
+    rec = {
+        "kernel": (re.search(r"sweep_single_kernel<[^>]*>", kname or "") or
+                   re.search(r".*", "sweep")).group(0),
+        "workload": "taylor_green_%dx%d" % (n, n), "storage": storage, "nodes": nodes,
+        "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
+        "dispatches": len(sweep_ns), "avg_duration_us": round(dur * 1e6, 3),
+        "algorithmic_bytes_per_launch": alg,
+        "achieved_GBps_algorithmic": round(alg / dur / 1e9, 1),
+        "fetch_counter_KiB": round(avg(fs), 1), "write_counter_KiB": round(avg(ws), 1),
+        "copy_fetch_counter_KiB": round(avg(fc), 1), "copy_write_counter_KiB": round(avg(wc), 1),
+        "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+        "hbm_read_bytes_per_launch": int(fetch_b), "hbm_write_bytes_per_launch": int(write_b),
+        "hbm_bytes_per_launch": int(fetch_b + write_b),
+        "traffic_over_algorithmic": round((fetch_b + write_b) / alg, 4),
+        "hbm_GBps_measured": round((fetch_b + write_b) / dur / 1e9, 1),
+        "copy_avg_duration_us": round(avg(copy_ns) * 1e-3, 3) if copy_ns else None,
+    }
+    cmd = ("python3 bench.py --profile --storage %s --n %d --steps %d --warmup %d"
+           % (storage, n, steps, warmup))
+    with open(out_prefix + "_hbm_counters.json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+    with open(out_prefix + ".md", "w") as fh:
+        fh.write("# Fused sweep, Taylor-Green %dx%d, %s storage\n\n" % (n, n, storage))
+        fh.write("Commands (run from the repository root, one profiler run each):\n\n")
+        fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
+        fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
+        fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)
+        fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --storage %s --n %d "
+                 "--steps %d --warmup %d --out %s\n\n" % (storage, n, steps, warmup,
+                                                         os.path.relpath(out_prefix, ROOT)))
+        fh.write("| quantity | value |\n|---|---|\n")
+        for k, v in rec.items():
+            fh.write("| %s | %s |\n" % (k, v))
+        fh.write("\nCounters are KiB per dispatch; the scale factors are 1 GiB divided by "
+                 "what the same counter reads for a plain 1 GiB device copy.\n")
+        stats = _csv(trace_dir, "kernel_stats.csv")
+        fh.write("\n`--kernel-trace --stats` summary (durations in ns):\n\n")
+        fh.write("| kernel | calls | average | min | max |\n|---|---|---|---|---|\n")
+        for r in stats:
+            nm = r["Name"]
+            m = re.search(r"(\w+_kernel<[^>]*>|copyBuffer)", nm)
+            fh.write("| %s | %s | %.0f | %s | %s |\n" % (m.group(1) if m else nm[:40],
+                     r["Calls"], float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("trace_dir")
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--run-log", default=None,
+                    help="stdout of the profiled bench.py run (carries the source hash the "
+                         "profiled kernel was built from)")
+    a = ap.parse_args()
+    rec = summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.storage, a.n, a.steps, a.warmup,
+                    os.path.join(ROOT, a.out) if not os.path.isabs(a.out) else a.out,
+                    run_log=a.run_log)
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,270 @@
+"""Continuous-batching solve server for parameter-sweep TRT-RLB requests.
+
+Requests (a lattice, its relaxation times, force, optional obstacle mask,
+initial fields and a step budget) arrive over time.  The scheduler admits a
+request as soon as a slot is free and its device footprint fits the memory
+budget, keeps every admitted lattice resident on the device, and advances
+all active lattices together in quanta of steps: one batched launch per step
+covers every active lattice (lattices with and without obstacles go in two
+launches).  A request that arrives while others run joins at the next
+quantum boundary; a finished request leaves at the quantum boundary where
+its budget is used up, its slot and memory are reused at once.  Latency is
+measured from arrival to the result being on the host.
+
+The scheduler talks to an executor; ``GpuExecutor`` runs the HIP library.
+Quanta never cross a request's budget, so each result is exactly the result
+of running that request alone (the sweep's arithmetic per node does not
+depend on which other lattices share the launch).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import math
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import inputs, params
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str                 # "cylinder", "poiseuille" or "taylor_green"
+    nx: int
+    ny: int
+    tau1: float
+    tau2: float
+    steps: int
+    g: tuple = (0.0, 0.0)
+    mask: Optional[np.ndarray] = None
+    fields: Optional[Callable[[], tuple]] = None   # -> (rho, ux, uy), float64 [ny, nx]
+    arrival: float = 0.0      # seconds since the start of the run
+    meta: dict = dataclasses.field(default_factory=dict)
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    diverged: bool
+    diagnostics: dict
+    nodes: int = 0
+    fields: Optional[tuple] = None  # (rho, ux, uy) numpy, when kept
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Scheduler:
+    """Admission by memory budget and slot count; FIFO order; quanta of at
+    most `quantum` steps that never cross a request's step budget."""
+
+    def __init__(self, executor, budget_bytes: int, max_slots: int = 4096,
+                 quantum: int = 100, keep_fields: bool = False, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_slots = max_slots
+        self.quantum = quantum
+        self.keep_fields = keep_fields
+        self.clock = clock
+        self.queue = collections.deque()
+        self.active = {}          # rid -> [request, handle, remaining, admitted_at, footprint]
+        self.used = 0
+        self.results = []
+        self.t0 = None
+        self.peak_used = 0
+        self.peak_active = 0
+        self.quanta = 0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def submit(self, req: Request):
+        fp = self.ex.footprint(req)
+        if fp > self.budget:
+            raise ValueError("request %d needs %d bytes, more than the whole budget" %
+                             (req.rid, fp))
+        self.queue.append((req, fp))
+
+    def _admit(self):
+        while self.queue and len(self.active) < self.max_slots:
+            req, fp = self.queue[0]
+            if self.used + fp > self.budget:
+                break  # FIFO: the head waits for memory, later requests wait behind it
+            self.queue.popleft()
+            handle = self.ex.start(req)
+            self.used += fp
+            self.active[req.rid] = [req, handle, req.steps, self.now(), fp]
+        self.peak_used = max(self.peak_used, self.used)
+        self.peak_active = max(self.peak_active, len(self.active))
+
+    def _retire(self, rid):
+        req, handle, _, admitted, fp = self.active.pop(rid)
+        diag, fields = self.ex.finish(handle, keep_fields=self.keep_fields)
+        self.ex.close(handle)
+        self.used -= fp
+        diverged = bool(diag.get("n_diverged", 0) > 0)
+        self.results.append(Result(req.rid, req.kind, req.arrival, admitted, self.now(),
+                                   req.steps, diverged, diag, req.nx * req.ny, fields))
+
+    def step_quantum(self):
+        """Advance every active request by one quantum (host-synchronous)."""
+        if not self.active:
+            return
+        q = min(self.quantum, min(a[2] for a in self.active.values()))
+        self.ex.step([a[1] for a in self.active.values()], q)
+        self.quanta += 1
+        done = []
+        for rid, a in self.active.items():
+            a[2] -= q
+            if a[2] <= 0:
+                done.append(rid)
+        for rid in done:
+            self._retire(rid)
+
+    def run(self, arrivals, idle_sleep: float = 2e-4):
+        """Serve a list of requests whose `arrival` times are seconds from
+        now; returns the results in completion order."""
+        pending = [(r.arrival, r.rid, r) for r in arrivals]
+        heapq.heapify(pending)
+        self.t0 = self.clock()
+        while pending or self.queue or self.active:
+            t = self.now()
+            while pending and pending[0][0] <= t:
+                _, _, r = heapq.heappop(pending)
+                self.submit(r)
+            self._admit()
+            if self.active:
+                self.step_quantum()
+            elif pending:
+                wait = pending[0][0] - self.now()
+                if wait > 0:
+                    time.sleep(min(wait, idle_sleep * 50))
+            elif self.queue:
+                raise RuntimeError("queued request cannot be admitted (budget or slots)")
+        return self.results
+
+
+def summarize(results, wall: float) -> dict:
+    lat = np.array([r.latency for r in results]) if results else np.zeros(1)
+    lups = sum(r.nodes * r.steps for r in results)
+    out = {"solves": len(results), "wall_s": round(wall, 3),
+           "solves_per_s": round(len(results) / wall, 2) if wall > 0 else None,
+           "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+           "mean_latency_s": round(float(np.mean(lat)), 4),
+           "diverged": int(sum(r.diverged for r in results))}
+    if lups:
+        out["aggregate_MLUPS"] = round(lups / wall / 1e6, 1)
+    return out
+
+
+class GpuExecutor:
+    """Runs requests on the GPU through the library (Lattice / Batch).
+
+    Active lattices without obstacles and with obstacles form two batches
+    (two launches per step); a batch is rebuilt only when its membership
+    changes, i.e. at quantum boundaries where requests join or leave."""
+
+    def __init__(self, storage: str = "f32", stream=None):
+        self.storage = storage
+        self.stream = stream
+        self._batches = {}   # tuple of lattice ids -> Batch
+
+    def footprint(self, req: Request) -> int:
+        from .lattice import footprint_bytes
+        return footprint_bytes(req.nx, req.ny, self.storage, req.mask is not None)
+
+    def start(self, req: Request):
+        from .lattice import Lattice
+        lat = Lattice(req.nx, req.ny, req.tau1, req.tau2, g=req.g, mask=req.mask,
+                      storage=self.storage, stream=self.stream)
+        rho, ux, uy = req.fields() if req.fields else inputs.rest_state(req.ny, req.nx)
+        lat.init_equilibrium(rho, ux, uy)
+        return lat
+
+    def _drop(self, keep=()):
+        for k in list(self._batches):
+            if k not in keep:
+                self._batches.pop(k).close()
+
+    def step(self, handles, nsteps: int):
+        from .lattice import Batch
+        groups = [g for g in ([h for h in handles if h.mask is None],
+                              [h for h in handles if h.mask is not None]) if g]
+        keys = [tuple(id(l) for l in g) for g in groups]
+        self._drop(keep=keys)
+        for k, g in zip(keys, groups):
+            if k not in self._batches:
+                self._batches[k] = Batch(g)
+        for k in keys:
+            self._batches[k].step(nsteps)
+        handles[0].stream.synchronize()
+
+    def finish(self, lat, keep_fields: bool = False):
+        self._drop(keep=[k for k in self._batches if id(lat) not in k])
+        diag = lat.diagnostics()
+        fields = tuple(t.cpu().numpy() for t in lat.macros()) if keep_fields else None
+        return diag, fields
+
+    def close(self, lat):
+        lat.close()
+
+    def shutdown(self):
+        self._drop()
+
+
+def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
+                     side_lo: int = 64, side_hi: int = 2048, steps=None):
+    """Poisson stream of solves: one third creeping flow past a centred
+    square obstacle in a 400 x 200 channel (force-driven, walls top and
+    bottom, Re log-uniform in [1e-7, 1], T = Ma^2/Re = 0.1, Lambda_s = 3/16),
+    one third force-driven Poiseuille channels and one third Taylor-Green
+    vortices with sides log-uniform in [side_lo, side_hi]."""
+    steps = steps or {"cylinder": 2000, "poiseuille": 1000, "taylor_green": 1000}
+    rng = np.random.default_rng(seed)
+    t, rid, out = 0.0, 0, []
+    cyl_mask = inputs.cylinder_channel_mask(400, 200, 20)
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        kind = ("cylinder", "poiseuille", "taylor_green")[rid % 3]
+        if kind == "cylinder":
+            re = math.exp(rng.uniform(math.log(1e-7), math.log(1.0)))
+            ma = params.mach_from_T(0.1, re)
+            u = params.u_from_mach(ma)
+            tau1 = params.tau_from_re(u, 20.0, re)
+            tau2 = params.tau2_from_magic(tau1, 3 / 16)
+            nu = params.nu_from_tau(tau1)
+            g = 8 * nu * u / 198.0 ** 2
+            req = Request(rid, kind, 400, 200, tau1, tau2, steps[kind], (g, 0.0), cyl_mask,
+                          None, t, {"re": re})
+        else:
+            n = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
+            if kind == "poiseuille":
+                tau1 = float(rng.uniform(0.51, 2.0))
+                tau2 = params.tau2_from_magic(tau1, 3 / 16)
+                nu = params.nu_from_tau(tau1)
+                g = 8 * nu * 0.01 / max(1, n - 2) ** 2
+                req = Request(rid, kind, n, n, tau1, tau2, steps[kind], (g, 0.0),
+                              inputs.channel_mask(n, n - 2), None, t, {})
+            else:
+                tau1 = 0.6
+                tau2 = params.tau2_from_magic(tau1, 0.25)
+                seed_k = rid
+                req = Request(rid, kind, n, n, tau1, tau2, steps[kind], (0.0, 0.0), None,
+                              (lambda n=n, s=seed_k: inputs.taylor_green(n, 0.01, seed=s)), t, {})
+        req.meta["nodes"] = req.nx * req.ny
+        out.append(req)
+        rid += 1
+    return out

@@ -1,0 +1,71 @@
+"""The solve server on the GPU: every request's result is bit-for-bit the
+result of running it alone, whatever shared its launches."""
+import numpy as np
+import pytest
+
+from gpu_util import say
+from paper_2312_10318_amd import inputs, params
+from paper_2312_10318_amd.serving import Request, Scheduler, summarize
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_10318_amd import lattice
+    return lattice
+
+
+def _requests():
+    rng = np.random.default_rng(3)
+    reqs, t = [], 0.0
+    mask = inputs.cylinder_channel_mask(160, 80, 12)
+    for k in range(14):
+        t += float(rng.exponential(0.004))
+        kind = ("cylinder", "poiseuille", "taylor_green")[k % 3]
+        if kind == "cylinder":
+            tau1 = float(np.exp(rng.uniform(np.log(0.6), np.log(300.0))))
+            tau2 = params.tau2_from_magic(tau1, 3 / 16)
+            g = 8 * params.nu_from_tau(tau1) * 1e-3 / 78.0 ** 2
+            r = Request(k, kind, 160, 80, tau1, tau2, 150 + 37 * k, (g, 0.0), mask, None, t)
+        elif kind == "poiseuille":
+            n = int(rng.integers(40, 130))
+            tau1 = float(rng.uniform(0.55, 1.5))
+            tau2 = params.tau2_from_magic(tau1, 3 / 16)
+            g = 8 * params.nu_from_tau(tau1) * 0.01 / (n - 2) ** 2
+            r = Request(k, kind, n, n, tau1, tau2, 100 + 29 * k, (g, 0.0),
+                        inputs.channel_mask(n, n - 2), None, t)
+        else:
+            n = int(rng.integers(64, 200))
+            r = Request(k, kind, n, n, 0.6, 3.0, 120 + 31 * k, (0.0, 0.0), None,
+                        (lambda n=n, s=k: inputs.taylor_green(n, 0.01, seed=s)), t)
+        reqs.append(r)
+    return reqs
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_served_results_equal_results_alone(L, storage):
+    from paper_2312_10318_amd.serving import GpuExecutor
+    reqs = _requests()
+    ex = GpuExecutor(storage)
+    sched = Scheduler(ex, budget_bytes=2 << 30, quantum=40, keep_fields=True)
+    res = sched.run(reqs)
+    ex.shutdown()
+    st = summarize(res, wall=max(r.finished for r in res))
+    say("case: serving %s, %d requests, peak active %d, quanta %d: %s" %
+        (storage, len(res), sched.peak_active, sched.quanta, st))
+    assert len(res) == len(reqs) and sched.peak_active >= 3
+    by = {r.rid: r for r in res}
+    for q in reqs:
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage)
+        rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
+        lat.init_equilibrium(rho, ux, uy).step(q.steps)
+        alone = [t.cpu().numpy() for t in lat.macros()]
+        lat.close()
+        got = by[q.rid].fields
+        for a, b in zip(alone, got):
+            assert np.array_equal(a, b), "request %d (%s) differs alone vs served" % (q.rid, q.kind)
+        assert not by[q.rid].diverged

@@ -210,7 +210,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tuning", default="", help="rows_per_wave,waves_per_block,xcd_remap")
+    ap.add_argument("--tuning", default="",
+                    help="rows_per_wave,waves_per_block,xcd_remap[,cols_per_lane]")
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
@@ -236,7 +237,7 @@ def main():
     lat = tg_lattice(n, storage, tuning=tuning)
     ms = time_steps(lat, args.steps, args.warmup)
     stable = lat.check()
-    rows, waves, remap = lat.tuning()
+    rows, waves, remap, cols = lat.tuning()
     lat.close()
     lups = n * n / (ms * 1e-3)
     mlups = lups / 1e6
@@ -262,12 +263,13 @@ def main():
         "config": {"workload": "taylor_green_%dx%d" % (n, n), "storage": storage + "_shifted"
                    if storage != "f64" else "f64", "tau_s": 0.6, "tau_s2": 3.0, "u0": 0.01,
                    "nodes": n * n, "launch": {"rows_per_wave": rows, "waves_per_block": waves,
-                                              "xcd_remap": remap},
+                                              "xcd_remap": remap, "cols_per_lane": cols},
                    "stable": bool(stable)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_lu": BYTES_PER_LU[storage],
-                     "kernel": "sweep_single_kernel<%s,nomask>" % storage,
+                     "kernel": ("sweep_pair_kernel<%s>" if cols == 2 else
+                                "sweep_single_kernel<%s,nomask>") % storage,
                      "source_hash": sweep_source_hash()},
     }
     if not args.no_extra:

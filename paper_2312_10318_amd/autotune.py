@@ -2,7 +2,8 @@
 
 For a lattice shape, storage type and mask presence it times the fused sweep
 over a grid of launch shapes (rows a wavefront marches, wavefronts per
-workgroup, XCD remap on/off) on a scratch lattice of that shape, and keeps
+workgroup, XCD remap on/off, one or two columns per lane where two apply)
+on a scratch lattice of that shape, and keeps
 the fastest.  Results persist in a JSON cache keyed by GPU architecture,
 storage, mask presence and size bucket; the cache path is
 $TRTLBM_TUNE_CACHE, else ~/.cache/trtlbm/tune.json.
@@ -17,6 +18,7 @@ import time
 ROWS = (4, 8, 16, 32, 64, 128)
 WAVES = (1, 2, 4)
 REMAP = (1, 0)
+COLS = (1, 2)
 
 
 def cache_path() -> str:
@@ -51,14 +53,16 @@ def save_cache(cache: dict, path: str | None = None) -> None:
     os.replace(tmp, path)
 
 
-def candidates(ny: int):
+def candidates(nx: int, ny: int, has_mask: bool = False):
+    cols = COLS if (nx % 2 == 0 and not has_mask) else (1,)
     out = []
-    for r in ROWS:
-        if r > max(4, ny):
-            continue
-        for w in WAVES:
-            for x in REMAP:
-                out.append((r, w, x))
+    for c in cols:
+        for r in ROWS:
+            if r > max(4, ny):
+                continue
+            for w in WAVES:
+                for x in REMAP:
+                    out.append((r, w, x, c))
     return out
 
 
@@ -88,7 +92,7 @@ def tune(nx: int, ny: int, storage: str = "f32", mask=None, steps: int | None = 
     if steps is None:
         steps = max(10, min(400, int(2e9 / max(1, nx * ny))))
     table = []
-    for shape in shapes or candidates(ny):
+    for shape in shapes or candidates(nx, ny, mask is not None):
         ms = time_shape(lat, shape, steps, max(2, steps // 10))
         table.append((list(shape), ms))
         if log:

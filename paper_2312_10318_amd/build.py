@@ -15,6 +15,12 @@ FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, never across
+    # statements: which products fuse is then fixed by the source, not by how
+    # a kernel's code is scheduled into blocks, so every sweep variant (one or
+    # two columns per lane, single or batched launch, any rows per
+    # wavefront) rounds each node's arithmetic identically
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 

@@ -41,7 +41,7 @@ class trt_problem(ctypes.Structure):
 
 class trt_tuning(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32)]
 
 
 class TrtError(RuntimeError):
@@ -134,15 +134,15 @@ def trt_create(p: trt_problem, f_a: int, f_b: int, stream: int) -> int:
 
 
 def trt_set_tuning(sim: int, rows_per_wave: int = 0, waves_per_block: int = 0,
-                   xcd_remap: int = -1) -> None:
-    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap)
+                   xcd_remap: int = -1, cols_per_lane: int = 0) -> None:
+    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
     _check(load().trt_set_tuning(sim, ctypes.byref(t)), "trt_set_tuning")
 
 
 def trt_get_tuning(sim: int) -> tuple:
     t = trt_tuning()
     _check(load().trt_get_tuning(sim, ctypes.byref(t)), "trt_get_tuning")
-    return t.rows_per_wave, t.waves_per_block, t.xcd_remap
+    return t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane
 
 
 def trt_init_equilibrium(sim: int, rho: int, ux: int, uy: int) -> None:
@@ -207,8 +207,8 @@ def trt_batch_diagnostics(batch: int, out: int) -> None:
 
 
 def trt_batch_set_tuning(batch: int, rows_per_wave: int = 0, waves_per_block: int = 0,
-                         xcd_remap: int = -1) -> None:
-    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap)
+                         xcd_remap: int = -1, cols_per_lane: int = 0) -> None:
+    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
     _check(load().trt_batch_set_tuning(batch, ctypes.byref(t)), "trt_batch_set_tuning")
 
 

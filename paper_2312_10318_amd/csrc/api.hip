@@ -36,7 +36,7 @@ trt_status fail_hip(hipError_t e, const char *what) {
 
 // Default launch shape: rows per wave chosen per lattice (auto_rows), four
 // wavefronts per workgroup, XCD-contiguous workgroup order.
-constexpr Launch kDefaultLaunch = {0, 4, 1};
+constexpr Launch kDefaultLaunch = {0, 4, 1, 0};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -80,6 +80,11 @@ trt_status check_launch(const trt_tuning *t, Launch &l) {
         if (t->xcd_remap != 0 && t->xcd_remap != 1)
             return fail(TRT_EINVAL, "xcd_remap must be -1, 0 or 1");
         l.xcd_remap = t->xcd_remap;
+    }
+    if (t->cols_per_lane != 0) {
+        if (t->cols_per_lane != 1 && t->cols_per_lane != 2)
+            return fail(TRT_EINVAL, "cols_per_lane must be 0 (automatic), 1 or 2");
+        l.cols_per_lane = t->cols_per_lane;
     }
     return TRT_OK;
 }
@@ -220,7 +225,7 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.pitch = trt_pitch(p->nx, p->storage);
     d.plane = trt_plane_stride(p->nx, p->ny, p->storage);
     d.cur = 0;
-    d.pad_ = 0;
+    d.cols = 1;
     d.omega1 = 1.0 - 1.0 / p->tau_s;
     d.omega2 = 1.0 - 1.0 / p->tau_s2;
     d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
@@ -262,6 +267,7 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     t->rows_per_wave = s->desc.rows;
     t->waves_per_block = s->launch.waves_per_block;
     t->xcd_remap = s->launch.xcd_remap;
+    t->cols_per_lane = s->desc.cols;
     return TRT_OK;
 }
 

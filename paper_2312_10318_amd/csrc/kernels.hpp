@@ -13,18 +13,26 @@ struct Launch {
     int rows_per_wave;  // 0: chosen per lattice by auto_rows()
     int waves_per_block;
     int xcd_remap;
+    int cols_per_lane;  // 0: two-column strips wherever they apply; 1 or 2
 };
+
+// Whether an instance can use two-column strips: no obstacles (the pair
+// path has no bounce-back), an even nx (a lane's pair never straddles the
+// periodic seam) and a lattice within one buffer resource.
+bool pair_eligible(const InstDesc &d, int storage);
 
 // Rows per wavefront when the launch shape leaves it open.  Long strips
 // re-read fewer halo rows, but a lattice must still give the 1024 SIMDs
 // enough wavefronts, and narrower storage needs more of them to keep enough
-// bytes in flight.  Measured optima on 4096^2: FP32 128 rows (~2048
-// wavefronts), FP64 64 rows (~4096), FP16 16-32 rows (~8192).  The rows are
-// the largest power of two in [4, 128] that leaves at least that many
-// wavefronts.
-inline int auto_rows(int nx, int ny, int storage) {
-    const int strips = (nx + kStripWidth - 1) / kStripWidth;
-    const long long target = storage == ST_F64 ? 4096 : (storage == ST_F32 ? 2048 : 8192);
+// bytes in flight.  Measured optima on 4096^2 with 64-column strips: FP32
+// 128 rows (~2048 wavefronts), FP64 64 rows (~4096), FP16 16-32 rows
+// (~8192); a two-column wavefront moves twice the bytes, so half as many
+// suffice.  The rows are the largest power of two in [4, 128] that leaves at
+// least that many wavefronts.
+inline int auto_rows(int nx, int ny, int storage, int cols) {
+    const int width = kStripWidth * cols;
+    const int strips = (nx + width - 1) / width;
+    const long long target = (storage == ST_F64 ? 4096 : (storage == ST_F32 ? 2048 : 8192)) / cols;
     const long long per = (long long)strips * ny / target;
     int r = 4;
     while (r < 128 && (long long)(2 * r) <= per) r *= 2;
@@ -33,8 +41,10 @@ inline int auto_rows(int nx, int ny, int storage) {
 
 // Tiling of one instance for a launch shape.
 inline void tile(InstDesc &d, const Launch &l, int storage) {
-    d.rows = l.rows_per_wave > 0 ? l.rows_per_wave : auto_rows(d.nx, d.ny, storage);
-    d.strips = (d.nx + kStripWidth - 1) / kStripWidth;
+    const bool can = pair_eligible(d, storage);
+    d.cols = (l.cols_per_lane == 1 || !can) ? 1 : (l.cols_per_lane == 2 || d.nx >= 2 * kStripWidth ? 2 : 1);
+    d.rows = l.rows_per_wave > 0 ? l.rows_per_wave : auto_rows(d.nx, d.ny, storage, d.cols);
+    d.strips = (d.nx + kStripWidth * d.cols - 1) / (kStripWidth * d.cols);
     d.rowblocks = (d.ny + d.rows - 1) / d.rows;
 }
 
@@ -49,7 +59,9 @@ bool buffer_addressable(const InstDesc &d, int storage);
 // One fused sweep of every instance of a batch.  descs: device InstDesc[n];
 // items: device int4[nitems] of (instance, strip, rowblock, 0); the lattice
 // read by instance k is buf[descs[k].cur ^ flip].  `buf` may be true only if
-// every instance is buffer_addressable.
+// every instance is buffer_addressable; instances with descs[k].cols == 2
+// are swept with two-column strips (only in a batch without obstacles with
+// `buf` true).
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);

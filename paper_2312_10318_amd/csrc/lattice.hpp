@@ -69,7 +69,7 @@ struct InstDesc {
     int32_t nx, ny, pitch;
     int32_t cur;          // lattice holding the state when the descriptor was built
     int32_t strips, rowblocks, rows;
-    int32_t pad_;
+    int32_t cols;         // columns per lane of the sweep: 1 or 2 (two-column strips)
     double omega1, omega2, phi, gx, gy;
 };
 
@@ -116,14 +116,27 @@ __device__ __forceinline__ float recip(float r) {
 
 // Moments of one node (Eqs. 12-13): base = sum_i f_i (shifted: delta rho),
 // rho, j = sum_i e_i f_i, and the He-shifted velocity u = j / rho + g / 2
-// (F = rho g, so (j + F/2) / rho = j / rho + g / 2).
+// (F = rho g, so (j + F/2) / rho = j / rho + g / 2); plus the raw moments the
+// collision needs, sum e_x^2 f, sum e_y^2 f, sum e_x e_y f, sum e_x^2 e_y f and
+// sum e_x e_y^2 f, which share partial sums with rho and j.  Once these are
+// formed the nine populations are no longer needed.
 template <class C, bool SHIFTED> struct Moments {
     C base, rho, jx, jy, ux, uy;
+    C pxx, pyy, pxy, qxxy, qxyy;
     __device__ __forceinline__ void compute(const C f[9], C gx, C gy) {
-        base = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const C s56 = f[5] + f[6], s78 = f[7] + f[8];
+        const C d56 = f[5] - f[6], d78 = f[7] - f[8];
+        const C diag = s56 + s78;
+        qxxy = s56 - s78;
+        pxy = d56 + d78;
+        qxyy = d56 - d78;
+        const C a13 = f[1] + f[3], a24 = f[2] + f[4];
+        pxx = a13 + diag;
+        pyy = a24 + diag;
+        jx = (f[1] - f[3]) + qxyy;
+        jy = (f[2] - f[4]) + qxxy;
+        base = (f[0] + a13) + (a24 + diag);
         rho = SHIFTED ? C(1) + base : base;
-        jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-        jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
         const C inv = recip(rho);
         ux = jx * inv + C(0.5) * gx;
         uy = jy * inv + C(0.5) * gy;
@@ -171,26 +184,20 @@ template <class C> struct Coeffs {
 };
 
 template <class C, bool SHIFTED>
-__device__ __forceinline__ Coeffs<C> collide_coeffs(const C f[9], const Moments<C, SHIFTED> &m,
-                                                    C dphix, C w1, C w2, C phi, C gx, C gy) {
+__device__ __forceinline__ Coeffs<C> collide_coeffs(const Moments<C, SHIFTED> &m, C dphix, C w1,
+                                                    C w2, C phi, C gx, C gy) {
     const C third = C(1) / C(3);
     const C Fx = m.rho * gx, Fy = m.rho * gy;
-    // raw moments of the (possibly shifted) populations
-    const C pxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
-    const C pyy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
-    const C pxy = (f[5] - f[6]) + (f[7] - f[8]);
-    const C qxxy = (f[5] + f[6]) - (f[7] + f[8]);
-    const C qxyy = (f[5] - f[6]) + (f[8] - f[7]);
     // equilibrium Hermite moments (Eq. 7)
     const C rux = m.rho * m.ux, ruy = m.rho * m.uy;
     const C exx = rux * m.ux, eyy = ruy * m.uy, exy = rux * m.uy;
     const C exxy = exy * m.ux, exyy = exy * m.uy;
-    // non-equilibrium Hermite moments (Eq. 6)
-    const C axx = pxx - m.base * third - exx;
-    const C ayy = pyy - m.base * third - eyy;
-    const C axy = pxy - exy;
-    const C axxy = qxxy - m.jy * third - exxy;
-    const C axyy = qxyy - m.jx * third - exyy;
+    // non-equilibrium Hermite moments (Eq. 6) from the raw moments
+    const C axx = m.pxx - m.base * third - exx;
+    const C ayy = m.pyy - m.base * third - eyy;
+    const C axy = m.pxy - exy;
+    const C axxy = m.qxxy - m.jy * third - exxy;
+    const C axyy = m.qxyy - m.jx * third - exyy;
     // collected Hermite coefficients of f* (relaxation + G_i + F_i)
     Coeffs<C> c;
     c.base = m.base;
@@ -204,11 +211,11 @@ __device__ __forceinline__ Coeffs<C> collide_coeffs(const C f[9], const Moments<
     return c;
 }
 
-// Collision of one node, Eq. 2 (post-collision state overwrites f).
+// Collision of one node, Eq. 2 (the post-collision state is written to f).
 template <class C, bool SHIFTED>
 __device__ __forceinline__ void collide(C f[9], const Moments<C, SHIFTED> &m, C dphix, C dphiy,
                                         C w1, C w2, C phi, C gx, C gy) {
-    Coeffs<C> c = collide_coeffs<C, SHIFTED>(f, m, dphix, w1, w2, phi, gx, gy);
+    Coeffs<C> c = collide_coeffs<C, SHIFTED>(m, dphix, w1, w2, phi, gx, gy);
     reconstruct<C>(f, c.base, c.bx, c.by, c.bxx, c.byy - phi * dphiy, c.bxy, c.bxxy, c.bxyy);
 }
 

@@ -94,8 +94,8 @@ __device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, const T *sr
     r.v[8] = in.ld(8 * plane + ep, col.om);
 }
 
+// One row's state per lane: moments (raw ones included) and Phi.
 template <class C, bool SHIFTED> struct RowState {
-    C f[9];
     Moments<C, SHIFTED> m;
     C phix, phiy;
     bool solid;
@@ -103,25 +103,37 @@ template <class C, bool SHIFTED> struct RowState {
 
 template <class T, class C, bool SHIFTED>
 __device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw, C gx, C gy) {
+    C f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r.f[i] = to_c(raw.v[i]);
+    for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
     r.solid = raw.solid;
-    r.m.compute(r.f, gx, gy);
+    r.m.compute(f, gx, gy);
     const C px = r.m.rho * r.m.ux * r.m.ux * r.m.ux;
     const C py = r.m.rho * r.m.uy * r.m.uy * r.m.uy;
     r.phix = r.solid ? C(0) : px;
     r.phiy = r.solid ? C(0) : py;
 }
 
-// Phi_x of a halo node from its raw populations (0 at a solid node).
+// Phi_x of a halo node from its raw populations (0 at a solid node): only
+// rho and j_x are needed.  The partial sums are taken in exactly the order of
+// Moments::compute, so a halo lane reproduces bit for bit the Phi_x that the
+// lane owning that column computes: results do not depend on where strips
+// begin and end.
 template <class T, class C, bool SHIFTED>
-__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx, C gy) {
+__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx) {
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
-    Moments<C, SHIFTED> m;
-    m.compute(f, gx, gy);
-    return raw.solid ? C(0) : m.rho * m.ux * m.ux * m.ux;
+    const C s56 = f[5] + f[6], s78 = f[7] + f[8];
+    const C d56 = f[5] - f[6], d78 = f[7] - f[8];
+    const C diag = s56 + s78;
+    const C qxyy = d56 - d78;
+    const C a13 = f[1] + f[3], a24 = f[2] + f[4];
+    const C jx = (f[1] - f[3]) + qxyy;
+    const C base = (f[0] + a13) + (a24 + diag);
+    const C rho = SHIFTED ? C(1) + base : base;
+    const C ux = jx * recip(rho) + C(0.5) * gx;
+    return raw.solid ? C(0) : rho * ux * ux * ux;
 }
 
 static_assert(kStripWidth == 64, "one strip column per lane of a 64-wide wavefront");
@@ -177,7 +189,7 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         if (edge) {
             Raw<T> h;
             gather_raw<T, MASK>(h, in, src, plane, pitch, mask, nx, ny, y0, hcol);
-            hphix = halo_phix<T, C, SH>(h, gx, gy);
+            hphix = halo_phix<T, C, SH>(h, gx);
         }
     }
 
@@ -193,7 +205,7 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         const C phix_l = (lane == 0) ? hphix : up;
         const C phix_r = (lane == kStripWidth - 1) ? hphix : dn;
         const C dphix = C(0.5) * (phix_r - phix_l);
-        Coeffs<C> cf = collide_coeffs<C, SH>(cur.f, cur.m, dphix, w1, w2, ph, gx, gy);
+        Coeffs<C> cf = collide_coeffs<C, SH>(cur.m, dphix, w1, w2, ph, gx, gy);
         // pin the coefficients here, ahead of the wait for row y+1's loads
         // (otherwise they are sunk into the masked store block below)
         asm volatile("" : "+v"(cf.base), "+v"(cf.bx), "+v"(cf.by), "+v"(cf.bxx), "+v"(cf.byy),
@@ -201,7 +213,7 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
 
         RowState<C, SH> nxt;
         widen<T, C, SH>(nxt, nraw, gx, gy);
-        const C nhphix = edge ? halo_phix<T, C, SH>(nhalo, gx, gy) : C(0);
+        const C nhphix = edge ? halo_phix<T, C, SH>(nhalo, gx) : C(0);
 
         const C dphiy = C(0.5) * (nxt.phiy - phiy_below);
         C fo[9];
@@ -216,6 +228,280 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         cur = nxt;
         hphix = nhphix;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Two columns per lane.  A wavefront owns an aligned strip of 128 columns,
+// lane l holding the adjacent pair (2l, 2l + 1) and moving both with one
+// access per population (4 bytes for FP16, 8 for FP32, 16 for FP64), which
+// halves the memory instructions per node and the share of halo work.  The
+// x-streamed populations take the missing neighbour element from the
+// adjacent lane with a DPP whole-wave shift; the strip's two edge lanes
+// supply the elements beyond the strip (and the two halo columns' Phi_x)
+// through DPP's "old" operand.  Used for lattices without obstacles with
+// even nx that fit one buffer resource.
+
+constexpr int kStripWidth2 = 128;
+
+// DPP whole-wavefront shifts: lane i receives lane i-1 (shr) or lane i+1
+// (shl); the lane with no source keeps `old`.
+__device__ __forceinline__ float dpp_shr(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, src),
+                                                                  0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_shl(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, src),
+                                                                  0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dpp_shr(double old, double src) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x138, 0xf,
+                                                    0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
+                                                    0x138, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double dpp_shl(double old, double src) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x130, 0xf,
+                                                    0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
+                                                    0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// One pair of adjacent storage elements as loaded/stored by one access.
+template <class T> struct PairIO;
+template <> struct PairIO<_Float16> {
+    typedef uint32_t W;
+    __device__ static __forceinline__ W ld(const BufAccess<_Float16> &a, int64_t e, uint32_t v) {
+        return __builtin_amdgcn_raw_buffer_load_b32(a.r, v, (uint32_t)(e * 2), 0);
+    }
+    __device__ static __forceinline__ void split(W w, float &x, float &y) {
+        x = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+        y = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+    }
+    __device__ static __forceinline__ void st(const BufAccess<_Float16> &a, int64_t e, uint32_t v,
+                                              float x, float y) {
+        const uint32_t lo = __builtin_bit_cast(unsigned short, (_Float16)x);
+        const uint32_t hi = __builtin_bit_cast(unsigned short, (_Float16)y);
+        __builtin_amdgcn_raw_buffer_store_b32(lo | (hi << 16), a.r, v, (uint32_t)(e * 2),
+                                              TRT_STORE_CPOL);
+    }
+};
+template <> struct PairIO<float> {
+    typedef u32x2 W;
+    __device__ static __forceinline__ W ld(const BufAccess<float> &a, int64_t e, uint32_t v) {
+        return __builtin_amdgcn_raw_buffer_load_b64(a.r, v, (uint32_t)(e * 4), 0);
+    }
+    __device__ static __forceinline__ void split(W w, float &x, float &y) {
+        // elements go through plain scalars: this compiler lowers
+        // __builtin_bit_cast of a vector element (w.y) to a read of element 0
+        const uint32_t lo = w.x, hi = w.y;
+        x = __builtin_bit_cast(float, lo);
+        y = __builtin_bit_cast(float, hi);
+    }
+    __device__ static __forceinline__ void st(const BufAccess<float> &a, int64_t e, uint32_t v,
+                                              float x, float y) {
+        W w;
+        w.x = __builtin_bit_cast(uint32_t, x);
+        w.y = __builtin_bit_cast(uint32_t, y);
+        __builtin_amdgcn_raw_buffer_store_b64(w, a.r, v, (uint32_t)(e * 4), TRT_STORE_CPOL);
+    }
+};
+template <> struct PairIO<double> {
+    typedef u32x4 W;
+    __device__ static __forceinline__ W ld(const BufAccess<double> &a, int64_t e, uint32_t v) {
+        return __builtin_amdgcn_raw_buffer_load_b128(a.r, v, (uint32_t)(e * 8), 0);
+    }
+    __device__ static __forceinline__ void split(W w, double &x, double &y) {
+        x = __builtin_bit_cast(double, ((uint64_t)w.y << 32) | w.x);
+        y = __builtin_bit_cast(double, ((uint64_t)w.w << 32) | w.z);
+    }
+    __device__ static __forceinline__ void st(const BufAccess<double> &a, int64_t e, uint32_t v,
+                                              double x, double y) {
+        const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+        W w;
+        w.x = (uint32_t)bx;
+        w.y = (uint32_t)(bx >> 32);
+        w.z = (uint32_t)by;
+        w.w = (uint32_t)(by >> 32);
+        __builtin_amdgcn_raw_buffer_store_b128(w, a.r, v, (uint32_t)(e * 8), TRT_STORE_CPOL);
+    }
+};
+
+// Raw populations of one row of a lane's pair, plus the lane's edge elements
+// (lanes 0 and 63 only) and its halo node (for the halo Phi_x).
+template <class T> struct PairRow {
+    typename PairIO<T>::W w[9];
+    T edge[3];
+    Raw<T> halo;
+};
+
+template <class T, bool HALO>
+__device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const BufAccess<T> &in,
+                                                const T *src, int64_t plane, int pitch, int nx,
+                                                int ny, int y, uint32_t opair, bool edge,
+                                                const uint32_t ve[3], const Column &hcol) {
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int64_t e0 = (int64_t)y * pitch, em = (int64_t)ym * pitch, ep = (int64_t)yp * pitch;
+    r.w[0] = PairIO<T>::ld(in, e0, opair);
+    r.w[1] = PairIO<T>::ld(in, plane + e0, opair);
+    r.w[2] = PairIO<T>::ld(in, 2 * plane + em, opair);
+    r.w[3] = PairIO<T>::ld(in, 3 * plane + e0, opair);
+    r.w[4] = PairIO<T>::ld(in, 4 * plane + ep, opair);
+    r.w[5] = PairIO<T>::ld(in, 5 * plane + em, opair);
+    r.w[6] = PairIO<T>::ld(in, 6 * plane + em, opair);
+    r.w[7] = PairIO<T>::ld(in, 7 * plane + ep, opair);
+    r.w[8] = PairIO<T>::ld(in, 8 * plane + ep, opair);
+    r.edge[0] = r.edge[1] = r.edge[2] = T(0);
+    if (edge) {
+        // lane 0: planes 1, 5, 8 at column x0 - 1; lane 63: planes 3, 6, 7 at
+        // column x0 + 128 (ve[] carries the plane and column per lane)
+        r.edge[0] = in.ld(e0, ve[0]);
+        r.edge[1] = in.ld(em, ve[1]);
+        r.edge[2] = in.ld(ep, ve[2]);
+        if (HALO) gather_raw<T, false>(r.halo, in, src, plane, pitch, nullptr, nx, ny, y, hcol);
+    }
+}
+
+// Widen a pair row into the two nodes' populations, streaming in x through
+// the lane neighbours, and form both nodes' moments and Phi.
+template <class T, class C, bool SHIFTED>
+__device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, SHIFTED> &b,
+                                           const PairRow<T> &r, C gx, C gy) {
+    C pa[9], pb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) PairIO<T>::split(r.w[i], pa[i], pb[i]);
+    const C h0 = to_c(r.edge[0]), h1 = to_c(r.edge[1]), h2 = to_c(r.edge[2]);
+    C fa[9], fb[9];
+    fa[0] = pa[0]; fb[0] = pb[0];
+    fa[2] = pa[2]; fb[2] = pb[2];
+    fa[4] = pa[4]; fb[4] = pb[4];
+    // e_x = +1: node A pulls from the previous lane's B (lane 0: edge element)
+    fa[1] = dpp_shr(h0, pb[1]); fb[1] = pa[1];
+    fa[5] = dpp_shr(h1, pb[5]); fb[5] = pa[5];
+    fa[8] = dpp_shr(h2, pb[8]); fb[8] = pa[8];
+    // e_x = -1: node B pulls from the next lane's A (lane 63: edge element)
+    fa[3] = pb[3]; fb[3] = dpp_shl(h0, pa[3]);
+    fa[6] = pb[6]; fb[6] = dpp_shl(h1, pa[6]);
+    fa[7] = pb[7]; fb[7] = dpp_shl(h2, pa[7]);
+    a.solid = b.solid = false;
+    a.m.compute(fa, gx, gy);
+    b.m.compute(fb, gx, gy);
+    a.phix = a.m.rho * a.m.ux * a.m.ux * a.m.ux;
+    a.phiy = a.m.rho * a.m.uy * a.m.uy * a.m.uy;
+    b.phix = b.m.rho * b.m.ux * b.m.ux * b.m.ux;
+    b.phiy = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
+}
+
+template <int ST>
+__device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int rb, int srcsel) {
+    using T = typename Store<ST>::T;
+    using C = typename Store<ST>::C;
+    constexpr bool SH = Store<ST>::shifted;
+
+    const int lane = threadIdx.x & 63;
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+    const int64_t plane = d.plane;
+    const T *__restrict__ src = static_cast<const T *>(srcsel ? d.buf[1] : d.buf[0]);
+    T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
+    const uint64_t bytes = 9ull * (uint64_t)plane * sizeof(T);
+    const BufAccess<T> in(src, bytes), out(dst, bytes);
+
+    const int x0 = strip * kStripWidth2;
+    const int ca = (x0 + 2 * lane) % nx;  // even, since nx is even
+    const uint32_t opair = (uint32_t)ca * (uint32_t)sizeof(T);
+    const bool writer = x0 + 2 * lane < nx;
+    const bool edge = lane == 0 || lane == 63;
+    const Column hcol = column_of(lane == 0 ? x0 - 1 : x0 + kStripWidth2, nx, sizeof(T));
+    const int pe0 = lane == 0 ? 1 : 3, pe1 = lane == 0 ? 5 : 6, pe2 = lane == 0 ? 8 : 7;
+    const uint32_t ve[3] = {(uint32_t)(pe0 * plane * (int64_t)sizeof(T)) + hcol.oc,
+                            (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hcol.oc,
+                            (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hcol.oc};
+
+    const C gx = (C)d.gx, gy = (C)d.gy;
+    const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
+    const int y0 = rb * d.rows;
+    const int y1 = min(y0 + d.rows, ny);
+
+    C phiy_below_a, phiy_below_b;
+    {
+        PairRow<T> t;
+        RowState<C, SH> a, b;
+        gather_pair_row<T, false>(t, in, src, plane, pitch, nx, ny, (y0 + ny - 1) % ny, opair,
+                                  edge, ve, hcol);
+        widen_pair<T, C, SH>(a, b, t, gx, gy);
+        phiy_below_a = a.phiy;
+        phiy_below_b = b.phiy;
+    }
+    RowState<C, SH> ca_, cb_;
+    C hphix = C(0);
+    {
+        PairRow<T> t;
+        gather_pair_row<T, true>(t, in, src, plane, pitch, nx, ny, y0, opair, edge, ve, hcol);
+        widen_pair<T, C, SH>(ca_, cb_, t, gx, gy);
+        if (edge) hphix = halo_phix<T, C, SH>(t.halo, gx);
+    }
+
+    for (int y = y0; y < y1; ++y) {
+        const int yn = (y + 1 == ny) ? 0 : y + 1;
+        PairRow<T> nr;
+        gather_pair_row<T, true>(nr, in, src, plane, pitch, nx, ny, yn, opair, edge, ve, hcol);
+
+        // row y: both nodes' coefficients except the y-gradient of Phi
+        const C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
+        const C right = dpp_shl(hphix, ca_.phix);  // x + 1 of node B
+        const C dpx_a = C(0.5) * (cb_.phix - left);
+        const C dpx_b = C(0.5) * (right - ca_.phix);
+        Coeffs<C> fa = collide_coeffs<C, SH>(ca_.m, dpx_a, w1, w2, ph, gx, gy);
+        Coeffs<C> fb = collide_coeffs<C, SH>(cb_.m, dpx_b, w1, w2, ph, gx, gy);
+        asm volatile("" : "+v"(fa.base), "+v"(fa.bx), "+v"(fa.by), "+v"(fa.bxx), "+v"(fa.byy),
+                     "+v"(fa.bxy), "+v"(fa.bxxy), "+v"(fa.bxyy));
+        asm volatile("" : "+v"(fb.base), "+v"(fb.bx), "+v"(fb.by), "+v"(fb.bxx), "+v"(fb.byy),
+                     "+v"(fb.bxy), "+v"(fb.bxxy), "+v"(fb.bxyy));
+
+        RowState<C, SH> na, nb;
+        widen_pair<T, C, SH>(na, nb, nr, gx, gy);
+        const C nhphix = edge ? halo_phix<T, C, SH>(nr.halo, gx) : C(0);
+
+        // the same operations per node as the one-column sweep
+        const C dphiy_a = C(0.5) * (na.phiy - phiy_below_a);
+        const C dphiy_b = C(0.5) * (nb.phiy - phiy_below_b);
+        C oa[9], ob[9];
+        reconstruct<C>(oa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dphiy_a, fa.bxy, fa.bxxy,
+                       fa.bxyy);
+        reconstruct<C>(ob, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dphiy_b, fb.bxy, fb.bxxy,
+                       fb.bxyy);
+        if (writer) {
+            const int64_t e0 = (int64_t)y * pitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, opair, oa[i], ob[i]);
+        }
+        phiy_below_a = ca_.phiy;
+        phiy_below_b = cb_.phiy;
+        ca_ = na;
+        cb_ = nb;
+        hphix = nhphix;
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void sweep_pair_kernel(InstDesc d, int srcsel, int remap) {
+    int b = blockIdx.x;
+    if (remap) b = xcd_remap(b, gridDim.x);
+    const int wpb = blockDim.x >> 6;
+    const int wave = b * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= d.strips * d.rowblocks) return;
+    const int rb = wave / d.strips;
+    const int strip = wave - rb * d.strips;
+    sweep_strip2<ST>(d, strip, rb, srcsel);
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -241,7 +527,10 @@ __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__rest
     if (wave >= nitems) return;
     const int4 it = items[wave];
     const InstDesc d = descs[it.x];
-    sweep_strip<ST, MASK, BUF>(d, it.y, it.z, d.cur ^ flip);
+    if (d.cols == 2)
+        sweep_strip2<ST>(d, it.y, it.z, d.cur ^ flip);
+    else
+        sweep_strip<ST, MASK, BUF>(d, it.y, it.z, d.cur ^ flip);
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -263,8 +552,18 @@ hipError_t launch_batch_t(const InstDesc *descs, const int4 *items, int nitems, 
     return hipGetLastError();
 }
 
+template <int ST>
+hipError_t launch_pair_t(const InstDesc &d, int src, const Launch &l, hipStream_t s) {
+    const int waves = d.strips * d.rowblocks;
+    const int wpb = l.waves_per_block;
+    const int blocks = (waves + wpb - 1) / wpb;
+    sweep_pair_kernel<ST><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
+    return hipGetLastError();
+}
+
 template <int ST, bool MASK>
 hipError_t launch_single_b(const InstDesc &d, int src, const Launch &l, bool buf, hipStream_t s) {
+    if (d.cols == 2) return launch_pair_t<ST>(d, src, l, s);
     return buf ? launch_single_t<ST, MASK, true>(d, src, l, s)
                : launch_single_t<ST, MASK, false>(d, src, l, s);
 }
@@ -283,8 +582,13 @@ bool buffer_addressable(const InstDesc &d, int storage) {
     return 9ull * (uint64_t)d.plane * es <= 0xffffffffull;
 }
 
+bool pair_eligible(const InstDesc &d, int storage) {
+    return d.mask == nullptr && d.nx % 2 == 0 && buffer_addressable(d, storage);
+}
+
 hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, const Launch &l,
                         hipStream_t stream) {
+    if (d.cols == 2 && !pair_eligible(d, storage)) return hipErrorInvalidValue;
     const bool buf = buffer_addressable(d, storage);
     switch (storage * 2 + (mask ? 1 : 0)) {
         case 0: return launch_single_b<ST_F64, false>(d, src, l, buf, stream);

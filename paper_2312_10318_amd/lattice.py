@@ -82,8 +82,8 @@ class Lattice:
         self.stream.synchronize()
 
     # ------------------------------------------------------------------- API
-    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1):
-        capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap)
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0):
+        capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
 
     def tuning(self):
         return capi.trt_get_tuning(self.handle)
@@ -173,8 +173,9 @@ class Batch:
         self._diag = torch.empty((len(self.lattices), capi.TRT_NDIAG), dtype=torch.float64,
                                  device=self.lattices[0].device)
 
-    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1):
-        capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap)
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0):
+        capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap,
+                                  cols_per_lane)
 
     def step(self, nsteps=1):
         capi.trt_batch_step(self.handle, int(nsteps))

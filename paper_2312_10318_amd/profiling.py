@@ -49,7 +49,7 @@ def _csv(d, suffix):
 
 
 def _is_sweep(name):
-    return "sweep_single_kernel" in name
+    return "sweep_single_kernel" in name or "sweep_pair_kernel" in name
 
 
 def _is_copy(name):
@@ -110,7 +110,7 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     alg = BYTES_PER_LU[storage] * nodes
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"sweep_single_kernel<[^>]*>", kname or "") or
+        "kernel": (re.search(r"sweep_(single|pair)_kernel<[^>]*>", kname or "") or
                    re.search(r".*", "sweep")).group(0),
         "workload": "taylor_green_%dx%d" % (n, n), "storage": storage, "nodes": nodes,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),

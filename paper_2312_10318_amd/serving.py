@@ -223,13 +223,17 @@ class GpuExecutor:
         self._drop()
 
 
+MAX_G_TAU1 = 0.05
+
+
 def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
                      side_lo: int = 64, side_hi: int = 2048, steps=None):
     """Poisson stream of solves: one third creeping flow past a centred
     square obstacle in a 400 x 200 channel (force-driven, walls top and
     bottom, Re log-uniform in [1e-7, 1], T = Ma^2/Re = 0.1, Lambda_s = 3/16),
     one third force-driven Poiseuille channels and one third Taylor-Green
-    vortices with sides log-uniform in [side_lo, side_hi]."""
+    vortices with sides log-uniform in [side_lo, side_hi].  Body forces are
+    capped at g tau1 <= MAX_G_TAU1 (stability of very viscous forced runs)."""
     steps = steps or {"cylinder": 2000, "poiseuille": 1000, "taylor_green": 1000}
     rng = np.random.default_rng(seed)
     t, rid, out = 0.0, 0, []
@@ -246,7 +250,10 @@ def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
             tau1 = params.tau_from_re(u, 20.0, re)
             tau2 = params.tau2_from_magic(tau1, 3 / 16)
             nu = params.nu_from_tau(tau1)
-            g = 8 * nu * u / 198.0 ** 2
+            # force for a channel velocity u, capped at g tau1 <= 0.05: a body
+            # force of g tau1 >~ 0.2 per step destabilises the very viscous
+            # runs; the creeping flow is linear in g, so the cap only rescales it
+            g = min(8 * nu * u / 198.0 ** 2, MAX_G_TAU1 / tau1)
             req = Request(rid, kind, 400, 200, tau1, tau2, steps[kind], (g, 0.0), cyl_mask,
                           None, t, {"re": re})
         else:
@@ -255,7 +262,7 @@ def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
                 tau1 = float(rng.uniform(0.51, 2.0))
                 tau2 = params.tau2_from_magic(tau1, 3 / 16)
                 nu = params.nu_from_tau(tau1)
-                g = 8 * nu * 0.01 / max(1, n - 2) ** 2
+                g = min(8 * nu * 0.01 / max(1, n - 2) ** 2, MAX_G_TAU1 / tau1)
                 req = Request(rid, kind, n, n, tau1, tau2, steps[kind], (g, 0.0),
                               inputs.channel_mask(n, n - 2), None, t, {})
             else:

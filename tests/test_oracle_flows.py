@@ -59,11 +59,18 @@ POIS_CASES = [
 ]
 
 
+def channel_velocity(N, tau1, uc=0.01, max_g_tau1=0.1):
+    """u_c for the test channel, lowered where needed so that the body force
+    stays at g tau1 <= max_g_tau1 (see test_forced_channel_stability_limit)."""
+    nu = params.nu_from_tau(tau1)
+    return min(uc, max_g_tau1 * N ** 2 / (8 * nu * tau1))
+
+
 @pytest.mark.parametrize("nx,N,tau1,lam", POIS_CASES)
 def test_poiseuille_profile_plus_slip(orc, nx, N, tau1, lam):
     tau2 = params.tau2_from_magic(tau1, lam)
     nu = params.nu_from_tau(tau1)
-    uc = 0.01
+    uc = channel_velocity(N, tau1)
     g = 8 * nu * uc / N ** 2
     _, r, u, v, _ = run_poiseuille(orc, nx, N, tau1, tau2, g)
     us = slip_closed_form(tau1, tau2, g)
@@ -289,3 +296,27 @@ def test_sound_attenuation_is_galilean_invariant(orc):
     assert abs(r0 - 1.0) < 0.01
     for U in (0.1, 0.2):
         assert abs(_sound_attenuation(orc, U) / r0 - 1.0) < 0.003
+
+
+@pytest.mark.parametrize("g_tau1,grows", [(0.1, False), (1.0, True)])
+def test_forced_channel_stability_limit(orc, g_tau1, grows):
+    """A finding, not a claim of the paper: a force-driven channel at very
+    high viscosity (tau1 = 100, Lambda_s = 3/16) is stable for a body force
+    of g tau1 = 0.1 per step and unstable for g tau1 = 1 -- an x-dependent
+    mode seeded at 1e-12 grows by orders of magnitude in 3000 steps.  With or
+    without the compensation term G_i alike.  The paper's forced Poiseuille
+    case (tau1 = 10.1, g = 2.5e-3, g tau1 = 0.025) lies in the stable range."""
+    N, nx, tau1 = 16, 32, 100.0
+    tau2 = params.tau2_from_magic(tau1, 3 / 16)
+    g = g_tau1 / tau1
+    mask = inputs.channel_mask(nx, N)
+    f = orc.init_equilibrium(*inputs.rest_state(N + 2, nx), mask)
+    rng = np.random.default_rng(0)
+    f = f + 1e-12 * rng.standard_normal(f.shape) * (f != 0)
+    f = orc.run(f, 3000, tau1, tau2, g, 0.0, mask)
+    _, _, v = orc.macros(f, g, 0.0, mask)
+    vmax = np.max(np.abs(v)) if np.all(np.isfinite(v)) else np.inf
+    if grows:
+        assert vmax > 1e-6
+    else:
+        assert vmax < 1e-12

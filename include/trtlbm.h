@@ -75,9 +75,10 @@ typedef struct {
 } trt_problem;
 
 /* Launch shape of the fused sweep.  Zero fields take the built-in default
- * (rows per wavefront chosen from the lattice size, 4 wavefronts per
- * workgroup, XCD remap on, two columns per lane where that applies).
- * trt_get_tuning reports the rows and columns per lane in effect.
+ * (rows per wavefront chosen from the lattice size, wavefronts per
+ * workgroup chosen per storage, XCD remap on, two columns per lane where
+ * that applies).  trt_get_tuning reports the rows, wavefronts per workgroup
+ * and columns per lane in effect.
  * Two columns per lane (a wavefront sweeps 128-column strips with one
  * paired access per population) applies to lattices without a mask, with
  * even nx and at most 4 GiB per lattice; elsewhere the sweep uses one
@@ -85,7 +86,9 @@ typedef struct {
  * arithmetic per node. */
 typedef struct {
     int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 (0: automatic) */
-    int32_t waves_per_block; /* wavefronts per workgroup: 1, 2 or 4 */
+    int32_t waves_per_block; /* wavefronts per workgroup: 1, 2, 4, 8 or 16 (0: automatic); the
+                                one-column and batched sweeps use at most 4, the two-column
+                                sweep at most 16 (FP64: 8) */
     int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default */
     int32_t cols_per_lane;   /* 1 or 2 columns per lane (0: 2 where it applies and nx >= 128) */
 } trt_tuning;

@@ -36,7 +36,7 @@ trt_status fail_hip(hipError_t e, const char *what) {
 
 // Default launch shape: rows per wave chosen per lattice (auto_rows), four
 // wavefronts per workgroup, XCD-contiguous workgroup order.
-constexpr Launch kDefaultLaunch = {0, 4, 1, 0};
+constexpr Launch kDefaultLaunch = {0, 0, 1, 0};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -72,8 +72,9 @@ trt_status check_launch(const trt_tuning *t, Launch &l) {
         l.rows_per_wave = t->rows_per_wave;
     }
     if (t->waves_per_block != 0) {
-        if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
-            return fail(TRT_EINVAL, "waves_per_block must be 1, 2 or 4");
+        const int w = t->waves_per_block;
+        if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16)
+            return fail(TRT_EINVAL, "waves_per_block must be 0 (automatic), 1, 2, 4, 8 or 16");
         l.waves_per_block = t->waves_per_block;
     }
     if (t->xcd_remap != -1) {
@@ -265,7 +266,7 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!t) return fail(TRT_EINVAL, "out is NULL");
     t->rows_per_wave = s->desc.rows;
-    t->waves_per_block = s->launch.waves_per_block;
+    t->waves_per_block = trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
     t->xcd_remap = s->launch.xcd_remap;
     t->cols_per_lane = s->desc.cols;
     return TRT_OK;

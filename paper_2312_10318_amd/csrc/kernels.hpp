@@ -10,11 +10,33 @@
 namespace trt {
 
 struct Launch {
-    int rows_per_wave;  // 0: chosen per lattice by auto_rows()
-    int waves_per_block;
+    int rows_per_wave;    // 0: chosen per lattice by auto_rows()
+    int waves_per_block;  // 0: chosen per storage and column mode
     int xcd_remap;
-    int cols_per_lane;  // 0: two-column strips wherever they apply; 1 or 2
+    int cols_per_lane;    // 0: two-column strips wherever they apply; 1 or 2
 };
+
+// Wavefronts per workgroup of a single-lattice sweep.  The one-column
+// kernels take at most 4 (256 threads), the two-column kernels 16 (FP64:
+// 8, for its register budget).  The two-column workgroups are synchronised
+// per row, and wider ones keep more adjacent strips in step: measured best
+// on 4096^2 are 8 (FP32) and 16 (FP16); FP64 gains nothing beyond 4.  A
+// workgroup never has more wavefronts than the lattice has strips (rounded
+// up to a power of two).
+inline int single_waves_per_block(const InstDesc &d, int storage, const Launch &l) {
+    if (d.cols != 2) return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
+    const int cap = storage == ST_F64 ? 8 : 16;
+    int w = l.waves_per_block > 0 ? l.waves_per_block
+                                  : (storage == ST_F16 ? 16 : (storage == ST_F32 ? 8 : 4));
+    if (w > cap) w = cap;
+    while (w > 1 && w / 2 >= d.strips) w /= 2;
+    return w;
+}
+
+// Wavefronts per workgroup of a batched sweep (at most 4; default 4).
+inline int batch_waves_per_block(const Launch &l) {
+    return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
+}
 
 // Whether an instance can use two-column strips: no obstacles (the pair
 // path has no bounce-back), an even nx (a lane's pair never straddles the
@@ -24,15 +46,16 @@ bool pair_eligible(const InstDesc &d, int storage);
 // Rows per wavefront when the launch shape leaves it open.  Long strips
 // re-read fewer halo rows, but a lattice must still give the 1024 SIMDs
 // enough wavefronts, and narrower storage needs more of them to keep enough
-// bytes in flight.  Measured optima on 4096^2 with 64-column strips: FP32
+// bytes in flight.  Measured optima on 4096^2: with 64-column strips FP32
 // 128 rows (~2048 wavefronts), FP64 64 rows (~4096), FP16 16-32 rows
-// (~8192); a two-column wavefront moves twice the bytes, so half as many
-// suffice.  The rows are the largest power of two in [4, 128] that leaves at
-// least that many wavefronts.
+// (~8192); with two-column strips in synchronised workgroups FP32 64 rows
+// (~2048), FP64 64 (~2048), FP16 32 (~4096).  The rows are the largest
+// power of two in [4, 128] that leaves at least that many wavefronts.
 inline int auto_rows(int nx, int ny, int storage, int cols) {
     const int width = kStripWidth * cols;
     const int strips = (nx + width - 1) / width;
-    const long long target = (storage == ST_F64 ? 4096 : (storage == ST_F32 ? 2048 : 8192)) / cols;
+    const long long target = cols == 2 ? (storage == ST_F16 ? 4096 : 2048)
+                                       : (storage == ST_F64 ? 4096 : (storage == ST_F32 ? 2048 : 8192));
     const long long per = (long long)strips * ny / target;
     int r = 4;
     while (r < 128 && (long long)(2 * r) <= per) r *= 2;

@@ -401,7 +401,7 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     b.phiy = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
 }
 
-template <int ST>
+template <int ST, bool SYNC>
 __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
@@ -489,19 +489,40 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
         ca_ = na;
         cb_ = nb;
         hphix = nhphix;
+        // keep the workgroup's wavefronts (adjacent strips) on the same row, so
+        // that their accesses to each population row stay contiguous in time
+        if (SYNC) __builtin_amdgcn_s_barrier();
     }
 }
 
+// A wavefront of a synchronised workgroup with no strip to sweep (the
+// lattice has fewer strips than the workgroup has wavefronts): it meets the
+// same barriers as its row block's sweeping wavefronts.
+__device__ __forceinline__ void idle_rows(const InstDesc &d, int rb) {
+    const int y0 = rb * d.rows;
+    const int y1 = min(y0 + d.rows, d.ny);
+    for (int y = y0; y < y1; ++y) __builtin_amdgcn_s_barrier();
+}
+
+// Two-column sweep of one lattice.  Workgroup b covers row block
+// b / groups and the strips [g * wpb, g * wpb + wpb) with g = b % groups;
+// every wavefront of it runs the same rows and meets one barrier per row, so
+// none may leave early: the grid is exactly rowblocks x groups workgroups.
 template <int ST>
-__global__ __launch_bounds__(256) void sweep_pair_kernel(InstDesc d, int srcsel, int remap) {
+__global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(InstDesc d,
+                                                                                 int srcsel,
+                                                                                 int remap) {
     int b = blockIdx.x;
     if (remap) b = xcd_remap(b, gridDim.x);
     const int wpb = blockDim.x >> 6;
-    const int wave = b * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= d.strips * d.rowblocks) return;
-    const int rb = wave / d.strips;
-    const int strip = wave - rb * d.strips;
-    sweep_strip2<ST>(d, strip, rb, srcsel);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int groups = (d.strips + wpb - 1) / wpb;
+    const int rb = b / groups;
+    const int strip = (b - rb * groups) * wpb + w;
+    if (strip < d.strips)
+        sweep_strip2<ST, true>(d, strip, rb, srcsel);
+    else
+        idle_rows(d, rb);
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -528,7 +549,7 @@ __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__rest
     const int4 it = items[wave];
     const InstDesc d = descs[it.x];
     if (d.cols == 2)
-        sweep_strip2<ST>(d, it.y, it.z, d.cur ^ flip);
+        sweep_strip2<ST, false>(d, it.y, it.z, d.cur ^ flip);
     else
         sweep_strip<ST, MASK, BUF>(d, it.y, it.z, d.cur ^ flip);
 }
@@ -536,7 +557,7 @@ __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__rest
 template <int ST, bool MASK, bool BUF>
 hipError_t launch_single_t(const InstDesc &d, int src, const Launch &l, hipStream_t s) {
     const int waves = d.strips * d.rowblocks;
-    const int wpb = l.waves_per_block;
+    const int wpb = single_waves_per_block(d, ST, l);
     const int blocks = (waves + wpb - 1) / wpb;
     sweep_single_kernel<ST, MASK, BUF><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
     return hipGetLastError();
@@ -545,7 +566,7 @@ hipError_t launch_single_t(const InstDesc &d, int src, const Launch &l, hipStrea
 template <int ST, bool MASK, bool BUF>
 hipError_t launch_batch_t(const InstDesc *descs, const int4 *items, int nitems, int flip,
                           const Launch &l, hipStream_t s) {
-    const int wpb = l.waves_per_block;
+    const int wpb = batch_waves_per_block(l);
     const int blocks = (nitems + wpb - 1) / wpb;
     sweep_batch_kernel<ST, MASK, BUF><<<blocks, 64 * wpb, 0, s>>>(descs, items, nitems, flip,
                                                                  l.xcd_remap);
@@ -554,9 +575,8 @@ hipError_t launch_batch_t(const InstDesc *descs, const int4 *items, int nitems, 
 
 template <int ST>
 hipError_t launch_pair_t(const InstDesc &d, int src, const Launch &l, hipStream_t s) {
-    const int waves = d.strips * d.rowblocks;
-    const int wpb = l.waves_per_block;
-    const int blocks = (waves + wpb - 1) / wpb;
+    const int wpb = single_waves_per_block(d, ST, l);
+    const int blocks = d.rowblocks * ((d.strips + wpb - 1) / wpb);
     sweep_pair_kernel<ST><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
     return hipGetLastError();
 }

@@ -99,7 +99,8 @@ def test_random_state_walls_force_fp64(L, shape, tiling):
     lat.close()
 
 
-PAIR_TILINGS = [(32, 4, 1, 2), (1, 1, 0, 2), (5, 2, 1, 2), (3, 1, 1, 2)]
+PAIR_TILINGS = [(32, 4, 1, 2), (1, 1, 0, 2), (5, 2, 1, 2), (3, 1, 1, 2), (5, 16, 1, 2),
+                (7, 8, 0, 2), (0, 0, -1, 2)]
 PAIR_SHAPES = [(130, 37), (62, 5), (256, 9), (2, 7), (128, 3), (384, 17), (254, 1)]
 
 
@@ -107,10 +108,11 @@ PAIR_SHAPES = [(130, 37), (62, 5), (256, 9), (2, 7), (128, 3), (384, 17), (254, 
 @pytest.mark.parametrize("shape", PAIR_SHAPES)
 def test_two_column_strips_fp64(L, shape, tiling):
     """Two columns per lane (128-column strips, DPP lane shifts, edge lanes
-    supplying the strip's outside elements): arbitrary states with body
-    force on even widths below, at and across strip multiples, ragged
-    heights, every launch shape; 7 steps against the oracle to round-off,
-    and bit for bit equal to the one-column sweep."""
+    supplying the strip's outside elements, workgroups synchronised per row
+    with idle wavefronts where the strips do not fill a workgroup):
+    arbitrary states with body force on even widths below, at and across
+    strip multiples, ragged heights, every launch shape; 7 steps against the
+    oracle to round-off, and bit for bit equal to the one-column sweep."""
     nx, ny = shape
     f, _, g, tau1, tau2 = _random_problem(hash((shape, tiling)) % 1000 + 7, nx, ny,
                                           with_mask=False)
@@ -159,6 +161,23 @@ def test_two_column_strips_shifted_storage(L, storage):
     emax, el2 = rel_errors(out[2][1][1], out[2][1][2], ur, vr)
     say("  one step vs oracle: rel max %.3e rel L2 %.3e" % (emax, el2))
     assert emax <= TOL[storage]
+
+
+def test_workgroup_size_in_effect(L):
+    """The wavefronts per workgroup reported are the ones launched: capped at
+    4 for one-column sweeps, 8 for FP64 and 16 otherwise for two-column
+    sweeps, where they also never exceed what the strips need (62 is below
+    the two-column width, so it sweeps one column per lane)."""
+    cases = [(4096, "f32", 0, 8), (4096, "f16", 0, 16), (4096, "f64", 0, 4),
+             (4096, "f64", 16, 8), (384, "f32", 16, 4), (130, "f16", 0, 2), (62, "f32", 0, 4),
+             (131, "f32", 16, 4)]
+    for nx, storage, asked, want in cases:
+        lat = L.Lattice(nx, 4, 0.8, 1.0, storage=storage)
+        lat.set_tuning(0, asked, -1, 0)
+        got = lat.tuning()[1]
+        lat.close()
+        say("case: nx=%d %s asked %d -> %d" % (nx, storage, asked, got))
+        assert got == want
 
 
 def test_two_column_request_falls_back_where_it_does_not_apply(L):

@@ -27,7 +27,8 @@ import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp"]
+SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp",
+                 "paper_2312_10318_amd/csrc/kernels.hpp"]
 COPY_BYTES = 1 << 30
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}
 

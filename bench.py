@@ -164,7 +164,8 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
 
 def run_extra(steps):
     """Companion measurements: the same lattice in FP16 and FP64 storage,
-    the batched workload, and the serving stream (FP16 and FP32)."""
+    the batched workload, the serving stream (FP16 and FP32) and the
+    double-shear-layer stability study."""
     out = {}
     for storage in ("f16", "f64"):
         lat = tg_lattice(4096, storage)
@@ -180,7 +181,20 @@ def run_extra(steps):
     for storage in ("f16", "f32"):
         out["serving_" + storage] = run_serving(storage)
         log("extra serving %s: %s" % (storage, out["serving_" + storage]))
+    out["dsl_critical_mach_f64"] = run_stability()
+    log("extra stability study: %s" % out["dsl_critical_mach_f64"])
     return out
+
+
+def run_stability():
+    """The double-shear-layer critical-Mach study of Sec. III.A (128^2, six
+    Reynolds numbers x twenty 1/tau_s2 values + RLB, bisection to dMa = 0.01,
+    stable up to t/t_c = 2) as batched rounds on the GPU, FP64."""
+    from paper_2312_10318_amd import stability
+    res = stability.critical_mach([5e3, 1e4, 5e4, 1e5, 1e6, 1e7],
+                                  [round(0.1 * k, 1) for k in range(1, 21)], storage="f64")
+    return {"cases": len(res["cases"]), "rounds": res["rounds"], "seconds": res["seconds"],
+            "per_re": {"%g" % k: v for k, v in stability.summary(res).items()}}
 
 
 def profile_run(n, storage, steps, warmup, tuning):

@@ -63,6 +63,12 @@ def _bind(lib):
     lib.orc_step.restype = i
     lib.orc_run.argtypes = [i, i, P, P, L, d, d, d, d]
     lib.orc_run.restype = i
+    lib.orc_step_open.argtypes = [i, i, P, P, P, d, d, d, d, d, d, d]
+    lib.orc_step_open.restype = i
+    lib.orc_run_open.argtypes = [i, i, P, P, L, d, d, d, d, d, d, d]
+    lib.orc_run_open.restype = i
+    lib.orc_wall_force.argtypes = [i, i, P, P, d, d, d, d, i, d, d, P]
+    lib.orc_wall_force.restype = i
     lib.orc_num_threads.restype = i
     return lib
 
@@ -176,6 +182,46 @@ class Oracle:
         return f
 
 
+    def step_open(self, f, tau1: float, tau2: float, u_in: float, rho_w: float = 1.0,
+                  rho_out: float = 1.0, gx: float = 0.0, gy: float = 0.0,
+                  mask=None) -> np.ndarray:
+        """One step with the inflow wall at x = -1/2 and the pressure outlet at
+        x = nx - 1 (periodic in y); returns a new [9, ny, nx] array."""
+        f = _f64(f)
+        _, ny, nx = f.shape
+        m = _mask(mask, ny, nx)
+        out = np.empty_like(f)
+        if self.lib.orc_step_open(nx, ny, _p(m), _p(f), _p(out), tau1, tau2, gx, gy, u_in,
+                                  rho_w, rho_out) != 0:
+            raise MemoryError("oracle step: allocation failed")
+        return out
+
+    def run_open(self, f, nsteps: int, tau1: float, tau2: float, u_in: float,
+                 rho_w: float = 1.0, rho_out: float = 1.0, gx: float = 0.0, gy: float = 0.0,
+                 mask=None) -> np.ndarray:
+        """nsteps steps of :meth:`step_open`; returns a new array."""
+        f = np.array(f, dtype=np.float64, order="C", copy=True)
+        _, ny, nx = f.shape
+        m = _mask(mask, ny, nx)
+        if self.lib.orc_run_open(nx, ny, _p(m), _p(f), int(nsteps), tau1, tau2, gx, gy, u_in,
+                                 rho_w, rho_out) != 0:
+            raise MemoryError("oracle run: allocation failed")
+        return f
+
+    def wall_force(self, f, tau1: float, tau2: float, gx: float = 0.0, gy: float = 0.0,
+                   mask=None, open_x: bool = False, u_in: float = 0.0,
+                   rho_w: float = 1.0) -> tuple:
+        """(F_x, F_y) handed to the solid nodes by the collision of state f."""
+        f = _f64(f)
+        _, ny, nx = f.shape
+        m = _mask(mask, ny, nx)
+        out = np.zeros(2)
+        if self.lib.orc_wall_force(nx, ny, _p(m), _p(f), tau1, tau2, gx, gy, int(open_x), u_in,
+                                   rho_w, _p(out)) != 0:
+            raise MemoryError("oracle wall force: allocation failed")
+        return float(out[0]), float(out[1])
+
+
 _default = None
 
 
@@ -224,6 +270,18 @@ def step(*a, **k):
 
 def run(*a, **k):
     return _inst().run(*a, **k)
+
+
+def step_open(*a, **k):
+    return _inst().step_open(*a, **k)
+
+
+def run_open(*a, **k):
+    return _inst().run_open(*a, **k)
+
+
+def wall_force(*a, **k):
+    return _inst().wall_force(*a, **k)
 
 
 def num_threads() -> int:

@@ -34,6 +34,21 @@
  *   R3  A link whose target is a solid node is bounced back half-way, link by
  *       link (Sec. II.D, half-way bounce-back rule), also for diagonal links.
  *   R4  Solid nodes are never collided; their outputs are 0.
+ * Open boundaries in x (the creeping flow of Sec. III.D; orc_step_open):
+ *   R5  The inlet is a half-way bounce-back wall at x = -1/2 moving with the
+ *       inflow velocity (u_in, 0): a population f*_i leaving column 0
+ *       through it returns to the same node as direction opp(i) with the
+ *       moving-wall momentum correction -2 w_i rho_w (e_i . u_wall) / c_s^2
+ *       (Ladd's moving-wall rule; the paper names the scheme, not the
+ *       formula), rho_w the prescribed wall density.
+ *   R6  The outlet column nx - 1 has a prescribed density rho_out and zero
+ *       transverse velocity: after streaming, its three populations with
+ *       e_x = -1 come from Zou and He's pressure rule applied to the six
+ *       known ones.  Populations streaming out through x = nx are lost.
+ *   R7  Phi beyond the inlet is the wall's, rho_w u_in^3 (x) and 0 (y);
+ *       beyond the outlet it equals the last column's (zero gradient).
+ *   R8  Moving walls and the outlet rule ignore the body force (the open
+ *       case of the paper is unforced).
  */
 #include <math.h>
 #include <stdint.h>
@@ -304,6 +319,172 @@ int orc_step(int nx, int ny, const uint8_t *solid, const double *fin, double *fo
     }
     free(phix);
     free(phiy);
+    return 0;
+}
+
+/* Post-collision populations fstar[9][ny][nx] of every fluid node (0 at
+ * solid nodes) for the state fin, with the Phi gradient of R1 and, when
+ * open_x is set, the boundary values of R7 at columns 0 and nx - 1.      */
+static int collide_field(int nx, int ny, const uint8_t *solid, const double *fin, double *fstar,
+                         double tau1, double tau2, double gx, double gy, int open_x,
+                         double u_in, double rho_w) {
+    const long n = (long)nx * ny;
+    double *px = (double *)malloc(sizeof(double) * n);
+    double *py = (double *)malloc(sizeof(double) * n);
+    if (!px || !py) {
+        free(px);
+        free(py);
+        return -1;
+    }
+#pragma omp parallel for schedule(static) if (n >= 16384)
+    for (long k = 0; k < n; ++k) {
+        double fl[Q], rho, ux, uy;
+        px[k] = py[k] = 0.0;
+        if (solid && solid[k]) continue;
+        for (int i = 0; i < Q; ++i) fl[i] = fin[(long)i * n + k];
+        orc_moments(fl, gx, gy, &rho, &ux, &uy);
+        px[k] = rho * ux * ux * ux;
+        py[k] = rho * uy * uy * uy;
+    }
+#pragma omp parallel for schedule(static) if (n >= 16384)
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            const long k = (long)y * nx + x;
+            double fl[Q], fs[Q];
+            if (solid && solid[k]) {
+                for (int i = 0; i < Q; ++i) fstar[(long)i * n + k] = 0.0;
+                continue;
+            }
+            for (int i = 0; i < Q; ++i) fl[i] = fin[(long)i * n + k];
+            /* Phi_x at the two x-neighbours (R1, with R7 at open ends) */
+            double left = px[(long)y * nx + wrap(x - 1, nx)];
+            double right = px[(long)y * nx + wrap(x + 1, nx)];
+            if (open_x && x == 0) left = rho_w * u_in * u_in * u_in;
+            if (open_x && x == nx - 1) right = px[k];
+            const double below = py[(long)wrap(y - 1, ny) * nx + x];
+            const double above = py[(long)wrap(y + 1, ny) * nx + x];
+            orc_collide_node(fl, gx, gy, 0.5 * (right - left), 0.5 * (above - below), tau1, tau2,
+                             fs);
+            for (int i = 0; i < Q; ++i) fstar[(long)i * n + k] = fs[i];
+        }
+    }
+    free(px);
+    free(py);
+    return 0;
+}
+
+/* One time step with an inflow wall at x = -1/2 and a pressure outlet at
+ * x = nx - 1 (R5-R8), periodic in y, half-way bounce-back at solid nodes:
+ * collision as in orc_step, then streaming f_i(x + e_i) = f*_i(x) inside
+ * the lattice, the moving-wall return at the inlet, loss through the
+ * outlet, and Zou and He's rule for the outlet's incoming populations.   */
+int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, double *fout,
+                  double tau1, double tau2, double gx, double gy, double u_in, double rho_w,
+                  double rho_out) {
+    const long n = (long)nx * ny;
+    double *fstar = (double *)malloc(sizeof(double) * Q * n);
+    if (!fstar) return -1;
+    if (collide_field(nx, ny, solid, fin, fstar, tau1, tau2, gx, gy, 1, u_in, rho_w) != 0) {
+        free(fstar);
+        return -1;
+    }
+    for (long k = 0; k < (long)Q * n; ++k) fout[k] = 0.0;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            const long k = (long)y * nx + x;
+            if (solid && solid[k]) continue;
+            for (int i = 0; i < Q; ++i) {
+                const double v = fstar[(long)i * n + k];
+                const int tx = x + E[i][0];
+                const int ty = wrap(y + E[i][1], ny);
+                const int back = opposite(i);
+                if (tx < 0) {
+                    /* R5: e_i . u_wall = e_ix u_in */
+                    fout[(long)back * n + k] = v - 2.0 * WGT[i] * rho_w * (E[i][0] * u_in) / CS2;
+                } else if (tx >= nx) {
+                    /* R6: leaves the lattice */
+                } else if (solid && solid[(long)ty * nx + tx]) {
+                    fout[(long)back * n + k] = v;
+                } else {
+                    fout[(long)i * n + (long)ty * nx + tx] = v;
+                }
+            }
+        }
+    }
+    /* R6: Zou and He's pressure rule, e = (1,0):1 (0,1):2 (-1,0):3 (0,-1):4
+     * (1,1):5 (-1,1):6 (-1,-1):7 (1,-1):8, with u_y = 0 at the outlet */
+    for (int y = 0; y < ny; ++y) {
+        const long k = (long)y * nx + (nx - 1);
+        if (solid && solid[k]) continue;
+        double f[Q];
+        for (int i = 0; i < Q; ++i) f[i] = fout[(long)i * n + k];
+        const double ux = -1.0 + (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / rho_out;
+        fout[3 * n + k] = f[1] - 2.0 / 3.0 * rho_out * ux;
+        fout[7 * n + k] = f[5] + 0.5 * (f[2] - f[4]) - 1.0 / 6.0 * rho_out * ux;
+        fout[6 * n + k] = f[8] - 0.5 * (f[2] - f[4]) - 1.0 / 6.0 * rho_out * ux;
+    }
+    free(fstar);
+    return 0;
+}
+
+/* Momentum handed to the solid nodes during the collision of state f(x, t)
+ * (Sec. III.D, momentum exchange): every link from a fluid node x_f to a
+ * solid node x_s = x_f + e_i carries e_i [f*_i(x_f, t) + f*_opp(i)(x_s, t)],
+ * where under half-way bounce-back the population returned from the wall is
+ * f*_i(x_f, t) itself, so the link gives 2 e_i f*_i(x_f, t).  Links leaving
+ * through open x ends (open_x) are not wall links.  out[0..1] = (F_x, F_y).
+ * Returns 0, or -1 when memory cannot be allocated.                      */
+int orc_wall_force(int nx, int ny, const uint8_t *solid, const double *f, double tau1,
+                   double tau2, double gx, double gy, int open_x, double u_in, double rho_w,
+                   double *out) {
+    const long n = (long)nx * ny;
+    double *fstar = (double *)malloc(sizeof(double) * Q * n);
+    if (!fstar) return -1;
+    if (collide_field(nx, ny, solid, f, fstar, tau1, tau2, gx, gy, open_x, u_in, rho_w) != 0) {
+        free(fstar);
+        return -1;
+    }
+    double fx = 0.0, fy = 0.0;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            const long k = (long)y * nx + x;
+            if (!solid || solid[k]) continue;
+            for (int i = 1; i < Q; ++i) {
+                int tx = x + E[i][0];
+                if (open_x && (tx < 0 || tx >= nx)) continue;
+                tx = wrap(tx, nx);
+                const int ty = wrap(y + E[i][1], ny);
+                if (!solid[(long)ty * nx + tx]) continue;
+                const double returned = fstar[(long)i * n + k];
+                fx += E[i][0] * (fstar[(long)i * n + k] + returned);
+                fy += E[i][1] * (fstar[(long)i * n + k] + returned);
+            }
+        }
+    }
+    out[0] = fx;
+    out[1] = fy;
+    free(fstar);
+    return 0;
+}
+
+/* nsteps steps of orc_step_open (in place).  Returns 0 or -1.            */
+int orc_run_open(int nx, int ny, const uint8_t *solid, double *f, long nsteps, double tau1,
+                 double tau2, double gx, double gy, double u_in, double rho_w, double rho_out) {
+    const long len = (long)Q * nx * ny;
+    double *tmp = (double *)malloc(sizeof(double) * len);
+    if (!tmp) return -1;
+    double *a = f, *b = tmp;
+    for (long s = 0; s < nsteps; ++s) {
+        if (orc_step_open(nx, ny, solid, a, b, tau1, tau2, gx, gy, u_in, rho_w, rho_out) != 0) {
+            free(tmp);
+            return -1;
+        }
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != f) memcpy(f, a, sizeof(double) * len);
+    free(tmp);
     return 0;
 }
 

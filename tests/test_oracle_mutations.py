@@ -12,6 +12,7 @@ import pytest
 import oracle
 import test_oracle_flows as flows
 import test_oracle_identities as ident
+import test_oracle_open as opn
 
 MUTATIONS = {
     "G dropped": (
@@ -47,6 +48,27 @@ MUTATIONS = {
     "diagonal weight 1/36 -> 1/18 for one direction": (
         "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};",
         "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 18.0};"),
+    "inflow wall correction with the wrong sign": (
+        "fout[(long)back * n + k] = v - 2.0 * WGT[i] * rho_w * (E[i][0] * u_in) / CS2;",
+        "fout[(long)back * n + k] = v + 2.0 * WGT[i] * rho_w * (E[i][0] * u_in) / CS2;"),
+    "inflow wall correction without 1/c_s^2": (
+        "fout[(long)back * n + k] = v - 2.0 * WGT[i] * rho_w * (E[i][0] * u_in) / CS2;",
+        "fout[(long)back * n + k] = v - 2.0 * WGT[i] * rho_w * (E[i][0] * u_in);"),
+    "outlet rule diagonal coefficient": (
+        "fout[7 * n + k] = f[5] + 0.5 * (f[2] - f[4]) - 1.0 / 6.0 * rho_out * ux;",
+        "fout[7 * n + k] = f[5] + 0.5 * (f[2] - f[4]) - 1.0 / 3.0 * rho_out * ux;"),
+    "outlet rule axis coefficient": (
+        "fout[3 * n + k] = f[1] - 2.0 / 3.0 * rho_out * ux;",
+        "fout[3 * n + k] = f[1] - 1.0 / 3.0 * rho_out * ux;"),
+    "outlet ghost Phi taken as 0": (
+        "if (open_x && x == nx - 1) right = px[k];",
+        "if (open_x && x == nx - 1) right = 0.0;"),
+    "inlet ghost Phi taken periodic": (
+        "if (open_x && x == 0) left = rho_w * u_in * u_in * u_in;",
+        "if (open_x && x == 0) left = left + 0.0 * rho_w;"),
+    "wall force without the returned population": (
+        "fx += E[i][0] * (fstar[(long)i * n + k] + returned);",
+        "fx += E[i][0] * (fstar[(long)i * n + k] + 0.0 * returned);"),
     "second-order projection coefficient 1/c_s^4": (
         "(1.0 - 1.0 / tau1) * WGT[i] * r2 / (2.0 * CS2 * CS2)",
         "(1.0 - 1.0 / tau1) * WGT[i] * r2 / (CS2 * CS2)"),
@@ -67,6 +89,10 @@ def _battery(o):
         ("momentum", lambda: flows.test_periodic_momentum_grows_by_the_force(o)),
         ("rotation", lambda: flows.test_rotation_symmetry(o)),
         ("sound", lambda: flows.test_sound_attenuation_is_galilean_invariant(o)),
+        ("uniform inflow", lambda: opn.test_uniform_inflow_is_a_fixed_point(o, 0.03, 0.8)),
+        ("outlet moments", lambda: opn.test_outlet_density_and_transverse_momentum(o, 0.97)),
+        ("wall force", lambda: opn.test_wall_force_balances_body_force_at_steady_state(o, 4e-5)),
+        ("open ends", lambda: opn.test_open_ends_do_not_see_each_other(o)),
     ]
     for name, fn in checks:
         try:

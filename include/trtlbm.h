@@ -64,14 +64,34 @@ typedef enum {
     TRT_F16_SHIFTED = 2  /* IEEE half storage of f - w, FP32 arithmetic */
 } trt_storage;
 
-/* One simulation: the problem statement of the paper (Sec. II.B-II.D). */
+typedef enum {
+    TRT_X_PERIODIC = 0,       /* periodic in x (and always in y) */
+    TRT_X_INFLOW_OUTFLOW = 1  /* inflow wall at x = -1/2, pressure outlet at x = nx - 1 */
+} trt_x_boundary;
+
+/* One simulation: the problem statement of the paper (Sec. II.B-II.D), and
+ * optionally the open x boundaries of the creeping flow of Sec. III.D:
+ *  - inflow: a half-way bounce-back wall at x = -1/2 moving with (u_in, 0);
+ *    a population leaving column 0 through it returns with the moving-wall
+ *    correction -2 w_i rho_in (e_i . u_wall) / c_s^2 (Ladd's rule);
+ *  - outflow: column nx - 1 held at density rho_out with zero transverse
+ *    velocity; its three populations entering from outside follow Zou and
+ *    He's pressure rule; populations leaving through x = nx are lost;
+ *  - the gradient of Phi = rho u^3 sees rho_in u_in^3 beyond the inflow
+ *    wall and the last column's value beyond the outlet.
+ * Neither rule includes the body force.  Open-boundary lattices run the
+ * one-column sweep. */
 typedef struct {
-    int32_t nx, ny;        /* lattice size, 1..46340 each; periodic in x and y */
+    int32_t nx, ny;        /* lattice size, 1..46340 each; periodic in y (and x unless open) */
     double tau_s;          /* tau_s1 > 1/2: viscosity nu = (tau_s - 1/2)/3 (Sec. II.C) */
     double tau_s2;         /* tau_s2 >= 1/2: free third-order rate (Sec. II.B) */
     double gx, gy;         /* body acceleration g; the force is F = rho g (Sec. II.D) */
     const uint8_t *mask;   /* device [ny][nx], nonzero = solid (half-way bounce-back); NULL = none */
     int32_t storage;       /* trt_storage */
+    int32_t x_boundary;    /* trt_x_boundary (0: periodic) */
+    double u_in;           /* inflow wall velocity (x), lattice units; open x only */
+    double rho_in;         /* density in the inflow wall's correction (> 0); open x only */
+    double rho_out;        /* outlet density (> 0); open x only */
 } trt_problem;
 
 /* Launch shape of the fused sweep.  Zero fields take the built-in default
@@ -166,6 +186,22 @@ trt_status trt_diagnostics(trt_sim *s, double *out);
 /* Mean of u_x over the fluid nodes of each row, FP64, into device
  * out[ny] (0 for a row without fluid) -- the slip measurement of Sec. III.C. */
 trt_status trt_row_mean_ux(trt_sim *s, double *out);
+
+/* Momentum handed to the solid nodes by the last collision (the drag of
+ * Sec. III.D, momentum exchange): every link from a fluid node x_f to a
+ * solid node x_f + e_i carries e_i [f*_i(x_f) + f*_opp(i)(x_s)] = 2 e_i
+ * f*_i(x_f) under half-way bounce-back.  Links through open x ends are not
+ * wall links.  Device FP64 out[2] = (F_x, F_y), fixed-order reduction.
+ * ESTATE before the first step after the state was set.  Uses library
+ * scratch: calls on one simulation are ordered by its stream. */
+trt_status trt_wall_force(trt_sim *s, double *out);
+
+/* Steady-state test (Sec. III, convergence criterion): compares the current
+ * He-shifted velocity with prev_ux, prev_uy (device FP64 [ny][nx], caller
+ * owned) over the fluid nodes and then overwrites them with the current
+ * velocity.  Device FP64 out[3] = (max over nodes and components of
+ * |u - u_prev|, sum |u - u_prev|^2, sum |u|^2).  Uses library scratch. */
+trt_status trt_velocity_change(trt_sim *s, double *prev_ux, double *prev_uy, double *out);
 
 /* Synchronous check: runs trt_diagnostics into library scratch, waits for
  * the stream, and returns TRT_EUNSTABLE if any fluid node diverged. */

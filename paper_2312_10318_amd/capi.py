@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("TRTLBM_LIB") or os.path.join(HERE, "libtrtlbm.so")
 
 TRT_OK, TRT_EINVAL, TRT_ENOMEM, TRT_EDEVICE, TRT_EUNSTABLE, TRT_ESTATE = range(6)
 TRT_F64, TRT_F32_SHIFTED, TRT_F16_SHIFTED = 0, 1, 2
+TRT_X_PERIODIC, TRT_X_INFLOW_OUTFLOW = 0, 1
 TRT_NDIAG = 8
 
 STATUS_NAMES = {0: "TRT_OK", 1: "TRT_EINVAL", 2: "TRT_ENOMEM", 3: "TRT_EDEVICE",
@@ -27,6 +28,7 @@ EXPORTED = [
     "trt_pitch", "trt_plane_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
     "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics", "trt_row_mean_ux",
+    "trt_wall_force", "trt_velocity_change",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_step",
     "trt_batch_diagnostics", "trt_batch_set_tuning", "trt_batch_destroy", "trt_last_error",
     "trt_version",
@@ -36,7 +38,9 @@ EXPORTED = [
 class trt_problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau_s", ctypes.c_double),
                 ("tau_s2", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
-                ("mask", ctypes.c_void_p), ("storage", ctypes.c_int32)]
+                ("mask", ctypes.c_void_p), ("storage", ctypes.c_int32),
+                ("x_boundary", ctypes.c_int32), ("u_in", ctypes.c_double),
+                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double)]
 
 
 class trt_tuning(ctypes.Structure):
@@ -82,6 +86,8 @@ def load():
         "trt_macros": (ctypes.c_int, [P, P, P, P]),
         "trt_diagnostics": (ctypes.c_int, [P, P]),
         "trt_row_mean_ux": (ctypes.c_int, [P, P]),
+        "trt_wall_force": (ctypes.c_int, [P, P]),
+        "trt_velocity_change": (ctypes.c_int, [P, P, P, P]),
         "trt_check": (ctypes.c_int, [P]),
         "trt_state": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]),
         "trt_destroy": (None, [P]),
@@ -107,8 +113,10 @@ def _check(st, where):
     return st
 
 
-def _prob(nx, ny, tau_s, tau_s2, gx, gy, mask_ptr, storage):
-    return trt_problem(nx, ny, tau_s, tau_s2, gx, gy, mask_ptr, storage)
+def _prob(nx, ny, tau_s, tau_s2, gx, gy, mask_ptr, storage, x_boundary=TRT_X_PERIODIC,
+          u_in=0.0, rho_in=1.0, rho_out=1.0):
+    return trt_problem(nx, ny, tau_s, tau_s2, gx, gy, mask_ptr, storage, x_boundary, u_in,
+                       rho_in, rho_out)
 
 
 def trt_pitch(nx: int, storage: int) -> int:
@@ -167,6 +175,14 @@ def trt_macros(sim: int, rho: int, ux: int, uy: int) -> None:
 
 def trt_diagnostics(sim: int, out: int) -> None:
     _check(load().trt_diagnostics(sim, out), "trt_diagnostics")
+
+
+def trt_wall_force(sim: int, out: int) -> None:
+    _check(load().trt_wall_force(sim, out), "trt_wall_force")
+
+
+def trt_velocity_change(sim: int, prev_ux: int, prev_uy: int, out: int) -> None:
+    _check(load().trt_velocity_change(sim, prev_ux, prev_uy, out), "trt_velocity_change")
 
 
 def trt_row_mean_ux(sim: int, out: int) -> None:

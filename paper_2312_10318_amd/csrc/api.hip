@@ -60,6 +60,14 @@ trt_status check_problem(const trt_problem *p) {
     if (!isfinite(p->tau_s2) || !(p->tau_s2 >= 0.5))
         return fail(TRT_EINVAL, "tau_s2 must be finite and >= 1/2");
     if (!isfinite(p->gx) || !isfinite(p->gy)) return fail(TRT_EINVAL, "g must be finite");
+    if (p->x_boundary != TRT_X_PERIODIC && p->x_boundary != TRT_X_INFLOW_OUTFLOW)
+        return fail(TRT_EINVAL, "x_boundary must be TRT_X_PERIODIC or TRT_X_INFLOW_OUTFLOW");
+    if (p->x_boundary == TRT_X_INFLOW_OUTFLOW) {
+        if (p->nx < 2) return fail(TRT_EINVAL, "open x boundaries need nx >= 2");
+        if (!isfinite(p->u_in) || !isfinite(p->rho_in) || !isfinite(p->rho_out) ||
+            !(p->rho_in > 0.0) || !(p->rho_out > 0.0))
+            return fail(TRT_EINVAL, "u_in must be finite and rho_in, rho_out finite and > 0");
+    }
     return TRT_OK;
 }
 
@@ -232,6 +240,11 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
     d.gx = p->gx;
     d.gy = p->gy;
+    d.xbc = p->x_boundary == TRT_X_INFLOW_OUTFLOW ? 1 : 0;
+    d.pad2_ = 0;
+    d.u_in = d.xbc ? p->u_in : 0.0;
+    d.rho_in = d.xbc ? p->rho_in : 1.0;
+    d.rho_out = d.xbc ? p->rho_out : 1.0;
     trt::tile(d, s->launch, p->storage);
 
     hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
@@ -342,6 +355,22 @@ trt_status trt_diagnostics(trt_sim *s, double *out) {
     return TRT_OK;
 }
 
+trt_status trt_wall_force(trt_sim *s, double *out) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    if (s->time == 0) return fail(TRT_ESTATE, "no step taken since the state was set");
+    TRT_HIP(trt::launch_wall_force(s->desc, s->prob.storage, s->cur, s->scratch, out, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_velocity_change(trt_sim *s, double *prev_ux, double *prev_uy, double *out) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!prev_ux || !prev_uy || !out) return fail(TRT_EINVAL, "prev_ux, prev_uy and out are required");
+    TRT_HIP(trt::launch_velocity_change(s->desc, s->prob.storage, s->cur, prev_ux, prev_uy,
+                                        s->scratch, out, s->stream));
+    return TRT_OK;
+}
+
 trt_status trt_row_mean_ux(trt_sim *s, double *out) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!out) return fail(TRT_EINVAL, "out is NULL");
@@ -432,7 +461,7 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     b->mask = false;
     b->buf = true;
     for (int k = 0; k < n; ++k) {
-        b->mask = b->mask || sims[k]->prob.mask != nullptr;
+        b->mask = b->mask || sims[k]->prob.mask != nullptr || sims[k]->prob.x_boundary != 0;
         b->buf = b->buf && trt::buffer_addressable(sims[k]->desc, sims[k]->prob.storage);
     }
     b->stream = sims[0]->stream;

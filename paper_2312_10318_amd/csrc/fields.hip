@@ -33,7 +33,11 @@ __device__ __forceinline__ bool is_solid(const uint8_t *mask, int nx, int x, int
 }
 
 // Scatter of one fluid node's pre-collision populations fi[9] (unshifted,
-// FP64) into lattice `lat`.
+// FP64) into lattice `lat`.  With open x boundaries, the populations that
+// enter column 0 through the inflow wall are stored in the slots the gather
+// reads them back from (minus the wall's momentum correction), and the
+// three that enter the outlet column from outside are not stored: the
+// outlet rule determines them.
 template <int ST>
 __device__ __forceinline__ void scatter_node(const InstDesc &d, void *lat, int x, int y,
                                              const double fi[9]) {
@@ -41,28 +45,45 @@ __device__ __forceinline__ void scatter_node(const InstDesc &d, void *lat, int x
     T *b = static_cast<T *>(lat);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const double v = Store<ST>::shifted ? fi[i] - weight(i) : fi[i];
-        const int sx = wrapi(x - kEx[i], d.nx), sy = wrapi(y - kEy[i], d.ny);
+        double v = Store<ST>::shifted ? fi[i] - weight(i) : fi[i];
+        const int tx = x - kEx[i];
+        if (d.xbc && tx >= d.nx) continue;
+        const int sx = wrapi(tx, d.nx), sy = wrapi(y - kEy[i], d.ny);
         int64_t idx;
-        if (is_solid(d.mask, d.nx, sx, sy))
+        if (d.xbc && tx < 0) {
+            v -= (i == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (d.rho_in * d.u_in);
             idx = kOpp[i] * d.plane + (int64_t)y * d.pitch + x;
-        else
+        } else if (is_solid(d.mask, d.nx, sx, sy)) {
+            idx = kOpp[i] * d.plane + (int64_t)y * d.pitch + x;
+        } else {
             idx = i * d.plane + (int64_t)sy * d.pitch + sx;
+        }
         b[idx] = (T)v;
     }
+}
+
+// Pre-collision populations of node (x, y) in the arithmetic precision,
+// including the open x boundaries' rules.
+template <int ST>
+__device__ __forceinline__ bool gather_state(const InstDesc &d, int srcsel, int x, int y,
+                                             typename Store<ST>::C f[9]) {
+    using T = typename Store<ST>::T;
+    using C = typename Store<ST>::C;
+    const int xm = (x == 0) ? d.nx - 1 : x - 1;
+    const int xp = (x == d.nx - 1) ? 0 : x + 1;
+    const bool solid = gather<T, C, true>(static_cast<const T *>(d.buf[srcsel]), d.plane, d.pitch,
+                                          d.mask, d.nx, d.ny, y, xm, x, xp, f, d.xbc != 0);
+    if (d.xbc)
+        open_x_fix<C, Store<ST>::shifted>(f, x, d.nx, (C)d.u_in, (C)d.rho_in, (C)d.rho_out);
+    return solid;
 }
 
 // Pre-collision populations of node (x, y), unshifted, FP64.
 template <int ST>
 __device__ __forceinline__ bool gather_node(const InstDesc &d, int srcsel, int x, int y,
                                             double fo[9]) {
-    using T = typename Store<ST>::T;
-    using C = typename Store<ST>::C;
-    const int xm = (x == 0) ? d.nx - 1 : x - 1;
-    const int xp = (x == d.nx - 1) ? 0 : x + 1;
-    C f[9];
-    const bool solid = gather<T, C, true>(static_cast<const T *>(d.buf[srcsel]), d.plane, d.pitch,
-                                          d.mask, d.nx, d.ny, y, xm, x, xp, f);
+    typename Store<ST>::C f[9];
+    const bool solid = gather_state<ST>(d, srcsel, x, y, f);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         fo[i] = Store<ST>::shifted ? (double)f[i] + weight(i) : (double)f[i];
@@ -110,13 +131,8 @@ __global__ void get_populations_kernel(InstDesc d, int srcsel, double *__restric
 template <int ST>
 __device__ __forceinline__ bool node_moments(const InstDesc &d, int srcsel, int x, int y,
                                              Moments<double, Store<ST>::shifted> &m) {
-    using T = typename Store<ST>::T;
-    using C = typename Store<ST>::C;
-    const int xm = (x == 0) ? d.nx - 1 : x - 1;
-    const int xp = (x == d.nx - 1) ? 0 : x + 1;
-    C f[9];
-    const bool solid = gather<T, C, true>(static_cast<const T *>(d.buf[srcsel]), d.plane, d.pitch,
-                                          d.mask, d.nx, d.ny, y, xm, x, xp, f);
+    typename Store<ST>::C f[9];
+    const bool solid = gather_state<ST>(d, srcsel, x, y, f);
     double fd[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
@@ -260,6 +276,95 @@ __global__ __launch_bounds__(256) void row_mean_kernel(InstDesc d, int srcsel,
     }
 }
 
+// Fixed-order block reduction of K sums (and, for K3MAX, a max in slot 0).
+template <int K, bool MAX0>
+__device__ void block_reduce_k(double v[K]) {
+    __shared__ double sh[kDiagThreads / 64][K];
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double o = __shfl_down(v[j], off);
+            v[j] = (MAX0 && j == 0) ? fmax(v[j], o) : v[j] + o;
+        }
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int j = 0; j < K; ++j) sh[w][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kDiagThreads / 64; ++k)
+            for (int j = 0; j < K; ++j) v[j] = (MAX0 && j == 0) ? fmax(v[j], sh[k][j]) : v[j] + sh[k][j];
+}
+
+template <int K, bool MAX0>
+__global__ void final_reduce_k(const double *__restrict__ partials, double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double v[K];
+    for (int j = 0; j < K; ++j) v[j] = partials[j];
+    for (int b = 1; b < kDiagBlocks; ++b)
+        for (int j = 0; j < K; ++j)
+            v[j] = (MAX0 && j == 0) ? fmax(v[j], partials[b * K + j]) : v[j] + partials[b * K + j];
+    for (int j = 0; j < K; ++j) out[j] = v[j];
+}
+
+// Momentum exchange with solid nodes (Sec. III.D): every link from a fluid
+// node x_f to a solid node x_f + e_i carries 2 e_i f*_i(x_f, t) under
+// half-way bounce-back; f* is the lattice after the step (post-collision
+// values stored at their own node).  Links leaving through open x ends are
+// not wall links.
+template <int ST>
+__global__ __launch_bounds__(kDiagThreads) void wall_force_kernel(InstDesc d, int src,
+                                                                 double *__restrict__ partials) {
+    using T = typename Store<ST>::T;
+    const T *b = static_cast<const T *>(d.buf[src]);
+    double v[2] = {0.0, 0.0};
+    const int64_t n = (int64_t)d.nx * d.ny;
+    if (d.mask != nullptr) {
+        for (int64_t k = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; k < n;
+             k += (int64_t)kDiagBlocks * kDiagThreads) {
+            const int y = (int)(k / d.nx), x = (int)(k - (int64_t)y * d.nx);
+            if (d.mask[k]) continue;
+            for (int i = 1; i < 9; ++i) {
+                const int tx = x + kEx[i];
+                if (d.xbc && (tx < 0 || tx >= d.nx)) continue;
+                if (!is_solid(d.mask, d.nx, wrapi(tx, d.nx), wrapi(y + kEy[i], d.ny))) continue;
+                const double fs = (double)b[i * d.plane + (int64_t)y * d.pitch + x] +
+                                  (Store<ST>::shifted ? weight(i) : 0.0);
+                v[0] += 2.0 * kEx[i] * fs;
+                v[1] += 2.0 * kEy[i] * fs;
+            }
+        }
+    }
+    block_reduce_k<2, false>(v);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x * 2 + 0] = v[0];
+        partials[blockIdx.x * 2 + 1] = v[1];
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kDiagThreads) void velocity_change_kernel(
+    InstDesc d, int srcsel, double *__restrict__ pux, double *__restrict__ puy,
+    double *__restrict__ partials) {
+    double v[3] = {0.0, 0.0, 0.0};
+    const int64_t n = (int64_t)d.nx * d.ny;
+    for (int64_t k = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; k < n;
+         k += (int64_t)kDiagBlocks * kDiagThreads) {
+        const int y = (int)(k / d.nx), x = (int)(k - (int64_t)y * d.nx);
+        Moments<double, Store<ST>::shifted> m;
+        if (node_moments<ST>(d, srcsel, x, y, m)) continue;
+        const double dx = m.ux - pux[k], dy = m.uy - puy[k];
+        v[0] = fmax(v[0], fmax(fabs(dx), fabs(dy)));
+        v[1] += dx * dx + dy * dy;
+        v[2] += m.ux * m.ux + m.uy * m.uy;
+        pux[k] = m.ux;
+        puy[k] = m.uy;
+    }
+    block_reduce_k<3, true>(v);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 3; ++j) partials[blockIdx.x * 3 + j] = v[j];
+}
+
 dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4); }
 
 #define TRT_DISPATCH(storage, CALL)                 \
@@ -304,6 +409,25 @@ hipError_t launch_diagnostics(const InstDesc &d, int storage, int src, double *p
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     diag_final_kernel<<<1, 64, 0, stream>>>(partials, out, time);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_force(const InstDesc &d, int storage, int src, double *partials,
+                             double *out, hipStream_t stream) {
+    TRT_DISPATCH(storage, (wall_force_kernel<S><<<kDiagBlocks, kDiagThreads, 0, stream>>>(d, src, partials)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    final_reduce_k<2, false><<<1, 64, 0, stream>>>(partials, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity_change(const InstDesc &d, int storage, int src, double *prev_ux,
+                                  double *prev_uy, double *partials, double *out,
+                                  hipStream_t stream) {
+    TRT_DISPATCH(storage, (velocity_change_kernel<S><<<kDiagBlocks, kDiagThreads, 0, stream>>>(d, src, prev_ux, prev_uy, partials)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    final_reduce_k<3, true><<<1, 64, 0, stream>>>(partials, out);
     return hipGetLastError();
 }
 

@@ -38,9 +38,10 @@ inline int batch_waves_per_block(const Launch &l) {
     return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
 }
 
-// Whether an instance can use two-column strips: no obstacles (the pair
-// path has no bounce-back), an even nx (a lane's pair never straddles the
-// periodic seam) and a lattice within one buffer resource.
+// Whether an instance can use two-column strips: no obstacles and periodic
+// in x (the pair path has neither bounce-back nor open boundaries), an even
+// nx (a lane's pair never straddles the periodic seam) and a lattice within
+// one buffer resource.
 bool pair_eligible(const InstDesc &d, int storage);
 
 // Rows per wavefront when the launch shape leaves it open.  Long strips
@@ -105,5 +106,18 @@ hipError_t launch_diagnostics(const InstDesc &d, int storage, int src, double *p
                               double *out, double time, hipStream_t stream);
 hipError_t launch_row_mean_ux(const InstDesc &d, int storage, int src, double *out,
                               hipStream_t stream);
+
+// Momentum handed to solid nodes by the last collision (the post-collision
+// lattice `src`): out[2] = (F_x, F_y).  partials as for the diagnostics.
+hipError_t launch_wall_force(const InstDesc &d, int storage, int src, double *partials,
+                             double *out, hipStream_t stream);
+
+// Change of the He-shifted velocity since the fields prev_ux, prev_uy (dense
+// FP64 [ny][nx], replaced by the current velocity): out[0] = max over fluid
+// nodes and components of |u - u_prev|, out[1] = sum |u - u_prev|^2,
+// out[2] = sum |u|^2.
+hipError_t launch_velocity_change(const InstDesc &d, int storage, int src, double *prev_ux,
+                                  double *prev_uy, double *partials, double *out,
+                                  hipStream_t stream);
 
 }  // namespace trt

@@ -71,6 +71,12 @@ struct InstDesc {
     int32_t strips, rowblocks, rows;
     int32_t cols;         // columns per lane of the sweep: 1 or 2 (two-column strips)
     double omega1, omega2, phi, gx, gy;
+    // open x boundaries (xbc = 1): inflow wall at x = -1/2 moving with
+    // (u_in, 0) at density rho_in, pressure outlet at x = nx - 1 held at
+    // rho_out; xbc = 0: periodic in x
+    int32_t xbc;
+    int32_t pad2_;
+    double u_in, rho_in, rho_out;
 };
 
 // Products w_i * X.  In FP32 the rounded weights fl(4/9), fl(1/9), fl(1/36)
@@ -320,31 +326,49 @@ __device__ __forceinline__ void gather_open(const T *__restrict__ src, int64_t p
     f[8] = to_c(ld_at(rp + 8 * plane, om));
 }
 
-// Raw pull-gather with walls: like gather() below but without widening;
+template <class T>
+__device__ __forceinline__ void open_x_sources(const T *a[9], const T *r0, int64_t plane, int xc,
+                                               int nx);
+
+// Raw pull-gather with walls (mask, may be null) and, when xbc is set, the
+// open x boundaries' sources: like gather() below but without widening;
 // returns whether the node itself is solid.
 template <class T>
 __device__ __forceinline__ bool gather_masked_raw(const T *__restrict__ src, int64_t plane,
                                                   int pitch, const uint8_t *__restrict__ mask,
                                                   int nx, int ym, int y, int yp, int xm, int xc,
-                                                  int xp, T v[9]) {
+                                                  int xp, bool xbc, T v[9]) {
     const T *r0 = src + (int64_t)y * pitch;
     const T *rm = src + (int64_t)ym * pitch;
     const T *rp = src + (int64_t)yp * pitch;
-    const uint8_t *mm = mask + (int64_t)ym * nx;
-    const uint8_t *m0 = mask + (int64_t)y * nx;
-    const uint8_t *mp = mask + (int64_t)yp * nx;
     const T *a[9] = {r0 + xc,
-                     m0[xm] ? r0 + 3 * plane + xc : r0 + plane + xm,
-                     mm[xc] ? r0 + 4 * plane + xc : rm + 2 * plane + xc,
-                     m0[xp] ? r0 + 1 * plane + xc : r0 + 3 * plane + xp,
-                     mp[xc] ? r0 + 2 * plane + xc : rp + 4 * plane + xc,
-                     mm[xm] ? r0 + 7 * plane + xc : rm + 5 * plane + xm,
-                     mm[xp] ? r0 + 8 * plane + xc : rm + 6 * plane + xp,
-                     mp[xp] ? r0 + 5 * plane + xc : rp + 7 * plane + xp,
-                     mp[xm] ? r0 + 6 * plane + xc : rp + 8 * plane + xm};
+                     r0 + plane + xm,
+                     rm + 2 * plane + xc,
+                     r0 + 3 * plane + xp,
+                     rp + 4 * plane + xc,
+                     rm + 5 * plane + xm,
+                     rm + 6 * plane + xp,
+                     rp + 7 * plane + xp,
+                     rp + 8 * plane + xm};
+    bool solid = false;
+    if (mask != nullptr) {
+        const uint8_t *mm = mask + (int64_t)ym * nx;
+        const uint8_t *m0 = mask + (int64_t)y * nx;
+        const uint8_t *mp = mask + (int64_t)yp * nx;
+        a[1] = m0[xm] ? r0 + 3 * plane + xc : a[1];
+        a[2] = mm[xc] ? r0 + 4 * plane + xc : a[2];
+        a[3] = m0[xp] ? r0 + 1 * plane + xc : a[3];
+        a[4] = mp[xc] ? r0 + 2 * plane + xc : a[4];
+        a[5] = mm[xm] ? r0 + 7 * plane + xc : a[5];
+        a[6] = mm[xp] ? r0 + 8 * plane + xc : a[6];
+        a[7] = mp[xp] ? r0 + 5 * plane + xc : a[7];
+        a[8] = mp[xm] ? r0 + 6 * plane + xc : a[8];
+        solid = m0[xc] != 0;
+    }
+    if (xbc) open_x_sources(a, r0, plane, xc, nx);
 #pragma unroll
     for (int i = 0; i < 9; ++i) v[i] = a[i][0];
-    return m0[xc] != 0;
+    return solid;
 }
 
 // Pull-gather of the pre-collision populations f_i(x, t) of node (xc, y)
@@ -355,7 +379,7 @@ __device__ __forceinline__ bool gather_masked_raw(const T *__restrict__ src, int
 template <class T, class C, bool MASK>
 __device__ __forceinline__ bool gather(const T *__restrict__ src, int64_t plane, int pitch,
                                        const uint8_t *__restrict__ mask, int nx, int ny, int y,
-                                       int xm, int xc, int xp, C f[9]) {
+                                       int xm, int xc, int xp, C f[9], bool xbc = false) {
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     const T *r0 = src + (int64_t)y * pitch;
@@ -385,9 +409,61 @@ __device__ __forceinline__ bool gather(const T *__restrict__ src, int64_t plane,
         if (mp[xp]) a[7] = r0 + 5 * plane + xc;
         if (mp[xm]) a[8] = r0 + 6 * plane + xc;
     }
+    if (xbc) open_x_sources(a, r0, plane, xc, nx);
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(a[i][0]);
     return solid;
+}
+
+// ---------------------------------------------------------------------------
+// Open x boundaries (the creeping flow of Sec. III.D).
+//
+// Inflow: a half-way bounce-back wall at x = -1/2 moving with (u_in, 0).  A
+// population f*_i leaving column 0 through it (e_ix = -1: i = 3, 6, 7)
+// returns to the same node as opp(i) with the moving-wall correction
+// -2 w_i rho_in (e_i . u_wall) / c_s^2 = +6 w_i rho_in u_in (Ladd's rule),
+// so in the pull form column 0 takes f_1, f_5, f_8 from its own slots 3, 7,
+// 6 plus 6 w rho_in u_in.  Outflow: the populations entering column nx - 1
+// from outside (e_ix = -1: 3, 6, 7) follow Zou and He's pressure rule for a
+// prescribed density rho_out and zero transverse velocity, computed from the
+// six known ones.  In shifted storage the weights cancel in both rules (w_i
+// = w_opp(i); w_2 = w_4; the known sum carries exactly 1 of weight).  Phi
+// beyond the inflow wall is the wall's rho_in u_in^3; beyond the outlet it
+// equals the last column's.  The body force is not part of either rule.
+
+// Redirect the pull sources of column 0 (inflow: own slots) and column
+// nx - 1 (outflow: any valid slot, replaced by open_x_fix).
+template <class T>
+__device__ __forceinline__ void open_x_sources(const T *a[9], const T *r0, int64_t plane, int xc,
+                                               int nx) {
+    if (xc == 0) {
+        a[1] = r0 + 3 * plane + xc;
+        a[5] = r0 + 7 * plane + xc;
+        a[8] = r0 + 6 * plane + xc;
+    }
+    if (xc == nx - 1) a[3] = a[6] = a[7] = r0 + xc;
+}
+
+// Complete the boundary columns' pre-collision populations (after the pull
+// sources of open_x_sources, widened to C).
+template <class C, bool SHIFTED>
+__device__ __forceinline__ void open_x_fix(C f[9], int xc, int nx, C u_in, C rho_in, C rho_out) {
+    if (xc == 0) {
+        const C m1 = C(2.0 / 3.0) * (rho_in * u_in);  // 6 w_1 rho_in u_in
+        const C m5 = C(1.0 / 6.0) * (rho_in * u_in);  // 6 w_5 rho_in u_in
+        f[1] += m1;
+        f[5] += m5;
+        f[8] += m5;
+    }
+    if (xc == nx - 1) {
+        const C known = (f[0] + f[2] + f[4]) + C(2) * (f[1] + f[5] + f[8]);
+        // rho_out u_x = (sum of the known, counted as Zou and He) - rho_out
+        const C rux = SHIFTED ? (known + C(1)) - rho_out : known - rho_out;
+        const C half24 = C(0.5) * (f[2] - f[4]);
+        f[3] = f[1] - C(2.0 / 3.0) * rux;
+        f[7] = f[5] + half24 - C(1.0 / 6.0) * rux;
+        f[6] = f[8] - half24 - C(1.0 / 6.0) * rux;
+    }
 }
 
 }  // namespace trt

@@ -73,13 +73,13 @@ template <class T> struct Raw {
 template <class T, bool MASK, class Acc>
 __device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, const T *src, int64_t plane,
                                            int pitch, const uint8_t *mask, int nx, int ny, int y,
-                                           const Column &col) {
+                                           const Column &col, bool xbc = false) {
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     r.solid = false;
-    if (MASK && mask != nullptr) {
+    if (MASK && (mask != nullptr || xbc)) {
         r.solid = gather_masked_raw<T>(src, plane, pitch, mask, nx, ym, y, yp, col.xm, col.xc,
-                                       col.xp, r.v);
+                                       col.xp, xbc, r.v);
         return;
     }
     const int64_t e0 = (int64_t)y * pitch, em = (int64_t)ym * pitch, ep = (int64_t)yp * pitch;
@@ -101,11 +101,20 @@ template <class C, bool SHIFTED> struct RowState {
     bool solid;
 };
 
+// Boundary data of open x boundaries, in the arithmetic precision.
+template <class C> struct OpenX {
+    bool on;
+    int nx;
+    C u_in, rho_in, rho_out, phi_wall;
+};
+
 template <class T, class C, bool SHIFTED>
-__device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw, C gx, C gy) {
+__device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw, C gx, C gy,
+                                      const OpenX<C> *ox = nullptr, int xc = 0) {
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
+    if (ox && ox->on) open_x_fix<C, SHIFTED>(f, xc, ox->nx, ox->u_in, ox->rho_in, ox->rho_out);
     r.solid = raw.solid;
     r.m.compute(f, gx, gy);
     const C px = r.m.rho * r.m.ux * r.m.ux * r.m.ux;
@@ -120,10 +129,12 @@ __device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw
 // lane owning that column computes: results do not depend on where strips
 // begin and end.
 template <class T, class C, bool SHIFTED>
-__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx) {
+__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx, const OpenX<C> *ox = nullptr,
+                                       int xc = 0) {
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
+    if (ox && ox->on) open_x_fix<C, SHIFTED>(f, xc, ox->nx, ox->u_in, ox->rho_in, ox->rho_out);
     const C s56 = f[5] + f[6], s78 = f[7] + f[8];
     const C d56 = f[5] - f[6], d78 = f[7] - f[8];
     const C diag = s56 + s78;
@@ -165,6 +176,15 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
 
     const C gx = (C)d.gx, gy = (C)d.gy;
     const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
+    // open x boundaries: only in the general (MASK) kernels
+    OpenX<C> ox;
+    ox.on = MASK && d.xbc != 0;
+    ox.nx = nx;
+    ox.u_in = (C)d.u_in;
+    ox.rho_in = (C)d.rho_in;
+    ox.rho_out = (C)d.rho_out;
+    ox.phi_wall = ox.rho_in * ox.u_in * ox.u_in * ox.u_in;
+    const OpenX<C> *oxp = MASK ? &ox : nullptr;
 
     const int y0 = rb * d.rows;
     const int y1 = min(y0 + d.rows, ny);
@@ -176,20 +196,21 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     {
         Raw<T> t;
         RowState<C, SH> w;
-        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, (y0 + ny - 1) % ny, col);
-        widen<T, C, SH>(w, t, gx, gy);
+        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, (y0 + ny - 1) % ny, col,
+                            ox.on);
+        widen<T, C, SH>(w, t, gx, gy, oxp, col.xc);
         phiy_below = w.phiy;
     }
     RowState<C, SH> cur;
     C hphix = C(0);
     {
         Raw<T> t;
-        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, y0, col);
-        widen<T, C, SH>(cur, t, gx, gy);
+        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, y0, col, ox.on);
+        widen<T, C, SH>(cur, t, gx, gy, oxp, col.xc);
         if (edge) {
             Raw<T> h;
-            gather_raw<T, MASK>(h, in, src, plane, pitch, mask, nx, ny, y0, hcol);
-            hphix = halo_phix<T, C, SH>(h, gx);
+            gather_raw<T, MASK>(h, in, src, plane, pitch, mask, nx, ny, y0, hcol, ox.on);
+            hphix = halo_phix<T, C, SH>(h, gx, oxp, hcol.xc);
         }
     }
 
@@ -197,13 +218,19 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         // row y+1: its Phi_y is needed now, its state in the next iteration
         const int yn = (y + 1 == ny) ? 0 : y + 1;
         Raw<T> nraw, nhalo;
-        gather_raw<T, MASK>(nraw, in, src, plane, pitch, mask, nx, ny, yn, col);
-        if (edge) gather_raw<T, MASK>(nhalo, in, src, plane, pitch, mask, nx, ny, yn, hcol);
+        gather_raw<T, MASK>(nraw, in, src, plane, pitch, mask, nx, ny, yn, col, ox.on);
+        if (edge)
+            gather_raw<T, MASK>(nhalo, in, src, plane, pitch, mask, nx, ny, yn, hcol, ox.on);
 
         // row y: everything of the collision except the y-gradient of Phi
         const C up = __shfl_up(cur.phix, 1), dn = __shfl_down(cur.phix, 1);
-        const C phix_l = (lane == 0) ? hphix : up;
-        const C phix_r = (lane == kStripWidth - 1) ? hphix : dn;
+        C phix_l = (lane == 0) ? hphix : up;
+        C phix_r = (lane == kStripWidth - 1) ? hphix : dn;
+        if (ox.on) {
+            // Phi beyond the inflow wall is the wall's; beyond the outlet, the last column's
+            if (col.xc == 0) phix_l = ox.phi_wall;
+            if (col.xc == nx - 1) phix_r = cur.phix;
+        }
         const C dphix = C(0.5) * (phix_r - phix_l);
         Coeffs<C> cf = collide_coeffs<C, SH>(cur.m, dphix, w1, w2, ph, gx, gy);
         // pin the coefficients here, ahead of the wait for row y+1's loads
@@ -212,8 +239,8 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
                      "+v"(cf.bxy), "+v"(cf.bxxy), "+v"(cf.bxyy));
 
         RowState<C, SH> nxt;
-        widen<T, C, SH>(nxt, nraw, gx, gy);
-        const C nhphix = edge ? halo_phix<T, C, SH>(nhalo, gx) : C(0);
+        widen<T, C, SH>(nxt, nraw, gx, gy, oxp, col.xc);
+        const C nhphix = edge ? halo_phix<T, C, SH>(nhalo, gx, oxp, hcol.xc) : C(0);
 
         const C dphiy = C(0.5) * (nxt.phiy - phiy_below);
         C fo[9];
@@ -603,12 +630,14 @@ bool buffer_addressable(const InstDesc &d, int storage) {
 }
 
 bool pair_eligible(const InstDesc &d, int storage) {
-    return d.mask == nullptr && d.nx % 2 == 0 && buffer_addressable(d, storage);
+    return d.mask == nullptr && d.xbc == 0 && d.nx % 2 == 0 && buffer_addressable(d, storage);
 }
 
 hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, const Launch &l,
                         hipStream_t stream) {
     if (d.cols == 2 && !pair_eligible(d, storage)) return hipErrorInvalidValue;
+    // open x boundaries live in the general (mask) kernels
+    if (d.xbc) mask = true;
     const bool buf = buffer_addressable(d, storage);
     switch (storage * 2 + (mask ? 1 : 0)) {
         case 0: return launch_single_b<ST_F64, false>(d, src, l, buf, stream);

@@ -18,10 +18,15 @@ def _torch():
     return torch
 
 
-def problem(nx, ny, tau_s, tau_s2, g=(0.0, 0.0), storage="f32", mask_ptr=None):
-    """The C problem struct (no device memory touched)."""
+def problem(nx, ny, tau_s, tau_s2, g=(0.0, 0.0), storage="f32", mask_ptr=None, inflow=None):
+    """The C problem struct (no device memory touched).  inflow = (u_in,
+    rho_in, rho_out) selects the open x boundaries (inflow wall, outlet)."""
+    xb, u_in, rho_in, rho_out = capi.TRT_X_PERIODIC, 0.0, 1.0, 1.0
+    if inflow is not None:
+        xb = capi.TRT_X_INFLOW_OUTFLOW
+        u_in, rho_in, rho_out = (float(v) for v in inflow)
     return capi.trt_problem(int(nx), int(ny), float(tau_s), float(tau_s2), float(g[0]),
-                            float(g[1]), mask_ptr, STORAGES[storage])
+                            float(g[1]), mask_ptr, STORAGES[storage], xb, u_in, rho_in, rho_out)
 
 
 def footprint_bytes(nx, ny, storage="f32", has_mask=False) -> int:
@@ -40,10 +45,13 @@ class Lattice:
     mask        optional [ny, nx] array, nonzero = solid (half-way bounce-back)
     storage     "f64", "f32" (f - w) or "f16" (f - w)
     stream      torch.cuda.Stream to enqueue on (default: the current stream)
+    inflow      optional (u_in, rho_in, rho_out): open x boundaries, an inflow
+                wall at x = -1/2 moving with (u_in, 0) and a pressure outlet
+                at x = nx - 1 (the creeping-flow set-up of Sec. III.D)
     """
 
     def __init__(self, nx, ny, tau_s, tau_s2, g=(0.0, 0.0), mask=None, storage="f32",
-                 stream=None, device="cuda"):
+                 stream=None, device="cuda", inflow=None):
         torch = _torch()
         self.nx, self.ny = int(nx), int(ny)
         self.tau_s, self.tau_s2 = float(tau_s), float(tau_s2)
@@ -57,8 +65,9 @@ class Lattice:
             if m.shape != (self.ny, self.nx):
                 raise ValueError("mask must have shape [ny, nx]")
             self.mask = torch.from_numpy(m).to(self.device)
+        self.inflow = None if inflow is None else tuple(float(v) for v in inflow)
         prob = problem(self.nx, self.ny, self.tau_s, self.tau_s2, self.g, storage,
-                       self.mask.data_ptr() if self.mask is not None else None)
+                       self.mask.data_ptr() if self.mask is not None else None, self.inflow)
         nbytes = capi.trt_lattice_bytes(prob)
         if nbytes == 0:
             capi.trt_create(prob, 0, 0, 0)  # raises with the validation message
@@ -138,6 +147,28 @@ class Lattice:
     def check(self) -> bool:
         """True while no fluid node has diverged (synchronous)."""
         return capi.trt_check(self.handle) == capi.TRT_OK
+
+    def wall_force(self):
+        """(F_x, F_y) handed to the solid nodes by the last collision
+        (momentum exchange, synchronous)."""
+        torch = _torch()
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        capi.trt_wall_force(self.handle, out.data_ptr())
+        self._sync()
+        v = out.cpu().numpy()
+        return float(v[0]), float(v[1])
+
+    def velocity_change(self, prev):
+        """Compare the velocity with prev = (ux, uy) device FP64 tensors (then
+        overwritten with the current velocity); returns (max |du|, sum |du|^2,
+        sum |u|^2) (synchronous)."""
+        torch = _torch()
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        capi.trt_velocity_change(self.handle, prev[0].data_ptr(), prev[1].data_ptr(),
+                                 out.data_ptr())
+        self._sync()
+        v = out.cpu().numpy()
+        return float(v[0]), float(v[1]), float(v[2])
 
     def state(self):
         """(index of the lattice holding the state, steps taken)."""

@@ -89,3 +89,23 @@ def test_null_handles_are_rejected(lib):
     lib.trt_batch_destroy(None)
     assert "batch" in capi.trt_last_error()
     assert "gfx950" in capi.trt_version()
+
+
+@pytest.mark.parametrize("xb,nx,u_in,rho_in,rho_out,msg", [
+    (2, 16, 0.0, 1.0, 1.0, "x_boundary"),
+    (1, 1, 0.01, 1.0, 1.0, "nx >= 2"),
+    (1, 16, float("nan"), 1.0, 1.0, "u_in"),
+    (1, 16, 0.01, 0.0, 1.0, "rho_in"),
+    (1, 16, 0.01, 1.0, -1.0, "rho_out"),
+])
+def test_create_rejects_invalid_open_boundaries(lib, xb, nx, u_in, rho_in, rho_out, msg):
+    p = capi.trt_problem(nx, 16, 0.6, 1.0, 0.0, 0.0, None, 1, xb, u_in, rho_in, rho_out)
+    with pytest.raises(capi.TrtError) as e:
+        capi.trt_create(p, 4096, 8192, 0)
+    assert e.value.status == capi.TRT_EINVAL and msg in str(e.value)
+
+
+def test_open_boundary_problem_is_valid(lib):
+    p = capi.trt_problem(16, 16, 0.6, 1.0, 0.0, 0.0, None, 1, capi.TRT_X_INFLOW_OUTFLOW, 0.01,
+                         1.0, 1.0)
+    assert capi.trt_lattice_bytes(p) == 9 * 16 * capi.trt_pitch(16, 1) * 4

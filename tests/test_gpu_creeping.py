@@ -1,0 +1,74 @@
+"""Creeping flow past a square cylinder (Sec. III.D) on the GPU.
+
+* Parity: on a small version of the set-up (D = 5, L = 6 D) the drag handed
+  to the cylinder after 1500 steps equals the oracle's (same inflow wall,
+  outlet rule and momentum exchange) to 1e-11 relative.
+* The paper's Table 1 (tests/golden/table1_creeping_flow.txt) at Re = 1e-3
+  on the full set-up (D = 21, L = 50 D, T = 0.1): the TRT-RLB viscous drag
+  coefficient C_d,mu = C_d Re converges to the printed 8.253 (held to 0.15%),
+  and the RLB model (tau_s2 = tau_s1) diverges, as printed.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import say
+from paper_2312_10318_amd import creeping
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_creeping_flow.txt")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_10318_amd import lattice
+    return lattice
+
+
+def table1():
+    rows = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            re_, ma, kn, tau1, trt, rlb = line.split()
+            rows[float(re_)] = (float(trt), None if rlb == "-" else float(rlb))
+    return rows
+
+
+def test_small_cylinder_drag_matches_oracle(L):
+    c = creeping.Case(0.1, D=5, ratio=6)
+    mask = creeping.cylinder_mask(c.n, c.D)
+    say("case: cylinder n=%d D=%d tau1=%.4f tau2=%.4f u0=%.4e" % (c.n, c.D, c.tau1, c.tau2, c.u0))
+    lat = L.Lattice(c.n, c.n, c.tau1, c.tau2, mask=mask, storage="f64",
+                    inflow=(c.u0, 1.0, 1.0))
+    lat.init_equilibrium(*creeping.initial_fields(c, mask))
+    f0 = lat.get_populations().cpu().numpy()
+    lat.step(1500)
+    fx, fy = lat.wall_force()
+    lat.close()
+    f = oracle.run_open(f0, 1499, c.tau1, c.tau2, u_in=c.u0, mask=mask)
+    rx, ry = oracle.wall_force(f, c.tau1, c.tau2, mask=mask, open_x=True, u_in=c.u0)
+    say("  F = (%.12e, %.3e) GPU, (%.12e, %.3e) oracle" % (fx, fy, rx, ry))
+    assert fx == pytest.approx(rx, rel=1e-11)
+    assert abs(fy - ry) < 1e-11 * abs(rx)
+
+
+def test_table1_low_reynolds_point():
+    want = table1()[1e-3]
+    cases = [creeping.Case(1e-3), creeping.Case(1e-3, rlb=True)]
+    say("case: Table 1, Re = 1e-3, D = 21, L = 50 D, TRT-RLB and RLB, FP64")
+    res = creeping.solve(cases, storage="f64", max_steps=200_000)
+    for r in res:
+        say("  %s: %s after %d steps, Cd_mu = %s" % (r["model"], r["status"], r["steps"],
+                                                    r.get("Cd_mu")))
+    trt, rlb = res
+    assert trt["status"] == "converged"
+    assert trt["Cd_mu"] == pytest.approx(want[0], rel=1.5e-3)
+    assert want[1] is None and rlb["status"] == "diverged"

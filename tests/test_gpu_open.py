@@ -1,0 +1,148 @@
+"""GPU parity of the open x boundaries (inflow wall, pressure outlet), the
+momentum exchange with solid nodes and the steady-state velocity change,
+against the oracle (Sec. III.D set-up).
+
+The GPU state after set_populations already follows the outlet rule (the
+outlet's three incoming populations are not stored), so each comparison
+starts the oracle from the state the GPU reads back.  FP64 populations are
+held to 1e-14; FP32 / FP16 velocities to 1e-5 / 1e-3 (relative max).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import TOL, rel_errors, say
+from paper_2312_10318_amd import inputs, params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_10318_amd import lattice
+    return lattice
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _case(seed, nx, ny, obstacle=True):
+    rng = np.random.default_rng(seed)
+    mask = None
+    if obstacle and nx >= 6 and ny >= 4:
+        mask = np.zeros((ny, nx), np.uint8)
+        for _ in range(max(1, nx * ny // 40)):
+            mask[rng.integers(0, ny), rng.integers(1, nx - 1)] = 1
+    f = inputs.random_populations(rng, (ny, nx), amp=0.05)
+    if mask is not None:
+        f[:, mask.astype(bool)] = 0.0
+    tau1 = float(rng.uniform(0.55, 3.0))
+    tau2 = float(rng.uniform(0.5, 2.0))
+    inflow = (float(rng.uniform(-0.05, 0.05)), float(rng.uniform(0.95, 1.05)),
+              float(rng.uniform(0.95, 1.05)))
+    return f, mask, tau1, tau2, inflow
+
+
+TILINGS = [(0, 0, -1, 1), (3, 1, 0, 1), (16, 4, 1, 1)]
+SHAPES = [(70, 13), (131, 9), (64, 5), (5, 7), (2, 3)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_open_boundaries_random_state_fp64(L, shape, tiling):
+    nx, ny = shape
+    f, mask, tau1, tau2, inflow = _case(hash((shape, tiling)) % 997, nx, ny)
+    say("case: open %dx%d mask=%s tiling=%s inflow=%s" % (nx, ny, mask is not None, tiling,
+                                                           inflow))
+    lat = L.Lattice(nx, ny, tau1, tau2, mask=mask, storage="f64", inflow=inflow)
+    lat.set_tuning(*tiling)
+    lat.set_populations(f)
+    f0 = _np(lat.get_populations())
+    lat.step(6)
+    got = _np(lat.get_populations())
+    lat.close()
+    want = oracle.run_open(f0, 6, tau1, tau2, u_in=inflow[0], rho_w=inflow[1],
+                           rho_out=inflow[2], mask=mask)
+    err = np.max(np.abs(got - want))
+    say("  max |f - f_oracle| = %.3e" % err)
+    assert err < 1e-14
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_uniform_inflow_stays_uniform(L, storage):
+    nx, ny, u0 = 96, 8, 0.02
+    tau1 = 0.9
+    tau2 = params.tau2_from_magic(tau1, 3 / 16)
+    rho, ux, uy = np.ones((ny, nx)), np.full((ny, nx), u0), np.zeros((ny, nx))
+    lat = L.Lattice(nx, ny, tau1, tau2, storage=storage, inflow=(u0, 1.0, 1.0))
+    lat.init_equilibrium(rho, ux, uy).step(200)
+    r, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    err = max(np.max(np.abs(u - u0)) / u0, np.max(np.abs(v)) / u0, np.max(np.abs(r - 1)))
+    say("case: uniform inflow %s: max deviation %.3e" % (storage, err))
+    assert err < {"f64": 1e-13, "f32": 1e-5, "f16": 2e-3}[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_open_boundaries_shifted_storage_one_step(L, storage):
+    nx, ny = 70, 13
+    f, mask, tau1, tau2, inflow = _case(21, nx, ny)
+    lat = L.Lattice(nx, ny, tau1, tau2, mask=mask, storage=storage, inflow=inflow)
+    lat.set_populations(f)
+    f0 = _np(lat.get_populations())
+    lat.step(1)
+    _, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    _, ur, vr = oracle.macros(oracle.step_open(f0, tau1, tau2, inflow[0], inflow[1], inflow[2],
+                                               mask=mask), mask=mask)
+    emax, el2 = rel_errors(u, v, ur, vr)
+    say("case: open %dx%d %s one step: rel max %.3e rel L2 %.3e" % (nx, ny, storage, emax, el2))
+    assert emax <= TOL[storage]
+
+
+@pytest.mark.parametrize("open_x", [False, True])
+def test_wall_force_matches_oracle(L, open_x):
+    nx, ny = 48, 20
+    f, mask, tau1, tau2, inflow = _case(5 + open_x, nx, ny)
+    mask[8:12, 20:26] = 1
+    f[:, mask.astype(bool)] = 0.0
+    g = (0.0, 0.0) if open_x else (2e-5, -1e-5)
+    lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f64",
+                    inflow=inflow if open_x else None)
+    lat.set_populations(f).step(3)
+    f2 = _np(lat.get_populations())
+    lat.step(1)
+    fx, fy = lat.wall_force()
+    lat.close()
+    ref = oracle.wall_force(f2, tau1, tau2, g[0], g[1], mask=mask, open_x=open_x,
+                            u_in=inflow[0], rho_w=inflow[1])
+    say("case: wall force open=%s: GPU (%.6e, %.6e) oracle (%.6e, %.6e)" %
+        (open_x, fx, fy, ref[0], ref[1]))
+    scale = 2.0 * mask.sum()   # the sums run over O(links) populations of O(0.1)
+    assert abs(fx - ref[0]) < 1e-13 * scale and abs(fy - ref[1]) < 1e-13 * scale
+
+
+def test_velocity_change_matches_the_fields(L):
+    import torch
+    nx, ny = 64, 24
+    rho, ux, uy = inputs.taylor_green(nx, 0.02, seed=3)
+    rho, ux, uy = rho[:ny], ux[:ny], uy[:ny]
+    lat = L.Lattice(nx, ny, 0.7, 1.0, storage="f64").init_equilibrium(rho, ux, uy).step(5)
+    _, u0, v0 = lat.macros()
+    prev = (u0.clone(), v0.clone())
+    lat.step(7)
+    _, u1, v1 = lat.macros()
+    mx, s2, n2 = lat.velocity_change(prev)
+    du, dv = _np(u1) - _np(u0), _np(v1) - _np(v0)
+    want = (max(np.abs(du).max(), np.abs(dv).max()), float((du ** 2 + dv ** 2).sum()),
+            float((_np(u1) ** 2 + _np(v1) ** 2).sum()))
+    say("case: velocity change: GPU %s, fields %s" % ((mx, s2, n2), want))
+    assert mx == pytest.approx(want[0], rel=1e-12)
+    assert s2 == pytest.approx(want[1], rel=1e-10)
+    assert n2 == pytest.approx(want[2], rel=1e-12)
+    assert torch.equal(prev[0], u1) and torch.equal(prev[1], v1)
+    lat.close()

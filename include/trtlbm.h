@@ -199,9 +199,18 @@ trt_status trt_wall_force(trt_sim *s, double *out);
 /* Steady-state test (Sec. III, convergence criterion): compares the current
  * He-shifted velocity with prev_ux, prev_uy (device FP64 [ny][nx], caller
  * owned) over the fluid nodes and then overwrites them with the current
- * velocity.  Device FP64 out[3] = (max over nodes and components of
- * |u - u_prev|, sum |u - u_prev|^2, sum |u|^2).  Uses library scratch. */
+ * velocity.  Device FP64 out[4] = (max over nodes and components of
+ * |u - u_prev|, sum |u - u_prev|^2, sum |u|^2, sum |u_prev|^2); the
+ * criterion of Sec. III is out[0] / u_c, a relative L2 change is
+ * sqrt(out[1] / out[2]).  Uses library scratch. */
 trt_status trt_velocity_change(trt_sim *s, double *prev_ux, double *prev_uy, double *out);
+
+/* Error against a reference velocity field (the relative L2 error of
+ * Sec. III): the same four sums as trt_velocity_change with ref_ux, ref_uy
+ * (device FP64 [ny][nx], not modified) in place of the previous field; the
+ * relative L2 error is sqrt(out[1] / out[3]).  Uses library scratch. */
+trt_status trt_velocity_error(trt_sim *s, const double *ref_ux, const double *ref_uy,
+                              double *out);
 
 /* Synchronous check: runs trt_diagnostics into library scratch, waits for
  * the stream, and returns TRT_EUNSTABLE if any fluid node diverged. */

@@ -28,7 +28,7 @@ EXPORTED = [
     "trt_pitch", "trt_plane_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
     "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics", "trt_row_mean_ux",
-    "trt_wall_force", "trt_velocity_change",
+    "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_step",
     "trt_batch_diagnostics", "trt_batch_set_tuning", "trt_batch_destroy", "trt_last_error",
     "trt_version",
@@ -88,6 +88,7 @@ def load():
         "trt_row_mean_ux": (ctypes.c_int, [P, P]),
         "trt_wall_force": (ctypes.c_int, [P, P]),
         "trt_velocity_change": (ctypes.c_int, [P, P, P, P]),
+        "trt_velocity_error": (ctypes.c_int, [P, P, P, P]),
         "trt_check": (ctypes.c_int, [P]),
         "trt_state": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]),
         "trt_destroy": (None, [P]),
@@ -183,6 +184,10 @@ def trt_wall_force(sim: int, out: int) -> None:
 
 def trt_velocity_change(sim: int, prev_ux: int, prev_uy: int, out: int) -> None:
     _check(load().trt_velocity_change(sim, prev_ux, prev_uy, out), "trt_velocity_change")
+
+
+def trt_velocity_error(sim: int, ref_ux: int, ref_uy: int, out: int) -> None:
+    _check(load().trt_velocity_error(sim, ref_ux, ref_uy, out), "trt_velocity_error")
 
 
 def trt_row_mean_ux(sim: int, out: int) -> None:

@@ -29,7 +29,6 @@ import dataclasses
 import math
 import sys
 import time
-from typing import Optional
 
 import numpy as np
 
@@ -129,7 +128,7 @@ def solve(cases, storage: str = "f64", check: int = 1000, tol: float = 1e-9,
                 if row[4] > 0:
                     r["status"] = "diverged"
                     continue
-                mx, s2, n2 = lats[i].velocity_change(prev[i])
+                mx, s2, n2, _ = lats[i].velocity_change(prev[i])
                 r["l2_change"] = math.sqrt(s2 / n2) if n2 > 0 else float("inf")
                 r["max_change"] = mx / cases[i].u0
                 if r["l2_change"] < tol:

@@ -366,8 +366,19 @@ trt_status trt_wall_force(trt_sim *s, double *out) {
 trt_status trt_velocity_change(trt_sim *s, double *prev_ux, double *prev_uy, double *out) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!prev_ux || !prev_uy || !out) return fail(TRT_EINVAL, "prev_ux, prev_uy and out are required");
-    TRT_HIP(trt::launch_velocity_change(s->desc, s->prob.storage, s->cur, prev_ux, prev_uy,
-                                        s->scratch, out, s->stream));
+    TRT_HIP(trt::launch_velocity_compare(s->desc, s->prob.storage, s->cur, prev_ux, prev_uy, true,
+                                         s->scratch, out, s->stream));
+    return TRT_OK;
+}
+
+trt_status trt_velocity_error(trt_sim *s, const double *ref_ux, const double *ref_uy,
+                              double *out) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (!ref_ux || !ref_uy || !out) return fail(TRT_EINVAL, "ref_ux, ref_uy and out are required");
+    TRT_HIP(trt::launch_velocity_compare(s->desc, s->prob.storage, s->cur,
+                                         const_cast<double *>(ref_ux),
+                                         const_cast<double *>(ref_uy), false, s->scratch, out,
+                                         s->stream));
     return TRT_OK;
 }
 

@@ -342,27 +342,34 @@ __global__ __launch_bounds__(kDiagThreads) void wall_force_kernel(InstDesc d, in
     }
 }
 
+// Velocity against a reference field over the fluid nodes: (max over nodes
+// and components of |u - u_ref|, sum |u - u_ref|^2, sum |u|^2,
+// sum |u_ref|^2); with `update` the reference is then replaced by u.
 template <int ST>
-__global__ __launch_bounds__(kDiagThreads) void velocity_change_kernel(
-    InstDesc d, int srcsel, double *__restrict__ pux, double *__restrict__ puy,
+__global__ __launch_bounds__(kDiagThreads) void velocity_compare_kernel(
+    InstDesc d, int srcsel, double *__restrict__ rux, double *__restrict__ ruy, int update,
     double *__restrict__ partials) {
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t n = (int64_t)d.nx * d.ny;
     for (int64_t k = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; k < n;
          k += (int64_t)kDiagBlocks * kDiagThreads) {
         const int y = (int)(k / d.nx), x = (int)(k - (int64_t)y * d.nx);
         Moments<double, Store<ST>::shifted> m;
         if (node_moments<ST>(d, srcsel, x, y, m)) continue;
-        const double dx = m.ux - pux[k], dy = m.uy - puy[k];
+        const double ax = rux[k], ay = ruy[k];
+        const double dx = m.ux - ax, dy = m.uy - ay;
         v[0] = fmax(v[0], fmax(fabs(dx), fabs(dy)));
         v[1] += dx * dx + dy * dy;
         v[2] += m.ux * m.ux + m.uy * m.uy;
-        pux[k] = m.ux;
-        puy[k] = m.uy;
+        v[3] += ax * ax + ay * ay;
+        if (update) {
+            rux[k] = m.ux;
+            ruy[k] = m.uy;
+        }
     }
-    block_reduce_k<3, true>(v);
+    block_reduce_k<4, true>(v);
     if (threadIdx.x == 0)
-        for (int j = 0; j < 3; ++j) partials[blockIdx.x * 3 + j] = v[j];
+        for (int j = 0; j < 4; ++j) partials[blockIdx.x * 4 + j] = v[j];
 }
 
 dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4); }
@@ -421,13 +428,13 @@ hipError_t launch_wall_force(const InstDesc &d, int storage, int src, double *pa
     return hipGetLastError();
 }
 
-hipError_t launch_velocity_change(const InstDesc &d, int storage, int src, double *prev_ux,
-                                  double *prev_uy, double *partials, double *out,
-                                  hipStream_t stream) {
-    TRT_DISPATCH(storage, (velocity_change_kernel<S><<<kDiagBlocks, kDiagThreads, 0, stream>>>(d, src, prev_ux, prev_uy, partials)));
+hipError_t launch_velocity_compare(const InstDesc &d, int storage, int src, double *ref_ux,
+                                   double *ref_uy, bool update, double *partials, double *out,
+                                   hipStream_t stream) {
+    TRT_DISPATCH(storage, (velocity_compare_kernel<S><<<kDiagBlocks, kDiagThreads, 0, stream>>>(d, src, ref_ux, ref_uy, update ? 1 : 0, partials)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    final_reduce_k<3, true><<<1, 64, 0, stream>>>(partials, out);
+    final_reduce_k<4, true><<<1, 64, 0, stream>>>(partials, out);
     return hipGetLastError();
 }
 

@@ -112,12 +112,12 @@ hipError_t launch_row_mean_ux(const InstDesc &d, int storage, int src, double *o
 hipError_t launch_wall_force(const InstDesc &d, int storage, int src, double *partials,
                              double *out, hipStream_t stream);
 
-// Change of the He-shifted velocity since the fields prev_ux, prev_uy (dense
-// FP64 [ny][nx], replaced by the current velocity): out[0] = max over fluid
-// nodes and components of |u - u_prev|, out[1] = sum |u - u_prev|^2,
-// out[2] = sum |u|^2.
-hipError_t launch_velocity_change(const InstDesc &d, int storage, int src, double *prev_ux,
-                                  double *prev_uy, double *partials, double *out,
-                                  hipStream_t stream);
+// He-shifted velocity against reference fields ref_ux, ref_uy (dense FP64
+// [ny][nx]) over the fluid nodes: out[0] = max over nodes and components of
+// |u - u_ref|, out[1] = sum |u - u_ref|^2, out[2] = sum |u|^2, out[3] =
+// sum |u_ref|^2; with `update` the reference fields are then replaced by u.
+hipError_t launch_velocity_compare(const InstDesc &d, int storage, int src, double *ref_ux,
+                                   double *ref_uy, bool update, double *partials, double *out,
+                                   hipStream_t stream);
 
 }  // namespace trt

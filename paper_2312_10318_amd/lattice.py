@@ -161,14 +161,26 @@ class Lattice:
     def velocity_change(self, prev):
         """Compare the velocity with prev = (ux, uy) device FP64 tensors (then
         overwritten with the current velocity); returns (max |du|, sum |du|^2,
-        sum |u|^2) (synchronous)."""
+        sum |u|^2, sum |u_prev|^2) (synchronous)."""
         torch = _torch()
-        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
         capi.trt_velocity_change(self.handle, prev[0].data_ptr(), prev[1].data_ptr(),
                                  out.data_ptr())
         self._sync()
+        return tuple(float(v) for v in out.cpu().numpy())
+
+    def velocity_error(self, ux_ref, uy_ref):
+        """Relative L2 error of the velocity against reference fields (the
+        error measure of Sec. III), computed on the device; also returns
+        the max-norm difference.  (rel_l2, max |u - u_ref|)."""
+        torch = _torch()
+        shape = (self.ny, self.nx)
+        a, b = self._dev64(ux_ref, shape), self._dev64(uy_ref, shape)
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        capi.trt_velocity_error(self.handle, a.data_ptr(), b.data_ptr(), out.data_ptr())
+        self._sync()
         v = out.cpu().numpy()
-        return float(v[0]), float(v[1]), float(v[2])
+        return (float(np.sqrt(v[1] / v[3])) if v[3] > 0 else float("inf"), float(v[0]))
 
     def state(self):
         """(index of the lattice holding the state, steps taken)."""

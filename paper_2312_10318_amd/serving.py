@@ -1,7 +1,8 @@
 """Continuous-batching solve server for parameter-sweep TRT-RLB requests.
 
 Requests (a lattice, its relaxation times, force, optional obstacle mask,
-initial fields and a step budget) arrive over time.  The scheduler admits a
+initial fields and a step budget, optionally a convergence tolerance)
+arrive over time.  The scheduler admits a
 request as soon as a slot is free and its device footprint fits the memory
 budget, keeps every admitted lattice resident on the device, and advances
 all active lattices together in quanta of steps: one batched launch per step
@@ -11,10 +12,16 @@ quantum boundary; a finished request leaves at the quantum boundary where
 its budget is used up, its slot and memory are reused at once.  Latency is
 measured from arrival to the result being on the host.
 
+A request with a tolerance ends early once it has converged: at check
+points every `check` steps of its own clock, the relative L2 change of its
+velocity field since the previous check point (computed on the device) is
+compared with the tolerance (the steady-state test of Sec. III).
+
 The scheduler talks to an executor; ``GpuExecutor`` runs the HIP library.
-Quanta never cross a request's budget, so each result is exactly the result
-of running that request alone (the sweep's arithmetic per node does not
-depend on which other lattices share the launch).
+Quanta never cross a request's budget or its next check point, so each
+result is exactly the result of running that request alone (the sweep's
+arithmetic per node does not depend on which other lattices share the
+launch).
 """
 from __future__ import annotations
 
@@ -44,6 +51,8 @@ class Request:
     fields: Optional[Callable[[], tuple]] = None   # -> (rho, ux, uy), float64 [ny, nx]
     arrival: float = 0.0      # seconds since the start of the run
     meta: dict = dataclasses.field(default_factory=dict)
+    tol: Optional[float] = None   # end when the velocity change per check is below tol
+    check: int = 1000             # steps between convergence checks (with tol)
 
 
 @dataclasses.dataclass
@@ -53,11 +62,13 @@ class Result:
     arrival: float
     admitted: float
     finished: float
-    steps: int
+    steps: int                      # steps taken
     diverged: bool
     diagnostics: dict
     nodes: int = 0
     fields: Optional[tuple] = None  # (rho, ux, uy) numpy, when kept
+    converged: Optional[bool] = None  # requests with a tolerance only
+    change: Optional[float] = None    # last relative L2 velocity change
 
     @property
     def latency(self) -> float:
@@ -66,7 +77,8 @@ class Result:
 
 class Scheduler:
     """Admission by memory budget and slot count; FIFO order; quanta of at
-    most `quantum` steps that never cross a request's step budget."""
+    most `quantum` steps that never cross a request's step budget or its
+    next convergence check point."""
 
     def __init__(self, executor, budget_bytes: int, max_slots: int = 4096,
                  quantum: int = 100, keep_fields: bool = False, clock=time.perf_counter):
@@ -77,7 +89,8 @@ class Scheduler:
         self.keep_fields = keep_fields
         self.clock = clock
         self.queue = collections.deque()
-        self.active = {}          # rid -> [request, handle, remaining, admitted_at, footprint]
+        # rid -> [request, handle, remaining, admitted_at, footprint, to_check, change]
+        self.active = {}
         self.used = 0
         self.results = []
         self.t0 = None
@@ -103,33 +116,47 @@ class Scheduler:
             self.queue.popleft()
             handle = self.ex.start(req)
             self.used += fp
-            self.active[req.rid] = [req, handle, req.steps, self.now(), fp]
+            to_check = req.check if req.tol is not None else None
+            self.active[req.rid] = [req, handle, req.steps, self.now(), fp, to_check, None]
         self.peak_used = max(self.peak_used, self.used)
         self.peak_active = max(self.peak_active, len(self.active))
 
-    def _retire(self, rid):
-        req, handle, _, admitted, fp = self.active.pop(rid)
+    def _retire(self, rid, converged=None):
+        req, handle, remaining, admitted, fp, _, change = self.active.pop(rid)
         diag, fields = self.ex.finish(handle, keep_fields=self.keep_fields)
         self.ex.close(handle)
         self.used -= fp
         diverged = bool(diag.get("n_diverged", 0) > 0)
+        if req.tol is not None and converged is None:
+            converged = False
         self.results.append(Result(req.rid, req.kind, req.arrival, admitted, self.now(),
-                                   req.steps, diverged, diag, req.nx * req.ny, fields))
+                                   req.steps - remaining, diverged, diag, req.nx * req.ny, fields,
+                                   converged, change))
 
     def step_quantum(self):
         """Advance every active request by one quantum (host-synchronous)."""
         if not self.active:
             return
-        q = min(self.quantum, min(a[2] for a in self.active.values()))
+        q = self.quantum
+        for a in self.active.values():
+            q = min(q, a[2] if a[5] is None else min(a[2], a[5]))
         self.ex.step([a[1] for a in self.active.values()], q)
         self.quanta += 1
         done = []
         for rid, a in self.active.items():
             a[2] -= q
-            if a[2] <= 0:
-                done.append(rid)
-        for rid in done:
-            self._retire(rid)
+            converged = None
+            if a[5] is not None:
+                a[5] -= q
+                if a[5] == 0:
+                    a[6] = self.ex.change(a[1])
+                    a[5] = a[0].check
+                    if a[6] < a[0].tol:
+                        converged = True
+            if converged or a[2] <= 0:
+                done.append((rid, converged))
+        for rid, converged in done:
+            self._retire(rid, converged)
 
     def run(self, arrivals, idle_sleep: float = 2e-4):
         """Serve a list of requests whose `arrival` times are seconds from
@@ -157,6 +184,7 @@ class Scheduler:
 def summarize(results, wall: float) -> dict:
     lat = np.array([r.latency for r in results]) if results else np.zeros(1)
     lups = sum(r.nodes * r.steps for r in results)
+    with_tol = [r for r in results if r.converged is not None]
     out = {"solves": len(results), "wall_s": round(wall, 3),
            "solves_per_s": round(len(results) / wall, 2) if wall > 0 else None,
            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
@@ -165,6 +193,9 @@ def summarize(results, wall: float) -> dict:
            "diverged": int(sum(r.diverged for r in results))}
     if lups:
         out["aggregate_MLUPS"] = round(lups / wall / 1e6, 1)
+    if with_tol:
+        out["converged"] = int(sum(bool(r.converged) for r in with_tol))
+        out["with_tolerance"] = len(with_tol)
     return out
 
 
@@ -190,7 +221,18 @@ class GpuExecutor:
                       storage=self.storage, stream=self.stream)
         rho, ux, uy = req.fields() if req.fields else inputs.rest_state(req.ny, req.nx)
         lat.init_equilibrium(rho, ux, uy)
+        lat._prev_u = None
+        if req.tol is not None:
+            import torch
+            z = torch.zeros((req.ny, req.nx), dtype=torch.float64, device=lat.device)
+            lat._prev_u = (z, z.clone())
+            lat.velocity_change(lat._prev_u)   # the initial velocity
         return lat
+
+    def change(self, lat) -> float:
+        """Relative L2 change of the velocity since the previous check."""
+        _, s2, n2, _ = lat.velocity_change(lat._prev_u)
+        return math.sqrt(s2 / n2) if n2 > 0 else math.inf
 
     def _drop(self, keep=()):
         for k in list(self._batches):

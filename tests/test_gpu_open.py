@@ -136,7 +136,7 @@ def test_velocity_change_matches_the_fields(L):
     prev = (u0.clone(), v0.clone())
     lat.step(7)
     _, u1, v1 = lat.macros()
-    mx, s2, n2 = lat.velocity_change(prev)
+    mx, s2, n2, p2 = lat.velocity_change(prev)
     du, dv = _np(u1) - _np(u0), _np(v1) - _np(v0)
     want = (max(np.abs(du).max(), np.abs(dv).max()), float((du ** 2 + dv ** 2).sum()),
             float((_np(u1) ** 2 + _np(v1) ** 2).sum()))
@@ -144,5 +144,25 @@ def test_velocity_change_matches_the_fields(L):
     assert mx == pytest.approx(want[0], rel=1e-12)
     assert s2 == pytest.approx(want[1], rel=1e-10)
     assert n2 == pytest.approx(want[2], rel=1e-12)
+    assert p2 == pytest.approx(float((_np(u0) ** 2 + _np(v0) ** 2).sum()), rel=1e-12)
     assert torch.equal(prev[0], u1) and torch.equal(prev[1], v1)
     lat.close()
+
+
+def test_velocity_error_against_the_analytic_taylor_green(L):
+    """On-device relative L2 error (Sec. III error measure) against the
+    analytic decaying Taylor-Green field equals the host computation from
+    the velocity read back."""
+    n, u0, tau1 = 64, 0.01, 0.6
+    tau2 = params.tau2_from_magic(tau1, 0.25)
+    rho, ux, uy = inputs.taylor_green(n, u0, seed=0)
+    lat = L.Lattice(n, n, tau1, tau2, storage="f64").init_equilibrium(rho, ux, uy).step(300)
+    _, ua, va = inputs.taylor_green(n, u0, seed=0, nu=params.nu_from_tau(tau1), t=300)
+    l2, mx = lat.velocity_error(ua, va)
+    _, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    want = np.sqrt(((u - ua) ** 2 + (v - va) ** 2).sum() / (ua ** 2 + va ** 2).sum())
+    say("case: TG 64^2 300 steps: on-device L2 %.6e, host %.6e" % (l2, want))
+    assert l2 == pytest.approx(want, rel=1e-10)
+    assert mx == pytest.approx(max(np.abs(u - ua).max(), np.abs(v - va).max()), rel=1e-12)
+    assert l2 < 1e-2   # second-order discretisation error at 64^2 (about 1.4e-3 here)

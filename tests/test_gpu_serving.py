@@ -69,3 +69,46 @@ def test_served_results_equal_results_alone(L, storage):
         for a, b in zip(alone, got):
             assert np.array_equal(a, b), "request %d (%s) differs alone vs served" % (q.rid, q.kind)
         assert not by[q.rid].diverged
+
+
+def test_converged_requests_equal_results_alone(L):
+    """Poiseuille channels served with a convergence tolerance end at a check
+    point; the same request run alone with the same check points converges
+    at the same step, with the same fields bit for bit."""
+    import torch
+    from paper_2312_10318_amd.serving import GpuExecutor
+    reqs = []
+    for k, n in enumerate((18, 26, 34)):
+        tau1 = 0.8 + 0.2 * k
+        tau2 = params.tau2_from_magic(tau1, 3 / 16)
+        g = 8 * params.nu_from_tau(tau1) * 0.01 / (n - 2) ** 2
+        r = Request(k, "poiseuille", 16, n, tau1, tau2, 60_000, (g, 0.0),
+                    inputs.channel_mask(16, n - 2), None, 0.001 * k)
+        r.tol, r.check = 1e-8, 250
+        reqs.append(r)
+    ex = GpuExecutor("f64")
+    sched = Scheduler(ex, budget_bytes=1 << 30, quantum=100, keep_fields=True)
+    res = {r.rid: r for r in sched.run(reqs)}
+    ex.shutdown()
+    for q in reqs:
+        r = res[q.rid]
+        say("case: served Poiseuille n=%d: converged=%s after %d steps (change %.2e)" %
+            (q.ny, r.converged, r.steps, r.change))
+        assert r.converged and r.steps % q.check == 0 and r.steps < q.steps
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage="f64")
+        lat.init_equilibrium(*inputs.rest_state(q.ny, q.nx))
+        prev = tuple(torch.zeros((q.ny, q.nx), dtype=torch.float64, device=lat.device)
+                     for _ in range(2))
+        lat.velocity_change(prev)
+        steps = 0
+        while True:
+            lat.step(q.check)
+            steps += q.check
+            _, s2, n2, _ = lat.velocity_change(prev)
+            if np.sqrt(s2 / n2) < q.tol:
+                break
+        assert steps == r.steps
+        alone = [t.cpu().numpy() for t in lat.macros()]
+        lat.close()
+        for a, b in zip(alone, r.fields):
+            assert np.array_equal(a, b)

@@ -26,6 +26,12 @@ class FakeExecutor:
         for h in handles:
             h["steps"] += n
 
+    def change(self, h):
+        """Scripted convergence: the change halves at every check."""
+        h["checks"] = h.get("checks", 0) + 1
+        self.log.append(("check", h["rid"], h["steps"]))
+        return 0.5 ** h["checks"]
+
     def finish(self, h, keep_fields=False):
         self.stepped[h["rid"]] = h["steps"]
         self.log.append(("finish", h["rid"]))
@@ -119,3 +125,24 @@ def test_serving_workload_mix_and_parameters():
             assert abs((r.tau1 - 0.5) * (r.tau2 - 0.5) - 3 / 16) < 1e-9
         else:
             assert 64 <= r.nx <= 2048 and r.nx == r.ny
+
+
+def test_requests_with_a_tolerance_end_at_their_first_converged_check():
+    ex = FakeExecutor()
+    s = Scheduler(ex, budget_bytes=10**9, quantum=64, clock=Clock())
+    reqs = [_req(0, 32, 10_000), _req(1, 40, 10_000), _req(2, 48, 500), _req(3, 56, 777)]
+    reqs[0].tol, reqs[0].check = 0.1, 100      # 0.5**4 < 0.1: converges at the 4th check
+    reqs[1].tol, reqs[1].check = 0.01, 37      # 0.5**7 < 0.01: 7th check
+    reqs[2].tol, reqs[2].check = 1e-9, 50      # never: ends on its budget, not converged
+    res = {r.rid: r for r in s.run(reqs)}
+    assert res[0].converged and res[0].steps == 400 and ex.stepped[0] == 400
+    assert res[1].converged and res[1].steps == 7 * 37 and ex.stepped[1] == 7 * 37
+    assert res[2].converged is False and res[2].steps == 500
+    assert res[3].converged is None and res[3].steps == 777
+    # every check happened exactly on the request's own check grid
+    for e in ex.log:
+        if e[0] == "check":
+            rid, at = e[1], e[2]
+            assert at % reqs[rid].check == 0
+    st = summarize(list(res.values()), wall=1.0)
+    assert st["converged"] == 2 and st["with_tolerance"] == 3

@@ -21,9 +21,12 @@
  *    (a hipStream_t passed as void*; NULL is the legacy default stream).
  *    Results in device memory are ready once that stream reaches them.
  *  - The caller owns and frees every lattice-sized buffer (population
- *    lattices, mask, field arrays).  The library owns only small scratch
- *    memory (reduction partials, batch tables) and HIP graphs, freed by the
- *    matching destroy call.
+ *    lattices, mask, field arrays).  The library owns small scratch memory
+ *    (reduction partials, batch tables), HIP graphs and, for a simulation
+ *    with a mask or open x boundaries, a link map of two bytes per node
+ *    (derived from the mask at creation: per node, whether it is solid and
+ *    which of its pull sources are solid), all freed by the matching
+ *    destroy call and counted by trt_footprint_bytes.
  *  - Population lattices are device buffers of trt_lattice_bytes() bytes,
  *    256-byte aligned, laid out as 9 planes [i][y][x] with row pitch
  *    trt_pitch(nx, storage) elements and plane stride
@@ -145,7 +148,9 @@ size_t trt_footprint_bytes(const trt_problem *p);
  * each step reads one and writes the other; they must not overlap).  The
  * state starts undefined: call trt_init_equilibrium or trt_set_populations
  * next.  The problem (including the mask pointer) is copied; the mask memory
- * must stay valid while the simulation exists.  EINVAL on a NULL or
+ * must stay valid while the simulation exists, and its contents must not
+ * change (the sweep reads the link map derived from it on the stream at
+ * creation).  EINVAL on a NULL or
  * misaligned pointer, a size out of range, tau_s <= 1/2, tau_s2 < 1/2 or a
  * non-finite parameter. */
 trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stream,

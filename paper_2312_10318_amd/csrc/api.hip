@@ -108,6 +108,7 @@ struct trt_sim {
     int cur;        // lattice holding the current state
     int64_t time;
     double *scratch;  // diagnostics partials + one TRT_NDIAG result
+    uint16_t *links;  // link map (mask or open x boundaries), else null
     hipStream_t cap_stream;
     hipGraphExec_t pair;  // captured sweeps 0 -> 1 -> 0
     bool in_batch;
@@ -197,12 +198,21 @@ size_t trt_lattice_bytes(const trt_problem *p) {
            (size_t)elem_size(p->storage);
 }
 
+namespace {
+// elements of a link-map row: nx rounded up to 256 bytes
+int64_t link_pitch(int32_t nx) { return ((int64_t)nx + 127) / 128 * 128; }
+bool needs_links(const trt_problem *p) {
+    return p->mask != nullptr || p->x_boundary == TRT_X_INFLOW_OUTFLOW;
+}
+}  // namespace
+
 size_t trt_footprint_bytes(const trt_problem *p) {
     const size_t lat = trt_lattice_bytes(p);
     if (lat == 0) return 0;
     const size_t mask = p->mask ? (size_t)p->nx * p->ny : 0;
+    const size_t links = needs_links(p) ? 2 * (size_t)link_pitch(p->nx) * p->ny : 0;
     const size_t scratch = (size_t)(trt::diag_partial_count() + 1) * TRT_NDIAG * sizeof(double);
-    return 2 * lat + mask + scratch;
+    return 2 * lat + mask + links + scratch;
 }
 
 trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stream,
@@ -245,7 +255,8 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.u_in = d.xbc ? p->u_in : 0.0;
     d.rho_in = d.xbc ? p->rho_in : 1.0;
     d.rho_out = d.xbc ? p->rho_out : 1.0;
-    trt::tile(d, s->launch, p->storage);
+    d.links = nullptr;
+    d.lpitch = link_pitch(p->nx);
 
     hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
                                                       TRT_NDIAG * sizeof(double));
@@ -253,9 +264,24 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
         delete s;
         return fail_hip(e, "hipMalloc(scratch)");
     }
+    if (needs_links(p)) {
+        e = hipMalloc((void **)&s->links, 2 * (size_t)d.lpitch * (size_t)p->ny);
+        if (e == hipSuccess) {
+            d.links = s->links;
+            e = trt::launch_link_map(d, s->stream);
+        }
+        if (e != hipSuccess) {
+            if (s->links) (void)hipFree(s->links);
+            (void)hipFree(s->scratch);
+            delete s;
+            return fail_hip(e, "link map");
+        }
+    }
+    trt::tile(d, s->launch, p->storage);
     e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(s->scratch);
+        if (s->links) (void)hipFree(s->links);
         delete s;
         return fail_hip(e, "hipStreamCreateWithFlags");
     }
@@ -418,6 +444,7 @@ void trt_destroy(trt_sim *s) {
     release_graph(s->pair);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->scratch) (void)hipFree(s->scratch);
+    if (s->links) (void)hipFree(s->links);
     delete s;
 }
 

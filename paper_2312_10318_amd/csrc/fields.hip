@@ -372,6 +372,24 @@ __global__ __launch_bounds__(kDiagThreads) void velocity_compare_kernel(
         for (int j = 0; j < 4; ++j) partials[blockIdx.x * 4 + j] = v[j];
 }
 
+__global__ void link_map_kernel(InstDesc d, uint16_t *__restrict__ links) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= d.nx || y >= d.ny) return;
+    uint32_t b = is_solid(d.mask, d.nx, x, y) ? 1u : 0u;
+    for (int i = 1; i < 9; ++i) {
+        const int tx = x - kEx[i];
+        if (d.xbc && tx < 0) {
+            b |= 1u << i;  // beyond the inflow wall: own slot opp(i), plus the wall's correction
+        } else if (d.xbc && tx >= d.nx) {
+            // beyond the outlet: the outlet rule replaces f_i
+        } else if (is_solid(d.mask, d.nx, wrapi(tx, d.nx), wrapi(y - kEy[i], d.ny))) {
+            b |= 1u << i;
+        }
+    }
+    links[(int64_t)y * d.lpitch + x] = (uint16_t)b;
+}
+
 dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4); }
 
 #define TRT_DISPATCH(storage, CALL)                 \
@@ -383,6 +401,11 @@ dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4
     }
 
 }  // namespace
+
+hipError_t launch_link_map(const InstDesc &d, hipStream_t stream) {
+    link_map_kernel<<<node_grid(d), dim3(64, 4), 0, stream>>>(d, const_cast<uint16_t *>(d.links));
+    return hipGetLastError();
+}
 
 hipError_t launch_set_populations(const InstDesc &d, int storage, int src, const double *f,
                                   hipStream_t stream) {

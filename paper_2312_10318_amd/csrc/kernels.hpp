@@ -38,10 +38,9 @@ inline int batch_waves_per_block(const Launch &l) {
     return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
 }
 
-// Whether an instance can use two-column strips: no obstacles and periodic
-// in x (the pair path has neither bounce-back nor open boundaries), an even
-// nx (a lane's pair never straddles the periodic seam) and a lattice within
-// one buffer resource.
+// Whether an instance can use two-column strips: an even nx (a lane's pair
+// never straddles the periodic seam), a lattice within one buffer resource,
+// and, with obstacles or open boundaries, its link map.
 bool pair_eligible(const InstDesc &d, int storage);
 
 // Rows per wavefront when the launch shape leaves it open.  Long strips
@@ -89,6 +88,11 @@ bool buffer_addressable(const InstDesc &d, int storage);
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);
+
+// Link map of an instance with a mask or open x boundaries: d.links (device,
+// ny * d.lpitch 16-bit codes) receives, per node, bit 0 = solid and bit i
+// (1..8) = the pull source x - e_i is solid or beyond the inflow wall.
+hipError_t launch_link_map(const InstDesc &d, hipStream_t stream);
 
 // Pre-collision state <-> device FP64 [9][ny][nx]; f^eq initialisation.
 hipError_t launch_set_populations(const InstDesc &d, int storage, int src, const double *f,

@@ -65,6 +65,12 @@ constexpr int kStripWidth = 64;
 struct InstDesc {
     void *buf[2];
     const uint8_t *mask;  // dense [ny][nx] or null
+    // link map [ny][lpitch] of 16-bit codes (null without mask and open
+    // boundaries): per node, bit 0 = the node is solid, bit i (1..8) = the
+    // pull source x - e_i is a solid node or the inflow wall, so f_i comes
+    // back from the node's own slot opp(i) (half-way bounce-back)
+    const uint16_t *links;
+    int64_t lpitch;  // elements
     int64_t plane;        // elements between population planes
     int32_t nx, ny, pitch;
     int32_t cur;          // lattice holding the state when the descriptor was built
@@ -306,6 +312,44 @@ template <class T> struct PtrAccess {
     __device__ __forceinline__ void st(int64_t e, uint32_t v, T x) const { st_at<T>(p + e, v, x); }
 };
 
+// Access to the link map (at most 2 x 46340^2 bytes: one buffer resource).
+// Offsets are in elements (16-bit codes).
+struct LinkAccess {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ LinkAccess(const uint16_t *base, uint64_t elems) {
+        r = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(base), 0,
+                                              (int)(uint32_t)(2 * elems), (int)kRawBufferWord3);
+    }
+    // the code of node (col, row): row_off = row * lpitch
+    __device__ __forceinline__ uint32_t ld1(uint32_t row_off, uint32_t col) const {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, 2 * col, 2 * row_off, 0);
+    }
+    // the codes of nodes col (low half) and col + 1 (high half), col even
+    __device__ __forceinline__ uint32_t ld2(uint32_t row_off, uint32_t col) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, 2 * col, 2 * row_off, 0);
+    }
+};
+
+constexpr int kOppDir[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Half-way bounce-back from the link bits: every direction i whose pull
+// source is solid (bit i of lk) takes the node's own slot opp(i) instead.
+// The own slots are loaded only for directions some lane of the wavefront
+// needs (a wave-uniform test), so rows away from walls cost nothing.  v[]
+// holds the pulled values; own(i) loads slot opp(i) of the node itself.
+template <class V, class Own>
+__device__ __forceinline__ void bounce_back(V v[9], uint32_t lk, const Own &own) {
+    // issue every needed load first, then select: one memory round trip
+    V o[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        o[i] = v[i];
+        if (__builtin_amdgcn_ballot_w64((lk >> i) & 1u) != 0) o[i] = own(kOppDir[i]);
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i) v[i] = ((lk >> i) & 1u) ? o[i] : v[i];
+}
+
 // Pull-gather for a lattice without solid nodes.  ym, y, yp are the wrapped
 // rows, om, oc, op the byte offsets of the wrapped columns x-1, x, x+1.
 template <class T, class C>
@@ -329,47 +373,6 @@ __device__ __forceinline__ void gather_open(const T *__restrict__ src, int64_t p
 template <class T>
 __device__ __forceinline__ void open_x_sources(const T *a[9], const T *r0, int64_t plane, int xc,
                                                int nx);
-
-// Raw pull-gather with walls (mask, may be null) and, when xbc is set, the
-// open x boundaries' sources: like gather() below but without widening;
-// returns whether the node itself is solid.
-template <class T>
-__device__ __forceinline__ bool gather_masked_raw(const T *__restrict__ src, int64_t plane,
-                                                  int pitch, const uint8_t *__restrict__ mask,
-                                                  int nx, int ym, int y, int yp, int xm, int xc,
-                                                  int xp, bool xbc, T v[9]) {
-    const T *r0 = src + (int64_t)y * pitch;
-    const T *rm = src + (int64_t)ym * pitch;
-    const T *rp = src + (int64_t)yp * pitch;
-    const T *a[9] = {r0 + xc,
-                     r0 + plane + xm,
-                     rm + 2 * plane + xc,
-                     r0 + 3 * plane + xp,
-                     rp + 4 * plane + xc,
-                     rm + 5 * plane + xm,
-                     rm + 6 * plane + xp,
-                     rp + 7 * plane + xp,
-                     rp + 8 * plane + xm};
-    bool solid = false;
-    if (mask != nullptr) {
-        const uint8_t *mm = mask + (int64_t)ym * nx;
-        const uint8_t *m0 = mask + (int64_t)y * nx;
-        const uint8_t *mp = mask + (int64_t)yp * nx;
-        a[1] = m0[xm] ? r0 + 3 * plane + xc : a[1];
-        a[2] = mm[xc] ? r0 + 4 * plane + xc : a[2];
-        a[3] = m0[xp] ? r0 + 1 * plane + xc : a[3];
-        a[4] = mp[xc] ? r0 + 2 * plane + xc : a[4];
-        a[5] = mm[xm] ? r0 + 7 * plane + xc : a[5];
-        a[6] = mm[xp] ? r0 + 8 * plane + xc : a[6];
-        a[7] = mp[xp] ? r0 + 5 * plane + xc : a[7];
-        a[8] = mp[xm] ? r0 + 6 * plane + xc : a[8];
-        solid = m0[xc] != 0;
-    }
-    if (xbc) open_x_sources(a, r0, plane, xc, nx);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) v[i] = a[i][0];
-    return solid;
-}
 
 // Pull-gather of the pre-collision populations f_i(x, t) of node (xc, y)
 // from the previous step's post-collision lattice: f_i(x, t) =

@@ -65,23 +65,28 @@ __device__ __forceinline__ Column column_of(int c, int nx, uint32_t elem) {
 
 // Raw (storage-precision) populations of one node, gathered but not yet
 // widened, so that a prefetched row costs as few registers as possible.
+// With a link map, lk holds the node's link code (bit 0: solid; bit i: f_i
+// bounces back) and own[i] the node's own slot opp(i) wherever some lane of
+// the wavefront needs it.
 template <class T> struct Raw {
     T v[9];
+    T own[9];
     bool solid;
+    uint32_t lk;
 };
 
-template <class T, bool MASK, class Acc>
-__device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, const T *src, int64_t plane,
-                                           int pitch, const uint8_t *mask, int nx, int ny, int y,
-                                           const Column &col, bool xbc = false) {
+// Pull-gather of node (col, y) (periodic wrap).  With a link map the node's
+// link code lk is already known (it is read one row ahead), so the own-slot
+// loads of the bounce-back directions are issued here, together with the
+// pulls; link_fix selects later, where the loads are waited for anyway.
+template <class T, class Acc>
+__device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, int64_t plane, int pitch,
+                                           int ny, int y, const Column &col, bool linked,
+                                           uint32_t lk) {
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     r.solid = false;
-    if (MASK && (mask != nullptr || xbc)) {
-        r.solid = gather_masked_raw<T>(src, plane, pitch, mask, nx, ym, y, yp, col.xm, col.xc,
-                                       col.xp, xbc, r.v);
-        return;
-    }
+    r.lk = lk;
     const int64_t e0 = (int64_t)y * pitch, em = (int64_t)ym * pitch, ep = (int64_t)yp * pitch;
     r.v[0] = in.ld(e0, col.oc);
     r.v[1] = in.ld(plane + e0, col.om);
@@ -92,6 +97,24 @@ __device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, const T *sr
     r.v[6] = in.ld(6 * plane + em, col.op);
     r.v[7] = in.ld(7 * plane + ep, col.op);
     r.v[8] = in.ld(8 * plane + ep, col.om);
+    if (linked && __builtin_amdgcn_ballot_w64((lk & 0xfffeu) != 0) != 0) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            if (__builtin_amdgcn_ballot_w64((lk >> i) & 1u) != 0)
+                r.own[i] = in.ld(kOppDir[i] * plane + e0, col.oc);
+    }
+}
+
+// Apply a gathered node's link code: bounce-back sources and solidity (only
+// rows that touch a wall or an obstacle do any work).
+template <class T>
+__device__ __forceinline__ void link_fix(Raw<T> &r) {
+    if (__builtin_amdgcn_ballot_w64(r.lk != 0) == 0) return;
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        if (__builtin_amdgcn_ballot_w64((r.lk >> i) & 1u) != 0)
+            r.v[i] = ((r.lk >> i) & 1u) ? r.own[i] : r.v[i];
+    r.solid = (r.lk & 1u) != 0;
 }
 
 // One row's state per lane: moments (raw ones included) and Phi.
@@ -110,11 +133,11 @@ template <class C> struct OpenX {
 
 template <class T, class C, bool SHIFTED>
 __device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw, C gx, C gy,
-                                      const OpenX<C> *ox = nullptr, int xc = 0) {
+                                      const OpenX<C> &ox, int xc) {
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
-    if (ox && ox->on) open_x_fix<C, SHIFTED>(f, xc, ox->nx, ox->u_in, ox->rho_in, ox->rho_out);
+    if (ox.on) open_x_fix<C, SHIFTED>(f, xc, ox.nx, ox.u_in, ox.rho_in, ox.rho_out);
     r.solid = raw.solid;
     r.m.compute(f, gx, gy);
     const C px = r.m.rho * r.m.ux * r.m.ux * r.m.ux;
@@ -129,12 +152,11 @@ __device__ __forceinline__ void widen(RowState<C, SHIFTED> &r, const Raw<T> &raw
 // lane owning that column computes: results do not depend on where strips
 // begin and end.
 template <class T, class C, bool SHIFTED>
-__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx, const OpenX<C> *ox = nullptr,
-                                       int xc = 0) {
+__device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx, const OpenX<C> &ox, int xc) {
     C f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = to_c(raw.v[i]);
-    if (ox && ox->on) open_x_fix<C, SHIFTED>(f, xc, ox->nx, ox->u_in, ox->rho_in, ox->rho_out);
+    if (ox.on) open_x_fix<C, SHIFTED>(f, xc, ox.nx, ox.u_in, ox.rho_in, ox.rho_out);
     const C s56 = f[5] + f[6], s78 = f[7] + f[8];
     const C d56 = f[5] - f[6], d78 = f[7] - f[8];
     const C diag = s56 + s78;
@@ -163,9 +185,12 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     // never spilled to scratch
     const T *__restrict__ src = static_cast<const T *>(srcsel ? d.buf[1] : d.buf[0]);
     T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
-    const uint8_t *mask = MASK ? d.mask : nullptr;
     const uint64_t bytes = 9ull * (uint64_t)plane * sizeof(T);
     const Acc in(src, bytes), out(dst, bytes);
+    // obstacles and open boundaries: the link map (general kernels only)
+    const bool linked = MASK && d.links != nullptr;
+    const LinkAccess la(d.links, (uint64_t)ny * (uint64_t)d.lpitch);
+    const int64_t lp = d.lpitch;
 
     const int x0 = strip * kStripWidth;
     const Column col = column_of(x0 + lane, nx, sizeof(T));
@@ -184,7 +209,6 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     ox.rho_in = (C)d.rho_in;
     ox.rho_out = (C)d.rho_out;
     ox.phi_wall = ox.rho_in * ox.u_in * ox.u_in * ox.u_in;
-    const OpenX<C> *oxp = MASK ? &ox : nullptr;
 
     const int y0 = rb * d.rows;
     const int y1 = min(y0 + d.rows, ny);
@@ -192,35 +216,48 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     // Register window.  Row y: widened state `cur` and its halo Phi_x; row
     // y+1: raw populations (and halo raw populations), gathered while row y's
     // collision is formed.  Phi_y of row y-1 is kept as a scalar.
+    // link codes (0 without a link map): rows y0 - 1 and y0 now, row y0 + 1
+    // one row ahead, and so on (for the halo column of the edge lanes too)
+    const auto code = [&](int row, const Column &c) -> uint32_t {
+        return linked ? la.ld1((uint32_t)((int64_t)row * lp), (uint32_t)c.xc) : 0u;
+    };
+    const int ym0 = (y0 + ny - 1) % ny, yp0 = (y0 + 1) % ny;
     C phiy_below;
     {
         Raw<T> t;
         RowState<C, SH> w;
-        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, (y0 + ny - 1) % ny, col,
-                            ox.on);
-        widen<T, C, SH>(w, t, gx, gy, oxp, col.xc);
+        gather_raw<T>(t, in, plane, pitch, ny, ym0, col, linked, code(ym0, col));
+        if (linked) link_fix(t);
+        widen<T, C, SH>(w, t, gx, gy, ox, col.xc);
         phiy_below = w.phiy;
     }
     RowState<C, SH> cur;
     C hphix = C(0);
     {
         Raw<T> t;
-        gather_raw<T, MASK>(t, in, src, plane, pitch, mask, nx, ny, y0, col, ox.on);
-        widen<T, C, SH>(cur, t, gx, gy, oxp, col.xc);
+        gather_raw<T>(t, in, plane, pitch, ny, y0, col, linked, code(y0, col));
+        if (linked) link_fix(t);
+        widen<T, C, SH>(cur, t, gx, gy, ox, col.xc);
         if (edge) {
             Raw<T> h;
-            gather_raw<T, MASK>(h, in, src, plane, pitch, mask, nx, ny, y0, hcol, ox.on);
-            hphix = halo_phix<T, C, SH>(h, gx, oxp, hcol.xc);
+            gather_raw<T>(h, in, plane, pitch, ny, y0, hcol, linked, code(y0, hcol));
+            if (linked) link_fix(h);
+            hphix = halo_phix<T, C, SH>(h, gx, ox, hcol.xc);
         }
     }
+    uint32_t lk_next = code(yp0, col);
+    uint32_t hlk_next = edge ? code(yp0, hcol) : 0u;
 
     for (int y = y0; y < y1; ++y) {
         // row y+1: its Phi_y is needed now, its state in the next iteration
         const int yn = (y + 1 == ny) ? 0 : y + 1;
         Raw<T> nraw, nhalo;
-        gather_raw<T, MASK>(nraw, in, src, plane, pitch, mask, nx, ny, yn, col, ox.on);
-        if (edge)
-            gather_raw<T, MASK>(nhalo, in, src, plane, pitch, mask, nx, ny, yn, hcol, ox.on);
+        gather_raw<T>(nraw, in, plane, pitch, ny, yn, col, linked, lk_next);
+        if (edge) gather_raw<T>(nhalo, in, plane, pitch, ny, yn, hcol, linked, hlk_next);
+        // the link codes of row y+2, for the next iteration's gather
+        const int ynn = (yn + 1 == ny) ? 0 : yn + 1;
+        lk_next = code(ynn, col);
+        hlk_next = edge ? code(ynn, hcol) : 0u;
 
         // row y: everything of the collision except the y-gradient of Phi
         const C up = __shfl_up(cur.phix, 1), dn = __shfl_down(cur.phix, 1);
@@ -239,8 +276,13 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
                      "+v"(cf.bxy), "+v"(cf.bxxy), "+v"(cf.bxyy));
 
         RowState<C, SH> nxt;
-        widen<T, C, SH>(nxt, nraw, gx, gy, oxp, col.xc);
-        const C nhphix = edge ? halo_phix<T, C, SH>(nhalo, gx, oxp, hcol.xc) : C(0);
+        if (linked) link_fix(nraw);
+        widen<T, C, SH>(nxt, nraw, gx, gy, ox, col.xc);
+        C nhphix = C(0);
+        if (edge) {
+            if (linked) link_fix(nhalo);
+            nhphix = halo_phix<T, C, SH>(nhalo, gx, ox, hcol.xc);
+        }
 
         const C dphiy = C(0.5) * (nxt.phiy - phiy_below);
         C fo[9];
@@ -363,46 +405,90 @@ template <> struct PairIO<double> {
 };
 
 // Raw populations of one row of a lane's pair, plus the lane's edge elements
-// (lanes 0 and 63 only) and its halo node (for the halo Phi_x).
+// (lanes 0 and 63 only), its halo node (for the halo Phi_x) and, with a link
+// map, the pair's link codes (node A in the low half, node B in the high one).
 template <class T> struct PairRow {
     typename PairIO<T>::W w[9];
+    typename PairIO<T>::W own[9];  // own slots opp(i) of bounce-back directions
     T edge[3];
     Raw<T> halo;
+    uint32_t lk;
 };
 
+// Where a lane's pair lives and how to reach its own slots.
+template <class T> struct PairCtx {
+    const BufAccess<T> &in;
+    int64_t plane;
+    int pitch, ny;
+    uint32_t opair;        // byte offset of the pair's first column
+    uint32_t ca;           // the pair's first column
+    bool edge;
+    const uint32_t *ve;    // edge elements: plane and column per edge lane
+    const Column &hcol;    // the edge lane's halo column
+    const LinkAccess &la;  // link map (used when `linked`)
+    bool linked;
+    int64_t lpitch;
+};
+
+// The link codes of row y: the pair's (ld2) and the edge lane's halo node.
+template <class T>
+__device__ __forceinline__ void pair_codes(const PairCtx<T> &c, int y, uint32_t &lk,
+                                           uint32_t &hlk) {
+    lk = hlk = 0u;
+    if (c.linked) {
+        const uint32_t ro = (uint32_t)((int64_t)y * c.lpitch);
+        lk = c.la.ld2(ro, c.ca);
+        if (c.edge) hlk = c.la.ld1(ro, (uint32_t)c.hcol.xc);
+    }
+}
+
+// Gather one row of a lane's pair.  The link codes lk (pair) and hlk (halo
+// node) of the row are already known (read one row ahead), so the own-slot
+// loads of bounce-back directions are issued together with the pulls.
 template <class T, bool HALO>
-__device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const BufAccess<T> &in,
-                                                const T *src, int64_t plane, int pitch, int nx,
-                                                int ny, int y, uint32_t opair, bool edge,
-                                                const uint32_t ve[3], const Column &hcol) {
-    const int ym = (y == 0) ? ny - 1 : y - 1;
-    const int yp = (y == ny - 1) ? 0 : y + 1;
-    const int64_t e0 = (int64_t)y * pitch, em = (int64_t)ym * pitch, ep = (int64_t)yp * pitch;
-    r.w[0] = PairIO<T>::ld(in, e0, opair);
-    r.w[1] = PairIO<T>::ld(in, plane + e0, opair);
-    r.w[2] = PairIO<T>::ld(in, 2 * plane + em, opair);
-    r.w[3] = PairIO<T>::ld(in, 3 * plane + e0, opair);
-    r.w[4] = PairIO<T>::ld(in, 4 * plane + ep, opair);
-    r.w[5] = PairIO<T>::ld(in, 5 * plane + em, opair);
-    r.w[6] = PairIO<T>::ld(in, 6 * plane + em, opair);
-    r.w[7] = PairIO<T>::ld(in, 7 * plane + ep, opair);
-    r.w[8] = PairIO<T>::ld(in, 8 * plane + ep, opair);
+__device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> &c, int y,
+                                                uint32_t lk, uint32_t hlk) {
+    const int ym = (y == 0) ? c.ny - 1 : y - 1;
+    const int yp = (y == c.ny - 1) ? 0 : y + 1;
+    const int64_t e0 = (int64_t)y * c.pitch, em = (int64_t)ym * c.pitch,
+                  ep = (int64_t)yp * c.pitch;
+    const int64_t plane = c.plane;
+    r.lk = lk;
+    r.w[0] = PairIO<T>::ld(c.in, e0, c.opair);
+    r.w[1] = PairIO<T>::ld(c.in, plane + e0, c.opair);
+    r.w[2] = PairIO<T>::ld(c.in, 2 * plane + em, c.opair);
+    r.w[3] = PairIO<T>::ld(c.in, 3 * plane + e0, c.opair);
+    r.w[4] = PairIO<T>::ld(c.in, 4 * plane + ep, c.opair);
+    r.w[5] = PairIO<T>::ld(c.in, 5 * plane + em, c.opair);
+    r.w[6] = PairIO<T>::ld(c.in, 6 * plane + em, c.opair);
+    r.w[7] = PairIO<T>::ld(c.in, 7 * plane + ep, c.opair);
+    r.w[8] = PairIO<T>::ld(c.in, 8 * plane + ep, c.opair);
+    const uint32_t both = (lk | (lk >> 16)) & 0xfffeu;
+    if (c.linked && __builtin_amdgcn_ballot_w64(both != 0) != 0) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            if (__builtin_amdgcn_ballot_w64((both >> i) & 1u) != 0)
+                r.own[i] = PairIO<T>::ld(c.in, kOppDir[i] * plane + e0, c.opair);
+    }
     r.edge[0] = r.edge[1] = r.edge[2] = T(0);
-    if (edge) {
+    if (c.edge) {
         // lane 0: planes 1, 5, 8 at column x0 - 1; lane 63: planes 3, 6, 7 at
         // column x0 + 128 (ve[] carries the plane and column per lane)
-        r.edge[0] = in.ld(e0, ve[0]);
-        r.edge[1] = in.ld(em, ve[1]);
-        r.edge[2] = in.ld(ep, ve[2]);
-        if (HALO) gather_raw<T, false>(r.halo, in, src, plane, pitch, nullptr, nx, ny, y, hcol);
+        r.edge[0] = c.in.ld(e0, c.ve[0]);
+        r.edge[1] = c.in.ld(em, c.ve[1]);
+        r.edge[2] = c.in.ld(ep, c.ve[2]);
+        if (HALO) gather_raw<T>(r.halo, c.in, plane, c.pitch, c.ny, y, c.hcol, c.linked, hlk);
     }
 }
 
 // Widen a pair row into the two nodes' populations, streaming in x through
-// the lane neighbours, and form both nodes' moments and Phi.
+// the lane neighbours, apply the link bits (half-way bounce-back from the
+// nodes' own slots, solid nodes) and the open x boundaries, and form both
+// nodes' moments and Phi.
 template <class T, class C, bool SHIFTED>
 __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, SHIFTED> &b,
-                                           const PairRow<T> &r, C gx, C gy) {
+                                           const PairRow<T> &r, const PairCtx<T> &c, C gx, C gy,
+                                           const OpenX<C> &ox) {
     C pa[9], pb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) PairIO<T>::split(r.w[i], pa[i], pb[i]);
@@ -420,15 +506,50 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     fa[6] = pb[6]; fb[6] = dpp_shl(h1, pa[6]);
     fa[7] = pb[7]; fb[7] = dpp_shl(h2, pa[7]);
     a.solid = b.solid = false;
+    if (c.linked && __builtin_amdgcn_ballot_w64(r.lk != 0) != 0) {
+        // only rows that touch a wall or an obstacle pay for the link codes
+        const uint32_t la_ = r.lk & 0xffffu, lb_ = r.lk >> 16;
+        const uint32_t both = (la_ | lb_) & 0xfffeu;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (__builtin_amdgcn_ballot_w64((both >> i) & 1u) != 0) {
+                C oa, ob;
+                PairIO<T>::split(r.own[i], oa, ob);
+                fa[i] = ((la_ >> i) & 1u) ? oa : fa[i];
+                fb[i] = ((lb_ >> i) & 1u) ? ob : fb[i];
+            }
+        }
+        a.solid = (la_ & 1u) != 0;
+        b.solid = (lb_ & 1u) != 0;
+    }
+    if (ox.on) {
+        open_x_fix<C, SHIFTED>(fa, (int)c.ca, ox.nx, ox.u_in, ox.rho_in, ox.rho_out);
+        open_x_fix<C, SHIFTED>(fb, (int)c.ca + 1, ox.nx, ox.u_in, ox.rho_in, ox.rho_out);
+    }
     a.m.compute(fa, gx, gy);
     b.m.compute(fb, gx, gy);
-    a.phix = a.m.rho * a.m.ux * a.m.ux * a.m.ux;
-    a.phiy = a.m.rho * a.m.uy * a.m.uy * a.m.uy;
-    b.phix = b.m.rho * b.m.ux * b.m.ux * b.m.ux;
-    b.phiy = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
+    const C pxa = a.m.rho * a.m.ux * a.m.ux * a.m.ux;
+    const C pya = a.m.rho * a.m.uy * a.m.uy * a.m.uy;
+    const C pxb = b.m.rho * b.m.ux * b.m.ux * b.m.ux;
+    const C pyb = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
+    a.phix = a.solid ? C(0) : pxa;
+    a.phiy = a.solid ? C(0) : pya;
+    b.phix = b.solid ? C(0) : pxb;
+    b.phiy = b.solid ? C(0) : pyb;
 }
 
-template <int ST, bool SYNC>
+// Halo Phi_x of an edge lane (the link bits and open boundaries applied as
+// for the node's own lane).
+template <class T, class C, bool SHIFTED>
+__device__ __forceinline__ C pair_halo_phix(Raw<T> &h, const PairCtx<T> &c, C gx,
+                                            const OpenX<C> &ox) {
+    if (c.linked) link_fix(h);
+    return halo_phix<T, C, SHIFTED>(h, gx, ox, c.hcol.xc);
+}
+
+// LINKED: the lattice may have obstacles or open x boundaries (link map);
+// without it the link code is compiled out.
+template <int ST, bool SYNC, bool LINKED>
 __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
@@ -441,10 +562,11 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
     const uint64_t bytes = 9ull * (uint64_t)plane * sizeof(T);
     const BufAccess<T> in(src, bytes), out(dst, bytes);
+    const LinkAccess lacc(d.links, (uint64_t)ny * (uint64_t)d.lpitch);
+    const bool linked = LINKED && d.links != nullptr;
 
     const int x0 = strip * kStripWidth2;
     const int ca = (x0 + 2 * lane) % nx;  // even, since nx is even
-    const uint32_t opair = (uint32_t)ca * (uint32_t)sizeof(T);
     const bool writer = x0 + 2 * lane < nx;
     const bool edge = lane == 0 || lane == 63;
     const Column hcol = column_of(lane == 0 ? x0 - 1 : x0 + kStripWidth2, nx, sizeof(T));
@@ -452,19 +574,30 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     const uint32_t ve[3] = {(uint32_t)(pe0 * plane * (int64_t)sizeof(T)) + hcol.oc,
                             (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hcol.oc,
                             (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hcol.oc};
+    const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)ca * (uint32_t)sizeof(T), (uint32_t)ca,
+                        edge, ve, hcol, lacc, linked, d.lpitch};
 
     const C gx = (C)d.gx, gy = (C)d.gy;
     const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
+    OpenX<C> ox;
+    ox.on = LINKED && d.xbc != 0;
+    ox.nx = nx;
+    ox.u_in = (C)d.u_in;
+    ox.rho_in = (C)d.rho_in;
+    ox.rho_out = (C)d.rho_out;
+    ox.phi_wall = ox.rho_in * ox.u_in * ox.u_in * ox.u_in;
     const int y0 = rb * d.rows;
     const int y1 = min(y0 + d.rows, ny);
 
     C phiy_below_a, phiy_below_b;
+    uint32_t lk, hlk;
     {
         PairRow<T> t;
         RowState<C, SH> a, b;
-        gather_pair_row<T, false>(t, in, src, plane, pitch, nx, ny, (y0 + ny - 1) % ny, opair,
-                                  edge, ve, hcol);
-        widen_pair<T, C, SH>(a, b, t, gx, gy);
+        const int ym0 = (y0 + ny - 1) % ny;
+        pair_codes(cx, ym0, lk, hlk);
+        gather_pair_row<T, false>(t, cx, ym0, lk, hlk);
+        widen_pair<T, C, SH>(a, b, t, cx, gx, gy, ox);
         phiy_below_a = a.phiy;
         phiy_below_b = b.phiy;
     }
@@ -472,19 +605,28 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     C hphix = C(0);
     {
         PairRow<T> t;
-        gather_pair_row<T, true>(t, in, src, plane, pitch, nx, ny, y0, opair, edge, ve, hcol);
-        widen_pair<T, C, SH>(ca_, cb_, t, gx, gy);
-        if (edge) hphix = halo_phix<T, C, SH>(t.halo, gx);
+        pair_codes(cx, y0, lk, hlk);
+        gather_pair_row<T, true>(t, cx, y0, lk, hlk);
+        widen_pair<T, C, SH>(ca_, cb_, t, cx, gx, gy, ox);
+        if (edge) hphix = pair_halo_phix<T, C, SH>(t.halo, cx, gx, ox);
     }
+    // link codes of the next row to gather, read one row ahead
+    pair_codes(cx, (y0 + 1) % ny, lk, hlk);
 
     for (int y = y0; y < y1; ++y) {
         const int yn = (y + 1 == ny) ? 0 : y + 1;
         PairRow<T> nr;
-        gather_pair_row<T, true>(nr, in, src, plane, pitch, nx, ny, yn, opair, edge, ve, hcol);
+        gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
+        pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
 
         // row y: both nodes' coefficients except the y-gradient of Phi
-        const C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
-        const C right = dpp_shl(hphix, ca_.phix);  // x + 1 of node B
+        C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
+        C right = dpp_shl(hphix, ca_.phix);  // x + 1 of node B
+        if (ox.on) {
+            // Phi beyond the inflow wall is the wall's; beyond the outlet, the last column's
+            if (ca == 0) left = ox.phi_wall;
+            if (ca + 1 == nx - 1) right = cb_.phix;
+        }
         const C dpx_a = C(0.5) * (cb_.phix - left);
         const C dpx_b = C(0.5) * (right - ca_.phix);
         Coeffs<C> fa = collide_coeffs<C, SH>(ca_.m, dpx_a, w1, w2, ph, gx, gy);
@@ -495,8 +637,9 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                      "+v"(fb.bxy), "+v"(fb.bxxy), "+v"(fb.bxyy));
 
         RowState<C, SH> na, nb;
-        widen_pair<T, C, SH>(na, nb, nr, gx, gy);
-        const C nhphix = edge ? halo_phix<T, C, SH>(nr.halo, gx) : C(0);
+        widen_pair<T, C, SH>(na, nb, nr, cx, gx, gy, ox);
+        C nhphix = C(0);
+        if (edge) nhphix = pair_halo_phix<T, C, SH>(nr.halo, cx, gx, ox);
 
         // the same operations per node as the one-column sweep
         const C dphiy_a = C(0.5) * (na.phiy - phiy_below_a);
@@ -506,10 +649,18 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                        fa.bxyy);
         reconstruct<C>(ob, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dphiy_b, fb.bxy, fb.bxxy,
                        fb.bxyy);
+        if (LINKED && __builtin_amdgcn_ballot_w64(ca_.solid || cb_.solid) != 0) {
+            // solid nodes keep zeros (their slots are never read)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                oa[i] = ca_.solid ? C(0) : oa[i];
+                ob[i] = cb_.solid ? C(0) : ob[i];
+            }
+        }
         if (writer) {
             const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, opair, oa[i], ob[i]);
+            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, oa[i], ob[i]);
         }
         phiy_below_a = ca_.phiy;
         phiy_below_b = cb_.phiy;
@@ -535,7 +686,7 @@ __device__ __forceinline__ void idle_rows(const InstDesc &d, int rb) {
 // b / groups and the strips [g * wpb, g * wpb + wpb) with g = b % groups;
 // every wavefront of it runs the same rows and meets one barrier per row, so
 // none may leave early: the grid is exactly rowblocks x groups workgroups.
-template <int ST>
+template <int ST, bool LINKED>
 __global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(InstDesc d,
                                                                                  int srcsel,
                                                                                  int remap) {
@@ -547,7 +698,7 @@ __global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(I
     const int rb = b / groups;
     const int strip = (b - rb * groups) * wpb + w;
     if (strip < d.strips)
-        sweep_strip2<ST, true>(d, strip, rb, srcsel);
+        sweep_strip2<ST, true, LINKED>(d, strip, rb, srcsel);
     else
         idle_rows(d, rb);
 }
@@ -576,7 +727,7 @@ __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__rest
     const int4 it = items[wave];
     const InstDesc d = descs[it.x];
     if (d.cols == 2)
-        sweep_strip2<ST, false>(d, it.y, it.z, d.cur ^ flip);
+        sweep_strip2<ST, false, MASK>(d, it.y, it.z, d.cur ^ flip);
     else
         sweep_strip<ST, MASK, BUF>(d, it.y, it.z, d.cur ^ flip);
 }
@@ -604,7 +755,10 @@ template <int ST>
 hipError_t launch_pair_t(const InstDesc &d, int src, const Launch &l, hipStream_t s) {
     const int wpb = single_waves_per_block(d, ST, l);
     const int blocks = d.rowblocks * ((d.strips + wpb - 1) / wpb);
-    sweep_pair_kernel<ST><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
+    if (d.links)
+        sweep_pair_kernel<ST, true><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
+    else
+        sweep_pair_kernel<ST, false><<<blocks, 64 * wpb, 0, s>>>(d, src, l.xcd_remap);
     return hipGetLastError();
 }
 
@@ -630,7 +784,9 @@ bool buffer_addressable(const InstDesc &d, int storage) {
 }
 
 bool pair_eligible(const InstDesc &d, int storage) {
-    return d.mask == nullptr && d.xbc == 0 && d.nx % 2 == 0 && buffer_addressable(d, storage);
+    // obstacles and open boundaries need the link map
+    const bool general = d.mask != nullptr || d.xbc != 0;
+    return d.nx % 2 == 0 && buffer_addressable(d, storage) && (!general || d.links != nullptr);
 }
 
 hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, const Launch &l,

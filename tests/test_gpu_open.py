@@ -47,7 +47,7 @@ def _case(seed, nx, ny, obstacle=True):
     return f, mask, tau1, tau2, inflow
 
 
-TILINGS = [(0, 0, -1, 1), (3, 1, 0, 1), (16, 4, 1, 1)]
+TILINGS = [(0, 0, -1, 1), (3, 1, 0, 1), (16, 4, 1, 1), (0, 0, -1, 2), (5, 8, 1, 2)]
 SHAPES = [(70, 13), (131, 9), (64, 5), (5, 7), (2, 3)]
 
 

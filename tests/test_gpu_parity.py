@@ -136,6 +136,53 @@ def test_two_column_strips_fp64(L, shape, tiling):
     assert np.array_equal(got, ref)
 
 
+WALL_PAIR_SHAPES = [(130, 37), (62, 9), (256, 20), (128, 3), (2, 7)]
+
+
+@pytest.mark.parametrize("tiling", [(32, 4, 1, 2), (1, 1, 0, 2), (5, 16, 1, 2), (0, 0, -1, 2)])
+@pytest.mark.parametrize("shape", WALL_PAIR_SHAPES)
+def test_two_column_strips_with_walls_fp64(L, shape, tiling):
+    """Two columns per lane with walls, random obstacles and body force
+    (link map: bounce-back from the nodes' own slots where some lane of the
+    wavefront needs it): 7 steps against the oracle to round-off, and bit
+    for bit equal to the one-column sweep."""
+    nx, ny = shape
+    f, mask, g, tau1, tau2 = _random_problem(hash((shape, tiling)) % 1000 + 11, nx, ny)
+    say("case: pair walls %dx%d mask=%s tiling=%s" % (nx, ny, mask is not None, tiling))
+    lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f64")
+    lat.set_tuning(*tiling)
+    assert lat.tuning()[3] == 2
+    got = _np(lat.set_populations(f).step(7).get_populations())
+    lat.close()
+    want = oracle.run(f, 7, tau1, tau2, g[0], g[1], mask)
+    err = np.max(np.abs(got - want))
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f64")
+    one.set_tuning(tiling[0], tiling[1], tiling[2], 1)
+    ref = _np(one.set_populations(f).step(7).get_populations())
+    one.close()
+    say("  max |f - f_oracle| = %.3e, differs from one-column sweep at %d entries" %
+        (err, int(np.sum(got != ref))))
+    assert err < 1e-14
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_two_column_strips_with_walls_shifted_storage(L, storage):
+    nx, ny = 322, 41
+    f, mask, g, tau1, tau2 = _random_problem(13, nx, ny)
+    out = {}
+    for cols in (1, 2):
+        lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage=storage)
+        lat.set_tuning(8, 2, 1, cols)
+        assert lat.tuning()[3] == cols
+        lat.set_populations(f).step(30)
+        out[cols] = [_np(t) for t in lat.macros()]
+        lat.close()
+    same = all(np.array_equal(a, b) for a, b in zip(out[1], out[2]))
+    say("case: pair walls %dx%d %s: equal to one-column sweep: %s" % (nx, ny, storage, same))
+    assert same
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_two_column_strips_shifted_storage(L, storage):
     """FP32 / FP16 storage with two columns per lane on an even width that
@@ -181,16 +228,17 @@ def test_workgroup_size_in_effect(L):
 
 
 def test_two_column_request_falls_back_where_it_does_not_apply(L):
-    """Odd widths and lattices with obstacles keep one column per lane even
-    when two are asked for; the automatic choice takes two on wide even
-    lattices without obstacles."""
+    """Odd widths keep one column per lane even when two are asked for; the
+    automatic choice takes two on wide even lattices, with or without
+    obstacles."""
     lat = L.Lattice(131, 8, 0.8, 1.0, storage="f32")
     lat.set_tuning(0, 0, -1, 2)
     assert lat.tuning()[3] == 1
     lat.close()
     mask = inputs.channel_mask(256, 6)
     lat = L.Lattice(256, 8, 0.8, 1.0, mask=mask, storage="f32")
-    lat.set_tuning(0, 0, -1, 2)
+    assert lat.tuning()[3] == 2   # obstacles run two columns per lane through the link map
+    lat.set_tuning(0, 0, -1, 1)
     assert lat.tuning()[3] == 1
     lat.close()
     lat = L.Lattice(256, 8, 0.8, 1.0, storage="f32")

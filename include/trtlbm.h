@@ -235,6 +235,13 @@ void trt_destroy(trt_sim *s);
 /* Build the tile work list over n >= 1 simulations. */
 trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out);
 
+/* Replace the members by n >= 1 simulations (same rules as create; members
+ * may stay).  Members that leave may be stepped on their own or destroyed
+ * afterwards; no device-wide wait is made (the new tables are copied on the
+ * batch's stream behind the launches already enqueued).  Serving uses this
+ * at every change of the active set. */
+trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
+
 /* Advance every member nsteps steps (graph-captured pairs of launches). */
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps);
 

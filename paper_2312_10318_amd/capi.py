@@ -29,7 +29,8 @@ EXPORTED = [
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
     "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics", "trt_row_mean_ux",
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
-    "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_step",
+    "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_update",
+    "trt_batch_step",
     "trt_batch_diagnostics", "trt_batch_set_tuning", "trt_batch_destroy", "trt_last_error",
     "trt_version",
 ]
@@ -93,6 +94,7 @@ def load():
         "trt_state": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]),
         "trt_destroy": (None, [P]),
         "trt_batch_create": (ctypes.c_int, [I32, PP, PP]),
+        "trt_batch_update": (ctypes.c_int, [P, I32, PP]),
         "trt_batch_step": (ctypes.c_int, [P, I64]),
         "trt_batch_diagnostics": (ctypes.c_int, [P, P]),
         "trt_batch_set_tuning": (ctypes.c_int, [P, tun]),
@@ -217,6 +219,11 @@ def trt_batch_create(sims) -> int:
     out = ctypes.c_void_p()
     _check(load().trt_batch_create(len(sims), arr, ctypes.byref(out)), "trt_batch_create")
     return out.value
+
+
+def trt_batch_update(batch: int, sims) -> None:
+    arr = (ctypes.c_void_p * len(sims))(*sims)
+    _check(load().trt_batch_update(batch, len(sims), arr), "trt_batch_update")
 
 
 def trt_batch_step(batch: int, nsteps: int) -> None:

@@ -121,8 +121,14 @@ struct trt_batch {
     bool buf;  // every member fits one buffer resource
     hipStream_t stream;
     Launch launch;
-    InstDesc *d_descs;
+    InstDesc *d_descs;  // device tables, grown by doubling and reused
     int4 *d_items;
+    size_t cap_descs, cap_items;
+    InstDesc *h_descs;  // pinned staging of the tables
+    int4 *h_items;
+    size_t hcap_descs, hcap_items;
+    hipEvent_t staged;  // the last table copy has read the staging buffers
+    bool staged_pending;
     int nitems;
     int parity;  // steps taken by the batch, mod 2
     hipStream_t cap_stream;
@@ -161,6 +167,13 @@ template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F bo
 
 trt_status sim_capture(trt_sim *s) {
     release_graph(s->pair);
+    if (!s->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            s->cap_stream = nullptr;
+            return fail_hip(e, "hipStreamCreateWithFlags");
+        }
+    }
     const int st = s->prob.storage;
     const bool m = s->prob.mask != nullptr;
     return capture(s->cap_stream, s->pair, [&](hipStream_t cs) {
@@ -278,13 +291,8 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
         }
     }
     trt::tile(d, s->launch, p->storage);
-    e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        (void)hipFree(s->scratch);
-        if (s->links) (void)hipFree(s->links);
-        delete s;
-        return fail_hip(e, "hipStreamCreateWithFlags");
-    }
+    // the capture stream is created at the first capture (batch members never
+    // capture their own step)
     *out = s;
     return TRT_OK;
 }
@@ -450,50 +458,102 @@ void trt_destroy(trt_sim *s) {
 
 // ---------------------------------------------------------------- batches
 
+// Grow a device or pinned host buffer to at least `need` elements (contents
+// are not kept).
+extern "C++" {
+template <class E>
+static hipError_t grow_device(E *&p, size_t &cap, size_t need) {
+    if (need <= cap && p) return hipSuccess;
+    size_t c = cap ? cap : 64;
+    while (c < need) c *= 2;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void **)&p, c * sizeof(E));
+    if (e == hipSuccess) cap = c;
+    return e;
+}
+template <class E>
+static hipError_t grow_pinned(E *&p, size_t &cap, size_t need) {
+    if (need <= cap && p) return hipSuccess;
+    size_t c = cap ? cap : 64;
+    while (c < need) c *= 2;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void **)&p, c * sizeof(E), hipHostMallocDefault);
+    if (e == hipSuccess) cap = c;
+    return e;
+}
+}  // extern "C++"
+
+// (Re)build the work list and descriptor tables of the current members.  The
+// tables are copied from pinned staging buffers on the batch's stream, so no
+// device-wide wait is needed: launches already enqueued read the old tables
+// first (stream order).  Only the staging buffers wait, for their previous
+// copy.
 static trt_status batch_build(trt_batch *b) {
-    std::vector<InstDesc> descs(b->sims.size());
-    std::vector<int4> items;
-    for (size_t k = 0; k < b->sims.size(); ++k) {
+    const size_t n = b->sims.size();
+    size_t nitems = 0;
+    std::vector<InstDesc> descs(n);
+    for (size_t k = 0; k < n; ++k) {
         InstDesc d = b->sims[k]->desc;
         d.cur = b->sims[k]->cur;
         trt::tile(d, b->launch, b->sims[k]->prob.storage);
         descs[k] = d;
-        for (int r = 0; r < d.rowblocks; ++r)
-            for (int c = 0; c < d.strips; ++c) items.push_back(make_int4((int)k, c, r, 0));
+        nitems += (size_t)d.rowblocks * (size_t)d.strips;
     }
-    if (b->d_descs) (void)hipFree(b->d_descs);
-    if (b->d_items) (void)hipFree(b->d_items);
-    b->d_descs = nullptr;
-    b->d_items = nullptr;
-    TRT_HIP(hipMalloc((void **)&b->d_descs, descs.size() * sizeof(InstDesc)));
-    TRT_HIP(hipMalloc((void **)&b->d_items, items.size() * sizeof(int4)));
-    TRT_HIP(hipMemcpyAsync(b->d_descs, descs.data(), descs.size() * sizeof(InstDesc),
-                           hipMemcpyHostToDevice, b->stream));
-    TRT_HIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int4),
-                           hipMemcpyHostToDevice, b->stream));
-    TRT_HIP(hipStreamSynchronize(b->stream));
-    b->nitems = (int)items.size();
+    if (nitems > (size_t)INT32_MAX) return fail(TRT_EINVAL, "batch work list too long");
+    if (b->staged_pending) {
+        TRT_HIP(hipEventSynchronize(b->staged));
+        b->staged_pending = false;
+    }
+    TRT_HIP(grow_pinned(b->h_descs, b->hcap_descs, n));
+    TRT_HIP(grow_pinned(b->h_items, b->hcap_items, nitems));
+    TRT_HIP(grow_device(b->d_descs, b->cap_descs, n));
+    TRT_HIP(grow_device(b->d_items, b->cap_items, nitems));
+    size_t j = 0;
+    for (size_t k = 0; k < n; ++k) {
+        b->h_descs[k] = descs[k];
+        for (int r = 0; r < descs[k].rowblocks; ++r)
+            for (int c = 0; c < descs[k].strips; ++c) b->h_items[j++] = make_int4((int)k, c, r, 0);
+    }
+    TRT_HIP(hipMemcpyAsync(b->d_descs, b->h_descs, n * sizeof(InstDesc), hipMemcpyHostToDevice,
+                           b->stream));
+    TRT_HIP(hipMemcpyAsync(b->d_items, b->h_items, nitems * sizeof(int4), hipMemcpyHostToDevice,
+                           b->stream));
+    TRT_HIP(hipEventRecord(b->staged, b->stream));
+    b->staged_pending = true;
+    b->nitems = (int)nitems;
     b->parity = 0;
     release_graph(b->pair);
     return TRT_OK;
 }
 
-trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
-    if (!out) return fail(TRT_EINVAL, "out is NULL");
-    *out = nullptr;
+// Membership checks shared by create and update: n >= 1 distinct members of
+// one storage type and stream, none in another batch.
+static trt_status check_members(int32_t n, trt_sim *const *sims, const trt_batch *self) {
     if (n < 1 || !sims) return fail(TRT_EINVAL, "a batch needs n >= 1 simulations");
     for (int k = 0; k < n; ++k) {
         if (!sims[k]) return fail(TRT_EINVAL, "NULL batch member");
-        if (sims[k]->in_batch) return fail(TRT_ESTATE, "simulation already in a batch");
+        bool mine = false;
+        if (self)
+            for (trt_sim *m : self->sims) mine = mine || m == sims[k];
+        if (sims[k]->in_batch && !mine) return fail(TRT_ESTATE, "simulation already in a batch");
         if (sims[k]->prob.storage != sims[0]->prob.storage)
             return fail(TRT_EINVAL, "batch members must share one storage type");
         if (sims[k]->stream != sims[0]->stream)
             return fail(TRT_EINVAL, "batch members must share one stream");
+        if (self && sims[k]->stream != self->stream)
+            return fail(TRT_EINVAL, "batch members must use the batch's stream");
         for (int j = 0; j < k; ++j)
             if (sims[j] == sims[k]) return fail(TRT_EINVAL, "duplicate batch member");
     }
-    trt_batch *b = new (std::nothrow) trt_batch();
-    if (!b) return fail(TRT_ENOMEM, "out of host memory");
+    return TRT_OK;
+}
+
+static void batch_set_members(trt_batch *b, int32_t n, trt_sim *const *sims) {
+    for (trt_sim *m : b->sims) m->in_batch = false;
     b->sims.assign(sims, sims + n);
     b->storage = sims[0]->prob.storage;
     b->mask = false;
@@ -501,22 +561,41 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     for (int k = 0; k < n; ++k) {
         b->mask = b->mask || sims[k]->prob.mask != nullptr || sims[k]->prob.x_boundary != 0;
         b->buf = b->buf && trt::buffer_addressable(sims[k]->desc, sims[k]->prob.storage);
+        sims[k]->in_batch = true;
     }
+}
+
+trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
+    if (!out) return fail(TRT_EINVAL, "out is NULL");
+    *out = nullptr;
+    trt_status st = check_members(n, sims, nullptr);
+    if (st != TRT_OK) return st;
+    trt_batch *b = new (std::nothrow) trt_batch();
+    if (!b) return fail(TRT_ENOMEM, "out of host memory");
     b->stream = sims[0]->stream;
     b->launch = kDefaultLaunch;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
     if (e != hipSuccess) {
-        delete b;
-        return fail_hip(e, "hipStreamCreateWithFlags");
+        trt_batch_destroy(b);
+        return fail_hip(e, "batch stream/event");
     }
-    trt_status st = batch_build(b);
+    batch_set_members(b, n, sims);
+    st = batch_build(b);
     if (st != TRT_OK) {
         trt_batch_destroy(b);
         return st;
     }
-    for (int k = 0; k < n; ++k) sims[k]->in_batch = true;
     *out = b;
     return TRT_OK;
+}
+
+trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims) {
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+    trt_status st = check_members(n, sims, b);
+    if (st != TRT_OK) return st;
+    batch_set_members(b, n, sims);
+    return batch_build(b);
 }
 
 trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
@@ -588,9 +667,13 @@ void trt_batch_destroy(trt_batch *b) {
     if (!b) return;
     for (trt_sim *s : b->sims) s->in_batch = false;
     release_graph(b->pair);
+    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+    if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->d_descs) (void)hipFree(b->d_descs);
     if (b->d_items) (void)hipFree(b->d_items);
+    if (b->h_descs) (void)hipHostFree(b->h_descs);
+    if (b->h_items) (void)hipHostFree(b->h_items);
     delete b;
 }
 

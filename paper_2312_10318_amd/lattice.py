@@ -64,7 +64,8 @@ class Lattice:
             m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
             if m.shape != (self.ny, self.nx):
                 raise ValueError("mask must have shape [ny, nx]")
-            self.mask = torch.from_numpy(m).to(self.device)
+            with torch.cuda.stream(self.stream):
+                self.mask = torch.from_numpy(m).pin_memory().to(self.device, non_blocking=True)
         self.inflow = None if inflow is None else tuple(float(v) for v in inflow)
         prob = problem(self.nx, self.ny, self.tau_s, self.tau_s2, self.g, storage,
                        self.mask.data_ptr() if self.mask is not None else None, self.inflow)
@@ -80,9 +81,17 @@ class Lattice:
 
     # ---------------------------------------------------------------- helpers
     def _dev64(self, a, shape):
+        """A device FP64 copy of `a` (numpy arrays go through pinned memory
+        and an asynchronous copy on the lattice's stream)."""
         torch = _torch()
-        t = torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a)
-        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if torch.is_tensor(a):
+            t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        else:
+            h = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+            if tuple(h.shape) != tuple(shape):
+                raise ValueError("expected shape %s, got %s" % (shape, tuple(h.shape)))
+            with torch.cuda.stream(self.stream):
+                t = h.pin_memory().to(self.device, non_blocking=True)
         if tuple(t.shape) != tuple(shape):
             raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
         return t
@@ -97,11 +106,14 @@ class Lattice:
     def tuning(self):
         return capi.trt_get_tuning(self.handle)
 
-    def init_equilibrium(self, rho, ux, uy):
+    def init_equilibrium(self, rho, ux, uy, sync=True):
+        """f(x, 0) = f^eq(rho, u).  With sync=False the call returns once the
+        work is enqueued (the inputs are copied asynchronously)."""
         shape = (self.ny, self.nx)
         r, u, v = self._dev64(rho, shape), self._dev64(ux, shape), self._dev64(uy, shape)
         capi.trt_init_equilibrium(self.handle, r.data_ptr(), u.data_ptr(), v.data_ptr())
-        self._sync()
+        if sync:
+            self._sync()
         return self
 
     def set_populations(self, f):
@@ -191,6 +203,12 @@ class Lattice:
         cur, t = self.state()
         return (self.fb if cur else self.fa).clone(), cur, t
 
+    def release(self):
+        """Give the lattice buffers back now (the simulation must not be used
+        again except for close(); the handle's own small scratch stays until
+        close, whose device-wide frees a caller may want to defer)."""
+        self.fa = self.fb = None
+
     def close(self):
         if getattr(self, "handle", None):
             capi.trt_destroy(self.handle)
@@ -220,6 +238,19 @@ class Batch:
         capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap,
                                   cols_per_lane)
 
+    def update(self, lattices):
+        """Replace the members (no device-wide wait)."""
+        lattices = list(lattices)
+        if not lattices:
+            raise ValueError("empty batch")
+        capi.trt_batch_update(self.handle, [l.handle for l in lattices])
+        self.lattices = lattices
+        if self._diag.shape[0] < len(lattices):
+            torch = _torch()
+            self._diag = torch.empty((len(lattices), capi.TRT_NDIAG), dtype=torch.float64,
+                                     device=self.lattices[0].device)
+        return self
+
     def step(self, nsteps=1):
         capi.trt_batch_step(self.handle, int(nsteps))
         return self
@@ -228,7 +259,7 @@ class Batch:
         """[n, TRT_NDIAG] numpy array (synchronous)."""
         capi.trt_batch_diagnostics(self.handle, self._diag.data_ptr())
         self.stream.synchronize()
-        return self._diag.cpu().numpy()
+        return self._diag[:len(self.lattices)].cpu().numpy()
 
     def close(self):
         if getattr(self, "handle", None):

@@ -93,6 +93,7 @@ class Scheduler:
         self.active = {}
         self.used = 0
         self.results = []
+        self.draining = []        # results on their way to the host (asynchronous executors)
         self.t0 = None
         self.peak_used = 0
         self.peak_active = 0
@@ -123,15 +124,39 @@ class Scheduler:
 
     def _retire(self, rid, converged=None):
         req, handle, remaining, admitted, fp, _, change = self.active.pop(rid)
+        if req.tol is not None and converged is None:
+            converged = False
+        info = (req, admitted, req.steps - remaining, converged, change)
+        if hasattr(self.ex, "finish_async"):
+            # the result is copied to the host behind the work already queued;
+            # the slot and the memory are free at once (the device reuses the
+            # lattice's memory only after the copy, in stream order)
+            ticket = self.ex.finish_async(handle, keep_fields=self.keep_fields)
+            self.ex.close(handle)
+            self.used -= fp
+            self.draining.append((info, ticket))
+            return
         diag, fields = self.ex.finish(handle, keep_fields=self.keep_fields)
         self.ex.close(handle)
         self.used -= fp
+        self._record(info, diag, fields)
+
+    def _record(self, info, diag, fields):
+        req, admitted, steps, converged, change = info
         diverged = bool(diag.get("n_diverged", 0) > 0)
-        if req.tol is not None and converged is None:
-            converged = False
-        self.results.append(Result(req.rid, req.kind, req.arrival, admitted, self.now(),
-                                   req.steps - remaining, diverged, diag, req.nx * req.ny, fields,
-                                   converged, change))
+        self.results.append(Result(req.rid, req.kind, req.arrival, admitted, self.now(), steps,
+                                   diverged, diag, req.nx * req.ny, fields, converged, change))
+
+    def _collect(self, wait: bool = False):
+        """Record the results that have reached the host."""
+        pending = []
+        for info, ticket in self.draining:
+            if wait or self.ex.ready(ticket):
+                diag, fields = self.ex.result(ticket)
+                self._record(info, diag, fields)
+            else:
+                pending.append((info, ticket))
+        self.draining = pending
 
     def step_quantum(self):
         """Advance every active request by one quantum (host-synchronous)."""
@@ -164,7 +189,7 @@ class Scheduler:
         pending = [(r.arrival, r.rid, r) for r in arrivals]
         heapq.heapify(pending)
         self.t0 = self.clock()
-        while pending or self.queue or self.active:
+        while pending or self.queue or self.active or self.draining:
             t = self.now()
             while pending and pending[0][0] <= t:
                 _, _, r = heapq.heappop(pending)
@@ -172,6 +197,9 @@ class Scheduler:
             self._admit()
             if self.active:
                 self.step_quantum()
+                self._collect()
+            elif self.draining:
+                self._collect(wait=not pending)
             elif pending:
                 wait = pending[0][0] - self.now()
                 if wait > 0:
@@ -203,13 +231,24 @@ class GpuExecutor:
     """Runs requests on the GPU through the library (Lattice / Batch).
 
     Active lattices without obstacles and with obstacles form two batches
-    (two launches per step); a batch is rebuilt only when its membership
-    changes, i.e. at quantum boundaries where requests join or leave."""
+    (two launches per step), kept across quanta and updated in place when
+    their membership changes.  Quanta are enqueued without waiting for the
+    device: at most `run_ahead` quanta are in flight, so the host admits and
+    prepares requests while the GPU steps.  Finished lattices hand their
+    buffers back at once; their handles are destroyed in groups (a destroy
+    waits for the device)."""
 
-    def __init__(self, storage: str = "f32", stream=None):
+    def __init__(self, storage: str = "f32", stream=None, run_ahead: int = 2,
+                 destroy_every: int = 128):
         self.storage = storage
         self.stream = stream
-        self._batches = {}   # tuple of lattice ids -> Batch
+        self.run_ahead = run_ahead
+        self.destroy_every = destroy_every
+        self._batches = [None, None]   # open, walled
+        self._members = [[], []]
+        self._events = collections.deque()
+        self._graveyard = []
+        self._rest = {}   # rest-state fields by lattice shape
 
     def footprint(self, req: Request) -> int:
         from .lattice import footprint_bytes
@@ -219,8 +258,14 @@ class GpuExecutor:
         from .lattice import Lattice
         lat = Lattice(req.nx, req.ny, req.tau1, req.tau2, g=req.g, mask=req.mask,
                       storage=self.storage, stream=self.stream)
-        rho, ux, uy = req.fields() if req.fields else inputs.rest_state(req.ny, req.nx)
-        lat.init_equilibrium(rho, ux, uy)
+        if req.fields:
+            rho, ux, uy = req.fields()
+        else:
+            key = (req.ny, req.nx)
+            if key not in self._rest:
+                self._rest[key] = inputs.rest_state(req.ny, req.nx)
+            rho, ux, uy = self._rest[key]
+        lat.init_equilibrium(rho, ux, uy, sync=False)
         lat._prev_u = None
         if req.tol is not None:
             import torch
@@ -234,35 +279,99 @@ class GpuExecutor:
         _, s2, n2, _ = lat.velocity_change(lat._prev_u)
         return math.sqrt(s2 / n2) if n2 > 0 else math.inf
 
-    def _drop(self, keep=()):
-        for k in list(self._batches):
-            if k not in keep:
-                self._batches.pop(k).close()
-
     def step(self, handles, nsteps: int):
+        import torch
+
         from .lattice import Batch
-        groups = [g for g in ([h for h in handles if h.mask is None],
-                              [h for h in handles if h.mask is not None]) if g]
-        keys = [tuple(id(l) for l in g) for g in groups]
-        self._drop(keep=keys)
-        for k, g in zip(keys, groups):
-            if k not in self._batches:
-                self._batches[k] = Batch(g)
-        for k in keys:
-            self._batches[k].step(nsteps)
-        handles[0].stream.synchronize()
+        groups = ([h for h in handles if h.mask is None], [h for h in handles if h.mask is not None])
+        for g in (0, 1):
+            members = groups[g]
+            if [id(l) for l in members] != [id(l) for l in self._members[g]]:
+                if not members:
+                    if self._batches[g] is not None:
+                        self._batches[g].close()
+                        self._batches[g] = None
+                elif self._batches[g] is None:
+                    self._batches[g] = Batch(members)
+                else:
+                    self._batches[g].update(members)
+                self._members[g] = list(members)
+        self._flush_graveyard()
+        for g in (0, 1):
+            if self._batches[g] is not None:
+                self._batches[g].step(nsteps)
+        ev = torch.cuda.Event()
+        ev.record(handles[0].stream)
+        self._events.append(ev)
+        while len(self._events) > self.run_ahead:
+            self._events.popleft().synchronize()
 
     def finish(self, lat, keep_fields: bool = False):
-        self._drop(keep=[k for k in self._batches if id(lat) not in k])
         diag = lat.diagnostics()
         fields = tuple(t.cpu().numpy() for t in lat.macros()) if keep_fields else None
         return diag, fields
 
+    def finish_async(self, lat, keep_fields: bool = False):
+        """Enqueue the result's extraction (diagnostics, optionally the fields)
+        and its copy to pinned host memory; returns a ticket for ready() /
+        result()."""
+        import torch
+
+        from . import capi
+        from .lattice import DIAG_NAMES
+        dev = torch.empty(capi.TRT_NDIAG, dtype=torch.float64, device=lat.device)
+        capi.trt_diagnostics(lat.handle, dev.data_ptr())
+        host = [torch.empty(capi.TRT_NDIAG, dtype=torch.float64, pin_memory=True)]
+        srcs = [dev]
+        if keep_fields:
+            out = torch.empty((3, lat.ny, lat.nx), dtype=torch.float64, device=lat.device)
+            n = lat.nx * lat.ny * 8
+            capi.trt_macros(lat.handle, out.data_ptr(), out.data_ptr() + n, out.data_ptr() + 2 * n)
+            for f in out:
+                host.append(torch.empty(f.shape, dtype=f.dtype, pin_memory=True))
+                srcs.append(f)
+        with torch.cuda.stream(lat.stream):
+            for h, d in zip(host, srcs):
+                h.copy_(d, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(lat.stream)
+        return (ev, host, srcs, DIAG_NAMES, keep_fields)
+
+    def ready(self, ticket) -> bool:
+        return ticket[0].query()
+
+    def result(self, ticket):
+        ev, host, _, names, keep = ticket
+        ev.synchronize()
+        diag = {k: float(v) for k, v in zip(names, host[0].numpy())}
+        fields = tuple(h.numpy() for h in host[1:]) if keep else None
+        return diag, fields
+
     def close(self, lat):
-        lat.close()
+        lat.release()
+        self._graveyard.append(lat)
+
+    def _flush_graveyard(self, force: bool = False):
+        # only lattices that no batch lists any more
+        if not self._graveyard or (len(self._graveyard) < self.destroy_every and not force):
+            return
+        live = {id(l) for m in self._members for l in m}
+        keep = []
+        for lat in self._graveyard:
+            if id(lat) in live:
+                keep.append(lat)
+            else:
+                lat.close()
+        self._graveyard = keep
 
     def shutdown(self):
-        self._drop()
+        for g in (0, 1):
+            if self._batches[g] is not None:
+                self._batches[g].close()
+                self._batches[g] = None
+            self._members[g] = []
+        self._events.clear()
+        self._flush_graveyard(force=True)
 
 
 MAX_G_TAU1 = 0.05

@@ -153,6 +153,45 @@ def test_batch_matches_instances_alone_bitwise(L):
         x.close()
 
 
+def test_batch_update_changes_members_without_changing_results(L):
+    """Members join and leave a batch in place (trt_batch_update): every
+    lattice gets exactly the bits it gets alone, stepped the same number of
+    times; a member that left may step alone again; a lattice already in
+    another batch is refused."""
+    from paper_2312_10318_amd import capi
+    specs = [(64, 40, 0.6, 3.0), (130, 70, 0.7, 1.1), (97, 33, 1.7, 1.2), (256, 64, 0.55, 1.6)]
+    mask = inputs.channel_mask(130, 68)
+    alone, members = [], []
+    for k, (nx, ny, t1, t2) in enumerate(specs):
+        rng = np.random.default_rng(40 + k)
+        f = inputs.random_populations(rng, (ny, nx), amp=0.05)
+        mk = mask if nx == 130 else None
+        if mk is not None:
+            f[:, mk.astype(bool)] = 0.0
+        alone.append(L.Lattice(nx, ny, t1, t2, mask=mk, storage="f32").set_populations(f))
+        members.append(L.Lattice(nx, ny, t1, t2, mask=mk, storage="f32").set_populations(f))
+    batch = L.Batch(members[:2])
+    batch.step(7)                         # 0, 1: 7 steps
+    batch.update(members[1:3])            # 1 stays, 0 leaves, 2 joins
+    batch.step(5)                         # 1: 12, 2: 5
+    members[0].step(4)                    # 0 alone again: 11
+    batch.update([members[3], members[1]])
+    batch.step(3)                         # 3: 3, 1: 15
+    other = L.Batch([members[2]])
+    with pytest.raises(capi.TrtError) as e:
+        batch.update([members[2]])
+    assert e.value.status == capi.TRT_ESTATE
+    other.close()
+    for a, n in zip(alone, (11, 15, 5, 3)):
+        a.step(n)
+    batch.close()
+    for a, m in zip(alone, members):
+        assert a.state() == m.state()
+        assert np.array_equal(_np(a.get_populations()), _np(m.get_populations()))
+    for x in alone + members:
+        x.close()
+
+
 def test_batch_member_cannot_step_alone(L):
     from paper_2312_10318_amd import capi
     a = L.Lattice(32, 32, 0.6, 1.0, storage="f32").init_equilibrium(*inputs.rest_state(32, 32))

@@ -28,9 +28,13 @@
  *    which of its pull sources are solid), all freed by the matching
  *    destroy call and counted by trt_footprint_bytes.
  *  - Population lattices are device buffers of trt_lattice_bytes() bytes,
- *    256-byte aligned, laid out as 9 planes [i][y][x] with row pitch
- *    trt_pitch(nx, storage) elements and plane stride
- *    trt_plane_stride(nx, ny, storage) elements.  Storage TRT_F64 holds f_i;
+ *    256-byte aligned, laid out row-interleaved as [y][i][x]: the nine
+ *    population rows of lattice row y follow one another, each
+ *    trt_pitch(nx, storage) elements long, so f_i of node (x, y) is element
+ *    y * trt_row_stride(nx, storage) + i * trt_pitch(nx, storage) + x.
+ *    (A row's pull reads then touch three consecutive lattice rows and its
+ *    writes one, which the memory system serves faster than nine separate
+ *    population planes.)  Storage TRT_F64 holds f_i;
  *    TRT_F32_SHIFTED / TRT_F16_SHIFTED hold f_i - w_i (the population minus
  *    its rest-state weight) rounded to nearest even.  The stored values are
  *    post-collision populations of the previous step (pull streaming); use
@@ -134,10 +138,12 @@ typedef struct trt_batch trt_batch;
  * Returns -1 for an invalid size or storage. */
 int32_t trt_pitch(int32_t nx, int32_t storage);
 
-/* Elements between population planes i and i+1 (ny * pitch).  -1 if invalid. */
-int64_t trt_plane_stride(int32_t nx, int32_t ny, int32_t storage);
+/* Elements between lattice rows y and y+1 of a population lattice (nine
+ * population rows: 9 * trt_pitch).  -1 if invalid. */
+int64_t trt_row_stride(int32_t nx, int32_t storage);
 
-/* Bytes of one population lattice (9 planes).  0 if the problem is invalid. */
+/* Bytes of one population lattice (ny * trt_row_stride elements).  0 if the
+ * problem is invalid. */
 size_t trt_lattice_bytes(const trt_problem *p);
 
 /* Device bytes one simulation needs: two lattices, the mask, and the

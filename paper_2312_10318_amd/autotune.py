@@ -16,7 +16,8 @@ import os
 import time
 
 ROWS = (4, 8, 16, 32, 64, 128)
-WAVES = (1, 2, 4)
+WAVES = (1, 2, 4)            # one column per lane: at most 4 wavefronts per workgroup
+WAVES_PAIR = (2, 4, 8, 16)   # two columns per lane (the library caps FP64 at 8)
 REMAP = (1, 0)
 COLS = (1, 2)
 
@@ -53,14 +54,19 @@ def save_cache(cache: dict, path: str | None = None) -> None:
     os.replace(tmp, path)
 
 
-def candidates(nx: int, ny: int, has_mask: bool = False):
-    cols = COLS if (nx % 2 == 0 and not has_mask) else (1,)
+def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
+    """Launch shapes (rows, waves per workgroup, XCD remap, columns per
+    lane) worth timing; two columns per lane apply to every even width (with
+    or without a mask: masked lattices use the link map)."""
+    cols = COLS if nx % 2 == 0 else (1,)
     out = []
     for c in cols:
+        waves = WAVES if c == 1 else tuple(w for w in WAVES_PAIR
+                                            if storage != "f64" or w <= 8)
         for r in ROWS:
             if r > max(4, ny):
                 continue
-            for w in WAVES:
+            for w in waves:
                 for x in REMAP:
                     out.append((r, w, x, c))
     return out
@@ -92,7 +98,7 @@ def tune(nx: int, ny: int, storage: str = "f32", mask=None, steps: int | None = 
     if steps is None:
         steps = max(10, min(400, int(2e9 / max(1, nx * ny))))
     table = []
-    for shape in shapes or candidates(nx, ny, mask is not None):
+    for shape in shapes or candidates(nx, ny, mask is not None, storage):
         ms = time_shape(lat, shape, steps, max(2, steps // 10))
         table.append((list(shape), ms))
         if log:

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "TRT_OK", 1: "TRT_EINVAL", 2: "TRT_ENOMEM", 3: "TRT_EDEVICE",
 
 # Symbols declared in include/trtlbm.h (checked against the header by the tests).
 EXPORTED = [
-    "trt_pitch", "trt_plane_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
+    "trt_pitch", "trt_row_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
     "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics", "trt_row_mean_ux",
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
@@ -74,7 +74,7 @@ def load():
     tun = ctypes.POINTER(trt_tuning)
     sig = {
         "trt_pitch": (I32, [I32, I32]),
-        "trt_plane_stride": (I64, [I32, I32, I32]),
+        "trt_row_stride": (I64, [I32, I32]),
         "trt_lattice_bytes": (ctypes.c_size_t, [prob]),
         "trt_footprint_bytes": (ctypes.c_size_t, [prob]),
         "trt_create": (ctypes.c_int, [prob, P, P, P, PP]),
@@ -126,8 +126,8 @@ def trt_pitch(nx: int, storage: int) -> int:
     return load().trt_pitch(nx, storage)
 
 
-def trt_plane_stride(nx: int, ny: int, storage: int) -> int:
-    return load().trt_plane_stride(nx, ny, storage)
+def trt_row_stride(nx: int, storage: int) -> int:
+    return load().trt_row_stride(nx, storage)
 
 
 def trt_lattice_bytes(p: trt_problem) -> int:

@@ -199,15 +199,15 @@ int32_t trt_pitch(int32_t nx, int32_t storage) {
     return (nx + per - 1) / per * per;
 }
 
-int64_t trt_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
+int64_t trt_row_stride(int32_t nx, int32_t storage) {
     const int32_t p = trt_pitch(nx, storage);
-    if (p < 0 || ny < 1 || ny > kMaxSide) return -1;
-    return (int64_t)p * ny;
+    if (p < 0) return -1;
+    return (int64_t)9 * p;
 }
 
 size_t trt_lattice_bytes(const trt_problem *p) {
     if (check_problem(p) != TRT_OK) return 0;
-    return (size_t)9 * (size_t)trt_plane_stride(p->nx, p->ny, p->storage) *
+    return (size_t)p->ny * (size_t)trt_row_stride(p->nx, p->storage) *
            (size_t)elem_size(p->storage);
 }
 
@@ -254,8 +254,8 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.mask = p->mask;
     d.nx = p->nx;
     d.ny = p->ny;
-    d.pitch = trt_pitch(p->nx, p->storage);
-    d.plane = trt_plane_stride(p->nx, p->ny, p->storage);
+    d.plane = trt_pitch(p->nx, p->storage);
+    d.pitch = (int32_t)trt_row_stride(p->nx, p->storage);
     d.cur = 0;
     d.cols = 1;
     d.omega1 = 1.0 - 1.0 / p->tau_s;

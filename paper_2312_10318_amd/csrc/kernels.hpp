@@ -49,12 +49,13 @@ bool pair_eligible(const InstDesc &d, int storage);
 // bytes in flight.  Measured optima on 4096^2: with 64-column strips FP32
 // 128 rows (~2048 wavefronts), FP64 64 rows (~4096), FP16 16-32 rows
 // (~8192); with two-column strips in synchronised workgroups FP32 64 rows
-// (~2048), FP64 64 (~2048), FP16 32 (~4096).  The rows are the largest
-// power of two in [4, 128] that leaves at least that many wavefronts.
+// (~2048), FP64 128 (~1024: one 4-wavefront workgroup per CU), FP16 32
+// (~4096).  The rows are the largest power of two in [4, 128] that leaves
+// at least that many wavefronts.
 inline int auto_rows(int nx, int ny, int storage, int cols) {
     const int width = kStripWidth * cols;
     const int strips = (nx + width - 1) / width;
-    const long long target = cols == 2 ? (storage == ST_F16 ? 4096 : 2048)
+    const long long target = cols == 2 ? (storage == ST_F16 ? 4096 : (storage == ST_F32 ? 2048 : 1024))
                                        : (storage == ST_F64 ? 4096 : (storage == ST_F32 ? 2048 : 8192));
     const long long per = (long long)strips * ny / target;
     int r = 4;

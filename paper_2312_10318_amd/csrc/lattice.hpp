@@ -71,8 +71,10 @@ struct InstDesc {
     // back from the node's own slot opp(i) (half-way bounce-back)
     const uint16_t *links;
     int64_t lpitch;  // elements
-    int64_t plane;        // elements between population planes
-    int32_t nx, ny, pitch;
+    // population lattice layout [y][i][x]: f_i of node (x, y) is element
+    // y * pitch + i * plane + x
+    int64_t plane;        // elements between populations i and i+1 of a node
+    int32_t nx, ny, pitch;  // pitch: elements between node rows y and y+1
     int32_t cur;          // lattice holding the state when the descriptor was built
     int32_t strips, rowblocks, rows;
     int32_t cols;         // columns per lane of the sweep: 1 or 2 (two-column strips)

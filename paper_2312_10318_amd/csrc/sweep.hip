@@ -185,7 +185,7 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     // never spilled to scratch
     const T *__restrict__ src = static_cast<const T *>(srcsel ? d.buf[1] : d.buf[0]);
     T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
-    const uint64_t bytes = 9ull * (uint64_t)plane * sizeof(T);
+    const uint64_t bytes = (uint64_t)ny * (uint64_t)pitch * sizeof(T);
     const Acc in(src, bytes), out(dst, bytes);
     // obstacles and open boundaries: the link map (general kernels only)
     const bool linked = MASK && d.links != nullptr;
@@ -560,7 +560,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     const int64_t plane = d.plane;
     const T *__restrict__ src = static_cast<const T *>(srcsel ? d.buf[1] : d.buf[0]);
     T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
-    const uint64_t bytes = 9ull * (uint64_t)plane * sizeof(T);
+    const uint64_t bytes = (uint64_t)ny * (uint64_t)pitch * sizeof(T);
     const BufAccess<T> in(src, bytes), out(dst, bytes);
     const LinkAccess lacc(d.links, (uint64_t)ny * (uint64_t)d.lpitch);
     const bool linked = LINKED && d.links != nullptr;
@@ -780,7 +780,7 @@ hipError_t launch_batch_b(const InstDesc *descs, const int4 *items, int nitems, 
 
 bool buffer_addressable(const InstDesc &d, int storage) {
     const uint64_t es = storage == ST_F64 ? 8 : (storage == ST_F32 ? 4 : 2);
-    return 9ull * (uint64_t)d.plane * es <= 0xffffffffull;
+    return (uint64_t)d.ny * (uint64_t)d.pitch * es <= 0xffffffffull;
 }
 
 bool pair_eligible(const InstDesc &d, int storage) {

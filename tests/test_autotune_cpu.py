@@ -1,0 +1,26 @@
+"""Host logic of the launch-shape autotuner (no GPU)."""
+from paper_2312_10318_amd import autotune
+
+
+def test_candidates_cover_both_column_modes_on_even_widths():
+    for has_mask in (False, True):
+        shapes = autotune.candidates(4096, 4096, has_mask, "f32")
+        assert {c for _, _, _, c in shapes} == {1, 2}
+        assert {w for _, w, _, c in shapes if c == 1} == {1, 2, 4}
+        assert {w for _, w, _, c in shapes if c == 2} == {2, 4, 8, 16}
+        assert {x for _, _, x, _ in shapes} == {0, 1}
+        assert len(shapes) == len(set(shapes))
+
+
+def test_candidates_respect_width_and_storage_limits():
+    odd = autotune.candidates(1025, 512, False, "f32")
+    assert {c for _, _, _, c in odd} == {1}
+    f64 = autotune.candidates(4096, 4096, False, "f64")
+    assert max(w for _, w, _, c in f64 if c == 2) == 8
+    short = autotune.candidates(256, 8, False, "f16")
+    assert max(r for r, _, _, _ in short) == 8
+
+
+def test_cache_key_buckets_sizes():
+    assert autotune.key(4000, 4100, "f32", False) == autotune.key(4096, 4096, "f32", False)
+    assert autotune.key(4096, 4096, "f32", True) != autotune.key(4096, 4096, "f32", False)

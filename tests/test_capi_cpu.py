@@ -41,7 +41,9 @@ def test_pitch_and_sizes(lib):
     assert capi.trt_pitch(400, capi.TRT_F16_SHIFTED) == 512
     assert capi.trt_pitch(0, capi.TRT_F64) == -1
     assert capi.trt_pitch(5, 7) == -1
-    assert capi.trt_plane_stride(64, 10, capi.TRT_F64) == 640
+    assert capi.trt_row_stride(64, capi.TRT_F64) == 9 * 64
+    assert capi.trt_row_stride(400, capi.TRT_F16_SHIFTED) == 9 * 512
+    assert capi.trt_row_stride(0, capi.TRT_F64) == -1
     p = lattice.problem(4096, 4096, 0.6, 3.0, storage="f32")
     assert capi.trt_lattice_bytes(p) == 9 * 4096 * 4096 * 4
     assert capi.trt_footprint_bytes(p) >= 2 * 9 * 4096 * 4096 * 4

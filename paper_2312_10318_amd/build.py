@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -22,7 +23,26 @@ FLAGS = [
     # wavefront) rounds each node's arithmetic identically
     "-ffp-contract=on",
     "-Wall", "-Wno-unused-command-line-argument",
+    # per-kernel register use (read back below: a sweep kernel that spills
+    # registers to scratch memory fails the build)
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+
+
+def spills(remarks: str) -> dict:
+    """{kernel: VGPRs spilled to scratch memory} from the compiler's resource
+    remarks.  (SGPR spills go to VGPR lanes, not to memory.)"""
+    out, name = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            out.setdefault(name, 0)
+            continue
+        m = re.search(r"remark:\s+VGPRs Spill: (\d+)", line)
+        if m and name is not None:
+            out[name] += int(m.group(1))
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -36,6 +56,10 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libtrtlbm.so")
+    spilled = {k: n for k, n in spills(r.stderr).items() if n > 0 and "sweep" in k}
+    if spilled:
+        os.remove(tmp)
+        raise RuntimeError("sweep kernels spill registers to scratch memory: %s" % spilled)
     os.replace(tmp, LIB)
     return LIB
 

@@ -31,6 +31,7 @@
 
 namespace trt {
 
+
 namespace {
 
 // Remap the hardware workgroup index so that each of the 8 XCDs (dispatched
@@ -357,10 +358,14 @@ template <> struct PairIO<_Float16> {
     }
     __device__ static __forceinline__ void st(const BufAccess<_Float16> &a, int64_t e, uint32_t v,
                                               float x, float y) {
-        const uint32_t lo = __builtin_bit_cast(unsigned short, (_Float16)x);
-        const uint32_t hi = __builtin_bit_cast(unsigned short, (_Float16)y);
-        __builtin_amdgcn_raw_buffer_store_b32(lo | (hi << 16), a.r, v, (uint32_t)(e * 2),
-                                              TRT_STORE_CPOL);
+        // a half-precision pair: each conversion writes its own half of the
+        // register, with no separate shift and merge
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        h2 h;
+        h.x = (_Float16)x;
+        h.y = (_Float16)y;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, h), a.r, v,
+                                              (uint32_t)(e * 2), TRT_STORE_CPOL);
     }
 };
 template <> struct PairIO<float> {
@@ -547,6 +552,27 @@ __device__ __forceinline__ C pair_halo_phix(Raw<T> &h, const PairCtx<T> &c, C gx
     return halo_phix<T, C, SHIFTED>(h, gx, ox, c.hcol.xc);
 }
 
+// Rows a two-column sweep gathers ahead of the row it finishes: 1 waits for
+// the next row's loads within the same iteration, 2 issues them one
+// iteration earlier (more bytes in flight per wavefront, one more gathered
+// row held in registers).  Measured on 4096^2: 2 gains a point for FP64
+// without a link map and loses 2-3 points for FP32 and FP16; with the link
+// map the extra row (own slots included) exceeds the FP64 register budget
+// and spills, so link-map sweeps always use 1.
+#ifndef TRT_AHEAD_F64
+#define TRT_AHEAD_F64 2
+#endif
+#ifndef TRT_AHEAD_F32
+#define TRT_AHEAD_F32 1
+#endif
+#ifndef TRT_AHEAD_F16
+#define TRT_AHEAD_F16 1
+#endif
+template <int ST, bool LINKED>
+constexpr int pair_ahead() {
+    return LINKED ? 1 : (ST == ST_F64 ? TRT_AHEAD_F64 : (ST == ST_F32 ? TRT_AHEAD_F32 : TRT_AHEAD_F16));
+}
+
 // LINKED: the lattice may have obstacles or open x boundaries (link map);
 // without it the link code is compiled out.
 template <int ST, bool SYNC, bool LINKED>
@@ -612,12 +638,25 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     }
     // link codes of the next row to gather, read one row ahead
     pair_codes(cx, (y0 + 1) % ny, lk, hlk);
+    constexpr int AHEAD = pair_ahead<ST, LINKED>();
+    PairRow<T> pend;  // AHEAD == 2: row y + 1, gathered one iteration earlier
+    if (AHEAD == 2) {
+        gather_pair_row<T, true>(pend, cx, (y0 + 1) % ny, lk, hlk);
+        pair_codes(cx, min(y0 + 2, y1) % ny, lk, hlk);
+    }
 
     for (int y = y0; y < y1; ++y) {
-        const int yn = (y + 1 == ny) ? 0 : y + 1;
         PairRow<T> nr;
-        gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
-        pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
+        if (AHEAD == 2) {
+            // row y + 2 (the last iteration gathers row y1 again: a cache hit
+            // that keeps every register defined)
+            gather_pair_row<T, true>(nr, cx, min(y + 2, y1) % ny, lk, hlk);
+            pair_codes(cx, min(y + 3, y1) % ny, lk, hlk);
+        } else {
+            const int yn = (y + 1 == ny) ? 0 : y + 1;
+            gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
+            pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
+        }
 
         // row y: both nodes' coefficients except the y-gradient of Phi
         C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
@@ -637,9 +676,10 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                      "+v"(fb.bxy), "+v"(fb.bxxy), "+v"(fb.bxyy));
 
         RowState<C, SH> na, nb;
-        widen_pair<T, C, SH>(na, nb, nr, cx, gx, gy, ox);
+        PairRow<T> &next = AHEAD == 2 ? pend : nr;
+        widen_pair<T, C, SH>(na, nb, next, cx, gx, gy, ox);
         C nhphix = C(0);
-        if (edge) nhphix = pair_halo_phix<T, C, SH>(nr.halo, cx, gx, ox);
+        if (edge) nhphix = pair_halo_phix<T, C, SH>(next.halo, cx, gx, ox);
 
         // the same operations per node as the one-column sweep
         const C dphiy_a = C(0.5) * (na.phiy - phiy_below_a);
@@ -667,6 +707,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
         ca_ = na;
         cb_ = nb;
         hphix = nhphix;
+        if (AHEAD == 2) pend = nr;
         // keep the workgroup's wavefronts (adjacent strips) on the same row, so
         // that their accesses to each population row stay contiguous in time
         if (SYNC) __builtin_amdgcn_s_barrier();

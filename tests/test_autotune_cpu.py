@@ -24,3 +24,17 @@ def test_candidates_respect_width_and_storage_limits():
 def test_cache_key_buckets_sizes():
     assert autotune.key(4000, 4100, "f32", False) == autotune.key(4096, 4096, "f32", False)
     assert autotune.key(4096, 4096, "f32", True) != autotune.key(4096, 4096, "f32", False)
+
+
+def test_build_reads_register_spills_from_compiler_remarks():
+    from paper_2312_10318_amd import build
+    text = "\n".join([
+        "a.hip:1:1: remark: Function Name: _Z5sweepv [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs: 207 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     SGPRs Spill: 7 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs Spill: 56 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark: Function Name: _Z4initv [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     SGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     VGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert build.spills(text) == {"_Z5sweepv": 56, "_Z4initv": 0}

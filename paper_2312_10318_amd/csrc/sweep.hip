@@ -497,7 +497,14 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     C pa[9], pb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) PairIO<T>::split(r.w[i], pa[i], pb[i]);
-    const C h0 = to_c(r.edge[0]), h1 = to_c(r.edge[1]), h2 = to_c(r.edge[2]);
+    // the edge elements are converted here, once the row is needed: left to
+    // itself the compiler moves an FP16 conversion into the edge lanes' load
+    // branch, and its wait for the element (memory operations complete in
+    // issue order) then waits for the whole row before the previous row's
+    // coefficients are formed
+    T e0 = r.edge[0], e1 = r.edge[1], e2 = r.edge[2];
+    asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2));
+    const C h0 = to_c(e0), h1 = to_c(e1), h2 = to_c(e2);
     C fa[9], fb[9];
     fa[0] = pa[0]; fb[0] = pb[0];
     fa[2] = pa[2]; fb[2] = pb[2];
@@ -550,27 +557,6 @@ __device__ __forceinline__ C pair_halo_phix(Raw<T> &h, const PairCtx<T> &c, C gx
                                             const OpenX<C> &ox) {
     if (c.linked) link_fix(h);
     return halo_phix<T, C, SHIFTED>(h, gx, ox, c.hcol.xc);
-}
-
-// Rows a two-column sweep gathers ahead of the row it finishes: 1 waits for
-// the next row's loads within the same iteration, 2 issues them one
-// iteration earlier (more bytes in flight per wavefront, one more gathered
-// row held in registers).  Measured on 4096^2: 2 gains a point for FP64
-// without a link map and loses 2-3 points for FP32 and FP16; with the link
-// map the extra row (own slots included) exceeds the FP64 register budget
-// and spills, so link-map sweeps always use 1.
-#ifndef TRT_AHEAD_F64
-#define TRT_AHEAD_F64 2
-#endif
-#ifndef TRT_AHEAD_F32
-#define TRT_AHEAD_F32 1
-#endif
-#ifndef TRT_AHEAD_F16
-#define TRT_AHEAD_F16 1
-#endif
-template <int ST, bool LINKED>
-constexpr int pair_ahead() {
-    return LINKED ? 1 : (ST == ST_F64 ? TRT_AHEAD_F64 : (ST == ST_F32 ? TRT_AHEAD_F32 : TRT_AHEAD_F16));
 }
 
 // LINKED: the lattice may have obstacles or open x boundaries (link map);
@@ -638,25 +624,12 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     }
     // link codes of the next row to gather, read one row ahead
     pair_codes(cx, (y0 + 1) % ny, lk, hlk);
-    constexpr int AHEAD = pair_ahead<ST, LINKED>();
-    PairRow<T> pend;  // AHEAD == 2: row y + 1, gathered one iteration earlier
-    if (AHEAD == 2) {
-        gather_pair_row<T, true>(pend, cx, (y0 + 1) % ny, lk, hlk);
-        pair_codes(cx, min(y0 + 2, y1) % ny, lk, hlk);
-    }
 
     for (int y = y0; y < y1; ++y) {
+        const int yn = (y + 1 == ny) ? 0 : y + 1;
         PairRow<T> nr;
-        if (AHEAD == 2) {
-            // row y + 2 (the last iteration gathers row y1 again: a cache hit
-            // that keeps every register defined)
-            gather_pair_row<T, true>(nr, cx, min(y + 2, y1) % ny, lk, hlk);
-            pair_codes(cx, min(y + 3, y1) % ny, lk, hlk);
-        } else {
-            const int yn = (y + 1 == ny) ? 0 : y + 1;
-            gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
-            pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
-        }
+        gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
+        pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
 
         // row y: both nodes' coefficients except the y-gradient of Phi
         C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
@@ -676,10 +649,9 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                      "+v"(fb.bxy), "+v"(fb.bxxy), "+v"(fb.bxyy));
 
         RowState<C, SH> na, nb;
-        PairRow<T> &next = AHEAD == 2 ? pend : nr;
-        widen_pair<T, C, SH>(na, nb, next, cx, gx, gy, ox);
+        widen_pair<T, C, SH>(na, nb, nr, cx, gx, gy, ox);
         C nhphix = C(0);
-        if (edge) nhphix = pair_halo_phix<T, C, SH>(next.halo, cx, gx, ox);
+        if (edge) nhphix = pair_halo_phix<T, C, SH>(nr.halo, cx, gx, ox);
 
         // the same operations per node as the one-column sweep
         const C dphiy_a = C(0.5) * (na.phiy - phiy_below_a);
@@ -707,7 +679,6 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
         ca_ = na;
         cb_ = nb;
         hphix = nhphix;
-        if (AHEAD == 2) pend = nr;
         // keep the workgroup's wavefronts (adjacent strips) on the same row, so
         // that their accesses to each population row stay contiguous in time
         if (SYNC) __builtin_amdgcn_s_barrier();

@@ -197,11 +197,32 @@ def run_stability():
             "per_re": {"%g" % k: v for k, v in stability.summary(res).items()}}
 
 
-def profile_run(n, storage, steps, warmup, tuning):
-    """Kernels for rocprofv3: `steps` sweeps of the benchmark lattice, then a
-    plain copy of 1 GiB (known bytes) to scale the HBM counters."""
+def creeping_lattice(storage, tuning=None):
+    """The creeping-flow geometry of Sec. III.D (Table 1, Re = 1e-3): 1050^2,
+    a 21 x 21 square cylinder, inflow wall and pressure outlet -- the sweep
+    with the link map."""
+    from paper_2312_10318_amd import creeping
+    from paper_2312_10318_amd.lattice import Lattice
+    c = creeping.Case(1e-3)
+    mask = creeping.cylinder_mask(c.n, c.D)
+    lat = Lattice(c.n, c.n, c.tau1, c.tau2, mask=mask, storage=storage,
+                  inflow=(c.u0, 1.0, 1.0))
+    if tuning:
+        lat.set_tuning(*tuning)
+    lat.init_equilibrium(*creeping.initial_fields(c, mask))
+    return lat
+
+
+def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
+    """Kernels for rocprofv3: `steps` sweeps of the benchmark lattice (or of
+    the creeping-flow lattice), then a plain copy of 1 GiB (known bytes) to
+    scale the HBM counters."""
     import torch
-    lat = tg_lattice(n, storage, tuning=tuning)
+    if workload == "creeping":
+        lat = creeping_lattice(storage, tuning)
+        n = lat.nx
+    else:
+        lat = tg_lattice(n, storage, tuning=tuning)
     lat.step(warmup + steps)
     torch.cuda.synchronize()
     lat.close()
@@ -211,7 +232,7 @@ def profile_run(n, storage, steps, warmup, tuning):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"profile": "done", "sweeps": warmup + steps, "copy_bytes": 1 << 30,
-                      "copies": 3, "storage": storage, "n": n,
+                      "copies": 3, "storage": storage, "n": n, "workload": workload,
                       "source_hash": sweep_source_hash()}), flush=True)
 
 
@@ -229,6 +250,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
+    ap.add_argument("--workload", default="tg", choices=["tg", "creeping"],
+                    help="lattice of --profile: the Taylor-Green benchmark (--n) or the "
+                         "creeping-flow cylinder of Table 1 (1050^2, link map)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -245,7 +269,7 @@ def main():
     n, storage = args.n, args.storage
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
     if args.profile:
-        profile_run(n, storage, args.steps, args.warmup, tuning)
+        profile_run(n, storage, args.steps, args.warmup, tuning, args.workload)
         return
     log("bench: TG %dx%d %s, warmup %d, steps %d" % (n, n, storage, args.warmup, args.steps))
     lat = tg_lattice(n, storage, tuning=tuning)

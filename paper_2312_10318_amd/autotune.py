@@ -17,7 +17,7 @@ import time
 
 ROWS = (4, 8, 16, 32, 64, 128)
 WAVES = (1, 2, 4)            # one column per lane: at most 4 wavefronts per workgroup
-WAVES_PAIR = (2, 4, 8, 16)   # two columns per lane (the library caps FP64 at 8)
+WAVES_PAIR = (1, 2, 4, 8, 16)  # two columns per lane (the library caps FP64 at 8)
 REMAP = (1, 0)
 COLS = (1, 2)
 

@@ -22,7 +22,11 @@ struct Launch {
 // per row, and wider ones keep more adjacent strips in step: measured best
 // on 4096^2 are 8 (FP32) and 16 (FP16); FP64 gains nothing beyond 4.  A
 // workgroup never has more wavefronts than the lattice has strips (rounded
-// up to a power of two).
+// up to a power of two).  When the choice is automatic it is also halved
+// until at most one in eight wavefronts of a row block's workgroups has no
+// strip: those only meet barriers, and on narrow lattices they cost more
+// than wide workgroups gain (1050^2, 9 strips: 8 wavefronts 27.3 GLUPS FP32,
+// 2 wavefronts 42.9).
 inline int single_waves_per_block(const InstDesc &d, int storage, const Launch &l) {
     if (d.cols != 2) return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
     const int cap = storage == ST_F64 ? 8 : 16;
@@ -30,6 +34,10 @@ inline int single_waves_per_block(const InstDesc &d, int storage, const Launch &
                                   : (storage == ST_F16 ? 16 : (storage == ST_F32 ? 8 : 4));
     if (w > cap) w = cap;
     while (w > 1 && w / 2 >= d.strips) w /= 2;
+    if (l.waves_per_block <= 0) {
+        auto slots = [&](int v) { return (d.strips + v - 1) / v * v; };
+        while (w > 1 && 8 * (slots(w) - d.strips) > slots(w)) w /= 2;
+    }
     return w;
 }
 

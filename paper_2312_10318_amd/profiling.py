@@ -95,8 +95,16 @@ def _run_hash(log_path):
     raise ValueError("no profile record in " + log_path)
 
 
+# Workloads of `bench.py --profile`: (title, name, link code bytes per node).
+WORKLOADS = {
+    "tg": ("Taylor-Green %dx%d", "taylor_green_%dx%d", 0),
+    "creeping": ("creeping flow past a square cylinder (Sec. III.D), %dx%d, obstacle, "
+                 "inflow wall and pressure outlet", "creeping_cylinder_%dx%d", 2),
+}
+
+
 def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_prefix,
-              skip_first=2, run_log=None):
+              skip_first=2, run_log=None, workload="tg"):
     sweep_ns, copy_ns, kname = kernel_durations(trace_dir)
     fs, fc = counter_values(fetch_dir, "FETCH_SIZE")
     ws, wc = counter_values(write_dir, "WRITE_SIZE")
@@ -107,13 +115,15 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     write_scale = COPY_BYTES / (avg(wc) * 1024.0)
     fetch_b = avg(fs) * 1024.0 * fetch_scale
     write_b = avg(ws) * 1024.0 * write_scale
+    title, wname, link_bytes = WORKLOADS[workload]
     nodes = n * n
-    alg = BYTES_PER_LU[storage] * nodes
+    # 9 populations read and written (+ the link code read, with a link map)
+    alg = (BYTES_PER_LU[storage] + link_bytes) * nodes
     dur = avg(sweep_ns) * 1e-9
     rec = {
         "kernel": (re.search(r"sweep_(single|pair)_kernel<[^>]*>", kname or "") or
                    re.search(r".*", "sweep")).group(0),
-        "workload": "taylor_green_%dx%d" % (n, n), "storage": storage, "nodes": nodes,
+        "workload": wname % (n, n), "storage": storage, "nodes": nodes,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
         "dispatches": len(sweep_ns), "avg_duration_us": round(dur * 1e6, 3),
         "algorithmic_bytes_per_launch": alg,
@@ -127,19 +137,23 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         "hbm_GBps_measured": round((fetch_b + write_b) / dur / 1e9, 1),
         "copy_avg_duration_us": round(avg(copy_ns) * 1e-3, 3) if copy_ns else None,
     }
-    cmd = ("python3 bench.py --profile --storage %s --n %d --steps %d --warmup %d"
-           % (storage, n, steps, warmup))
+    if workload == "tg":
+        cmd = ("python3 bench.py --profile --storage %s --n %d --steps %d --warmup %d"
+               % (storage, n, steps, warmup))
+    else:
+        cmd = ("python3 bench.py --profile --workload %s --storage %s --steps %d --warmup %d"
+               % (workload, storage, steps, warmup))
     with open(out_prefix + "_hbm_counters.json", "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(out_prefix + ".md", "w") as fh:
-        fh.write("# Fused sweep, Taylor-Green %dx%d, %s storage\n\n" % (n, n, storage))
+        fh.write("# Fused sweep, %s, %s storage\n\n" % (title % (n, n), storage))
         fh.write("Commands (run from the repository root, one profiler run each):\n\n")
         fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)
-        fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --storage %s --n %d "
-                 "--steps %d --warmup %d --out %s\n\n" % (storage, n, steps, warmup,
-                                                         os.path.relpath(out_prefix, ROOT)))
+        fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --workload %s "
+                 "--storage %s --n %d --steps %d --warmup %d --out %s\n\n"
+                 % (workload, storage, n, steps, warmup, os.path.relpath(out_prefix, ROOT)))
         fh.write("| quantity | value |\n|---|---|\n")
         for k, v in rec.items():
             fh.write("| %s | %s |\n" % (k, v))
@@ -163,6 +177,7 @@ def main():
     ap.add_argument("write_dir")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--workload", default="tg", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--out", required=True)
@@ -172,7 +187,7 @@ def main():
     a = ap.parse_args()
     rec = summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.storage, a.n, a.steps, a.warmup,
                     os.path.join(ROOT, a.out) if not os.path.isabs(a.out) else a.out,
-                    run_log=a.run_log)
+                    run_log=a.run_log, workload=a.workload)
     print(json.dumps(rec, indent=1))
 
 

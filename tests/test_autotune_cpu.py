@@ -7,7 +7,7 @@ def test_candidates_cover_both_column_modes_on_even_widths():
         shapes = autotune.candidates(4096, 4096, has_mask, "f32")
         assert {c for _, _, _, c in shapes} == {1, 2}
         assert {w for _, w, _, c in shapes if c == 1} == {1, 2, 4}
-        assert {w for _, w, _, c in shapes if c == 2} == {2, 4, 8, 16}
+        assert {w for _, w, _, c in shapes if c == 2} == {1, 2, 4, 8, 16}
         assert {x for _, _, x, _ in shapes} == {0, 1}
         assert len(shapes) == len(set(shapes))
 

@@ -214,10 +214,13 @@ def test_workgroup_size_in_effect(L):
     """The wavefronts per workgroup reported are the ones launched: capped at
     4 for one-column sweeps, 8 for FP64 and 16 otherwise for two-column
     sweeps, where they also never exceed what the strips need (62 is below
-    the two-column width, so it sweeps one column per lane)."""
+    the two-column width, so it sweeps one column per lane).  The automatic
+    choice leaves at most one in eight wavefronts without a strip (1050: 9
+    strips, so 2 per workgroup); an explicit request is kept."""
     cases = [(4096, "f32", 0, 8), (4096, "f16", 0, 16), (4096, "f64", 0, 4),
              (4096, "f64", 16, 8), (384, "f32", 16, 4), (130, "f16", 0, 2), (62, "f32", 0, 4),
-             (131, "f32", 16, 4)]
+             (131, "f32", 16, 4), (1050, "f32", 0, 2), (1050, "f16", 0, 2), (1050, "f64", 0, 2),
+             (1050, "f32", 8, 8)]
     for nx, storage, asked, want in cases:
         lat = L.Lattice(nx, 4, 0.8, 1.0, storage=storage)
         lat.set_tuning(0, asked, -1, 0)

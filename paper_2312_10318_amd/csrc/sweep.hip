@@ -172,6 +172,35 @@ __device__ __forceinline__ C halo_phix(const Raw<T> &raw, C gx, const OpenX<C> &
 
 static_assert(kStripWidth == 64, "one strip column per lane of a 64-wide wavefront");
 
+// DPP whole-wavefront shifts: lane i receives lane i-1 (shr) or lane i+1
+// (shl); the lane with no source keeps `old`.
+__device__ __forceinline__ float dpp_shr(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, src),
+                                                                  0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_shl(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, src),
+                                                                  0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dpp_shr(double old, double src) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x138, 0xf,
+                                                    0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
+                                                    0x138, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double dpp_shl(double old, double src) {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x130, 0xf,
+                                                    0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
+                                                    0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <int ST, bool MASK, bool BUF>
 __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
@@ -261,9 +290,10 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         hlk_next = edge ? code(ynn, hcol) : 0u;
 
         // row y: everything of the collision except the y-gradient of Phi
-        const C up = __shfl_up(cur.phix, 1), dn = __shfl_down(cur.phix, 1);
-        C phix_l = (lane == 0) ? hphix : up;
-        C phix_r = (lane == kStripWidth - 1) ? hphix : dn;
+        // x-neighbours' Phi_x from the adjacent lanes (lanes 0 and 63: the
+        // halo column's, through the shift's `old` operand)
+        C phix_l = dpp_shr(hphix, cur.phix);
+        C phix_r = dpp_shl(hphix, cur.phix);
         if (ox.on) {
             // Phi beyond the inflow wall is the wall's; beyond the outlet, the last column's
             if (col.xc == 0) phix_l = ox.phi_wall;
@@ -312,35 +342,6 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
 // even nx that fit one buffer resource.
 
 constexpr int kStripWidth2 = 128;
-
-// DPP whole-wavefront shifts: lane i receives lane i-1 (shr) or lane i+1
-// (shl); the lane with no source keeps `old`.
-__device__ __forceinline__ float dpp_shr(float old, float src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
-                                                                  __builtin_bit_cast(int, src),
-                                                                  0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float dpp_shl(float old, float src) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
-                                                                  __builtin_bit_cast(int, src),
-                                                                  0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double dpp_shr(double old, double src) {
-    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
-    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x138, 0xf,
-                                                    0xf, false);
-    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
-                                                    0x138, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double dpp_shl(double old, double src) {
-    const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
-    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x130, 0xf,
-                                                    0xf, false);
-    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
-                                                    0x130, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

@@ -367,7 +367,7 @@ def test_double_shear_layer_1024_full_size_step(L, storage):
     assert emax <= TOL[storage] and el2 <= TOL[storage]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_taylor_green_4096_full_size_step(L, storage):
     """The roofline workload (Taylor-Green 4096^2, tau_s = 0.6,
     Lambda_s = 1/4) in the benchmark's launch shape: one GPU step equals the

@@ -243,8 +243,10 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out);
 
 /* Replace the members by n >= 1 simulations (same rules as create; members
  * may stay).  Members that leave may be stepped on their own or destroyed
- * afterwards; no device-wide wait is made (the new tables are copied on the
- * batch's stream behind the launches already enqueued).  Serving uses this
+ * afterwards.  The call does not wait for the launches already enqueued:
+ * the new tables are copied on the batch's stream behind them, from one of
+ * a ring of pinned staging buffers, and the call waits at most for the copy
+ * that last used that buffer (several updates earlier).  Serving uses this
  * at every change of the active set. */
 trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
 

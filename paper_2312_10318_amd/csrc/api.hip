@@ -124,11 +124,23 @@ struct trt_batch {
     InstDesc *d_descs;  // device tables, grown by doubling and reused
     int4 *d_items;
     size_t cap_descs, cap_items;
-    InstDesc *h_descs;  // pinned staging of the tables
-    int4 *h_items;
-    size_t hcap_descs, hcap_items;
-    hipEvent_t staged;  // the last table copy has read the staging buffers
-    bool staged_pending;
+    // Pinned staging of the tables: a ring of slots, each reused only once
+    // the copy that last read it has run (its event), so a membership
+    // change waits for a copy several changes old, not for the work queued
+    // on the stream ahead of the latest one.
+    struct Staging {
+        InstDesc *descs;
+        int4 *items;
+        size_t cap_descs, cap_items;
+        hipEvent_t done;
+        bool pending;
+    };
+    static constexpr int kStagingSlots = 4;
+    Staging stage[kStagingSlots];
+    int next_stage;
+    // Outgrown tables and staging buffers, freed with the batch: freeing
+    // them at once would wait for the launches queued on the stream.
+    std::vector<void *> retired_dev, retired_host;
     int nitems;
     int parity;  // steps taken by the batch, mod 2
     hipStream_t cap_stream;
@@ -461,12 +473,18 @@ void trt_destroy(trt_sim *s) {
 // Grow a device or pinned host buffer to at least `need` elements (contents
 // are not kept).
 extern "C++" {
+// Table capacity for `need` entries: at least 4096, growing fourfold, so a
+// batch whose membership keeps changing reallocates rarely.
+static size_t table_capacity(size_t cap, size_t need) {
+    size_t c = cap ? cap : 4096;
+    while (c < need) c *= 4;
+    return c;
+}
 template <class E>
-static hipError_t grow_device(E *&p, size_t &cap, size_t need) {
+static hipError_t grow_device(E *&p, size_t &cap, size_t need, std::vector<void *> &retired) {
     if (need <= cap && p) return hipSuccess;
-    size_t c = cap ? cap : 64;
-    while (c < need) c *= 2;
-    if (p) (void)hipFree(p);
+    const size_t c = table_capacity(cap, need);
+    if (p) retired.push_back(p);
     p = nullptr;
     cap = 0;
     hipError_t e = hipMalloc((void **)&p, c * sizeof(E));
@@ -474,11 +492,10 @@ static hipError_t grow_device(E *&p, size_t &cap, size_t need) {
     return e;
 }
 template <class E>
-static hipError_t grow_pinned(E *&p, size_t &cap, size_t need) {
+static hipError_t grow_pinned(E *&p, size_t &cap, size_t need, std::vector<void *> &retired) {
     if (need <= cap && p) return hipSuccess;
-    size_t c = cap ? cap : 64;
-    while (c < need) c *= 2;
-    if (p) (void)hipHostFree(p);
+    const size_t c = table_capacity(cap, need);
+    if (p) retired.push_back(p);
     p = nullptr;
     cap = 0;
     hipError_t e = hipHostMalloc((void **)&p, c * sizeof(E), hipHostMallocDefault);
@@ -490,8 +507,8 @@ static hipError_t grow_pinned(E *&p, size_t &cap, size_t need) {
 // (Re)build the work list and descriptor tables of the current members.  The
 // tables are copied from pinned staging buffers on the batch's stream, so no
 // device-wide wait is needed: launches already enqueued read the old tables
-// first (stream order).  Only the staging buffers wait, for their previous
-// copy.
+// first (stream order).  Only a staging slot waits, for the copy that last
+// read it (several rebuilds ago).
 static trt_status batch_build(trt_batch *b) {
     const size_t n = b->sims.size();
     size_t nitems = 0;
@@ -504,26 +521,28 @@ static trt_status batch_build(trt_batch *b) {
         nitems += (size_t)d.rowblocks * (size_t)d.strips;
     }
     if (nitems > (size_t)INT32_MAX) return fail(TRT_EINVAL, "batch work list too long");
-    if (b->staged_pending) {
-        TRT_HIP(hipEventSynchronize(b->staged));
-        b->staged_pending = false;
+    trt_batch::Staging &sg = b->stage[b->next_stage];
+    b->next_stage = (b->next_stage + 1) % trt_batch::kStagingSlots;
+    if (sg.pending) {
+        TRT_HIP(hipEventSynchronize(sg.done));
+        sg.pending = false;
     }
-    TRT_HIP(grow_pinned(b->h_descs, b->hcap_descs, n));
-    TRT_HIP(grow_pinned(b->h_items, b->hcap_items, nitems));
-    TRT_HIP(grow_device(b->d_descs, b->cap_descs, n));
-    TRT_HIP(grow_device(b->d_items, b->cap_items, nitems));
+    TRT_HIP(grow_pinned(sg.descs, sg.cap_descs, n, b->retired_host));
+    TRT_HIP(grow_pinned(sg.items, sg.cap_items, nitems, b->retired_host));
+    TRT_HIP(grow_device(b->d_descs, b->cap_descs, n, b->retired_dev));
+    TRT_HIP(grow_device(b->d_items, b->cap_items, nitems, b->retired_dev));
     size_t j = 0;
     for (size_t k = 0; k < n; ++k) {
-        b->h_descs[k] = descs[k];
+        sg.descs[k] = descs[k];
         for (int r = 0; r < descs[k].rowblocks; ++r)
-            for (int c = 0; c < descs[k].strips; ++c) b->h_items[j++] = make_int4((int)k, c, r, 0);
+            for (int c = 0; c < descs[k].strips; ++c) sg.items[j++] = make_int4((int)k, c, r, 0);
     }
-    TRT_HIP(hipMemcpyAsync(b->d_descs, b->h_descs, n * sizeof(InstDesc), hipMemcpyHostToDevice,
+    TRT_HIP(hipMemcpyAsync(b->d_descs, sg.descs, n * sizeof(InstDesc), hipMemcpyHostToDevice,
                            b->stream));
-    TRT_HIP(hipMemcpyAsync(b->d_items, b->h_items, nitems * sizeof(int4), hipMemcpyHostToDevice,
+    TRT_HIP(hipMemcpyAsync(b->d_items, sg.items, nitems * sizeof(int4), hipMemcpyHostToDevice,
                            b->stream));
-    TRT_HIP(hipEventRecord(b->staged, b->stream));
-    b->staged_pending = true;
+    TRT_HIP(hipEventRecord(sg.done, b->stream));
+    sg.pending = true;
     b->nitems = (int)nitems;
     b->parity = 0;
     release_graph(b->pair);
@@ -575,7 +594,8 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     b->stream = sims[0]->stream;
     b->launch = kDefaultLaunch;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    for (auto &sg : b->stage)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         trt_batch_destroy(b);
         return fail_hip(e, "batch stream/event");
@@ -667,13 +687,17 @@ void trt_batch_destroy(trt_batch *b) {
     if (!b) return;
     for (trt_sim *s : b->sims) s->in_batch = false;
     release_graph(b->pair);
-    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
-    if (b->staged) (void)hipEventDestroy(b->staged);
+    for (auto &sg : b->stage) {
+        if (sg.pending) (void)hipEventSynchronize(sg.done);
+        if (sg.done) (void)hipEventDestroy(sg.done);
+        if (sg.descs) (void)hipHostFree(sg.descs);
+        if (sg.items) (void)hipHostFree(sg.items);
+    }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->d_descs) (void)hipFree(b->d_descs);
     if (b->d_items) (void)hipFree(b->d_items);
-    if (b->h_descs) (void)hipHostFree(b->h_descs);
-    if (b->h_items) (void)hipHostFree(b->h_items);
+    for (void *p : b->retired_dev) (void)hipFree(p);
+    for (void *p : b->retired_host) (void)hipHostFree(p);
     delete b;
 }
 

@@ -19,7 +19,7 @@ from . import params
 
 
 def taylor_green(n: int, u0: float = 0.01, rho0: float = 1.0, *, nu: float = 0.0,
-                 t: float = 0.0, seed: int | None = 0, phase=None):
+                 t: float = 0.0, seed: int | None = 0, phase=None, device=None):
     """Decaying Taylor-Green vortex on an n x n periodic lattice (Sec. III.B).
 
     u_x = -u0 cos(2 pi x) sin(2 pi y) e^{-t/t_d},
@@ -29,7 +29,10 @@ def taylor_green(n: int, u0: float = 0.01, rho0: float = 1.0, *, nu: float = 0.0
     in units of the domain side (nu here is the lattice viscosity, so
     t_d = n^2 / (8 nu pi^2) steps).  The phase (phi_x, phi_y) is drawn from
     ``seed`` in [0, n)^2 unless given; seed=None means no phase.
-    Returns (rho, ux, uy), float64 [n, n], indexed [y, x].
+    Returns (rho, ux, uy), float64 [n, n], indexed [y, x]: numpy arrays, or
+    torch tensors on `device` when one is given (the per-axis factors are
+    formed on the host and the n x n products and sums on the device, in the
+    same order, so the values are the same bits).
     """
     if phase is None:
         phase = (0.0, 0.0) if seed is None else tuple(np.random.default_rng(seed).uniform(0, n, 2))
@@ -42,10 +45,27 @@ def taylor_green(n: int, u0: float = 0.01, rho0: float = 1.0, *, nu: float = 0.0
         decay = math.exp(-t / td)
     else:
         decay = 1.0
+    coef = rho0 * u0 ** 2 / (4.0 * params.CS2)
+    if device is not None:
+        import torch
+
+        def dev(a):
+            # pinned and asynchronous on the current stream: a pageable copy
+            # would wait for the work already queued there
+            h = torch.from_numpy(np.ascontiguousarray(a))
+            if torch.device(device).type == "cuda":
+                h = h.pin_memory()
+            return h.to(device, non_blocking=True)
+        ax, sy = dev(-u0 * np.cos(2 * np.pi * x)), dev(np.sin(2 * np.pi * y))
+        ay, sx = dev(u0 * np.cos(2 * np.pi * y)), dev(np.sin(2 * np.pi * x))
+        cx4, cy4 = dev(np.cos(4 * np.pi * x)), dev(np.cos(4 * np.pi * y))
+        ux = (ax * sy * decay).contiguous()
+        uy = (ay * sx * decay).contiguous()
+        rho = (rho0 - coef * (cx4 + cy4) * decay ** 2).contiguous()
+        return rho, ux, uy
     ux = -u0 * np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y) * decay
     uy = u0 * np.cos(2 * np.pi * y) * np.sin(2 * np.pi * x) * decay
-    rho = rho0 - rho0 * u0 ** 2 / (4.0 * params.CS2) * (
-        np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) * decay ** 2
+    rho = rho0 - coef * (np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) * decay ** 2
     return (np.ascontiguousarray(rho), np.ascontiguousarray(np.broadcast_to(ux, (n, n))),
             np.ascontiguousarray(np.broadcast_to(uy, (n, n))))
 
@@ -94,8 +114,13 @@ def cylinder_channel_mask(nx: int = 400, ny: int = 200, side: int = 20) -> np.nd
     return m
 
 
-def rest_state(ny: int, nx: int, rho0: float = 1.0):
-    """Uniform fluid at rest."""
+def rest_state(ny: int, nx: int, rho0: float = 1.0, device=None):
+    """Uniform fluid at rest (numpy arrays, or torch tensors on `device`)."""
+    if device is not None:
+        import torch
+        return (torch.full((ny, nx), rho0, dtype=torch.float64, device=device),
+                torch.zeros((ny, nx), dtype=torch.float64, device=device),
+                torch.zeros((ny, nx), dtype=torch.float64, device=device))
     return np.full((ny, nx), rho0), np.zeros((ny, nx)), np.zeros((ny, nx))
 
 

@@ -82,10 +82,15 @@ class Lattice:
     # ---------------------------------------------------------------- helpers
     def _dev64(self, a, shape):
         """A device FP64 copy of `a` (numpy arrays go through pinned memory
-        and an asynchronous copy on the lattice's stream)."""
+        and an asynchronous copy on the lattice's stream; a tensor made on
+        the current stream is ordered before the lattice stream's use)."""
         torch = _torch()
         if torch.is_tensor(a):
             t = a.to(device=self.device, dtype=torch.float64).contiguous()
+            cur = torch.cuda.current_stream(self.device)
+            if cur != self.stream:
+                self.stream.wait_stream(cur)
+                t.record_stream(self.stream)
         else:
             h = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
             if tuple(h.shape) != tuple(shape):

@@ -48,7 +48,9 @@ class Request:
     steps: int
     g: tuple = (0.0, 0.0)
     mask: Optional[np.ndarray] = None
-    fields: Optional[Callable[[], tuple]] = None   # -> (rho, ux, uy), float64 [ny, nx]
+    # (rho, ux, uy), float64 [ny, nx]: fields(device=None) may return numpy
+    # arrays, or tensors on the device the GPU executor passes
+    fields: Optional[Callable[..., tuple]] = None
     arrival: float = 0.0      # seconds since the start of the run
     meta: dict = dataclasses.field(default_factory=dict)
     tol: Optional[float] = None   # end when the velocity change per check is below tol
@@ -248,7 +250,6 @@ class GpuExecutor:
         self._members = [[], []]
         self._events = collections.deque()
         self._graveyard = []
-        self._rest = {}   # rest-state fields by lattice shape
 
     def footprint(self, req: Request) -> int:
         from .lattice import footprint_bytes
@@ -259,12 +260,9 @@ class GpuExecutor:
         lat = Lattice(req.nx, req.ny, req.tau1, req.tau2, g=req.g, mask=req.mask,
                       storage=self.storage, stream=self.stream)
         if req.fields:
-            rho, ux, uy = req.fields()
+            rho, ux, uy = req.fields(device=lat.device)
         else:
-            key = (req.ny, req.nx)
-            if key not in self._rest:
-                self._rest[key] = inputs.rest_state(req.ny, req.nx)
-            rho, ux, uy = self._rest[key]
+            rho, ux, uy = inputs.rest_state(req.ny, req.nx, device=lat.device)
         lat.init_equilibrium(rho, ux, uy, sync=False)
         lat._prev_u = None
         if req.tol is not None:
@@ -421,7 +419,8 @@ def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
                 tau2 = params.tau2_from_magic(tau1, 0.25)
                 seed_k = rid
                 req = Request(rid, kind, n, n, tau1, tau2, steps[kind], (0.0, 0.0), None,
-                              (lambda n=n, s=seed_k: inputs.taylor_green(n, 0.01, seed=s)), t, {})
+                              (lambda device=None, n=n, s=seed_k:
+                               inputs.taylor_green(n, 0.01, seed=s, device=device)), t, {})
         req.meta["nodes"] = req.nx * req.ny
         out.append(req)
         rid += 1

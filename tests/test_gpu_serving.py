@@ -40,8 +40,10 @@ def _requests():
                         inputs.channel_mask(n, n - 2), None, t)
         else:
             n = int(rng.integers(64, 200))
+            # served: fields built on the device; alone: numpy (the same bits)
             r = Request(k, kind, n, n, 0.6, 3.0, 120 + 31 * k, (0.0, 0.0), None,
-                        (lambda n=n, s=k: inputs.taylor_green(n, 0.01, seed=s)), t)
+                        (lambda device=None, n=n, s=k:
+                         inputs.taylor_green(n, 0.01, seed=s, device=device)), t)
         reqs.append(r)
     return reqs
 
@@ -112,3 +114,15 @@ def test_converged_requests_equal_results_alone(L):
         lat.close()
         for a, b in zip(alone, r.fields):
             assert np.array_equal(a, b)
+
+
+def test_device_taylor_green_fields_equal_host_fields(L):
+    """The serving workload builds Taylor-Green fields on the GPU; they are
+    the host generator's values bit for bit."""
+    import torch
+    for n, kw in ((64, {}), (2048, {"seed": 7}), (129, {"nu": 0.02, "t": 50.0, "seed": 3})):
+        host = inputs.taylor_green(n, 0.01, **kw)
+        dev = inputs.taylor_green(n, 0.01, device="cuda", **kw)
+        for h, d in zip(host, dev):
+            assert d.is_cuda and d.dtype == torch.float64 and d.is_contiguous()
+            assert np.array_equal(h, d.cpu().numpy())

@@ -164,8 +164,9 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
 
 def run_extra(steps):
     """Companion measurements: the same lattice in FP16 and FP64 storage,
-    the batched workload, the serving stream (FP16 and FP32) and the
-    double-shear-layer stability study."""
+    the batched workload, the serving stream (FP16 and FP32), the
+    double-shear-layer stability study and the Taylor-Green convergence
+    study."""
     out = {}
     for storage in ("f16", "f64"):
         lat = tg_lattice(4096, storage)
@@ -183,6 +184,8 @@ def run_extra(steps):
         log("extra serving %s: %s" % (storage, out["serving_" + storage]))
     out["dsl_critical_mach_f64"] = run_stability()
     log("extra stability study: %s" % out["dsl_critical_mach_f64"])
+    out["tg_convergence_f64"] = run_convergence()
+    log("extra convergence study: %s" % out["tg_convergence_f64"])
     return out
 
 
@@ -195,6 +198,19 @@ def run_stability():
                                   [round(0.1 * k, 1) for k in range(1, 21)], storage="f64")
     return {"cases": len(res["cases"]), "rounds": res["rounds"], "seconds": res["seconds"],
             "per_re": {"%g" % k: v for k, v in stability.summary(res).items()}}
+
+
+def run_convergence():
+    """Taylor-Green grid convergence of Sec. III.B (N = 32 ... 512, FP64):
+    L2 error at t_d and the orders, TRT-RLB and RLB."""
+    from paper_2312_10318_amd import convergence
+    out = {}
+    for rlb in (False, True):
+        r = convergence.run(convergence.PAPER_NS, "f64", rlb=rlb)
+        out[r["model"]] = {"l2": [float("%.4e" % e) for e in r["l2"]],
+                           "order": [round(o, 3) for o in r["order"]], "seconds": r["seconds"]}
+    out["n"] = list(convergence.PAPER_NS)
+    return out
 
 
 def creeping_lattice(storage, tuning=None):

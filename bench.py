@@ -165,8 +165,8 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
 def run_extra(steps):
     """Companion measurements: the same lattice in FP16 and FP64 storage,
     the batched workload, the serving stream (FP16 and FP32), the
-    double-shear-layer stability study and the Taylor-Green convergence
-    study."""
+    double-shear-layer stability study, the Taylor-Green convergence study
+    and the Poiseuille slip study."""
     out = {}
     for storage in ("f16", "f64"):
         lat = tg_lattice(4096, storage)
@@ -186,6 +186,8 @@ def run_extra(steps):
     log("extra stability study: %s" % out["dsl_critical_mach_f64"])
     out["tg_convergence_f64"] = run_convergence()
     log("extra convergence study: %s" % out["tg_convergence_f64"])
+    out["poiseuille_slip_f64"] = run_poiseuille()
+    log("extra Poiseuille slip study: %s" % out["poiseuille_slip_f64"])
     return out
 
 
@@ -198,6 +200,16 @@ def run_stability():
                                   [round(0.1 * k, 1) for k in range(1, 21)], storage="f64")
     return {"cases": len(res["cases"]), "rounds": res["rounds"], "seconds": res["seconds"],
             "per_re": {"%g" % k: v for k, v in stability.summary(res).items()}}
+
+
+def run_poiseuille():
+    """Poiseuille slip against Lambda_s, the set-up of Sec. III.C (4 x 32,
+    u_c = 0.1, Re = 1): steady relative L2 error per Lambda_s and for RLB."""
+    from paper_2312_10318_amd import poiseuille
+    res = poiseuille.sweep()
+    return {"l2": {("RLB" if r["model"] == "RLB" else "%.5g" % r["lambda"]): float("%.4e" % r["l2"])
+                   for r in res},
+            "seconds": res[-1]["seconds"]}
 
 
 def run_convergence():

@@ -134,8 +134,9 @@ typedef struct trt_batch trt_batch;
  *   [7] time steps taken since creation or the last trt_set_populations */
 #define TRT_NDIAG 8
 
-/* Row pitch in elements: nx rounded up so each row is a multiple of 256 B.
- * Returns -1 for an invalid size or storage. */
+/* Elements of one population row: nx rounded up so each population row is
+ * a multiple of 256 B (the nine population rows of a lattice row follow one
+ * another; see trt_row_stride).  Returns -1 for an invalid size or storage. */
 int32_t trt_pitch(int32_t nx, int32_t storage);
 
 /* Elements between lattice rows y and y+1 of a population lattice (nine

@@ -92,8 +92,7 @@ bool buffer_addressable(const InstDesc &d, int storage);
 // items: device int4[nitems] of (instance, strip, rowblock, 0); the lattice
 // read by instance k is buf[descs[k].cur ^ flip].  `buf` may be true only if
 // every instance is buffer_addressable; instances with descs[k].cols == 2
-// are swept with two-column strips (only in a batch without obstacles with
-// `buf` true).
+// (tiled so only where pair_eligible) are swept with two-column strips.
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);

@@ -334,44 +334,6 @@ struct LinkAccess {
 
 constexpr int kOppDir[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-// Half-way bounce-back from the link bits: every direction i whose pull
-// source is solid (bit i of lk) takes the node's own slot opp(i) instead.
-// The own slots are loaded only for directions some lane of the wavefront
-// needs (a wave-uniform test), so rows away from walls cost nothing.  v[]
-// holds the pulled values; own(i) loads slot opp(i) of the node itself.
-template <class V, class Own>
-__device__ __forceinline__ void bounce_back(V v[9], uint32_t lk, const Own &own) {
-    // issue every needed load first, then select: one memory round trip
-    V o[9];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        o[i] = v[i];
-        if (__builtin_amdgcn_ballot_w64((lk >> i) & 1u) != 0) o[i] = own(kOppDir[i]);
-    }
-#pragma unroll
-    for (int i = 1; i < 9; ++i) v[i] = ((lk >> i) & 1u) ? o[i] : v[i];
-}
-
-// Pull-gather for a lattice without solid nodes.  ym, y, yp are the wrapped
-// rows, om, oc, op the byte offsets of the wrapped columns x-1, x, x+1.
-template <class T, class C>
-__device__ __forceinline__ void gather_open(const T *__restrict__ src, int64_t plane, int pitch,
-                                            int ym, int y, int yp, uint32_t om, uint32_t oc,
-                                            uint32_t op, C f[9]) {
-    const T *r0 = src + (int64_t)y * pitch;
-    const T *rm = src + (int64_t)ym * pitch;
-    const T *rp = src + (int64_t)yp * pitch;
-    f[0] = to_c(ld_at(r0, oc));
-    f[1] = to_c(ld_at(r0 + plane, om));
-    f[2] = to_c(ld_at(rm + 2 * plane, oc));
-    f[3] = to_c(ld_at(r0 + 3 * plane, op));
-    f[4] = to_c(ld_at(rp + 4 * plane, oc));
-    f[5] = to_c(ld_at(rm + 5 * plane, om));
-    f[6] = to_c(ld_at(rm + 6 * plane, op));
-    f[7] = to_c(ld_at(rp + 7 * plane, op));
-    f[8] = to_c(ld_at(rp + 8 * plane, om));
-}
-
 template <class T>
 __device__ __forceinline__ void open_x_sources(const T *a[9], const T *r0, int64_t plane, int xc,
                                                int nx);

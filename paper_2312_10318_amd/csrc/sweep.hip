@@ -338,8 +338,9 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
 // x-streamed populations take the missing neighbour element from the
 // adjacent lane with a DPP whole-wave shift; the strip's two edge lanes
 // supply the elements beyond the strip (and the two halo columns' Phi_x)
-// through DPP's "old" operand.  Used for lattices without obstacles with
-// even nx that fit one buffer resource.
+// through DPP's "old" operand.  Used for every lattice with even nx that
+// fits one buffer resource (obstacles and open boundaries through the link
+// map).
 
 constexpr int kStripWidth2 = 128;
 

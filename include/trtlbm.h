@@ -25,8 +25,9 @@
  *    (reduction partials, batch tables), HIP graphs and, for a simulation
  *    with a mask or open x boundaries, a link map of two bytes per node
  *    (derived from the mask at creation: per node, whether it is solid and
- *    which of its pull sources are solid), all freed by the matching
- *    destroy call and counted by trt_footprint_bytes.
+ *    which of its pull sources are solid) with a summary of four bytes per
+ *    row and 64 columns, all freed by the matching destroy call and counted
+ *    by trt_footprint_bytes.
  *  - Population lattices are device buffers of trt_lattice_bytes() bytes,
  *    256-byte aligned, laid out row-interleaved as [y][i][x]: the nine
  *    population rows of lattice row y follow one another, each

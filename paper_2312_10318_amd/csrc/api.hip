@@ -226,8 +226,18 @@ size_t trt_lattice_bytes(const trt_problem *p) {
 namespace {
 // elements of a link-map row: nx rounded up to 256 bytes
 int64_t link_pitch(int32_t nx) { return ((int64_t)nx + 127) / 128 * 128; }
+// entries of a link-summary row: two per 128-column strip
+int32_t summary_count(int32_t nx) { return 2 * ((nx + 127) / 128); }
 bool needs_links(const trt_problem *p) {
     return p->mask != nullptr || p->x_boundary == TRT_X_INFLOW_OUTFLOW;
+}
+// one allocation: the link map, then (256-byte aligned) the link summary
+size_t link_map_bytes(int32_t nx) { return 2 * (size_t)link_pitch(nx); }  // per row
+size_t summary_offset(int32_t nx, int32_t ny) {
+    return (link_map_bytes(nx) * (size_t)ny + 255) / 256 * 256;
+}
+size_t link_alloc_bytes(int32_t nx, int32_t ny) {
+    return summary_offset(nx, ny) + 4 * (size_t)summary_count(nx) * (size_t)ny;
 }
 }  // namespace
 
@@ -235,7 +245,7 @@ size_t trt_footprint_bytes(const trt_problem *p) {
     const size_t lat = trt_lattice_bytes(p);
     if (lat == 0) return 0;
     const size_t mask = p->mask ? (size_t)p->nx * p->ny : 0;
-    const size_t links = needs_links(p) ? 2 * (size_t)link_pitch(p->nx) * p->ny : 0;
+    const size_t links = needs_links(p) ? link_alloc_bytes(p->nx, p->ny) : 0;
     const size_t scratch = (size_t)(trt::diag_partial_count() + 1) * TRT_NDIAG * sizeof(double);
     return 2 * lat + mask + links + scratch;
 }
@@ -282,6 +292,9 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     d.rho_out = d.xbc ? p->rho_out : 1.0;
     d.links = nullptr;
     d.lpitch = link_pitch(p->nx);
+    d.rowsum = nullptr;
+    d.nsum = summary_count(p->nx);
+    d.pad3_ = 0;
 
     hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
                                                       TRT_NDIAG * sizeof(double));
@@ -290,9 +303,11 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
         return fail_hip(e, "hipMalloc(scratch)");
     }
     if (needs_links(p)) {
-        e = hipMalloc((void **)&s->links, 2 * (size_t)d.lpitch * (size_t)p->ny);
+        e = hipMalloc((void **)&s->links, link_alloc_bytes(p->nx, p->ny));
         if (e == hipSuccess) {
             d.links = s->links;
+            d.rowsum = reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const char *>(s->links) + summary_offset(p->nx, p->ny));
             e = trt::launch_link_map(d, s->stream);
         }
         if (e != hipSuccess) {

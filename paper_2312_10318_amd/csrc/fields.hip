@@ -390,6 +390,19 @@ __global__ void link_map_kernel(InstDesc d, uint16_t *__restrict__ links) {
     links[(int64_t)y * d.lpitch + x] = (uint16_t)b;
 }
 
+// Link summary: entry (y, s) is the OR of the codes of row y over columns
+// 64 s - 1 ... 64 s + 64, wrapped (entries past the lattice's width cover
+// wrapped columns, as the sweep's lanes past the width do).
+__global__ void link_summary_kernel(InstDesc d, const uint16_t *__restrict__ links,
+                                    uint32_t *__restrict__ sum) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (s >= d.nsum || y >= d.ny) return;
+    uint32_t acc = 0u;
+    for (int k = -1; k <= 64; ++k) acc |= links[(int64_t)y * d.lpitch + wrapi(64 * s + k, d.nx)];
+    sum[(int64_t)y * d.nsum + s] = acc;
+}
+
 dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4); }
 
 #define TRT_DISPATCH(storage, CALL)                 \
@@ -404,6 +417,10 @@ dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4
 
 hipError_t launch_link_map(const InstDesc &d, hipStream_t stream) {
     link_map_kernel<<<node_grid(d), dim3(64, 4), 0, stream>>>(d, const_cast<uint16_t *>(d.links));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    link_summary_kernel<<<dim3((d.nsum + 63) / 64, d.ny), 64, 0, stream>>>(
+        d, d.links, const_cast<uint32_t *>(d.rowsum));
     return hipGetLastError();
 }
 

@@ -99,7 +99,8 @@ hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nite
 
 // Link map of an instance with a mask or open x boundaries: d.links (device,
 // ny * d.lpitch 16-bit codes) receives, per node, bit 0 = solid and bit i
-// (1..8) = the pull source x - e_i is solid or beyond the inflow wall.
+// (1..8) = the pull source x - e_i is solid or beyond the inflow wall; then
+// d.rowsum receives the link summary (see InstDesc).
 hipError_t launch_link_map(const InstDesc &d, hipStream_t stream);
 
 // Pre-collision state <-> device FP64 [9][ny][nx]; f^eq initialisation.

@@ -71,6 +71,13 @@ struct InstDesc {
     // back from the node's own slot opp(i) (half-way bounce-back)
     const uint16_t *links;
     int64_t lpitch;  // elements
+    // link summary [ny][nsum] (with the link map): for row y and 64-column
+    // strip s, the OR of the codes of columns 64 s - 1 ... 64 s + 64 (the
+    // strip and the column on either side, wrapped); 0 means the strip's
+    // pulls and halo need no link step in that row.  nsum is even, so a
+    // 128-column strip k reads entries 2k and 2k + 1.
+    const uint32_t *rowsum;
+    int32_t nsum, pad3_;
     // population lattice layout [y][i][x]: f_i of node (x, y) is element
     // y * pitch + i * plane + x
     int64_t plane;        // elements between populations i and i+1 of a node
@@ -333,6 +340,25 @@ struct LinkAccess {
 };
 
 constexpr int kOppDir[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// The link summary of a row, read with scalar loads (row and strip are
+// wave-uniform), so deciding whether a row needs its link codes and own-slot
+// loads never waits on vector memory.
+struct RowSum {
+    const __attribute__((address_space(4))) uint32_t *p;
+    int nsum;
+    __device__ __forceinline__ RowSum(const uint32_t *q, int n)
+        : p((const __attribute__((address_space(4))) uint32_t *)q), nsum(n) {}
+    // 64-column strip s of row y
+    __device__ __forceinline__ uint32_t one(int y, int s) const {
+        return p[(int64_t)y * nsum + s];
+    }
+    // 128-column strip k of row y (64-column strips 2k and 2k + 1)
+    __device__ __forceinline__ uint32_t two(int y, int k) const {
+        const int64_t i = (int64_t)y * nsum + 2 * k;
+        return p[i] | p[i + 1];
+    }
+};
 
 template <class T>
 __device__ __forceinline__ void open_x_sources(const T *a[9], const T *r0, int64_t plane, int xc,

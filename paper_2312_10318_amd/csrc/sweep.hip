@@ -83,7 +83,7 @@ template <class T> struct Raw {
 template <class T, class Acc>
 __device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, int64_t plane, int pitch,
                                            int ny, int y, const Column &col, bool linked,
-                                           uint32_t lk) {
+                                           uint32_t lk, uint32_t own) {
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     r.solid = false;
@@ -98,11 +98,10 @@ __device__ __forceinline__ void gather_raw(Raw<T> &r, const Acc &in, int64_t pla
     r.v[6] = in.ld(6 * plane + em, col.op);
     r.v[7] = in.ld(7 * plane + ep, col.op);
     r.v[8] = in.ld(8 * plane + ep, col.om);
-    if (linked && __builtin_amdgcn_ballot_w64((lk & 0xfffeu) != 0) != 0) {
+    if (linked && (own & 0xfffeu) != 0u) {
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-            if (__builtin_amdgcn_ballot_w64((lk >> i) & 1u) != 0)
-                r.own[i] = in.ld(kOppDir[i] * plane + e0, col.oc);
+            if ((own >> i) & 1u) r.own[i] = in.ld(kOppDir[i] * plane + e0, col.oc);
     }
 }
 
@@ -248,15 +247,20 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     // collision is formed.  Phi_y of row y-1 is kept as a scalar.
     // link codes (0 without a link map): rows y0 - 1 and y0 now, row y0 + 1
     // one row ahead, and so on (for the halo column of the edge lanes too)
-    const auto code = [&](int row, const Column &c) -> uint32_t {
-        return linked ? la.ld1((uint32_t)((int64_t)row * lp), (uint32_t)c.xc) : 0u;
+    // the strip's link summary of a row (scalar; 0: no link step), and a
+    // node's code, read only in rows whose summary is not 0
+    const RowSum rsum(d.rowsum, d.nsum);
+    const auto summary = [&](int row) -> uint32_t { return linked ? rsum.one(row, strip) : 0u; };
+    const auto code = [&](int row, const Column &c, uint32_t rs) -> uint32_t {
+        return (linked && rs != 0u) ? la.ld1((uint32_t)((int64_t)row * lp), (uint32_t)c.xc) : 0u;
     };
     const int ym0 = (y0 + ny - 1) % ny, yp0 = (y0 + 1) % ny;
     C phiy_below;
     {
         Raw<T> t;
         RowState<C, SH> w;
-        gather_raw<T>(t, in, plane, pitch, ny, ym0, col, linked, code(ym0, col));
+        const uint32_t rs = summary(ym0);
+        gather_raw<T>(t, in, plane, pitch, ny, ym0, col, linked, code(ym0, col, rs), rs);
         if (linked) link_fix(t);
         widen<T, C, SH>(w, t, gx, gy, ox, col.xc);
         phiy_below = w.phiy;
@@ -265,29 +269,30 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
     C hphix = C(0);
     {
         Raw<T> t;
-        gather_raw<T>(t, in, plane, pitch, ny, y0, col, linked, code(y0, col));
+        const uint32_t rs = summary(y0);
+        gather_raw<T>(t, in, plane, pitch, ny, y0, col, linked, code(y0, col, rs), rs);
         if (linked) link_fix(t);
         widen<T, C, SH>(cur, t, gx, gy, ox, col.xc);
         if (edge) {
             Raw<T> h;
-            gather_raw<T>(h, in, plane, pitch, ny, y0, hcol, linked, code(y0, hcol));
+            gather_raw<T>(h, in, plane, pitch, ny, y0, hcol, linked, code(y0, hcol, rs), rs);
             if (linked) link_fix(h);
             hphix = halo_phix<T, C, SH>(h, gx, ox, hcol.xc);
         }
     }
-    uint32_t lk_next = code(yp0, col);
-    uint32_t hlk_next = edge ? code(yp0, hcol) : 0u;
+    // link summaries are read one row ahead of the gather they gate; codes
+    // with the row's populations (needed only where those are)
+    uint32_t rs_next = summary(yp0);
 
     for (int y = y0; y < y1; ++y) {
         // row y+1: its Phi_y is needed now, its state in the next iteration
         const int yn = (y + 1 == ny) ? 0 : y + 1;
         Raw<T> nraw, nhalo;
-        gather_raw<T>(nraw, in, plane, pitch, ny, yn, col, linked, lk_next);
-        if (edge) gather_raw<T>(nhalo, in, plane, pitch, ny, yn, hcol, linked, hlk_next);
-        // the link codes of row y+2, for the next iteration's gather
-        const int ynn = (yn + 1 == ny) ? 0 : yn + 1;
-        lk_next = code(ynn, col);
-        hlk_next = edge ? code(ynn, hcol) : 0u;
+        gather_raw<T>(nraw, in, plane, pitch, ny, yn, col, linked, code(yn, col, rs_next), rs_next);
+        if (edge)
+            gather_raw<T>(nhalo, in, plane, pitch, ny, yn, hcol, linked, code(yn, hcol, rs_next),
+                          rs_next);
+        rs_next = summary((yn + 1 == ny) ? 0 : yn + 1);
 
         // row y: everything of the collision except the y-gradient of Phi
         // x-neighbours' Phi_x from the adjacent lanes (lanes 0 and 63: the
@@ -420,6 +425,7 @@ template <class T> struct PairRow {
     T edge[3];
     Raw<T> halo;
     uint32_t lk;
+    uint32_t rs;  // the row's link summary for this strip (wave-uniform)
 };
 
 // Where a lane's pair lives and how to reach its own slots.
@@ -439,10 +445,10 @@ template <class T> struct PairCtx {
 
 // The link codes of row y: the pair's (ld2) and the edge lane's halo node.
 template <class T>
-__device__ __forceinline__ void pair_codes(const PairCtx<T> &c, int y, uint32_t &lk,
+__device__ __forceinline__ void pair_codes(const PairCtx<T> &c, int y, uint32_t rs, uint32_t &lk,
                                            uint32_t &hlk) {
     lk = hlk = 0u;
-    if (c.linked) {
+    if (c.linked && rs != 0u) {
         const uint32_t ro = (uint32_t)((int64_t)y * c.lpitch);
         lk = c.la.ld2(ro, c.ca);
         if (c.edge) hlk = c.la.ld1(ro, (uint32_t)c.hcol.xc);
@@ -454,13 +460,19 @@ __device__ __forceinline__ void pair_codes(const PairCtx<T> &c, int y, uint32_t 
 // loads of bounce-back directions are issued together with the pulls.
 template <class T, bool HALO>
 __device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> &c, int y,
-                                                uint32_t lk, uint32_t hlk) {
+                                                uint32_t rs) {
+    // the row's link codes are loaded with its populations, straight into the
+    // row (rows whose summary is 0 load none): they are needed only where the
+    // populations are, so they add no earlier wait
+    uint32_t lk, hlk;
+    pair_codes(c, y, rs, lk, hlk);
     const int ym = (y == 0) ? c.ny - 1 : y - 1;
     const int yp = (y == c.ny - 1) ? 0 : y + 1;
     const int64_t e0 = (int64_t)y * c.pitch, em = (int64_t)ym * c.pitch,
                   ep = (int64_t)yp * c.pitch;
     const int64_t plane = c.plane;
     r.lk = lk;
+    r.rs = rs;
     r.w[0] = PairIO<T>::ld(c.in, e0, c.opair);
     r.w[1] = PairIO<T>::ld(c.in, plane + e0, c.opair);
     r.w[2] = PairIO<T>::ld(c.in, 2 * plane + em, c.opair);
@@ -470,12 +482,10 @@ __device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> 
     r.w[6] = PairIO<T>::ld(c.in, 6 * plane + em, c.opair);
     r.w[7] = PairIO<T>::ld(c.in, 7 * plane + ep, c.opair);
     r.w[8] = PairIO<T>::ld(c.in, 8 * plane + ep, c.opair);
-    const uint32_t both = (lk | (lk >> 16)) & 0xfffeu;
-    if (c.linked && __builtin_amdgcn_ballot_w64(both != 0) != 0) {
+    if (c.linked && (rs & 0xfffeu) != 0u) {
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-            if (__builtin_amdgcn_ballot_w64((both >> i) & 1u) != 0)
-                r.own[i] = PairIO<T>::ld(c.in, kOppDir[i] * plane + e0, c.opair);
+            if ((rs >> i) & 1u) r.own[i] = PairIO<T>::ld(c.in, kOppDir[i] * plane + e0, c.opair);
     }
     r.edge[0] = r.edge[1] = r.edge[2] = T(0);
     if (c.edge) {
@@ -484,7 +494,7 @@ __device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> 
         r.edge[0] = c.in.ld(e0, c.ve[0]);
         r.edge[1] = c.in.ld(em, c.ve[1]);
         r.edge[2] = c.in.ld(ep, c.ve[2]);
-        if (HALO) gather_raw<T>(r.halo, c.in, plane, c.pitch, c.ny, y, c.hcol, c.linked, hlk);
+        if (HALO) gather_raw<T>(r.halo, c.in, plane, c.pitch, c.ny, y, c.hcol, c.linked, hlk, rs);
     }
 }
 
@@ -520,15 +530,19 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     fa[6] = pb[6]; fb[6] = dpp_shl(h1, pa[6]);
     fa[7] = pb[7]; fb[7] = dpp_shl(h2, pa[7]);
     a.solid = b.solid = false;
-    if (c.linked && __builtin_amdgcn_ballot_w64(r.lk != 0) != 0) {
+    if (c.linked && r.rs != 0u) {
         // only rows that touch a wall or an obstacle pay for the link codes
         const uint32_t la_ = r.lk & 0xffffu, lb_ = r.lk >> 16;
-        const uint32_t both = (la_ | lb_) & 0xfffeu;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            if (__builtin_amdgcn_ballot_w64((both >> i) & 1u) != 0) {
+            if ((r.rs >> i) & 1u) {
+                // used here, after the row's wait: left free, the compiler
+                // merges this select into the load's branch (same condition)
+                // and waits for the row there
+                typename PairIO<T>::W o = r.own[i];
+                asm volatile("" : "+v"(o));
                 C oa, ob;
-                PairIO<T>::split(r.own[i], oa, ob);
+                PairIO<T>::split(o, oa, ob);
                 fa[i] = ((la_ >> i) & 1u) ? oa : fa[i];
                 fb[i] = ((lb_ >> i) & 1u) ? ob : fb[i];
             }
@@ -603,14 +617,16 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     const int y0 = rb * d.rows;
     const int y1 = min(y0 + d.rows, ny);
 
+    // the strip's link summary of a row (scalar; 0: no link step)
+    const RowSum rsum(d.rowsum, d.nsum);
+    const auto summary = [&](int row) -> uint32_t { return linked ? rsum.two(row, strip) : 0u; };
+
     C phiy_below_a, phiy_below_b;
-    uint32_t lk, hlk;
     {
         PairRow<T> t;
         RowState<C, SH> a, b;
         const int ym0 = (y0 + ny - 1) % ny;
-        pair_codes(cx, ym0, lk, hlk);
-        gather_pair_row<T, false>(t, cx, ym0, lk, hlk);
+        gather_pair_row<T, false>(t, cx, ym0, summary(ym0));
         widen_pair<T, C, SH>(a, b, t, cx, gx, gy, ox);
         phiy_below_a = a.phiy;
         phiy_below_b = b.phiy;
@@ -619,19 +635,18 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     C hphix = C(0);
     {
         PairRow<T> t;
-        pair_codes(cx, y0, lk, hlk);
-        gather_pair_row<T, true>(t, cx, y0, lk, hlk);
+        gather_pair_row<T, true>(t, cx, y0, summary(y0));
         widen_pair<T, C, SH>(ca_, cb_, t, cx, gx, gy, ox);
         if (edge) hphix = pair_halo_phix<T, C, SH>(t.halo, cx, gx, ox);
     }
-    // link codes of the next row to gather, read one row ahead
-    pair_codes(cx, (y0 + 1) % ny, lk, hlk);
+    // link summaries are read one row ahead of the gather they gate
+    uint32_t rs_next = summary((y0 + 1) % ny);
 
     for (int y = y0; y < y1; ++y) {
         const int yn = (y + 1 == ny) ? 0 : y + 1;
         PairRow<T> nr;
-        gather_pair_row<T, true>(nr, cx, yn, lk, hlk);
-        pair_codes(cx, (yn + 1 == ny) ? 0 : yn + 1, lk, hlk);
+        gather_pair_row<T, true>(nr, cx, yn, rs_next);
+        rs_next = summary((yn + 1 == ny) ? 0 : yn + 1);
 
         // row y: both nodes' coefficients except the y-gradient of Phi
         C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A

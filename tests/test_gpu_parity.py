@@ -99,6 +99,41 @@ def test_random_state_walls_force_fp64(L, shape, tiling):
     lat.close()
 
 
+@pytest.mark.parametrize("cols", [1, 2])
+@pytest.mark.parametrize("nx,xs", [
+    (260, (1, 62, 63, 64, 65, 126, 127, 128, 129, 191, 192, 255, 259)),
+    (193, (0, 1, 62, 63, 64, 65, 128, 191, 192)),
+    (130, (0, 1, 62, 65, 126, 127, 128, 129))])
+def test_link_summary_at_strip_edges(L, cols, nx, xs):
+    """Single solid nodes, each in a row of its own, on and next to the
+    columns where one 64- or 128-column strip meets the next (and at the
+    periodic seam).  A solid one column past a strip's halo column (x0 - 2 or
+    x0 + width + 1) gives links only to that halo node, not to the strip's
+    own nodes: such a row's summary must still include the halo column, or
+    the halo node's Phi_x would miss its bounce-back.  One and two columns
+    per lane, FP64, against the oracle."""
+    if cols == 2 and nx % 2:
+        pytest.skip("two columns per lane need an even width")
+    ny = 3 * len(xs) + 2
+    rng = np.random.default_rng(nx + 7 * cols)
+    mask = np.zeros((ny, nx), np.uint8)
+    for k, x in enumerate(xs):
+        mask[1 + 3 * k, x] = 1
+    f = inputs.random_populations(rng, (ny, nx), amp=0.1)
+    f[:, mask.astype(bool)] = 0.0
+    tau1, tau2 = 0.7, 1.3
+    lat = L.Lattice(nx, ny, tau1, tau2, mask=mask, storage="f64")
+    lat.set_tuning(4, 2, 1, cols)
+    assert lat.tuning()[3] == cols
+    lat.set_populations(f).step(5)
+    got = _np(lat.get_populations())
+    lat.close()
+    want = oracle.run(f, 5, tau1, tau2, 0.0, 0.0, mask)
+    err = np.max(np.abs(got - want))
+    say("case: strip-edge obstacles nx=%d cols=%d: max |f - f_oracle| = %.3e" % (nx, cols, err))
+    assert err < 1e-14
+
+
 PAIR_TILINGS = [(32, 4, 1, 2), (1, 1, 0, 2), (5, 2, 1, 2), (3, 1, 1, 2), (5, 16, 1, 2),
                 (7, 8, 0, 2), (0, 0, -1, 2)]
 PAIR_SHAPES = [(130, 37), (62, 5), (256, 9), (2, 7), (128, 3), (384, 17), (254, 1)]

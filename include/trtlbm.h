@@ -117,7 +117,8 @@ typedef struct {
     int32_t waves_per_block; /* wavefronts per workgroup: 1, 2, 4, 8 or 16 (0: automatic); the
                                 one-column and batched sweeps use at most 4, the two-column
                                 sweep at most 16 (FP64: 8) */
-    int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default */
+    int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default
+                                (on for one simulation, off for a batch) */
     int32_t cols_per_lane;   /* 1 or 2 columns per lane (0: 2 where it applies and nx >= 128) */
 } trt_tuning;
 

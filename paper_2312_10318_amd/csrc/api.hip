@@ -37,6 +37,11 @@ trt_status fail_hip(hipError_t e, const char *what) {
 // Default launch shape: rows per wave chosen per lattice (auto_rows), four
 // wavefronts per workgroup, XCD-contiguous workgroup order.
 constexpr Launch kDefaultLaunch = {0, 0, 1, 0};
+// Batches: no XCD remap by default.  A batch's work list runs member by
+// member, and spreading each member's items over all XCDs (the hardware's
+// round-robin) measured 3% faster than giving XCDs contiguous ranges of the
+// list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -71,8 +76,8 @@ trt_status check_problem(const trt_problem *p) {
     return TRT_OK;
 }
 
-trt_status check_launch(const trt_tuning *t, Launch &l) {
-    l = kDefaultLaunch;
+trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) {
+    l = defaults;
     if (!t) return TRT_OK;
     if (t->rows_per_wave != 0) {
         if (t->rows_per_wave < 1 || t->rows_per_wave > 4096)
@@ -327,7 +332,7 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
 trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     Launch l;
-    trt_status st = check_launch(t, l);
+    trt_status st = check_launch(t, l, kDefaultLaunch);
     if (st != TRT_OK) return st;
     if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
     s->launch = l;
@@ -607,7 +612,7 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     trt_batch *b = new (std::nothrow) trt_batch();
     if (!b) return fail(TRT_ENOMEM, "out of host memory");
     b->stream = sims[0]->stream;
-    b->launch = kDefaultLaunch;
+    b->launch = kBatchDefaultLaunch;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     for (auto &sg : b->stage)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
@@ -636,7 +641,7 @@ trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims) {
 trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
     if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
     Launch l;
-    trt_status st = check_launch(t, l);
+    trt_status st = check_launch(t, l, kBatchDefaultLaunch);
     if (st != TRT_OK) return st;
     // members' cur already reflects every step taken; rebuilding restarts
     // the batch parity from there

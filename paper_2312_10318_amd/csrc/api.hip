@@ -18,14 +18,35 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-trt_status fail(trt_status st, const std::string &msg) {
-    g_err = msg;
+// Record the message of a failing call.  No C++ exception may leave the C
+// ABI: a message that cannot be stored (out of host memory) is dropped.
+trt_status fail(trt_status st, const char *msg) noexcept {
+    try {
+        g_err = msg;
+    } catch (...) {
+    }
     return st;
 }
 
-trt_status fail_hip(hipError_t e, const char *what) {
-    g_err = std::string(what) + ": " + hipGetErrorString(e);
+trt_status fail_hip(hipError_t e, const char *what) noexcept {
+    try {
+        g_err = std::string(what) + ": " + hipGetErrorString(e);
+    } catch (...) {
+    }
     return TRT_EDEVICE;
+}
+
+// Run an entry point's body that uses host containers; an allocation
+// failure becomes TRT_ENOMEM instead of an exception crossing the C ABI.
+template <class F>
+trt_status guarded(F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(TRT_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(TRT_EDEVICE, "unexpected host error");
+    }
 }
 
 #define TRT_HIP(expr)                                    \
@@ -592,8 +613,9 @@ static trt_status check_members(int32_t n, trt_sim *const *sims, const trt_batch
 }
 
 static void batch_set_members(trt_batch *b, int32_t n, trt_sim *const *sims) {
+    std::vector<trt_sim *> next(sims, sims + n);  // may throw: nothing changed yet
     for (trt_sim *m : b->sims) m->in_batch = false;
-    b->sims.assign(sims, sims + n);
+    b->sims.swap(next);
     b->storage = sims[0]->prob.storage;
     b->mask = false;
     b->buf = true;
@@ -611,17 +633,16 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
     if (st != TRT_OK) return st;
     trt_batch *b = new (std::nothrow) trt_batch();
     if (!b) return fail(TRT_ENOMEM, "out of host memory");
-    b->stream = sims[0]->stream;
-    b->launch = kBatchDefaultLaunch;
-    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    for (auto &sg : b->stage)
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        trt_batch_destroy(b);
-        return fail_hip(e, "batch stream/event");
-    }
-    batch_set_members(b, n, sims);
-    st = batch_build(b);
+    st = guarded([&]() -> trt_status {
+        b->stream = sims[0]->stream;
+        b->launch = kBatchDefaultLaunch;
+        hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        for (auto &sg : b->stage)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
+        if (e != hipSuccess) return fail_hip(e, "batch stream/event");
+        batch_set_members(b, n, sims);
+        return batch_build(b);
+    });
     if (st != TRT_OK) {
         trt_batch_destroy(b);
         return st;
@@ -631,11 +652,13 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out) {
 }
 
 trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims) {
-    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
-    trt_status st = check_members(n, sims, b);
-    if (st != TRT_OK) return st;
-    batch_set_members(b, n, sims);
-    return batch_build(b);
+    return guarded([&]() -> trt_status {
+        if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+        trt_status st = check_members(n, sims, b);
+        if (st != TRT_OK) return st;
+        batch_set_members(b, n, sims);
+        return batch_build(b);
+    });
 }
 
 trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
@@ -646,8 +669,7 @@ trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
     // members' cur already reflects every step taken; rebuilding restarts
     // the batch parity from there
     b->launch = l;
-    st = batch_build(b);
-    return st;
+    return guarded([&] { return batch_build(b); });
 }
 
 static void batch_sync_members(trt_batch *b, int64_t n) {

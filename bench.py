@@ -89,9 +89,35 @@ def cpu_baseline(n=4096, budget_s=12.0):
     t2 = time.perf_counter() - t0
     steps = 1 + extra
     total = t1 + t2
+    cores = oracle.num_threads()
+    # one thread, on a smaller sample (1024^2, one step: ~0.2-0.5 s)
+    m = 1024
+    r1, u1, v1 = inputs.taylor_green(m, 0.01, seed=0)
+    f1 = oracle.init_equilibrium(r1, u1, v1)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(f1, tau1, tau2)
+        single = m * m / (time.perf_counter() - t0) / 1e6
+    finally:
+        oracle.set_num_threads(cores)
     return {"value": round(n * n * steps / total / 1e6, 3), "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total)}
+            "cores": cores, "kind": "oracle",
+            "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total),
+            "single_thread_MLUPS": round(single, 3),
+            "single_thread_sample": "Taylor-Green %dx%d FP64, one step" % (m, m),
+            "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def traffic_from_counters(n, storage):

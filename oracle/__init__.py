@@ -70,6 +70,8 @@ def _bind(lib):
     lib.orc_wall_force.argtypes = [i, i, P, P, d, d, d, d, i, d, d, P]
     lib.orc_wall_force.restype = i
     lib.orc_num_threads.restype = i
+    lib.orc_set_num_threads.argtypes = [i]
+    lib.orc_set_num_threads.restype = None
     return lib
 
 
@@ -287,6 +289,12 @@ def wall_force(*a, **k):
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_inst().lib.orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops (for timing; results do not
+    depend on it)."""
+    _inst().lib.orc_set_num_threads(int(n))
 
 
 def build_variant(source_text: str, out_path: str) -> str:

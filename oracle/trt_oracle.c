@@ -518,3 +518,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Set the number of threads of the OpenMP loops (timing only: the
+ * arithmetic of a step does not depend on it). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

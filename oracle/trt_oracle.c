@@ -24,30 +24,30 @@
  * State layout: populations f[i][y][x] (i = 0..8), dense, x fastest, holding
  * the PRE-collision distribution f(x, t).  Solid nodes (mask != 0) hold 0.
  *
- * Readings taken where the paper is silent (each is listed in the design
+ * Readings taken where the paper is silent (numbered as in the design
  * notes of the repository):
  *   R1  The gradient in G_i is a second-order central difference of the
  *       fields rho*u_x^3, rho*u_y^3 taken at the same time level t, with
  *       periodic wrap; at a solid neighbour the field is taken as 0.
  *   R2  The body force is F = rho * g with g an acceleration (Sec. II.D,
  *       the Poiseuille set-up), and dt = 1.
- *   R3  A link whose target is a solid node is bounced back half-way, link by
+ *   R12 Solid nodes are never collided; their outputs are 0.
+ *   R13 A link whose target is a solid node is bounced back half-way, link by
  *       link (Sec. II.D, half-way bounce-back rule), also for diagonal links.
- *   R4  Solid nodes are never collided; their outputs are 0.
  * Open boundaries in x (the creeping flow of Sec. III.D; orc_step_open):
- *   R5  The inlet is a half-way bounce-back wall at x = -1/2 moving with the
+ *   R17 The inlet is a half-way bounce-back wall at x = -1/2 moving with the
  *       inflow velocity (u_in, 0): a population f*_i leaving column 0
  *       through it returns to the same node as direction opp(i) with the
  *       moving-wall momentum correction -2 w_i rho_w (e_i . u_wall) / c_s^2
  *       (Ladd's moving-wall rule; the paper names the scheme, not the
  *       formula), rho_w the prescribed wall density.
- *   R6  The outlet column nx - 1 has a prescribed density rho_out and zero
+ *   R18 The outlet column nx - 1 has a prescribed density rho_out and zero
  *       transverse velocity: after streaming, its three populations with
  *       e_x = -1 come from Zou and He's pressure rule applied to the six
  *       known ones.  Populations streaming out through x = nx are lost.
- *   R7  Phi beyond the inlet is the wall's, rho_w u_in^3 (x) and 0 (y);
+ *   R19 Phi beyond the inlet is the wall's, rho_w u_in^3 (x) and 0 (y);
  *       beyond the outlet it equals the last column's (zero gradient).
- *   R8  Moving walls and the outlet rule ignore the body force (the open
+ *   R20 Moving walls and the outlet rule ignore the body force (the open
  *       case of the paper is unforced).
  */
 #include <math.h>
@@ -324,7 +324,7 @@ int orc_step(int nx, int ny, const uint8_t *solid, const double *fin, double *fo
 
 /* Post-collision populations fstar[9][ny][nx] of every fluid node (0 at
  * solid nodes) for the state fin, with the Phi gradient of R1 and, when
- * open_x is set, the boundary values of R7 at columns 0 and nx - 1.      */
+ * open_x is set, the boundary values of R19 at columns 0 and nx - 1.      */
 static int collide_field(int nx, int ny, const uint8_t *solid, const double *fin, double *fstar,
                          double tau1, double tau2, double gx, double gy, int open_x,
                          double u_in, double rho_w) {
@@ -356,7 +356,7 @@ static int collide_field(int nx, int ny, const uint8_t *solid, const double *fin
                 continue;
             }
             for (int i = 0; i < Q; ++i) fl[i] = fin[(long)i * n + k];
-            /* Phi_x at the two x-neighbours (R1, with R7 at open ends) */
+            /* Phi_x at the two x-neighbours (R1, with R19 at open ends) */
             double left = px[(long)y * nx + wrap(x - 1, nx)];
             double right = px[(long)y * nx + wrap(x + 1, nx)];
             if (open_x && x == 0) left = rho_w * u_in * u_in * u_in;
@@ -374,7 +374,7 @@ static int collide_field(int nx, int ny, const uint8_t *solid, const double *fin
 }
 
 /* One time step with an inflow wall at x = -1/2 and a pressure outlet at
- * x = nx - 1 (R5-R8), periodic in y, half-way bounce-back at solid nodes:
+ * x = nx - 1 (R17-R20), periodic in y, half-way bounce-back at solid nodes:
  * collision as in orc_step, then streaming f_i(x + e_i) = f*_i(x) inside
  * the lattice, the moving-wall return at the inlet, loss through the
  * outlet, and Zou and He's rule for the outlet's incoming populations.   */
@@ -399,10 +399,10 @@ int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, doubl
                 const int ty = wrap(y + E[i][1], ny);
                 const int back = opposite(i);
                 if (tx < 0) {
-                    /* R5: e_i . u_wall = e_ix u_in */
+                    /* R17: e_i . u_wall = e_ix u_in */
                     fout[(long)back * n + k] = v - 2.0 * WGT[i] * rho_w * (E[i][0] * u_in) / CS2;
                 } else if (tx >= nx) {
-                    /* R6: leaves the lattice */
+                    /* R18: leaves the lattice */
                 } else if (solid && solid[(long)ty * nx + tx]) {
                     fout[(long)back * n + k] = v;
                 } else {
@@ -411,7 +411,7 @@ int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, doubl
             }
         }
     }
-    /* R6: Zou and He's pressure rule, e = (1,0):1 (0,1):2 (-1,0):3 (0,-1):4
+    /* R18: Zou and He's pressure rule, e = (1,0):1 (0,1):2 (-1,0):3 (0,-1):4
      * (1,1):5 (-1,1):6 (-1,-1):7 (1,-1):8, with u_y = 0 at the outlet */
     for (int y = 0; y < ny; ++y) {
         const long k = (long)y * nx + (nx - 1);

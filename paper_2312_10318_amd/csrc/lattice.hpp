@@ -145,24 +145,59 @@ template <class C, bool SHIFTED> struct Moments {
     C base, rho, jx, jy, ux, uy;
     C pxx, pyy, pxy, qxxy, qxyy;
     __device__ __forceinline__ void compute(const C f[9], C gx, C gy) {
-        const C s56 = f[5] + f[6], s78 = f[7] + f[8];
-        const C d56 = f[5] - f[6], d78 = f[7] - f[8];
+        const C a13 = f[1] + f[3];
+        finish(f[5] + f[6], f[5] - f[6], f[7] + f[8], f[7] - f[8], a13, f[1] - f[3],
+               f[2] + f[4], f[2] - f[4], f[0] + a13, gx, gy);
+    }
+    // The same from the sums and differences of opposite populations
+    // (f0a13 = f_0 + (f_1 + f_3)).
+    __device__ __forceinline__ void finish(C s56, C d56, C s78, C d78, C a13, C m13, C a24, C m24,
+                                           C f0a13, C gx, C gy) {
         const C diag = s56 + s78;
         qxxy = s56 - s78;
         pxy = d56 + d78;
         qxyy = d56 - d78;
-        const C a13 = f[1] + f[3], a24 = f[2] + f[4];
         pxx = a13 + diag;
         pyy = a24 + diag;
-        jx = (f[1] - f[3]) + qxyy;
-        jy = (f[2] - f[4]) + qxxy;
-        base = (f[0] + a13) + (a24 + diag);
+        jx = m13 + qxyy;
+        jy = m24 + qxxy;
+        base = f0a13 + (a24 + diag);
         rho = SHIFTED ? C(1) + base : base;
         const C inv = recip(rho);
         ux = jx * inv + C(0.5) * gx;
         uy = jy * inv + C(0.5) * gy;
     }
 };
+
+// Sums of FP16 populations held in halves of 32-bit registers, formed in
+// FP32 without separate conversions (FP16 to FP32 is exact, so each result
+// is the FP32 sum of the converted values): a + b or a - b of the high (HI)
+// or low halves of a and b, and h + c of one half of h and an FP32 c.  The
+// operands are 32-bit words (uint32_t) or single FP16 values (_Float16, in
+// the low half of their register, passed without widening).
+template <bool HI, bool NEG, class U>
+__device__ __forceinline__ float hsum(U a, U b) {
+    static_assert(sizeof(U) == 4 || sizeof(U) == 2, "a word or an FP16 value");
+    float r;
+    if (HI && NEG)
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if (HI)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if (NEG)
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+template <bool HI, class U>
+__device__ __forceinline__ float hadd(U h, float c) {
+    float r;
+    if (HI)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(c));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(c));
+    return r;
+}
 
 // f_i from the seven Hermite coefficients (see the file comment).
 template <class C>
@@ -185,6 +220,75 @@ __device__ __forceinline__ void reconstruct(C f[9], C base, C bx, C by, C bxx, C
     f[7] = Wt<C>::w5(sp - d57);
     f[6] = Wt<C>::w5(sm + d68);
     f[8] = Wt<C>::w5(sm - d68);
+}
+
+// FP16 storage.  Opposite directions share the even part of the
+// reconstruction above and differ in the sign of its odd part:
+// f*_i - w_i = w_i X + s w_i Y with s = +1 for i = 1, 2, 5, 6 and -1 for their
+// opposites 3, 4, 7, 8, and f*_0 - w_0 = w_0 X_0.  X and Y are the FP32
+// values the reconstruction forms (ax and dx for the pair (1,3), ay and dy
+// for (2,4), s +- 9 b_xy and the diagonal odd parts for (5,7) and (6,8));
+// here w_i X is formed once per pair and every output is one mixed-precision
+// multiply-add, s Y w_i + (w_i X), rounded once from its exact value to FP16
+// and written into one half of a 32-bit register.  The FP32 roundings before
+// it (of X, Y, w_i X and of w_i itself) lie far below FP16 resolution, so the
+// weights need none of the FP32 path's care.
+struct HalfPairs {
+    float x0;     // X_0
+    float wx[4];  // w_i X of the pairs (1,3), (2,4), (5,7), (6,8)
+    float y[4];   // their Y
+};
+
+__device__ __forceinline__ void reconstruct_pairs(HalfPairs &p, float base, float bx, float by,
+                                                  float bxx, float byy, float bxy, float bxxy,
+                                                  float bxyy) {
+    p.x0 = base - 1.5f * (bxx + byy);
+    const float ax = base + 3.0f * bxx - 1.5f * byy;
+    p.y[0] = 3.0f * bx - 4.5f * bxyy;
+    const float ay = base + 3.0f * byy - 1.5f * bxx;
+    p.y[1] = 3.0f * by - 4.5f * bxxy;
+    const float s = base + 3.0f * (bxx + byy);
+    const float sp = s + 9.0f * bxy, sm = s - 9.0f * bxy;
+    p.y[2] = 3.0f * (bx + by) + 9.0f * (bxxy + bxyy);
+    p.y[3] = 3.0f * (by - bx) + 9.0f * (bxxy - bxyy);
+    p.wx[0] = Wt<float>::h1 * ax;
+    p.wx[1] = Wt<float>::h1 * ay;
+    p.wx[2] = Wt<float>::h5 * sp;
+    p.wx[3] = Wt<float>::h5 * sm;
+}
+
+// fma(s a, b, c) rounded once to FP16 into the low (LO) or high half of r;
+// the other half of r is kept.  The instructions take FP32 operands.
+template <bool NEG>
+__device__ __forceinline__ uint32_t mix_lo(float a, float b, float c) {
+    uint32_t r;
+    if (NEG)
+        asm("v_fma_mixlo_f16 %0, -%1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    else
+        asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+template <bool NEG>
+__device__ __forceinline__ uint32_t mix_hi(uint32_t r, float a, float b, float c) {
+    if (NEG)
+        asm("v_fma_mixhi_f16 %0, -%1, %2, %3" : "+v"(r) : "v"(a), "v"(b), "v"(c));
+    else
+        asm("v_fma_mixhi_f16 %0, %1, %2, %3" : "+v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Population i of one node in the low half of a register (HI: the high half
+// of r instead, its low half kept).
+template <int I, bool HI>
+__device__ __forceinline__ uint32_t half_out(const HalfPairs &p, uint32_t r = 0u) {
+    constexpr int k = I == 0 ? 0 : (I == 1 || I == 3) ? 0 : (I == 2 || I == 4) ? 1 : (I == 5 || I == 7) ? 2 : 3;
+    constexpr bool neg = I == 3 || I == 4 || I == 7 || I == 8;
+    const float w = I == 0 ? Wt<float>::h0 : I < 5 ? Wt<float>::h1 : Wt<float>::h5;
+    const float a = I == 0 ? w : p.y[k];
+    const float b = I == 0 ? p.x0 : w;
+    const float c = I == 0 ? 0.0f : p.wx[k];
+    if (HI) return mix_hi<neg>(r, a, b, c);
+    return mix_lo<neg>(a, b, c);
 }
 
 // Third-order Hermite equilibrium (Eq. 5) in coefficient form: the

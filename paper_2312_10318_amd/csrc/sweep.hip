@@ -183,6 +183,12 @@ __device__ __forceinline__ float dpp_shl(float old, float src) {
                                                                   __builtin_bit_cast(int, src),
                                                                   0x130, 0xf, 0xf, false));
 }
+__device__ __forceinline__ uint32_t dpp_shr(uint32_t old, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t dpp_shl(uint32_t old, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x130, 0xf, 0xf, false);
+}
 __device__ __forceinline__ double dpp_shr(double old, double src) {
     const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
     const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, 0x138, 0xf,
@@ -198,6 +204,12 @@ __device__ __forceinline__ double dpp_shl(double old, double src) {
     const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32),
                                                     0x130, 0xf, 0xf, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Store the FP16 population held in the low half of a register.
+template <class Acc>
+__device__ __forceinline__ void store_half(const Acc &out, int64_t e, uint32_t oc, uint32_t r) {
+    out.st(e, oc, __builtin_bit_cast(_Float16, (unsigned short)(r & 0xffffu)));
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -321,13 +333,32 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
         }
 
         const C dphiy = C(0.5) * (nxt.phiy - phiy_below);
-        C fo[9];
-        reconstruct<C>(fo, cf.base, cf.bx, cf.by, cf.bxx, cf.byy - ph * dphiy, cf.bxy, cf.bxxy,
-                       cf.bxyy);
-        if (writer && !cur.solid) {
-            const int64_t e0 = (int64_t)y * pitch;
+        if constexpr (ST == ST_F16) {
+            // the same single FP16 rounding per population as the two-column sweep
+            HalfPairs p;
+            reconstruct_pairs(p, cf.base, cf.bx, cf.by, cf.bxx, cf.byy - ph * dphiy, cf.bxy,
+                              cf.bxxy, cf.bxyy);
+            if (writer && !cur.solid) {
+                const int64_t e0 = (int64_t)y * pitch;
+                store_half(out, e0, col.oc, half_out<0, false>(p));
+                store_half(out, plane + e0, col.oc, half_out<1, false>(p));
+                store_half(out, 2 * plane + e0, col.oc, half_out<2, false>(p));
+                store_half(out, 3 * plane + e0, col.oc, half_out<3, false>(p));
+                store_half(out, 4 * plane + e0, col.oc, half_out<4, false>(p));
+                store_half(out, 5 * plane + e0, col.oc, half_out<5, false>(p));
+                store_half(out, 6 * plane + e0, col.oc, half_out<6, false>(p));
+                store_half(out, 7 * plane + e0, col.oc, half_out<7, false>(p));
+                store_half(out, 8 * plane + e0, col.oc, half_out<8, false>(p));
+            }
+        } else {
+            C fo[9];
+            reconstruct<C>(fo, cf.base, cf.bx, cf.by, cf.bxx, cf.byy - ph * dphiy, cf.bxy,
+                           cf.bxxy, cf.bxyy);
+            if (writer && !cur.solid) {
+                const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out.st(i * plane + e0, col.oc, from_c<T, C>(fo[i]));
+                for (int i = 0; i < 9; ++i) out.st(i * plane + e0, col.oc, from_c<T, C>(fo[i]));
+            }
         }
         phiy_below = cur.phiy;
         cur = nxt;
@@ -441,6 +472,7 @@ template <class T> struct PairCtx {
     const LinkAccess &la;  // link map (used when `linked`)
     bool linked;
     int64_t lpitch;
+    uint32_t edge_shift;   // 16 in lane 0, else 0 (FP16 edge elements as words)
 };
 
 // The link codes of row y: the pair's (ld2) and the edge lane's halo node.
@@ -502,10 +534,54 @@ __device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> 
 // the lane neighbours, apply the link bits (half-way bounce-back from the
 // nodes' own slots, solid nodes) and the open x boundaries, and form both
 // nodes' moments and Phi.
-template <class T, class C, bool SHIFTED>
+// HALVES (FP16 storage without a link map or open boundaries): the words are
+// shifted across lanes whole and the moments summed from their FP16 halves.
+template <class T, class C, bool SHIFTED, bool HALVES = false>
 __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, SHIFTED> &b,
                                            const PairRow<T> &r, const PairCtx<T> &c, C gx, C gy,
                                            const OpenX<C> &ox) {
+    if constexpr (HALVES) {
+        static_assert(sizeof(T) == 2 && sizeof(C) == 4, "FP16 storage only");
+        // edge elements as words: lane 0 feeds node A's high half (a
+        // previous lane's node B), lane 63 node B's low half (a next lane's
+        // node A); pinned here as the FP16 path pins its conversions
+        T e0 = r.edge[0], e1 = r.edge[1], e2 = r.edge[2];
+        asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2));
+        const uint32_t sh = c.edge_shift;
+        const uint32_t h0 = (uint32_t)__builtin_bit_cast(unsigned short, e0) << sh;
+        const uint32_t h1 = (uint32_t)__builtin_bit_cast(unsigned short, e1) << sh;
+        const uint32_t h2 = (uint32_t)__builtin_bit_cast(unsigned short, e2) << sh;
+        // e_x = +1 (planes 1, 5, 8): node A pulls the previous lane's node B;
+        // e_x = -1 (planes 3, 6, 7): node B pulls the next lane's node A
+        const uint32_t w1 = dpp_shr(h0, r.w[1]), w5 = dpp_shr(h1, r.w[5]), w8 = dpp_shr(h2, r.w[8]);
+        const uint32_t w3 = dpp_shl(h0, r.w[3]), w6 = dpp_shl(h1, r.w[6]), w7 = dpp_shl(h2, r.w[7]);
+        // node A: f0 f2 f4 in the low halves of its own words; f1 f5 f8 in
+        // the high halves of the shifted ones; f3 f6 f7 in the high halves of
+        // its own (node B's column)
+        {
+            const float a13 = hsum<true, false>(w1, r.w[3]);
+            a.m.finish(hsum<true, false>(w5, r.w[6]), hsum<true, true>(w5, r.w[6]),
+                       hsum<true, false>(r.w[7], w8), hsum<true, true>(r.w[7], w8), a13,
+                       hsum<true, true>(w1, r.w[3]), hsum<false, false>(r.w[2], r.w[4]),
+                       hsum<false, true>(r.w[2], r.w[4]), hadd<false>(r.w[0], a13), gx, gy);
+        }
+        // node B: f0 f2 f4 in the high halves of its own words; f1 f5 f8 in
+        // the low halves of its own (node A's column); f3 f6 f7 in the low
+        // halves of the shifted ones
+        {
+            const float a13 = hsum<false, false>(r.w[1], w3);
+            b.m.finish(hsum<false, false>(r.w[5], w6), hsum<false, true>(r.w[5], w6),
+                       hsum<false, false>(w7, r.w[8]), hsum<false, true>(w7, r.w[8]), a13,
+                       hsum<false, true>(r.w[1], w3), hsum<true, false>(r.w[2], r.w[4]),
+                       hsum<true, true>(r.w[2], r.w[4]), hadd<true>(r.w[0], a13), gx, gy);
+        }
+        a.solid = b.solid = false;
+        a.phix = a.m.rho * a.m.ux * a.m.ux * a.m.ux;
+        a.phiy = a.m.rho * a.m.uy * a.m.uy * a.m.uy;
+        b.phix = b.m.rho * b.m.ux * b.m.ux * b.m.ux;
+        b.phiy = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
+        return;
+    }
     C pa[9], pb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) PairIO<T>::split(r.w[i], pa[i], pb[i]);
@@ -568,11 +644,26 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
 
 // Halo Phi_x of an edge lane (the link bits and open boundaries applied as
 // for the node's own lane).
-template <class T, class C, bool SHIFTED>
+template <class T, class C, bool SHIFTED, bool HALVES>
 __device__ __forceinline__ C pair_halo_phix(Raw<T> &h, const PairCtx<T> &c, C gx,
                                             const OpenX<C> &ox) {
-    if (c.linked) link_fix(h);
-    return halo_phix<T, C, SHIFTED>(h, gx, ox, c.hcol.xc);
+    if constexpr (HALVES) {
+        // halo_phix's operations, summed from the FP16 values directly
+        const _Float16 *v = h.v;
+        const float s56 = hsum<false, false>(v[5], v[6]), s78 = hsum<false, false>(v[7], v[8]);
+        const float d56 = hsum<false, true>(v[5], v[6]), d78 = hsum<false, true>(v[7], v[8]);
+        const float diag = s56 + s78;
+        const float qxyy = d56 - d78;
+        const float a13 = hsum<false, false>(v[1], v[3]), a24 = hsum<false, false>(v[2], v[4]);
+        const float jx = hsum<false, true>(v[1], v[3]) + qxyy;
+        const float base = hadd<false>(v[0], a13) + (a24 + diag);
+        const float rho = 1.0f + base;
+        const float ux = jx * recip(rho) + 0.5f * gx;
+        return rho * ux * ux * ux;
+    } else {
+        if (c.linked) link_fix(h);
+        return halo_phix<T, C, SHIFTED>(h, gx, ox, c.hcol.xc);
+    }
 }
 
 // LINKED: the lattice may have obstacles or open x boundaries (link map);
@@ -582,6 +673,8 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
     constexpr bool SH = Store<ST>::shifted;
+    // FP16 without a link map: moments straight from the stored halves
+    constexpr bool HALVES = ST == ST_F16 && !LINKED;
 
     const int lane = threadIdx.x & 63;
     const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -603,7 +696,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                             (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hcol.oc,
                             (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hcol.oc};
     const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)ca * (uint32_t)sizeof(T), (uint32_t)ca,
-                        edge, ve, hcol, lacc, linked, d.lpitch};
+                        edge, ve, hcol, lacc, linked, d.lpitch, lane == 0 ? 16u : 0u};
 
     const C gx = (C)d.gx, gy = (C)d.gy;
     const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
@@ -627,7 +720,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
         RowState<C, SH> a, b;
         const int ym0 = (y0 + ny - 1) % ny;
         gather_pair_row<T, false>(t, cx, ym0, summary(ym0));
-        widen_pair<T, C, SH>(a, b, t, cx, gx, gy, ox);
+        widen_pair<T, C, SH, HALVES>(a, b, t, cx, gx, gy, ox);
         phiy_below_a = a.phiy;
         phiy_below_b = b.phiy;
     }
@@ -636,8 +729,8 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     {
         PairRow<T> t;
         gather_pair_row<T, true>(t, cx, y0, summary(y0));
-        widen_pair<T, C, SH>(ca_, cb_, t, cx, gx, gy, ox);
-        if (edge) hphix = pair_halo_phix<T, C, SH>(t.halo, cx, gx, ox);
+        widen_pair<T, C, SH, HALVES>(ca_, cb_, t, cx, gx, gy, ox);
+        if (edge) hphix = pair_halo_phix<T, C, SH, HALVES>(t.halo, cx, gx, ox);
     }
     // link summaries are read one row ahead of the gather they gate
     uint32_t rs_next = summary((y0 + 1) % ny);
@@ -666,30 +759,65 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
                      "+v"(fb.bxy), "+v"(fb.bxxy), "+v"(fb.bxyy));
 
         RowState<C, SH> na, nb;
-        widen_pair<T, C, SH>(na, nb, nr, cx, gx, gy, ox);
+        widen_pair<T, C, SH, HALVES>(na, nb, nr, cx, gx, gy, ox);
         C nhphix = C(0);
-        if (edge) nhphix = pair_halo_phix<T, C, SH>(nr.halo, cx, gx, ox);
+        if (edge) nhphix = pair_halo_phix<T, C, SH, HALVES>(nr.halo, cx, gx, ox);
 
         // the same operations per node as the one-column sweep
         const C dphiy_a = C(0.5) * (na.phiy - phiy_below_a);
         const C dphiy_b = C(0.5) * (nb.phiy - phiy_below_b);
-        C oa[9], ob[9];
-        reconstruct<C>(oa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dphiy_a, fa.bxy, fa.bxxy,
-                       fa.bxyy);
-        reconstruct<C>(ob, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dphiy_b, fb.bxy, fb.bxxy,
-                       fb.bxyy);
-        if (LINKED && __builtin_amdgcn_ballot_w64(ca_.solid || cb_.solid) != 0) {
-            // solid nodes keep zeros (their slots are never read)
+        if constexpr (ST == ST_F16) {
+            // each store word: node A's population in the low half, node B's
+            // in the high one, each rounded once
+            HalfPairs pa, pb;
+            reconstruct_pairs(pa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dphiy_a, fa.bxy,
+                              fa.bxxy, fa.bxyy);
+            reconstruct_pairs(pb, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dphiy_b, fb.bxy,
+                              fb.bxxy, fb.bxyy);
+            uint32_t wd[9];
+            wd[0] = half_out<0, true>(pb, half_out<0, false>(pa));
+            wd[1] = half_out<1, true>(pb, half_out<1, false>(pa));
+            wd[2] = half_out<2, true>(pb, half_out<2, false>(pa));
+            wd[3] = half_out<3, true>(pb, half_out<3, false>(pa));
+            wd[4] = half_out<4, true>(pb, half_out<4, false>(pa));
+            wd[5] = half_out<5, true>(pb, half_out<5, false>(pa));
+            wd[6] = half_out<6, true>(pb, half_out<6, false>(pa));
+            wd[7] = half_out<7, true>(pb, half_out<7, false>(pa));
+            wd[8] = half_out<8, true>(pb, half_out<8, false>(pa));
+            if (LINKED && __builtin_amdgcn_ballot_w64(ca_.solid || cb_.solid) != 0) {
+                // solid nodes keep zeros (their slots are never read)
+                const uint32_t keep = (ca_.solid ? 0u : 0x0000ffffu) | (cb_.solid ? 0u : 0xffff0000u);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                oa[i] = ca_.solid ? C(0) : oa[i];
-                ob[i] = cb_.solid ? C(0) : ob[i];
+                for (int i = 0; i < 9; ++i) wd[i] &= keep;
             }
-        }
-        if (writer) {
-            const int64_t e0 = (int64_t)y * pitch;
+            if (writer) {
+                const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, oa[i], ob[i]);
+                for (int i = 0; i < 9; ++i)
+                    __builtin_amdgcn_raw_buffer_store_b32(wd[i], out.r, cx.opair,
+                                                          (uint32_t)((i * plane + e0) * 2),
+                                                          TRT_STORE_CPOL);
+            }
+        } else {
+            C oa[9], ob[9];
+            reconstruct<C>(oa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dphiy_a, fa.bxy,
+                           fa.bxxy, fa.bxyy);
+            reconstruct<C>(ob, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dphiy_b, fb.bxy,
+                           fb.bxxy, fb.bxyy);
+            if (LINKED && __builtin_amdgcn_ballot_w64(ca_.solid || cb_.solid) != 0) {
+                // solid nodes keep zeros (their slots are never read)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    oa[i] = ca_.solid ? C(0) : oa[i];
+                    ob[i] = cb_.solid ? C(0) : ob[i];
+                }
+            }
+            if (writer) {
+                const int64_t e0 = (int64_t)y * pitch;
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    PairIO<T>::st(out, i * plane + e0, cx.opair, oa[i], ob[i]);
+            }
         }
         phiy_below_a = ca_.phiy;
         phiy_below_b = cb_.phiy;

@@ -108,10 +108,10 @@ typedef struct {
  * that applies).  trt_get_tuning reports the rows, wavefronts per workgroup
  * and columns per lane in effect.
  * Two columns per lane (a wavefront sweeps 128-column strips with one
- * paired access per population) applies to lattices without a mask, with
- * even nx and at most 4 GiB per lattice; elsewhere the sweep uses one
- * column per lane whatever is asked.  The two shapes compute the same
- * arithmetic per node. */
+ * paired access per population) applies to lattices of at most 4 GiB whose
+ * width is not 1 mod 128, with or without a mask or open boundaries;
+ * elsewhere the sweep uses one column per lane whatever is asked.  The two
+ * shapes compute the same arithmetic per node. */
 typedef struct {
     int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 (0: automatic) */
     int32_t waves_per_block; /* wavefronts per workgroup: 1, 2, 4, 8 or 16 (0: automatic); the

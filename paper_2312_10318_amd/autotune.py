@@ -56,9 +56,10 @@ def save_cache(cache: dict, path: str | None = None) -> None:
 
 def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
     """Launch shapes (rows, waves per workgroup, XCD remap, columns per
-    lane) worth timing; two columns per lane apply to every even width (with
-    or without a mask: masked lattices use the link map)."""
-    cols = COLS if nx % 2 == 0 else (1,)
+    lane) worth timing; two columns per lane apply to every width that is
+    not 1 mod 128 (with or without a mask: masked lattices use the link
+    map)."""
+    cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
         waves = WAVES if c == 1 else tuple(w for w in WAVES_PAIR

@@ -49,9 +49,10 @@ inline int batch_waves_per_block(const Launch &l) {
     return l.waves_per_block > 0 ? (l.waves_per_block < 4 ? l.waves_per_block : 4) : 4;
 }
 
-// Whether an instance can use two-column strips: an even nx (a lane's pair
-// never straddles the periodic seam), a lattice within one buffer resource,
-// and, with obstacles or open boundaries, its link map.
+// Whether an instance can use two-column strips: nx not 1 mod 128 (the
+// last strip holds at least two columns, so no lane is both edges), a
+// lattice within one buffer resource, and, with obstacles or open
+// boundaries, its link map.
 bool pair_eligible(const InstDesc &d, int storage);
 
 // Rows per wavefront when the launch shape leaves it open.  Long strips

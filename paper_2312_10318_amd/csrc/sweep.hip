@@ -374,9 +374,12 @@ __device__ __forceinline__ void sweep_strip(const InstDesc &d, int strip, int rb
 // x-streamed populations take the missing neighbour element from the
 // adjacent lane with a DPP whole-wave shift; the strip's two edge lanes
 // supply the elements beyond the strip (and the two halo columns' Phi_x)
-// through DPP's "old" operand.  Used for every lattice with even nx that
-// fits one buffer resource (obstacles and open boundaries through the link
-// map).
+// through DPP's "old" operand.  With an odd width the lane holding the last
+// column (its node A; node B falls in the row padding and is never read as
+// data) also takes column 0's elements and Phi_x as a right edge.  Used for
+// every lattice that fits one buffer resource, except widths whose last strip
+// holds a single column (nx = 1 mod 128, where lane 0 would be both edges);
+// obstacles and open boundaries go through the link map.
 
 constexpr int kStripWidth2 = 128;
 
@@ -472,7 +475,8 @@ template <class T> struct PairCtx {
     const LinkAccess &la;  // link map (used when `linked`)
     bool linked;
     int64_t lpitch;
-    uint32_t edge_shift;   // 16 in lane 0, else 0 (FP16 edge elements as words)
+    uint32_t edge_shift;   // 16 where an edge element feeds a node A (FP16 words)
+    bool tail;             // holds an odd width's last column as its node A
 };
 
 // The link codes of row y: the pair's (ld2) and the edge lane's halo node.
@@ -557,12 +561,15 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
         const uint32_t w3 = dpp_shl(h0, r.w[3]), w6 = dpp_shl(h1, r.w[6]), w7 = dpp_shl(h2, r.w[7]);
         // node A: f0 f2 f4 in the low halves of its own words; f1 f5 f8 in
         // the high halves of the shifted ones; f3 f6 f7 in the high halves of
-        // its own (node B's column)
+        // its own (node B's column), or of the edge words for an odd width's
+        // last column
         {
-            const float a13 = hsum<true, false>(w1, r.w[3]);
-            a.m.finish(hsum<true, false>(w5, r.w[6]), hsum<true, true>(w5, r.w[6]),
-                       hsum<true, false>(r.w[7], w8), hsum<true, true>(r.w[7], w8), a13,
-                       hsum<true, true>(w1, r.w[3]), hsum<false, false>(r.w[2], r.w[4]),
+            const uint32_t o3 = c.tail ? h0 : r.w[3], o6 = c.tail ? h1 : r.w[6],
+                           o7 = c.tail ? h2 : r.w[7];
+            const float a13 = hsum<true, false>(w1, o3);
+            a.m.finish(hsum<true, false>(w5, o6), hsum<true, true>(w5, o6),
+                       hsum<true, false>(o7, w8), hsum<true, true>(o7, w8), a13,
+                       hsum<true, true>(w1, o3), hsum<false, false>(r.w[2], r.w[4]),
                        hsum<false, true>(r.w[2], r.w[4]), hadd<false>(r.w[0], a13), gx, gy);
         }
         // node B: f0 f2 f4 in the high halves of its own words; f1 f5 f8 in
@@ -601,10 +608,12 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     fa[1] = dpp_shr(h0, pb[1]); fb[1] = pa[1];
     fa[5] = dpp_shr(h1, pb[5]); fb[5] = pa[5];
     fa[8] = dpp_shr(h2, pb[8]); fb[8] = pa[8];
-    // e_x = -1: node B pulls from the next lane's A (lane 63: edge element)
-    fa[3] = pb[3]; fb[3] = dpp_shl(h0, pa[3]);
-    fa[6] = pb[6]; fb[6] = dpp_shl(h1, pa[6]);
-    fa[7] = pb[7]; fb[7] = dpp_shl(h2, pa[7]);
+    // e_x = -1: node B pulls from the next lane's A (lane 63: edge element);
+    // node A from its own B, or, at an odd width's last column, from the
+    // edge elements of column 0
+    fa[3] = c.tail ? h0 : pb[3]; fb[3] = dpp_shl(h0, pa[3]);
+    fa[6] = c.tail ? h1 : pb[6]; fb[6] = dpp_shl(h1, pa[6]);
+    fa[7] = c.tail ? h2 : pb[7]; fb[7] = dpp_shl(h2, pa[7]);
     a.solid = b.solid = false;
     if (c.linked && r.rs != 0u) {
         // only rows that touch a wall or an obstacle pay for the link codes
@@ -687,16 +696,25 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
     const bool linked = LINKED && d.links != nullptr;
 
     const int x0 = strip * kStripWidth2;
-    const int ca = (x0 + 2 * lane) % nx;  // even, since nx is even
-    const bool writer = x0 + 2 * lane < nx;
-    const bool edge = lane == 0 || lane == 63;
-    const Column hcol = column_of(lane == 0 ? x0 - 1 : x0 + kStripWidth2, nx, sizeof(T));
+    const int c2 = x0 + 2 * lane;
+    // lanes past the last column hold a wrapped, even column (with an even
+    // width exactly the columns that follow the seam, so the lane shifts
+    // also carry the periodic wrap)
+    const int ca = c2 < nx ? c2 : (c2 % nx) & ~1;
+    const bool writer = c2 < nx;
+    // odd width: the lane holding the last column nx - 1 (as its node A;
+    // its node B lies in the row padding) takes that column's x + 1
+    // neighbour, column 0, as a right edge lane does
+    const bool tail = (nx & 1) && c2 == nx - 1;
+    const bool edge = lane == 0 || lane == 63 || tail;
+    const Column hcol = column_of(lane == 0 ? x0 - 1 : (tail ? nx : x0 + kStripWidth2), nx, sizeof(T));
     const int pe0 = lane == 0 ? 1 : 3, pe1 = lane == 0 ? 5 : 6, pe2 = lane == 0 ? 8 : 7;
     const uint32_t ve[3] = {(uint32_t)(pe0 * plane * (int64_t)sizeof(T)) + hcol.oc,
                             (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hcol.oc,
                             (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hcol.oc};
     const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)ca * (uint32_t)sizeof(T), (uint32_t)ca,
-                        edge, ve, hcol, lacc, linked, d.lpitch, lane == 0 ? 16u : 0u};
+                        edge, ve, hcol, lacc, linked, d.lpitch,
+                        (lane == 0 || tail) ? 16u : 0u, tail};
 
     const C gx = (C)d.gx, gy = (C)d.gy;
     const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
@@ -744,12 +762,14 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
         // row y: both nodes' coefficients except the y-gradient of Phi
         C left = dpp_shr(hphix, cb_.phix);   // x - 1 of node A
         C right = dpp_shl(hphix, ca_.phix);  // x + 1 of node B
+        C right_a = tail ? hphix : cb_.phix;  // x + 1 of node A
         if (ox.on) {
             // Phi beyond the inflow wall is the wall's; beyond the outlet, the last column's
             if (ca == 0) left = ox.phi_wall;
             if (ca + 1 == nx - 1) right = cb_.phix;
+            if (ca == nx - 1) right_a = ca_.phix;
         }
-        const C dpx_a = C(0.5) * (cb_.phix - left);
+        const C dpx_a = C(0.5) * (right_a - left);
         const C dpx_b = C(0.5) * (right - ca_.phix);
         Coeffs<C> fa = collide_coeffs<C, SH>(ca_.m, dpx_a, w1, w2, ph, gx, gy);
         Coeffs<C> fb = collide_coeffs<C, SH>(cb_.m, dpx_b, w1, w2, ph, gx, gy);
@@ -941,9 +961,11 @@ bool buffer_addressable(const InstDesc &d, int storage) {
 }
 
 bool pair_eligible(const InstDesc &d, int storage) {
-    // obstacles and open boundaries need the link map
+    // obstacles and open boundaries need the link map; an odd width whose
+    // last strip holds a single column would need lane 0 as both edges
     const bool general = d.mask != nullptr || d.xbc != 0;
-    return d.nx % 2 == 0 && buffer_addressable(d, storage) && (!general || d.links != nullptr);
+    return d.nx % kStripWidth2 != 1 && buffer_addressable(d, storage) &&
+           (!general || d.links != nullptr);
 }
 
 hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, const Launch &l,

@@ -13,8 +13,10 @@ def test_candidates_cover_both_column_modes_on_even_widths():
 
 
 def test_candidates_respect_width_and_storage_limits():
-    odd = autotune.candidates(1025, 512, False, "f32")
-    assert {c for _, _, _, c in odd} == {1}
+    single = autotune.candidates(1025, 512, False, "f32")   # last strip: one column
+    assert {c for _, _, _, c in single} == {1}
+    odd = autotune.candidates(1027, 512, True, "f32")
+    assert {c for _, _, _, c in odd} == {1, 2}
     f64 = autotune.candidates(4096, 4096, False, "f64")
     assert max(w for _, w, _, c in f64 if c == 2) == 8
     short = autotune.candidates(256, 8, False, "f16")

@@ -13,9 +13,10 @@ output path misses this by orders of magnitude.  Nearly every value also
 equals the FP16 rounding of the oracle's value exactly (only values within
 the FP32 margin of a rounding tie may differ): at least 99%.
 
-Cases: an open even width (two columns per lane, moments summed from the
-stored halves), an odd width (one column per lane), and walls with
-obstacles and a body force (link map).  Solid nodes are excluded (the oracle
+Cases: open even and odd widths (two columns per lane, moments summed from
+the stored halves; the odd width's last column takes column 0 as its right
+edge), a width of 1 mod 128 (one column per lane), and walls with obstacles
+and a body force (link map), even and odd.  Solid nodes are excluded (the oracle
 outputs 0 there; the sweep leaves them untouched).
 """
 import numpy as np
@@ -65,8 +66,9 @@ def _case(seed, nx, ny, walls):
     return f, mask, g, tau1, tau2
 
 
-@pytest.mark.parametrize("nx, ny, walls, cols", [(322, 41, False, 2), (131, 37, False, 1),
-                                                (322, 41, True, 2)])
+@pytest.mark.parametrize("nx, ny, walls, cols", [(322, 41, False, 2), (131, 37, False, 2),
+                                                (129, 37, False, 1), (322, 41, True, 2),
+                                                (131, 41, True, 2)])
 def test_fp16_one_step_rounds_each_population_once(L, nx, ny, walls, cols):
     f, mask, g, tau1, tau2 = _case(17 + nx + int(walls), nx, ny, walls)
     lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f16").set_populations(f)

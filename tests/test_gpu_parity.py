@@ -112,8 +112,6 @@ def test_link_summary_at_strip_edges(L, cols, nx, xs):
     own nodes: such a row's summary must still include the halo column, or
     the halo node's Phi_x would miss its bounce-back.  One and two columns
     per lane, FP64, against the oracle."""
-    if cols == 2 and nx % 2:
-        pytest.skip("two columns per lane need an even width")
     ny = 3 * len(xs) + 2
     rng = np.random.default_rng(nx + 7 * cols)
     mask = np.zeros((ny, nx), np.uint8)
@@ -136,7 +134,8 @@ def test_link_summary_at_strip_edges(L, cols, nx, xs):
 
 PAIR_TILINGS = [(32, 4, 1, 2), (1, 1, 0, 2), (5, 2, 1, 2), (3, 1, 1, 2), (5, 16, 1, 2),
                 (7, 8, 0, 2), (0, 0, -1, 2)]
-PAIR_SHAPES = [(130, 37), (62, 5), (256, 9), (2, 7), (128, 3), (384, 17), (254, 1)]
+PAIR_SHAPES = [(130, 37), (62, 5), (256, 9), (2, 7), (128, 3), (384, 17), (254, 1),
+               (131, 37), (3, 7), (255, 5), (127, 4)]
 
 
 @pytest.mark.parametrize("tiling", PAIR_TILINGS)
@@ -145,8 +144,9 @@ def test_two_column_strips_fp64(L, shape, tiling):
     """Two columns per lane (128-column strips, DPP lane shifts, edge lanes
     supplying the strip's outside elements, workgroups synchronised per row
     with idle wavefronts where the strips do not fill a workgroup):
-    arbitrary states with body force on even widths below, at and across
-    strip multiples, ragged heights, every launch shape; 7 steps against the
+    arbitrary states with body force on even and odd widths below, at and
+    across strip multiples (an odd width's last column takes column 0 as its
+    right edge), ragged heights, every launch shape; 7 steps against the
     oracle to round-off, and bit for bit equal to the one-column sweep."""
     nx, ny = shape
     f, _, g, tau1, tau2 = _random_problem(hash((shape, tiling)) % 1000 + 7, nx, ny,
@@ -171,7 +171,7 @@ def test_two_column_strips_fp64(L, shape, tiling):
     assert np.array_equal(got, ref)
 
 
-WALL_PAIR_SHAPES = [(130, 37), (62, 9), (256, 20), (128, 3), (2, 7)]
+WALL_PAIR_SHAPES = [(130, 37), (62, 9), (256, 20), (128, 3), (2, 7), (131, 37), (5, 9)]
 
 
 @pytest.mark.parametrize("tiling", [(32, 4, 1, 2), (1, 1, 0, 2), (5, 16, 1, 2), (0, 0, -1, 2)])
@@ -201,9 +201,13 @@ def test_two_column_strips_with_walls_fp64(L, shape, tiling):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("nx", [322, 323])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_two_column_strips_with_walls_shifted_storage(L, storage):
-    nx, ny = 322, 41
+def test_two_column_strips_with_walls_shifted_storage(L, storage, nx):
+    """FP32 / FP16 storage, walls, obstacles and a force through the link
+    map, even and odd widths: 30 steps with two columns per lane equal the
+    one-column sweep bit for bit."""
+    ny = 41
     f, mask, g, tau1, tau2 = _random_problem(13, nx, ny)
     out = {}
     for cols in (1, 2):
@@ -218,12 +222,14 @@ def test_two_column_strips_with_walls_shifted_storage(L, storage):
     assert same
 
 
+@pytest.mark.parametrize("nx", [322, 323])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_two_column_strips_shifted_storage(L, storage):
-    """FP32 / FP16 storage with two columns per lane on an even width that
-    is not a strip multiple: 50 steps, bit for bit equal to the one-column
-    sweep, and one step within the storage tolerance of the oracle."""
-    nx, ny = 322, 41
+def test_two_column_strips_shifted_storage(L, storage, nx):
+    """FP32 / FP16 storage with two columns per lane on an even and an odd
+    width that are not strip multiples: 50 steps, bit for bit equal to the
+    one-column sweep, and one step within the storage tolerance of the
+    oracle."""
+    ny = 41
     f, _, g, tau1, tau2 = _random_problem(11, nx, ny, with_mask=False)
     out = {}
     for cols in (1, 2):
@@ -254,8 +260,8 @@ def test_workgroup_size_in_effect(L):
     strips, so 2 per workgroup); an explicit request is kept."""
     cases = [(4096, "f32", 0, 8), (4096, "f16", 0, 16), (4096, "f64", 0, 4),
              (4096, "f64", 16, 8), (384, "f32", 16, 4), (130, "f16", 0, 2), (62, "f32", 0, 4),
-             (131, "f32", 16, 4), (1050, "f32", 0, 2), (1050, "f16", 0, 2), (1050, "f64", 0, 2),
-             (1050, "f32", 8, 8)]
+             (129, "f32", 16, 4), (131, "f32", 16, 2), (1050, "f32", 0, 2),
+             (1050, "f16", 0, 2), (1050, "f64", 0, 2), (1050, "f32", 8, 8)]
     for nx, storage, asked, want in cases:
         lat = L.Lattice(nx, 4, 0.8, 1.0, storage=storage)
         lat.set_tuning(0, asked, -1, 0)
@@ -266,12 +272,17 @@ def test_workgroup_size_in_effect(L):
 
 
 def test_two_column_request_falls_back_where_it_does_not_apply(L):
-    """Odd widths keep one column per lane even when two are asked for; the
-    automatic choice takes two on wide even lattices, with or without
+    """Widths whose last 128-column strip would hold a single column keep
+    one column per lane even when two are asked for; the automatic choice
+    takes two on other wide lattices, even or odd, with or without
     obstacles."""
+    for nx in (129, 385, 1):
+        lat = L.Lattice(nx, 8, 0.8, 1.0, storage="f32")
+        lat.set_tuning(0, 0, -1, 2)
+        assert lat.tuning()[3] == 1
+        lat.close()
     lat = L.Lattice(131, 8, 0.8, 1.0, storage="f32")
-    lat.set_tuning(0, 0, -1, 2)
-    assert lat.tuning()[3] == 1
+    assert lat.tuning()[3] == 2
     lat.close()
     mask = inputs.channel_mask(256, 6)
     lat = L.Lattice(256, 8, 0.8, 1.0, mask=mask, storage="f32")

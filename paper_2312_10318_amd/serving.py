@@ -83,11 +83,12 @@ class Scheduler:
     next convergence check point."""
 
     def __init__(self, executor, budget_bytes: int, max_slots: int = 4096,
-                 quantum: int = 100, keep_fields: bool = False, clock=time.perf_counter):
+                 quantum: int = 100, keep_fields=False, clock=time.perf_counter):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_slots = max_slots
         self.quantum = quantum
+        # True / False, or the ids of the requests whose final fields are kept
         self.keep_fields = keep_fields
         self.clock = clock
         self.queue = collections.deque()
@@ -129,16 +130,18 @@ class Scheduler:
         if req.tol is not None and converged is None:
             converged = False
         info = (req, admitted, req.steps - remaining, converged, change)
+        keep = (self.keep_fields if isinstance(self.keep_fields, bool)
+                else rid in self.keep_fields)
         if hasattr(self.ex, "finish_async"):
             # the result is copied to the host behind the work already queued;
             # the slot and the memory are free at once (the device reuses the
             # lattice's memory only after the copy, in stream order)
-            ticket = self.ex.finish_async(handle, keep_fields=self.keep_fields)
+            ticket = self.ex.finish_async(handle, keep_fields=keep)
             self.ex.close(handle)
             self.used -= fp
             self.draining.append((info, ticket))
             return
-        diag, fields = self.ex.finish(handle, keep_fields=self.keep_fields)
+        diag, fields = self.ex.finish(handle, keep_fields=keep)
         self.ex.close(handle)
         self.used -= fp
         self._record(info, diag, fields)

@@ -224,3 +224,44 @@ def test_batch_vs_oracle_mixed_workload(L):
             (m.kind, m.n, m.tau1, m.tau2, emax, el2))
         assert emax <= 1e-5
     b.close()
+
+
+def test_full_batch_workload_sampled_members_vs_oracle(L):
+    """The benchmark's batch as it is timed (256 members from the same
+    generator and seeds, FP32, one launch per step, automatic launch shape):
+    after 3 batched steps, sampled members (smallest, largest, odd and even
+    widths, both flow kinds) match the oracle run of that member alone, and
+    every member conserves its mass."""
+    members = inputs.batch_workload(256, seed=0)
+    lats = []
+    for k, m in enumerate(members):
+        rho, ux, uy = inputs.member_fields(m, seed=k)
+        lats.append(L.Lattice(m.n, m.n, m.tau1, m.tau2, storage="f32").init_equilibrium(rho, ux, uy))
+    b = L.Batch(lats)
+    d0 = b.diagnostics()
+    b.step(3)
+    d1 = b.diagnostics()
+    drift = np.abs(d1[:, 0] - d0[:, 0]) / d0[:, 0]
+    say("case: full batch, %d members, %d nodes: max relative mass drift %.2e" %
+        (len(members), sum(m.n * m.n for m in members), float(drift.max())))
+    assert np.all(d1[:, 4] == 0) and np.all(d1[:, 7] == 3)
+    assert float(drift.max()) <= 1e-8
+    sizes = [m.n for m in members]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    pick.update([k for k, m in enumerate(members) if m.n % 2 == 1][:2])
+    pick.update([k for k, m in enumerate(members) if m.n % 2 == 0 and m.n >= 128][:2])
+    pick.update([k for k, m in enumerate(members) if m.n % 128 == 1][:1])
+    pick.update([k for k, m in enumerate(members) if m.kind == "dsl"][:1])
+    for k in sorted(pick):
+        m = members[k]
+        rho, ux, uy = inputs.member_fields(m, seed=k)
+        ref = oracle.run(oracle.init_equilibrium(rho, ux, uy), 3, m.tau1, m.tau2)
+        _, u, v = (_np(t) for t in lats[k].macros())
+        _, ur, vr = oracle.macros(ref)
+        emax, el2 = rel_errors(u, v, ur, vr)
+        say("  member %d %s n=%d cols=%d tau1=%.4f tau2=%.3f: rel max %.3e L2 %.3e" %
+            (k, m.kind, m.n, lats[k].tuning()[3], m.tau1, m.tau2, emax, el2))
+        assert emax <= 1e-5
+    b.close()
+    for x in lats:
+        x.close()

@@ -126,3 +126,37 @@ def test_device_taylor_green_fields_equal_host_fields(L):
         for h, d in zip(host, dev):
             assert d.is_cuda and d.dtype == torch.float64 and d.is_contiguous()
             assert np.array_equal(h, d.cpu().numpy())
+
+
+def test_full_serving_stream_sampled_requests_equal_results_alone(L):
+    """The benchmark's serving run as it is timed (Poisson arrivals at
+    200 solves/s for 2 s, FP16 storage, 64 GiB budget, quanta of 100 steps):
+    a sample of requests of every kind, the largest Taylor-Green one
+    included, gives bit for bit the result it gives alone."""
+    from paper_2312_10318_amd import serving
+    from paper_2312_10318_amd.serving import GpuExecutor
+    reqs = serving.serving_workload(rate=200.0, duration=2.0, seed=0)
+    pick = set()
+    for kind in ("cylinder", "poiseuille", "taylor_green"):
+        ks = [q for q in reqs if q.kind == kind]
+        pick.update(q.rid for q in (ks[0], ks[len(ks) // 2], max(ks, key=lambda q: q.nx * q.ny)))
+    ex = GpuExecutor("f16")
+    sched = Scheduler(ex, budget_bytes=64 << 30, quantum=100, keep_fields=pick)
+    res = sched.run(reqs)
+    ex.shutdown()
+    say("case: full serving stream, %d requests, peak active %d, %d sampled" %
+        (len(res), sched.peak_active, len(pick)))
+    assert len(res) == len(reqs) and sched.peak_active >= 10
+    by = {r.rid: r for r in res}
+    for q in reqs:
+        if q.rid not in pick:
+            continue
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage="f16")
+        rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
+        lat.init_equilibrium(rho, ux, uy).step(q.steps)
+        alone = [t.cpu().numpy() for t in lat.macros()]
+        lat.close()
+        say("  request %d %s %dx%d, %d steps" % (q.rid, q.kind, q.nx, q.ny, q.steps))
+        for a, b in zip(alone, by[q.rid].fields):
+            assert np.array_equal(a, b), "request %d (%s) differs alone vs served" % (q.rid, q.kind)
+        assert not by[q.rid].diverged

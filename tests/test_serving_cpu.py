@@ -35,7 +35,7 @@ class FakeExecutor:
     def finish(self, h, keep_fields=False):
         self.stepped[h["rid"]] = h["steps"]
         self.log.append(("finish", h["rid"]))
-        return {"n_diverged": 0.0}, None
+        return {"n_diverged": 0.0}, (("fields", h["rid"]) if keep_fields else None)
 
     def close(self, h):
         pass
@@ -146,3 +146,12 @@ def test_requests_with_a_tolerance_end_at_their_first_converged_check():
             assert at % reqs[rid].check == 0
     st = summarize(list(res.values()), wall=1.0)
     assert st["converged"] == 2 and st["with_tolerance"] == 3
+
+
+def test_fields_are_kept_for_all_none_or_the_listed_requests():
+    for keep, want in ((True, set(range(6))), (False, set()), ({1, 4}, {1, 4})):
+        s = Scheduler(FakeExecutor(), budget_bytes=10**9, quantum=16, keep_fields=keep,
+                      clock=Clock())
+        res = s.run([_req(k, 32, 20 + k) for k in range(6)])
+        assert {r.rid for r in res if r.fields is not None} == want
+        assert all(r.fields == ("fields", r.rid) for r in res if r.fields is not None)

@@ -7,20 +7,22 @@
 // (Eqs. 8-10) from the neighbours' moments at the same time level, the
 // regularized TRT collision, and one store per population.
 //
-// Work decomposition.  A wavefront owns an aligned strip of 64 columns and
-// marches down `rows` consecutive rows, lane l holding column 64*strip + l,
-// so every load and store of a population row is one aligned, fully used
-// segment.  The x-neighbours' Phi_x come from the adjacent lanes (cross-lane
-// shuffle); at the strip edges, lanes 0 and 63 also gather the two halo
-// columns 64*strip - 1 and 64*strip + 64 (a predicated gather with two
-// active lanes) to form their Phi_x;
-// the y-neighbours' Phi_y come from a register window (Phi_y of the row
-// below is kept from the previous iteration; the row above is gathered
-// while the current row's collision coefficients are formed, and becomes
-// the current row of the next iteration).  Each population is read once per node from HBM and written
-// once; the edge lanes and the first/last row of a strip re-read data that
-// neighbouring strips also read (served by L2).  No LDS, no barriers: waves
-// are independent.
+// Work decomposition (one column per lane; the two-column variant below
+// keeps the same structure with 128-column strips).  A wavefront owns an
+// aligned strip of 64 columns and marches down `rows` consecutive rows, lane
+// l holding column 64*strip + l, so every load and store of a population row
+// is one aligned, fully used segment.  The x-neighbours' Phi_x come from the
+// adjacent lanes (DPP whole-wave shifts); at the strip edges, lanes 0 and 63
+// also gather the two halo columns 64*strip - 1 and 64*strip + 64 (a
+// predicated gather with two active lanes) to form their Phi_x; the
+// y-neighbours' Phi_y come from a register window (Phi_y of the row below is
+// kept from the previous iteration; the row above is gathered while the
+// current row's collision coefficients are formed, and becomes the current
+// row of the next iteration).  Each population is read once per node from
+// HBM and written once; the edge lanes and the first/last row of a strip
+// re-read data that neighbouring strips also read (served by L2).  No LDS.
+// One-column wavefronts are independent; single-lattice two-column launches
+// keep the adjacent strips of a workgroup in step with one barrier per row.
 //
 // The gradient d_gamma Phi is the central difference of rho u_x^3 (rho u_y^3)
 // between the two neighbours in x (y) at time t; a solid neighbour
@@ -546,9 +548,10 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
                                            const OpenX<C> &ox) {
     if constexpr (HALVES) {
         static_assert(sizeof(T) == 2 && sizeof(C) == 4, "FP16 storage only");
-        // edge elements as words: lane 0 feeds node A's high half (a
-        // previous lane's node B), lane 63 node B's low half (a next lane's
-        // node A); pinned here as the FP16 path pins its conversions
+        // edge elements as words: lane 0 (and an odd width's last lane)
+        // feeds node A's high half (a previous lane's node B, or column 0),
+        // lane 63 node B's low half (a next lane's node A); pinned here as
+        // the FP16 path pins its conversions
         T e0 = r.edge[0], e1 = r.edge[1], e2 = r.edge[2];
         asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2));
         const uint32_t sh = c.edge_shift;

@@ -33,11 +33,21 @@ COPY_BYTES = 1 << 30
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}
 
 
+def code_of(text: str) -> str:
+    """C++ source without its comments, trailing blanks and blank lines
+    (the sweep sources hold no string literal with a comment marker)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def sweep_source_hash() -> str:
+    """Hash of the sweep's code (comments and blank lines excluded, so a
+    comment edit keeps profiles valid)."""
     h = hashlib.sha256()
     for p in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -75,3 +75,11 @@ def test_summary_scales_counters_by_the_copy_kernel(tmp_path, workload, link):
     md = open(out + ".md").read()
     assert ("--workload creeping" in md) == (workload == "creeping")
     assert json.load(open(out + "_hbm_counters.json")) == rec
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    from paper_2312_10318_amd.profiling import code_of
+    a = "int x;  // one\n// two\n\nint y;\n"
+    b = "int x;\n/* three\n   four */\nint y;   \n"
+    assert code_of(a) == code_of(b) == "int x;\nint y;"
+    assert code_of("int x;\nint z;\n") != code_of(a)

@@ -11,7 +11,6 @@ near 1.5e-3.  Multi-step FP16 runs are therefore held to 1e-3 in the L2 norm
 (the paper's error measure, Sec. III) and to 2e-3 in the max norm; single
 steps meet 1e-3 in both norms.
 """
-import math
 
 import numpy as np
 import pytest

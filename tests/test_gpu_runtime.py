@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from gpu_util import rel_errors, say
-from paper_2312_10318_amd import inputs, params
+from paper_2312_10318_amd import inputs
 
 pytestmark = pytest.mark.gpu
 

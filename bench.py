@@ -137,16 +137,21 @@ def run_batch(count=256, steps=5000, storage="f32", seed=0):
     """The batched workload: `count` independent periodic lattices (sides
     log-uniform in [64, 1024], half Taylor-Green and half double shear layer,
     Re log-uniform in [1e2, 1e7], tau_s2 uniform in [0.5, 2]) advanced by one
-    batched launch per step (graph-captured pairs)."""
+    batched launch per step (graph-captured pairs), in the launch shape the
+    autotuner picks on scratch copies of the members (before the timed
+    region)."""
     import torch
-    from paper_2312_10318_amd import inputs
+    from paper_2312_10318_amd import autotune, inputs
     from paper_2312_10318_amd.lattice import Batch, Lattice
     members = inputs.batch_workload(count, seed=seed)
     lats = []
     for k, m in enumerate(members):
         rho, ux, uy = inputs.member_fields(m, seed=k)
         lats.append(Lattice(m.n, m.n, m.tau1, m.tau2, storage=storage).init_equilibrium(rho, ux, uy))
+    tuned = autotune.tune_batch(lats)
+    table = {tuple(s): ms for s, ms in tuned["table"]}
     b = Batch(lats)
+    b.set_tuning(*tuned["best"])
     b.step(20)
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -164,6 +169,9 @@ def run_batch(count=256, steps=5000, storage="f32", seed=0):
     return {"instances": count, "steps": steps, "storage": storage, "nodes": nodes,
             "seconds": round(sec, 4), "solves_per_s": round(count / sec, 3),
             "aggregate_MLUPS": round(nodes * steps / sec / 1e6, 1),
+            "launch_shape": list(tuned["best"]),
+            "tuned_ms_per_step": round(tuned["ms"], 4),
+            "default_ms_per_step": round(table.get((0, 4, 0, 0), float("nan")), 4),
             "diverged_instances": len(bad),
             "diverged": ["%s n=%d Re=%.3g 1/tau2=%.3f" % (members[k].kind, members[k].n,
                                                          members[k].re, 1 / members[k].tau2)

@@ -4,8 +4,10 @@ For a lattice shape, storage type and mask presence it times the fused sweep
 over a grid of launch shapes (rows a wavefront marches, wavefronts per
 workgroup, XCD remap on/off, one or two columns per lane where two apply)
 on a scratch lattice of that shape, and keeps
-the fastest.  Results persist in a JSON cache keyed by GPU architecture,
-storage, mask presence and size bucket; the cache path is
+the fastest.  For a batch it times the batched step (rows, wavefronts per
+workgroup, XCD remap) on scratch copies of the members.  Results persist in
+a JSON cache keyed by GPU architecture, storage, mask presence and size
+buckets (for a batch: its member count and size mix); the cache path is
 $TRTLBM_TUNE_CACHE, else ~/.cache/trtlbm/tune.json.
 """
 from __future__ import annotations
@@ -126,6 +128,102 @@ def best_shape(nx: int, ny: int, storage: str = "f32", has_mask: bool = False,
         mask = np.zeros((ny, nx), np.uint8)
         mask[0] = mask[-1] = 1
     res = tune(nx, ny, storage, mask=mask, log=log)
+    cache[k] = {"best": res["best"], "ms": res["ms"], "when": res["when"]}
+    save_cache(cache)
+    return tuple(res["best"])
+
+
+# Batched launches: rows per wavefront (0: each member's own automatic
+# choice), wavefronts per workgroup (at most 4) and XCD remap; each member
+# keeps its column mode.
+BATCH_ROWS = (0, 4, 8, 16, 32)
+BATCH_WAVES = (1, 2, 4)
+
+
+def batch_candidates():
+    """Launch shapes (rows, waves per workgroup, XCD remap, columns) worth
+    timing for a batch."""
+    return [(r, w, x, 0) for r in BATCH_ROWS for w in BATCH_WAVES for x in REMAP]
+
+
+def batch_key(sizes, storage: str, has_mask: bool, arch: str = "gfx950") -> str:
+    """Cache key of a batch: storage, mask presence, member count and the
+    members' node counts in power-of-two buckets (the shape of the work, not
+    its exact sizes)."""
+    hist = {}
+    for nx, ny in sizes:
+        b = _bucket(int(round(math.sqrt(max(1, nx * ny)))))
+        hist[b] = hist.get(b, 0) + 1
+    comp = ",".join("%dx%d" % (b, hist[b]) for b in sorted(hist))
+    return "%s|%s|%s|batch|%d|%s" % (arch, storage, "mask" if has_mask else "open",
+                                     len(sizes), comp)
+
+
+def time_batch_shape(batch, shape, steps: int, warmup: int) -> float:
+    """Milliseconds per batched step for one launch shape."""
+    import torch
+    batch.set_tuning(*shape)
+    batch.step(warmup)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(batch.stream)
+    batch.step(steps)
+    end.record(batch.stream)
+    end.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def tune_batch(lattices, steps: int | None = None, shapes=None, log=None) -> dict:
+    """Time every candidate batch launch shape on scratch copies of the
+    members (same sizes, relaxation times, forces, masks, open boundaries
+    and storage, started at rest), so the batch's own state is untouched;
+    returns {"best": shape, "ms": ..., "table": [(shape, ms), ...]}."""
+    import numpy as np
+
+    from .lattice import Batch, Lattice
+    scratch = []
+    try:
+        for l in lattices:
+            mask = None if l.mask is None else l.mask.cpu().numpy()
+            s = Lattice(l.nx, l.ny, l.tau_s, l.tau_s2, g=l.g, mask=mask, storage=l.storage,
+                        device=l.device, inflow=l.inflow)
+            s.init_equilibrium(np.ones((l.ny, l.nx)), np.zeros((l.ny, l.nx)),
+                               np.zeros((l.ny, l.nx)))
+            scratch.append(s)
+        nodes = sum(l.nx * l.ny for l in lattices)
+        if steps is None:
+            steps = max(10, min(200, int(4e9 / max(1, nodes))))
+        b = Batch(scratch)
+        table = []
+        try:
+            for shape in shapes or batch_candidates():
+                ms = time_batch_shape(b, shape, steps, max(2, steps // 10))
+                table.append((list(shape), ms))
+                if log:
+                    log("tune batch of %d %s: %.4f ms" % (len(lattices), shape, ms))
+        finally:
+            b.close()
+    finally:
+        for s in scratch:
+            s.close()
+    table.sort(key=lambda t: t[1])
+    return {"best": table[0][0], "ms": table[0][1], "table": table,
+            "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+
+
+def best_batch_shape(lattices, autotune: bool = False, log=None):
+    """Cached best launch shape of a batch of these lattices, tuning (and
+    caching) on a miss when `autotune` is set; None when unknown (the
+    library default applies)."""
+    lats = list(lattices)
+    k = batch_key([(l.nx, l.ny) for l in lats], lats[0].storage,
+                  any(l.mask is not None or l.inflow is not None for l in lats))
+    cache = load_cache()
+    if k in cache:
+        return tuple(cache[k]["best"])
+    if not autotune:
+        return None
+    res = tune_batch(lats, log=log)
     cache[k] = {"best": res["best"], "ms": res["ms"], "when": res["when"]}
     save_cache(cache)
     return tuple(res["best"])

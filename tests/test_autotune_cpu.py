@@ -40,3 +40,17 @@ def test_build_reads_register_spills_from_compiler_remarks():
         "a.hip:9:1: remark:     VGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
     ])
     assert build.spills(text) == {"_Z5sweepv": 56, "_Z4initv": 0}
+
+
+def test_batch_candidates_and_key():
+    shapes = autotune.batch_candidates()
+    assert (0, 4, 0, 0) in shapes                       # the library's batch default
+    assert {w for _, w, _, _ in shapes} <= {1, 2, 4}     # batched workgroups hold at most 4
+    assert {c for _, _, _, c in shapes} == {0}           # members keep their column mode
+    assert len(shapes) == len(set(shapes))
+    a = autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f32", False)
+    b = autotune.batch_key([(1024, 1024), (64, 64), (1010, 1000)], "f32", False)
+    assert a == b                                        # order and small size changes
+    assert a != autotune.batch_key([(64, 64), (1000, 1000)], "f32", False)
+    assert a != autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f16", False)
+    assert a != autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f32", True)

@@ -265,3 +265,39 @@ def test_full_batch_workload_sampled_members_vs_oracle(L):
     b.close()
     for x in lats:
         x.close()
+
+
+def test_batch_autotune_leaves_members_untouched_and_results_unchanged(L):
+    """The batch tuner times every candidate shape on scratch copies of the
+    members: the members' state is untouched, the best shape is one of the
+    candidates, and a batch in that shape gives the bits of the default
+    shape."""
+    from paper_2312_10318_amd import autotune
+    members = inputs.batch_workload(6, seed=2, side_lo=40, side_hi=300, re_hi=1e4)
+
+    def make():
+        out = []
+        for k, m in enumerate(members):
+            rho, ux, uy = inputs.member_fields(m, seed=k)
+            out.append(L.Lattice(m.n, m.n, m.tau1, m.tau2, storage="f32")
+                       .init_equilibrium(rho, ux, uy))
+        return out
+    a, b = make(), make()
+    before = [_np(x.get_populations()) for x in a]
+    res = autotune.tune_batch(a, steps=10)
+    say("case: batch tuner, %d members: best %s %.4f ms" % (len(a), res["best"], res["ms"]))
+    assert tuple(res["best"]) in autotune.batch_candidates()
+    assert len(res["table"]) == len(autotune.batch_candidates())
+    for x, f in zip(a, before):
+        assert x.state()[1] == 0          # no member was stepped
+        assert np.array_equal(_np(x.get_populations()), f)
+    ba, bb = L.Batch(a), L.Batch(b)
+    ba.set_tuning(*res["best"])
+    ba.step(15)
+    bb.step(15)
+    for x, y in zip(a, b):
+        assert np.array_equal(_np(x.get_populations()), _np(y.get_populations()))
+    ba.close()
+    bb.close()
+    for x in a + b:
+        x.close()

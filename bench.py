@@ -119,9 +119,9 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def traffic_from_counters(n, storage):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current sweep source; else None."""
+def profile_record(n, storage):
+    """The committed rocprofv3 summary of this workload, if it was taken on
+    the current sweep source; else None."""
     try:
         with open(COUNTERS_FILE % (n, storage)) as fh:
             c = json.load(fh)
@@ -130,7 +130,14 @@ def traffic_from_counters(n, storage):
     if c.get("source_hash") != sweep_source_hash() or c.get("nodes") != n * n or \
             c.get("storage") != storage:
         return None
-    return c.get("hbm_bytes_per_launch")
+    return c
+
+
+def traffic_from_counters(n, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current sweep source; else None."""
+    c = profile_record(n, storage)
+    return None if c is None else c.get("hbm_bytes_per_launch")
 
 
 def run_batch(count=256, steps=5000, storage="f32", seed=0):
@@ -369,7 +376,13 @@ def main():
                      "traffic": traffic, "bytes_per_lu": BYTES_PER_LU[storage],
                      "kernel": ("sweep_pair_kernel<%s>" if cols == 2 else
                                 "sweep_single_kernel<%s,nomask>") % storage,
-                     "source_hash": sweep_source_hash()},
+                     "source_hash": sweep_source_hash(),
+                     # live average duration per launch (HIP events on the
+                     # sweep's stream) next to the traced one of the committed
+                     # rocprofv3 summary (traced dispatches run slightly slower)
+                     "avg_duration_us": round(ms * 1e3, 2),
+                     "profiled_avg_duration_us":
+                         (profile_record(n, storage) or {}).get("avg_duration_us")},
     }
     if not args.no_extra:
         rec["extra"] = run_extra(max(200, args.steps // 4))

@@ -126,7 +126,8 @@ def test_divergence_is_detected_from_a_forced_nan(L):
 def test_batch_matches_instances_alone_bitwise(L):
     """Instances of uneven size and parameters in one batch give exactly the
     bits they give alone (same launch shape)."""
-    specs = [(64, 64, 0.6, 3.0), (200, 130, 0.51, 0.7), (97, 33, 1.7, 1.2), (128, 256, 0.55, 1.6)]
+    specs = [(64, 64, 0.6, 3.0), (200, 130, 0.51, 0.7), (97, 33, 1.7, 1.2), (128, 256, 0.55, 1.6),
+             (131, 40, 0.8, 1.1), (385, 9, 0.7, 0.9)]
     alone, members = [], []
     for k, (nx, ny, t1, t2) in enumerate(specs):
         rng = np.random.default_rng(10 + k)
@@ -146,8 +147,9 @@ def test_batch_matches_instances_alone_bitwise(L):
     for a, m in zip(alone, members):
         assert a.state() == m.state()
         assert np.array_equal(_np(a.get_populations()), _np(m.get_populations()))
+    assert [m.tuning()[3] for m in members] == [1, 2, 1, 2, 2, 1]  # odd 131: two columns
     dg = batch.diagnostics()
-    assert dg.shape == (4, 8) and np.all(dg[:, 4] == 0)
+    assert dg.shape == (6, 8) and np.all(dg[:, 4] == 0)
     batch.close()
     for x in alone + members:
         x.close()

@@ -204,7 +204,7 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
 
 def run_extra(steps):
     """Companion measurements: the same lattice in FP16 and FP64 storage,
-    the batched workload, the serving stream (FP16 and FP32), the
+    the batched workload (FP32 and FP16), the serving stream (FP16 and FP32), the
     double-shear-layer stability study, the Taylor-Green convergence study
     and the Poiseuille slip study."""
     out = {}
@@ -219,6 +219,9 @@ def run_extra(steps):
         log("extra %s: %.1f MLUPS" % (storage, mlups))
     out["batch256_f32"] = run_batch()
     log("extra batch: %s" % out["batch256_f32"])
+    # the same batch in FP16 storage (set against single-instance FP64 above)
+    out["batch256_f16"] = run_batch(storage="f16")
+    log("extra batch f16: %s" % out["batch256_f16"])
     for storage in ("f16", "f32"):
         out["serving_" + storage] = run_serving(storage)
         log("extra serving %s: %s" % (storage, out["serving_" + storage]))

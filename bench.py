@@ -289,14 +289,35 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
     the creeping-flow lattice), then a plain copy of 1 GiB (known bytes) to
     scale the HBM counters."""
     import torch
-    if workload == "creeping":
-        lat = creeping_lattice(storage, tuning)
-        n = lat.nx
+    nodes = None
+    if workload == "batch":
+        # the benchmark's 256-member batch in the library's default batch shape
+        from paper_2312_10318_amd import inputs
+        from paper_2312_10318_amd.lattice import Batch, Lattice
+        members = inputs.batch_workload(256, seed=0)
+        lats = []
+        for k, m in enumerate(members):
+            rho, ux, uy = inputs.member_fields(m, seed=k)
+            lats.append(Lattice(m.n, m.n, m.tau1, m.tau2, storage=storage)
+                        .init_equilibrium(rho, ux, uy))
+        b = Batch(lats)
+        if tuning:
+            b.set_tuning(*tuning)
+        b.step(warmup + steps)
+        torch.cuda.synchronize()
+        b.close()
+        for l in lats:
+            l.close()
+        nodes = sum(m.n * m.n for m in members)
     else:
-        lat = tg_lattice(n, storage, tuning=tuning)
-    lat.step(warmup + steps)
-    torch.cuda.synchronize()
-    lat.close()
+        if workload == "creeping":
+            lat = creeping_lattice(storage, tuning)
+            n = lat.nx
+        else:
+            lat = tg_lattice(n, storage, tuning=tuning)
+        lat.step(warmup + steps)
+        torch.cuda.synchronize()
+        lat.close()
     src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -304,6 +325,7 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
     torch.cuda.synchronize()
     print(json.dumps({"profile": "done", "sweeps": warmup + steps, "copy_bytes": 1 << 30,
                       "copies": 3, "storage": storage, "n": n, "workload": workload,
+                      "nodes": nodes if nodes is not None else n * n,
                       "source_hash": sweep_source_hash()}), flush=True)
 
 
@@ -321,9 +343,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
-    ap.add_argument("--workload", default="tg", choices=["tg", "creeping"],
-                    help="lattice of --profile: the Taylor-Green benchmark (--n) or the "
-                         "creeping-flow cylinder of Table 1 (1050^2, link map)")
+    ap.add_argument("--workload", default="tg", choices=["tg", "creeping", "batch"],
+                    help="lattice of --profile: the Taylor-Green benchmark (--n), the "
+                         "creeping-flow cylinder of Table 1 (1050^2, link map) or the "
+                         "256-member batch")
     args = ap.parse_args()
 
     if args.gpus != 1:

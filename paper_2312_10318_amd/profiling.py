@@ -60,7 +60,8 @@ def _csv(d, suffix):
 
 
 def _is_sweep(name):
-    return "sweep_single_kernel" in name or "sweep_pair_kernel" in name
+    return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
+            "sweep_batch_kernel" in name)
 
 
 def _is_copy(name):
@@ -110,11 +111,13 @@ WORKLOADS = {
     "tg": ("Taylor-Green %dx%d", "taylor_green_%dx%d", 0),
     "creeping": ("creeping flow past a square cylinder (Sec. III.D), %dx%d, obstacle, "
                  "inflow wall and pressure outlet", "creeping_cylinder_%dx%d", 2),
+    "batch": ("the 256-member batch (Taylor-Green and double-shear-layer members, sides "
+              "64 to 1024, %d nodes in all, one launch per step)", "batch256", 0),
 }
 
 
 def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_prefix,
-              skip_first=2, run_log=None, workload="tg"):
+              skip_first=2, run_log=None, workload="tg", nodes=None):
     sweep_ns, copy_ns, kname = kernel_durations(trace_dir)
     fs, fc = counter_values(fetch_dir, "FETCH_SIZE")
     ws, wc = counter_values(write_dir, "WRITE_SIZE")
@@ -126,14 +129,20 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     fetch_b = avg(fs) * 1024.0 * fetch_scale
     write_b = avg(ws) * 1024.0 * write_scale
     title, wname, link_bytes = WORKLOADS[workload]
-    nodes = n * n
+    if workload == "batch":
+        if not nodes:
+            raise ValueError("the batch workload needs its node count")
+        label, wlabel = title % nodes, wname
+    else:
+        nodes = n * n
+        label, wlabel = title % (n, n), wname % (n, n)
     # 9 populations read and written (+ the link code read, with a link map)
     alg = (BYTES_PER_LU[storage] + link_bytes) * nodes
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"sweep_(single|pair)_kernel<[^>]*>", kname or "") or
+        "kernel": (re.search(r"sweep_(single|pair|batch)_kernel<[^>]*>", kname or "") or
                    re.search(r".*", "sweep")).group(0),
-        "workload": wname % (n, n), "storage": storage, "nodes": nodes,
+        "workload": wlabel, "storage": storage, "nodes": nodes,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
         "dispatches": len(sweep_ns), "avg_duration_us": round(dur * 1e6, 3),
         "algorithmic_bytes_per_launch": alg,
@@ -156,14 +165,16 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     with open(out_prefix + "_hbm_counters.json", "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(out_prefix + ".md", "w") as fh:
-        fh.write("# Fused sweep, %s, %s storage\n\n" % (title % (n, n), storage))
+        fh.write("# Fused sweep, %s, %s storage\n\n" % (label, storage))
         fh.write("Commands (run from the repository root, one profiler run each):\n\n")
         fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)
         fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --workload %s "
-                 "--storage %s --n %d --steps %d --warmup %d --out %s\n\n"
-                 % (workload, storage, n, steps, warmup, os.path.relpath(out_prefix, ROOT)))
+                 "--storage %s --n %d --steps %d --warmup %d%s --out %s\n\n"
+                 % (workload, storage, n, steps, warmup,
+                    " --nodes %d" % nodes if workload == "batch" else "",
+                    os.path.relpath(out_prefix, ROOT)))
         fh.write("| quantity | value |\n|---|---|\n")
         for k, v in rec.items():
             fh.write("| %s | %s |\n" % (k, v))
@@ -194,10 +205,13 @@ def main():
     ap.add_argument("--run-log", default=None,
                     help="stdout of the profiled bench.py run (carries the source hash the "
                          "profiled kernel was built from)")
+    ap.add_argument("--nodes", type=int, default=None,
+                    help="lattice updates per launch of the batch workload (printed by the "
+                         "profiled run)")
     a = ap.parse_args()
     rec = summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.storage, a.n, a.steps, a.warmup,
                     os.path.join(ROOT, a.out) if not os.path.isabs(a.out) else a.out,
-                    run_log=a.run_log, workload=a.workload)
+                    run_log=a.run_log, workload=a.workload, nodes=a.nodes)
     print(json.dumps(rec, indent=1))
 
 

@@ -128,9 +128,10 @@ def test_device_taylor_green_fields_equal_host_fields(L):
             assert np.array_equal(h, d.cpu().numpy())
 
 
-def test_full_serving_stream_sampled_requests_equal_results_alone(L):
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_full_serving_stream_sampled_requests_equal_results_alone(L, storage):
     """The benchmark's serving run as it is timed (Poisson arrivals at
-    200 solves/s for 2 s, FP16 storage, 64 GiB budget, quanta of 100 steps):
+    200 solves/s for 2 s, FP16 and FP32 storage, 64 GiB budget, quanta of 100 steps):
     a sample of requests of every kind, the largest Taylor-Green one
     included, gives bit for bit the result it gives alone."""
     from paper_2312_10318_amd import serving
@@ -140,18 +141,18 @@ def test_full_serving_stream_sampled_requests_equal_results_alone(L):
     for kind in ("cylinder", "poiseuille", "taylor_green"):
         ks = [q for q in reqs if q.kind == kind]
         pick.update(q.rid for q in (ks[0], ks[len(ks) // 2], max(ks, key=lambda q: q.nx * q.ny)))
-    ex = GpuExecutor("f16")
+    ex = GpuExecutor(storage)
     sched = Scheduler(ex, budget_bytes=64 << 30, quantum=100, keep_fields=pick)
     res = sched.run(reqs)
     ex.shutdown()
-    say("case: full serving stream, %d requests, peak active %d, %d sampled" %
-        (len(res), sched.peak_active, len(pick)))
+    say("case: full serving stream %s, %d requests, peak active %d, %d sampled" %
+        (storage, len(res), sched.peak_active, len(pick)))
     assert len(res) == len(reqs) and sched.peak_active >= 10
     by = {r.rid: r for r in res}
     for q in reqs:
         if q.rid not in pick:
             continue
-        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage="f16")
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage)
         rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
         lat.init_equilibrium(rho, ux, uy).step(q.steps)
         alone = [t.cpu().numpy() for t in lat.macros()]

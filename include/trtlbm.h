@@ -88,7 +88,7 @@ typedef enum {
  *  - the gradient of Phi = rho u^3 sees rho_in u_in^3 beyond the inflow
  *    wall and the last column's value beyond the outlet.
  * Neither rule includes the body force.  Open-boundary lattices run the
- * one-column sweep. */
+ * sweep with the link map (one or two columns per lane). */
 typedef struct {
     int32_t nx, ny;        /* lattice size, 1..46340 each; periodic in y (and x unless open) */
     double tau_s;          /* tau_s1 > 1/2: viscosity nu = (tau_s - 1/2)/3 (Sec. II.C) */

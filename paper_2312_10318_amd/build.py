@@ -64,5 +64,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+EXAMPLE_SRC = os.path.join(HERE, "examples", "taylor_green.cpp")
+EXAMPLE = os.path.join(HERE, "examples", "taylor_green")
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile the C-ABI example (host code only) against libtrtlbm.so."""
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O2", "-std=c++17", EXAMPLE_SRC, "-o", EXAMPLE,
+           "-L" + HERE, "-ltrtlbm", "-Wl,-rpath,$ORIGIN/.."]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the C-ABI example")
+    return EXAMPLE
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_example(verbose=True))

@@ -197,6 +197,30 @@ trt_status trt_macros(trt_sim *s, double *rho, double *ux, double *uy);
  * reduced in a fixed order (bitwise reproducible). */
 trt_status trt_diagnostics(trt_sim *s, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of trt_diagnostics for a population lattice the caller holds,
+ * with no simulation object and no allocation of any kind.
+ *  - p: the problem the lattice belongs to (validated as by trt_create; its
+ *    mask, if any, is read on the device).
+ *  - lattice: the lattice holding the current state (the one trt_state
+ *    names), 256-byte aligned, trt_lattice_bytes(p) bytes, storage p->storage.
+ *  - time: copied to out[7].
+ *  - out: device FP64 out[TRT_NDIAG], bitwise equal to trt_diagnostics on
+ *    the same state (same kernels, same fixed reduction order).
+ *  - hip_stream: the stream to enqueue on (NULL: the legacy default stream).
+ * Scratch: the reduction partials live in one static device array of 512 x
+ * TRT_NDIAG doubles (32 KiB) per GPU, held until the process ends; every
+ * lattice trt_create accepts needs exactly that many, and any other size or
+ * argument trt_create would refuse is rejected with TRT_EINVAL before any HIP
+ * call.  The first call on a device looks the array's address up there (a
+ * HIP call that must not run under stream capture: make one call on each
+ * device before capturing).  All calls on one GPU share the array: calls
+ * whose work overlaps on that GPU (different streams, no ordering between
+ * them) race and may return wrong sums; calls ordered on one stream do not. */
+trt_status trt_diagnostics_noalloc(const trt_problem *p, const void *lattice, int64_t time,
+                                   double *out, void *hip_stream);
+
 /* Mean of u_x over the fluid nodes of each row, FP64, into device
  * out[ny] (0 for a row without fluid) -- the slip measurement of Sec. III.C. */
 trt_status trt_row_mean_ux(trt_sim *s, double *out);

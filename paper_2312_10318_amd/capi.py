@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "TRT_OK", 1: "TRT_EINVAL", 2: "TRT_ENOMEM", 3: "TRT_EDEVICE",
 EXPORTED = [
     "trt_pitch", "trt_row_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
-    "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics", "trt_row_mean_ux",
+    "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics",
+    "trt_diagnostics_noalloc", "trt_row_mean_ux",
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_update",
     "trt_batch_step",
@@ -86,6 +87,7 @@ def load():
         "trt_step": (ctypes.c_int, [P, I64]),
         "trt_macros": (ctypes.c_int, [P, P, P, P]),
         "trt_diagnostics": (ctypes.c_int, [P, P]),
+        "trt_diagnostics_noalloc": (ctypes.c_int, [prob, P, I64, P, P]),
         "trt_row_mean_ux": (ctypes.c_int, [P, P]),
         "trt_wall_force": (ctypes.c_int, [P, P]),
         "trt_velocity_change": (ctypes.c_int, [P, P, P, P]),
@@ -178,6 +180,12 @@ def trt_macros(sim: int, rho: int, ux: int, uy: int) -> None:
 
 def trt_diagnostics(sim: int, out: int) -> None:
     _check(load().trt_diagnostics(sim, out), "trt_diagnostics")
+
+
+def trt_diagnostics_noalloc(p: trt_problem, lattice: int, time: int, out: int,
+                            stream: int) -> None:
+    _check(load().trt_diagnostics_noalloc(ctypes.byref(p), lattice, time, out, stream),
+           "trt_diagnostics_noalloc")
 
 
 def trt_wall_force(sim: int, out: int) -> None:

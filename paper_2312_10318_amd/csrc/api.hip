@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -267,6 +268,37 @@ size_t link_alloc_bytes(int32_t nx, int32_t ny) {
 }
 }  // namespace
 
+namespace {
+// The descriptor of a problem over the lattices f_a, f_b (no link map yet;
+// tiled for the default launch shape by the caller).
+void fill_desc(InstDesc &d, const trt_problem *p, void *f_a, void *f_b) {
+    d.buf[0] = f_a;
+    d.buf[1] = f_b;
+    d.mask = p->mask;
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.plane = trt_pitch(p->nx, p->storage);
+    d.pitch = (int32_t)trt_row_stride(p->nx, p->storage);
+    d.cur = 0;
+    d.cols = 1;
+    d.omega1 = 1.0 - 1.0 / p->tau_s;
+    d.omega2 = 1.0 - 1.0 / p->tau_s2;
+    d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
+    d.gx = p->gx;
+    d.gy = p->gy;
+    d.xbc = p->x_boundary == TRT_X_INFLOW_OUTFLOW ? 1 : 0;
+    d.pad2_ = 0;
+    d.u_in = d.xbc ? p->u_in : 0.0;
+    d.rho_in = d.xbc ? p->rho_in : 1.0;
+    d.rho_out = d.xbc ? p->rho_out : 1.0;
+    d.links = nullptr;
+    d.lpitch = link_pitch(p->nx);
+    d.rowsum = nullptr;
+    d.nsum = summary_count(p->nx);
+    d.pad3_ = 0;
+}
+}  // namespace
+
 size_t trt_footprint_bytes(const trt_problem *p) {
     const size_t lat = trt_lattice_bytes(p);
     if (lat == 0) return 0;
@@ -297,30 +329,7 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
     s->cur = 0;
     s->time = 0;
     InstDesc &d = s->desc;
-    d.buf[0] = f_a;
-    d.buf[1] = f_b;
-    d.mask = p->mask;
-    d.nx = p->nx;
-    d.ny = p->ny;
-    d.plane = trt_pitch(p->nx, p->storage);
-    d.pitch = (int32_t)trt_row_stride(p->nx, p->storage);
-    d.cur = 0;
-    d.cols = 1;
-    d.omega1 = 1.0 - 1.0 / p->tau_s;
-    d.omega2 = 1.0 - 1.0 / p->tau_s2;
-    d.phi = 1.0 - 1.0 / (2.0 * p->tau_s);
-    d.gx = p->gx;
-    d.gy = p->gy;
-    d.xbc = p->x_boundary == TRT_X_INFLOW_OUTFLOW ? 1 : 0;
-    d.pad2_ = 0;
-    d.u_in = d.xbc ? p->u_in : 0.0;
-    d.rho_in = d.xbc ? p->rho_in : 1.0;
-    d.rho_out = d.xbc ? p->rho_out : 1.0;
-    d.links = nullptr;
-    d.lpitch = link_pitch(p->nx);
-    d.rowsum = nullptr;
-    d.nsum = summary_count(p->nx);
-    d.pad3_ = 0;
+    fill_desc(d, p, f_a, f_b);
 
     hipError_t e = hipMalloc((void **)&s->scratch, (size_t)(trt::diag_partial_count() + 1) *
                                                       TRT_NDIAG * sizeof(double));
@@ -439,6 +448,77 @@ trt_status trt_diagnostics(trt_sim *s, double *out) {
     if (!out) return fail(TRT_EINVAL, "out is NULL");
     TRT_HIP(trt::launch_diagnostics(s->desc, s->prob.storage, s->cur, s->scratch, out,
                                     (double)s->time, s->stream));
+    return TRT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- diagnostics without allocation
+//
+// trt_diagnostics_noalloc keeps its reduction partials in one file-scope
+// device array.  Host code never passes the array's name to a kernel (on the
+// host it names a stand-in, not device memory): the first call on a device
+// resolves the array's address there with hipGetSymbolAddress, and every
+// later call on that device uses the resolved pointer.
+namespace {
+constexpr size_t kNoAllocDoubles = 512 * TRT_NDIAG;  // 32 KiB per GPU
+__device__ __align__(256) double noalloc_scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kMaxDevices];  // device address of noalloc_scratch, per device
+
+// The array's address on device `dev` (made current for the lookup).
+trt_status noalloc_scratch_on(int dev, double **ptr) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TRT_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        int prev = -1;
+        TRT_HIP(hipGetDevice(&prev));
+        if (prev != dev) TRT_HIP(hipSetDevice(dev));
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (prev != dev) {
+            hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(noalloc_scratch)");
+        if (!p) return fail(TRT_EDEVICE, "hipGetSymbolAddress returned NULL");
+        g_noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return TRT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+trt_status trt_diagnostics_noalloc(const trt_problem *p, const void *lattice, int64_t time,
+                                   double *out, void *hip_stream) {
+    trt_status st = check_problem(p);
+    if (st != TRT_OK) return st;
+    if (!lattice || !out) return fail(TRT_EINVAL, "lattice and out are required");
+    if (!aligned(lattice, 256)) return fail(TRT_EINVAL, "the lattice must be 256-byte aligned");
+    if (time < 0) return fail(TRT_EINVAL, "time must be >= 0");
+    const size_t need = (size_t)trt::diag_partial_count() * TRT_NDIAG;
+    if (need > kNoAllocDoubles)
+        return fail(TRT_EINVAL, "diagnostics need more partials than the static scratch holds");
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    int dev = -1;
+    if (stream) {
+        hipDevice_t sd;
+        TRT_HIP(hipStreamGetDevice(stream, &sd));
+        dev = (int)sd;
+    } else {
+        TRT_HIP(hipGetDevice(&dev));
+    }
+    double *partials = nullptr;
+    st = noalloc_scratch_on(dev, &partials);
+    if (st != TRT_OK) return st;
+    InstDesc d;
+    fill_desc(d, p, const_cast<void *>(lattice), const_cast<void *>(lattice));
+    // every partial is written before it is read: nothing needs clearing
+    TRT_HIP(trt::launch_diagnostics(d, p->storage, 0, partials, out, (double)time, stream));
     return TRT_OK;
 }
 

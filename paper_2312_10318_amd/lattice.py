@@ -69,6 +69,7 @@ class Lattice:
         self.inflow = None if inflow is None else tuple(float(v) for v in inflow)
         prob = problem(self.nx, self.ny, self.tau_s, self.tau_s2, self.g, storage,
                        self.mask.data_ptr() if self.mask is not None else None, self.inflow)
+        self.prob = prob  # the C problem struct (its mask pointer stays valid with self.mask)
         nbytes = capi.trt_lattice_bytes(prob)
         if nbytes == 0:
             capi.trt_create(prob, 0, 0, 0)  # raises with the validation message

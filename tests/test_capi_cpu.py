@@ -111,3 +111,16 @@ def test_open_boundary_problem_is_valid(lib):
     p = capi.trt_problem(16, 16, 0.6, 1.0, 0.0, 0.0, None, 1, capi.TRT_X_INFLOW_OUTFLOW, 0.01,
                          1.0, 1.0)
     assert capi.trt_lattice_bytes(p) == 9 * 16 * capi.trt_pitch(16, 1) * 4
+
+
+def test_diagnostics_noalloc_validates_before_any_device_call(lib):
+    p = capi.trt_problem(16, 16, 0.6, 1.0, 0.0, 0.0, None, 1)
+    bad = capi.trt_problem(0, 16, 0.6, 1.0, 0.0, 0.0, None, 1)
+    for prob, lat, t, out, msg in [(bad, 4096, 0, 8192, "nx and ny"),
+                                   (p, 0, 0, 8192, "required"),
+                                   (p, 4096, 0, 0, "required"),
+                                   (p, 4096 + 8, 0, 8192, "aligned"),
+                                   (p, 4096, -1, 8192, "time")]:
+        with pytest.raises(capi.TrtError) as e:
+            capi.trt_diagnostics_noalloc(prob, lat, t, out, 0)
+        assert e.value.status == capi.TRT_EINVAL and msg in str(e.value)

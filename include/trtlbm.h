@@ -161,7 +161,9 @@ size_t trt_footprint_bytes(const trt_problem *p);
  * change (the sweep reads the link map derived from it on the stream at
  * creation).  EINVAL on a NULL or
  * misaligned pointer, a size out of range, tau_s <= 1/2, tau_s2 < 1/2 or a
- * non-finite parameter. */
+ * non-finite parameter.  With a mask or open x boundaries the link map
+ * (2 * ny * (nx rounded up to 128) bytes) must stay below 4 GiB, which
+ * excludes nx > 46336 together with ny > 46218. */
 trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stream,
                       trt_sim **out);
 

@@ -89,6 +89,15 @@ trt_status check_problem(const trt_problem *p) {
     if (!isfinite(p->gx) || !isfinite(p->gy)) return fail(TRT_EINVAL, "g must be finite");
     if (p->x_boundary != TRT_X_PERIODIC && p->x_boundary != TRT_X_INFLOW_OUTFLOW)
         return fail(TRT_EINVAL, "x_boundary must be TRT_X_PERIODIC or TRT_X_INFLOW_OUTFLOW");
+    // The link map of a lattice with a mask or open x boundaries (two bytes
+    // per node, rows of nx rounded up to 128 codes) is read through one
+    // buffer resource, whose byte range and offsets are 32-bit: it must stay
+    // below 4 GiB (this excludes only nx > 46336 with ny > 46218).
+    if ((p->mask != nullptr || p->x_boundary == TRT_X_INFLOW_OUTFLOW) &&
+        2 * (uint64_t)p->ny * (((uint64_t)p->nx + 127) / 128 * 128) >= (1ull << 32))
+        return fail(TRT_EINVAL,
+                    "with a mask or open x boundaries, 2 * ny * (nx rounded up to 128) must be "
+                    "below 2^32 (the link map's 4 GiB limit)");
     if (p->x_boundary == TRT_X_INFLOW_OUTFLOW) {
         if (p->nx < 2) return fail(TRT_EINVAL, "open x boundaries need nx >= 2");
         if (!isfinite(p->u_in) || !isfinite(p->rho_in) || !isfinite(p->rho_out) ||

@@ -425,8 +425,10 @@ template <class T> struct PtrAccess {
     __device__ __forceinline__ void st(int64_t e, uint32_t v, T x) const { st_at<T>(p + e, v, x); }
 };
 
-// Access to the link map (at most 2 x 46340^2 bytes: one buffer resource).
-// Offsets are in elements (16-bit codes).
+// Access to the link map through one buffer resource: trt_create refuses
+// problems whose map would reach 4 GiB, so the byte range and the byte
+// offsets 2 * (row * lpitch + col) below fit in 32 bits.  Offsets are in
+// elements (16-bit codes).
 struct LinkAccess {
     __amdgpu_buffer_rsrc_t r;
     __device__ __forceinline__ LinkAccess(const uint16_t *base, uint64_t elems) {

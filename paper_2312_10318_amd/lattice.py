@@ -74,11 +74,15 @@ class Lattice:
         if nbytes == 0:
             capi.trt_create(prob, 0, 0, 0)  # raises with the validation message
         self.lattice_bytes = nbytes
-        self.fa = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.fb = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # allocated on the lattice's stream, where every sweep runs: the
+        # caching allocator then reuses this memory only in that stream's
+        # order once it is released
+        with torch.cuda.stream(self.stream):
+            self.fa = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.fb = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._diag = torch.empty(capi.TRT_NDIAG, dtype=torch.float64, device=self.device)
         self.handle = capi.trt_create(prob, self.fa.data_ptr(), self.fb.data_ptr(),
                                       self.stream.cuda_stream)
-        self._diag = torch.empty(capi.TRT_NDIAG, dtype=torch.float64, device=self.device)
 
     # ---------------------------------------------------------------- helpers
     def _dev64(self, a, shape):

@@ -124,3 +124,24 @@ def test_diagnostics_noalloc_validates_before_any_device_call(lib):
         with pytest.raises(capi.TrtError) as e:
             capi.trt_diagnostics_noalloc(prob, lat, t, out, 0)
         assert e.value.status == capi.TRT_EINVAL and msg in str(e.value)
+
+
+@pytest.mark.parametrize("nx,ny,masked,xb,ok", [
+    (46340, 46340, True, 0, False),    # link map 2 * 46340 * 46464 B > 4 GiB
+    (46340, 46340, False, 1, False),   # open x boundaries need the link map too
+    (46337, 46219, True, 0, False),
+    (46336, 46340, True, 0, True),     # 2 * 46340 * 46336 B < 4 GiB
+    (46340, 46218, True, 0, True),     # 2 * 46218 * 46464 B < 4 GiB
+    (46340, 46219, True, 0, False),
+    (46340, 46340, False, 0, True),    # no link map: only the side limit applies
+])
+def test_link_map_limit_at_the_largest_sides(lib, nx, ny, masked, xb, ok):
+    p = capi.trt_problem(nx, ny, 0.6, 1.0, 0.0, 0.0, 4096 if masked else None, 1, xb, 0.01,
+                         1.0, 1.0)
+    if ok:
+        assert capi.trt_lattice_bytes(p) == ny * 9 * capi.trt_pitch(nx, 1) * 4
+        return
+    assert capi.trt_lattice_bytes(p) == 0 and capi.trt_footprint_bytes(p) == 0
+    with pytest.raises(capi.TrtError) as e:
+        capi.trt_create(p, 4096, 1 << 40, 0)
+    assert e.value.status == capi.TRT_EINVAL and "link map" in str(e.value)

@@ -373,21 +373,24 @@ static int collide_field(int nx, int ny, const uint8_t *solid, const double *fin
     return 0;
 }
 
-/* One time step with an inflow wall at x = -1/2 and a pressure outlet at
+/* Post-collision populations fstar[9][ny][nx] of the state fin: the
+ * collision of every fluid node as in orc_step (0 at solid nodes), with the
+ * open-end values of Phi (R19) when open_x is set.  Returns 0 or -1.     */
+int orc_collide(int nx, int ny, const uint8_t *solid, const double *fin, double *fstar,
+                double tau1, double tau2, double gx, double gy, int open_x, double u_in,
+                double rho_w) {
+    return collide_field(nx, ny, solid, fin, fstar, tau1, tau2, gx, gy, open_x, u_in, rho_w);
+}
+
+/* Streaming of post-collision populations fstar into the pre-collision
+ * state fout with an inflow wall at x = -1/2 and a pressure outlet at
  * x = nx - 1 (R17-R20), periodic in y, half-way bounce-back at solid nodes:
- * collision as in orc_step, then streaming f_i(x + e_i) = f*_i(x) inside
- * the lattice, the moving-wall return at the inlet, loss through the
- * outlet, and Zou and He's rule for the outlet's incoming populations.   */
-int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, double *fout,
-                  double tau1, double tau2, double gx, double gy, double u_in, double rho_w,
-                  double rho_out) {
+ * f_i(x + e_i) = f*_i(x) inside the lattice, the moving-wall return at the
+ * inlet, loss through the outlet, and Zou and He's rule for the outlet's
+ * incoming populations.                                                  */
+void orc_stream_open(int nx, int ny, const uint8_t *solid, const double *fstar, double *fout,
+                     double u_in, double rho_w, double rho_out) {
     const long n = (long)nx * ny;
-    double *fstar = (double *)malloc(sizeof(double) * Q * n);
-    if (!fstar) return -1;
-    if (collide_field(nx, ny, solid, fin, fstar, tau1, tau2, gx, gy, 1, u_in, rho_w) != 0) {
-        free(fstar);
-        return -1;
-    }
     for (long k = 0; k < (long)Q * n; ++k) fout[k] = 0.0;
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
@@ -423,6 +426,21 @@ int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, doubl
         fout[7 * n + k] = f[5] + 0.5 * (f[2] - f[4]) - 1.0 / 6.0 * rho_out * ux;
         fout[6 * n + k] = f[8] - 0.5 * (f[2] - f[4]) - 1.0 / 6.0 * rho_out * ux;
     }
+}
+
+/* One time step with the open x boundaries: orc_collide with the open-end
+ * Phi, then orc_stream_open.                                             */
+int orc_step_open(int nx, int ny, const uint8_t *solid, const double *fin, double *fout,
+                  double tau1, double tau2, double gx, double gy, double u_in, double rho_w,
+                  double rho_out) {
+    const long n = (long)nx * ny;
+    double *fstar = (double *)malloc(sizeof(double) * Q * n);
+    if (!fstar) return -1;
+    if (collide_field(nx, ny, solid, fin, fstar, tau1, tau2, gx, gy, 1, u_in, rho_w) != 0) {
+        free(fstar);
+        return -1;
+    }
+    orc_stream_open(nx, ny, solid, fstar, fout, u_in, rho_w, rho_out);
     free(fstar);
     return 0;
 }

@@ -87,3 +87,32 @@ def test_open_ends_do_not_see_each_other(orc):
     assert np.array_equal(sa[:, :, -1], sc[:, :, -1])
     # control: the columns next to the changed ones do change
     assert not np.array_equal(sa[:, :, -3], sb[:, :, -3])
+
+
+def test_collide_then_stream_open_is_step_open(orc):
+    """The two halves the oracle exposes compose to its open step exactly."""
+    rng = np.random.default_rng(11)
+    nx, ny = 14, 9
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[3:5, 6:8] = 1
+    f = inputs.random_populations(rng, (ny, nx))
+    f[:, mask.astype(bool)] = 0.0
+    tau1, tau2, u = 0.7, 1.3, 0.02
+    want = orc.step_open(f, tau1, tau2, u, 1.01, 0.99, 1e-5, -2e-6, mask)
+    fs = orc.collide(f, tau1, tau2, 1e-5, -2e-6, mask, True, u, 1.01)
+    assert np.array_equal(orc.stream_open(fs, u, 1.01, 0.99, mask), want)
+    assert np.all(fs[:, mask.astype(bool)] == 0.0)
+
+
+def test_periodic_collide_streams_into_step(orc):
+    """Without solids, rolling each post-collision plane by e_i gives the
+    periodic step exactly."""
+    rng = np.random.default_rng(12)
+    f = inputs.random_populations(rng, (7, 10))
+    tau1, tau2, gx, gy = 0.65, 2.0, 3e-6, 1e-6
+    fs = orc.collide(f, tau1, tau2, gx, gy)
+    want = orc.step(f, tau1, tau2, gx, gy)
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    got = np.stack([np.roll(fs[i], (ey[i], ex[i]), axis=(0, 1)) for i in range(9)])
+    assert np.array_equal(got, want)

@@ -47,8 +47,9 @@ def test_small_cylinder_drag_matches_oracle(L):
     say("case: cylinder n=%d D=%d tau1=%.4f tau2=%.4f u0=%.4e" % (c.n, c.D, c.tau1, c.tau2, c.u0))
     lat = L.Lattice(c.n, c.n, c.tau1, c.tau2, mask=mask, storage="f64",
                     inflow=(c.u0, 1.0, 1.0))
-    lat.init_equilibrium(*creeping.initial_fields(c, mask))
-    f0 = lat.get_populations().cpu().numpy()
+    fields = creeping.initial_fields(c, mask)
+    lat.init_equilibrium(*fields)
+    f0 = oracle.init_equilibrium(*fields, mask)
     lat.step(1500)
     fx, fy = lat.wall_force()
     lat.close()

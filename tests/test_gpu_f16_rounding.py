@@ -3,7 +3,8 @@ value once.
 
 The sweep stores g_i = f*_i - w_i (the shifted form; the weights w_i of
 Sec. II.B) in FP16 and computes in FP32.  Starting from a state that is
-exactly representable in the storage (read back after set_populations), the
+exactly representable in the storage (the seeded state rounded to FP16 (f - w)
+on the host, which is exactly what set_populations stores), the
 FP64 oracle's post-collision g_i is the exact value up to FP64 rounding; the
 stored g_i must then lie within half an FP16 unit in the last place of it,
 plus a margin for the FP32 arithmetic before the final rounding (terms of
@@ -22,6 +23,7 @@ outputs 0 there; the sweep leaves them untouched).
 import numpy as np
 import pytest
 
+import f16_harness
 import oracle
 from gpu_util import say
 from paper_2312_10318_amd import inputs
@@ -73,7 +75,7 @@ def test_fp16_one_step_rounds_each_population_once(L, nx, ny, walls, cols):
     f, mask, g, tau1, tau2 = _case(17 + nx + int(walls), nx, ny, walls)
     lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f16").set_populations(f)
     assert lat.tuning()[3] == cols
-    f0 = lat.get_populations().cpu().numpy()
+    f0 = f16_harness.to_f16_storage(f, mask)
     lat.step(1)
     f1 = lat.get_populations().cpu().numpy()
     lat.close()

@@ -2,16 +2,19 @@
 momentum exchange with solid nodes and the steady-state velocity change,
 against the oracle (Sec. III.D set-up).
 
-The GPU state after set_populations already follows the outlet rule (the
-outlet's three incoming populations are not stored), so each comparison
-starts the oracle from the state the GPU reads back.  FP64 populations are
-held to 1e-14; FP32 / FP16 velocities to 1e-5 / 1e-3 (relative max).
+A lattice with open x boundaries does not store the outlet's three incoming
+populations (the outlet rule recomputes them from the others), so a random
+state is first made consistent by one oracle step (whose outlet populations
+follow the rule); the GPU and the oracle then both start from that state
+(for FP32 / FP16 storage rounded on the host as the storage holds it).  No
+oracle input is read back from the GPU.  FP64 populations are held to
+1e-14; FP32 / FP16 velocities to 1e-5 / 1e-3 (relative max and L2).
 """
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import TOL, rel_errors, say
+from gpu_util import TOL, rel_errors, say, stored_state
 from paper_2312_10318_amd import inputs, params
 
 pytestmark = pytest.mark.gpu
@@ -28,6 +31,12 @@ def L():
 
 def _np(t):
     return t.detach().cpu().numpy()
+
+
+def _consistent(f, mask, tau1, tau2, inflow, g=(0.0, 0.0)):
+    """One oracle step from a random state: its outlet populations follow
+    the outlet rule, as a GPU lattice's always do."""
+    return oracle.step_open(f, tau1, tau2, inflow[0], inflow[1], inflow[2], g[0], g[1], mask)
 
 
 def _case(seed, nx, ny, obstacle=True):
@@ -58,10 +67,10 @@ def test_open_boundaries_random_state_fp64(L, shape, tiling):
     f, mask, tau1, tau2, inflow = _case(hash((shape, tiling)) % 997, nx, ny)
     say("case: open %dx%d mask=%s tiling=%s inflow=%s" % (nx, ny, mask is not None, tiling,
                                                            inflow))
+    f0 = _consistent(f, mask, tau1, tau2, inflow)
     lat = L.Lattice(nx, ny, tau1, tau2, mask=mask, storage="f64", inflow=inflow)
     lat.set_tuning(*tiling)
-    lat.set_populations(f)
-    f0 = _np(lat.get_populations())
+    lat.set_populations(f0)
     lat.step(6)
     got = _np(lat.get_populations())
     lat.close()
@@ -84,24 +93,28 @@ def test_uniform_inflow_stays_uniform(L, storage):
     lat.close()
     err = max(np.max(np.abs(u - u0)) / u0, np.max(np.abs(v)) / u0, np.max(np.abs(r - 1)))
     say("case: uniform inflow %s: max deviation %.3e" % (storage, err))
-    assert err < {"f64": 1e-13, "f32": 1e-5, "f16": 2e-3}[storage]
+    assert err < {"f64": 1e-13, "f32": 1e-5, "f16": 1e-3}[storage]
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_open_boundaries_shifted_storage_one_step(L, storage):
     nx, ny = 70, 13
     f, mask, tau1, tau2, inflow = _case(21, nx, ny)
+    fc = _consistent(f, mask, tau1, tau2, inflow)
     lat = L.Lattice(nx, ny, tau1, tau2, mask=mask, storage=storage, inflow=inflow)
-    lat.set_populations(f)
-    f0 = _np(lat.get_populations())
+    lat.set_populations(fc)
     lat.step(1)
     _, u, v = (_np(t) for t in lat.macros())
     lat.close()
+    # the stored state: f - w rounded (at the open ends the GPU rounds the
+    # inflow slots without the wall's correction and recomputes the outlet's
+    # three populations from rounded values: within one storage step)
+    f0 = stored_state(fc, storage, mask)
     _, ur, vr = oracle.macros(oracle.step_open(f0, tau1, tau2, inflow[0], inflow[1], inflow[2],
                                                mask=mask), mask=mask)
     emax, el2 = rel_errors(u, v, ur, vr)
     say("case: open %dx%d %s one step: rel max %.3e rel L2 %.3e" % (nx, ny, storage, emax, el2))
-    assert emax <= TOL[storage]
+    assert emax <= TOL[storage] and el2 <= TOL[storage]
 
 
 @pytest.mark.parametrize("open_x", [False, True])
@@ -111,11 +124,15 @@ def test_wall_force_matches_oracle(L, open_x):
     mask[8:12, 20:26] = 1
     f[:, mask.astype(bool)] = 0.0
     g = (0.0, 0.0) if open_x else (2e-5, -1e-5)
+    if open_x:
+        f = _consistent(f, mask, tau1, tau2, inflow)
+        f2 = oracle.run_open(f, 3, tau1, tau2, u_in=inflow[0], rho_w=inflow[1],
+                             rho_out=inflow[2], mask=mask)
+    else:
+        f2 = oracle.run(f, 3, tau1, tau2, g[0], g[1], mask)
     lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f64",
                     inflow=inflow if open_x else None)
-    lat.set_populations(f).step(3)
-    f2 = _np(lat.get_populations())
-    lat.step(1)
+    lat.set_populations(f).step(4)
     fx, fy = lat.wall_force()
     lat.close()
     ref = oracle.wall_force(f2, tau1, tau2, g[0], g[1], mask=mask, open_x=open_x,
@@ -126,25 +143,32 @@ def test_wall_force_matches_oracle(L, open_x):
     assert abs(fx - ref[0]) < 1e-13 * scale and abs(fy - ref[1]) < 1e-13 * scale
 
 
-def test_velocity_change_matches_the_fields(L):
+def test_velocity_change_matches_the_oracle(L):
+    """The on-device steady-state test (Sec. III convergence criterion)
+    equals the same sums formed on the host from the oracle's fields at the
+    two times; the previous field is then replaced by the current one."""
     import torch
     nx, ny = 64, 24
     rho, ux, uy = inputs.taylor_green(nx, 0.02, seed=3)
     rho, ux, uy = rho[:ny], ux[:ny], uy[:ny]
-    lat = L.Lattice(nx, ny, 0.7, 1.0, storage="f64").init_equilibrium(rho, ux, uy).step(5)
+    tau1, tau2 = 0.7, 1.0
+    lat = L.Lattice(nx, ny, tau1, tau2, storage="f64").init_equilibrium(rho, ux, uy).step(5)
     _, u0, v0 = lat.macros()
     prev = (u0.clone(), v0.clone())
     lat.step(7)
-    _, u1, v1 = lat.macros()
     mx, s2, n2, p2 = lat.velocity_change(prev)
-    du, dv = _np(u1) - _np(u0), _np(v1) - _np(v0)
+    f5 = oracle.run(oracle.init_equilibrium(rho, ux, uy), 5, tau1, tau2)
+    _, a0, b0 = oracle.macros(f5)
+    _, a1, b1 = oracle.macros(oracle.run(f5, 7, tau1, tau2))
+    du, dv = a1 - a0, b1 - b0
     want = (max(np.abs(du).max(), np.abs(dv).max()), float((du ** 2 + dv ** 2).sum()),
-            float((_np(u1) ** 2 + _np(v1) ** 2).sum()))
-    say("case: velocity change: GPU %s, fields %s" % ((mx, s2, n2), want))
-    assert mx == pytest.approx(want[0], rel=1e-12)
+            float((a1 ** 2 + b1 ** 2).sum()), float((a0 ** 2 + b0 ** 2).sum()))
+    say("case: velocity change: GPU %s, oracle %s" % ((mx, s2, n2, p2), want))
+    assert mx == pytest.approx(want[0], rel=1e-11)
     assert s2 == pytest.approx(want[1], rel=1e-10)
     assert n2 == pytest.approx(want[2], rel=1e-12)
-    assert p2 == pytest.approx(float((_np(u0) ** 2 + _np(v0) ** 2).sum()), rel=1e-12)
+    assert p2 == pytest.approx(want[3], rel=1e-12)
+    _, u1, v1 = lat.macros()
     assert torch.equal(prev[0], u1) and torch.equal(prev[1], v1)
     lat.close()
 

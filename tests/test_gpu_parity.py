@@ -4,19 +4,18 @@ Tolerances on the velocity (relative max and relative L2, both stated for
 every run): 1e-12 for FP64 storage, 1e-5 for FP32 (f - w) storage, 1e-3 for
 FP16 (f - w) storage.  Each test prints the case and the measured errors.
 
-FP16 storage keeps 11 significant bits of f - w, about 5e-4 of the local
-velocity per stored population and step; over a 1000-step run that
-quantisation noise gives a relative L2 error near 5e-4 and a max-norm error
-near 1.5e-3.  Multi-step FP16 runs are therefore held to 1e-3 in the L2 norm
-(the paper's error measure, Sec. III) and to 2e-3 in the max norm; single
-steps meet 1e-3 in both norms.
+Every oracle run starts from the seeded input (for FP32 / FP16 storage,
+rounded on the host exactly as set_populations stores it), never from a
+state read back from the GPU.  Multi-step FP16 runs, whose error against the
+unrounded oracle is set by the format itself, are checked against an
+FP16-rounded oracle in test_gpu_f16_harness.py.
 """
 
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import TOL, rel_errors, say
+from gpu_util import TOL, rel_errors, say, stored_state
 from paper_2312_10318_amd import inputs, params
 
 pytestmark = pytest.mark.gpu
@@ -35,7 +34,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_taylor_green_64_1000_steps(L, storage):
     """Taylor-Green 64 x 64, u0 = 0.01, tau_s = 0.6, Lambda_s = 1/4 (Sec. III.B),
     1000 steps, against the oracle."""
@@ -49,8 +48,7 @@ def test_taylor_green_64_1000_steps(L, storage):
     _, ur, vr = oracle.macros(oracle.run(oracle.init_equilibrium(rho, ux, uy), steps, tau1, tau2))
     emax, el2 = rel_errors(u, v, ur, vr)
     say("  rel max %.3e  rel L2 %.3e  (tol %.0e)" % (emax, el2, TOL[storage]))
-    assert el2 <= TOL[storage]
-    assert emax <= (2 * TOL[storage] if storage == "f16" else TOL[storage])
+    assert el2 <= TOL[storage] and emax <= TOL[storage]
     lat.close()
 
 
@@ -225,9 +223,9 @@ def test_two_column_strips_with_walls_shifted_storage(L, storage, nx):
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_two_column_strips_shifted_storage(L, storage, nx):
     """FP32 / FP16 storage with two columns per lane on an even and an odd
-    width that are not strip multiples: 50 steps, bit for bit equal to the
-    one-column sweep, and one step within the storage tolerance of the
-    oracle."""
+    width that are not strip multiples: one step within the storage
+    tolerance of the oracle, then 50 more steps bit for bit equal to the
+    one-column sweep."""
     ny = 41
     f, _, g, tau1, tau2 = _random_problem(11, nx, ny, with_mask=False)
     out = {}
@@ -235,19 +233,19 @@ def test_two_column_strips_shifted_storage(L, storage, nx):
         lat = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage)
         lat.set_tuning(8, 2, 1, cols)
         assert lat.tuning()[3] == cols
-        lat.set_populations(f).step(50)
-        f0 = _np(lat.get_populations())
-        lat.step(1)
-        out[cols] = (f0, [_np(t) for t in lat.macros()])
+        lat.set_populations(f).step(1)
+        first = [_np(t) for t in lat.macros()]
+        lat.step(50)
+        out[cols] = (first, _np(lat.get_populations()))
         lat.close()
-    same = all(np.array_equal(a, b) for a, b in zip(out[1][1], out[2][1]))
+    same = all(np.array_equal(a, b) for a, b in zip(out[1][0], out[2][0]))
     say("case: pair %dx%d %s: equal to one-column sweep: %s" % (nx, ny, storage, same))
-    assert np.array_equal(out[1][0], out[2][0]) and same
-    f0 = out[2][0]
+    assert np.array_equal(out[1][1], out[2][1]) and same
+    f0 = stored_state(f, storage)
     _, ur, vr = oracle.macros(oracle.step(f0, tau1, tau2, g[0], g[1]), g[0], g[1])
-    emax, el2 = rel_errors(out[2][1][1], out[2][1][2], ur, vr)
+    emax, el2 = rel_errors(out[2][0][1], out[2][0][2], ur, vr)
     say("  one step vs oracle: rel max %.3e rel L2 %.3e" % (emax, el2))
-    assert emax <= TOL[storage]
+    assert emax <= TOL[storage] and el2 <= TOL[storage]
 
 
 def test_workgroup_size_in_effect(L):
@@ -305,7 +303,7 @@ def test_random_state_shifted_storage_one_step(L, storage):
     nx, ny = 131, 37
     f, mask, g, tau1, tau2 = _random_problem(5, nx, ny)
     lat = L.Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage=storage).set_populations(f)
-    f0 = _np(lat.get_populations())
+    f0 = stored_state(f, storage, mask)
     lat.step(1)
     _, u, v = (_np(t) for t in lat.macros())
     _, ur, vr = oracle.macros(oracle.step(f0, tau1, tau2, g[0], g[1], mask), g[0], g[1], mask)
@@ -337,8 +335,8 @@ def test_poiseuille_channel_vs_oracle(L, N, g):
     lat = L.Lattice(nx, N + 2, tau1, tau2, g=(g, 0.0), mask=mask, storage="f64")
     lat.init_equilibrium(rho, ux, uy).step(3000)
     got = _np(lat.get_populations())
+    _, u, v = (_np(t) for t in lat.macros())
     want = oracle.run(oracle.init_equilibrium(rho, ux, uy, mask), 3000, tau1, tau2, g, 0.0, mask)
-    _, u, v = oracle.macros(got, g, 0.0, mask)
     _, ur, vr = oracle.macros(want, g, 0.0, mask)
     emax, el2 = rel_errors(u, v, ur, vr)
     ferr = np.max(np.abs(got - want))
@@ -385,43 +383,31 @@ def test_poiseuille_slip_on_gpu(L, tau1, lam, uc):
     del torch
 
 
-def _one_step_full_size(L, storage, rho, ux, uy, tau1, tau2, warm, tuning=None):
+def _full_size_run(L, storage, rho, ux, uy, tau1, tau2, steps, tuning=None):
+    """GPU and oracle from the same seeded fields over `steps` steps (the
+    oracle from the fields' equilibrium rounded as the storage holds it)."""
     n = rho.shape[0]
     lat = L.Lattice(n, n, tau1, tau2, storage=storage)
     if tuning:
         lat.set_tuning(*tuning)
-    lat.init_equilibrium(rho, ux, uy).step(warm)
-    f0 = _np(lat.get_populations())
-    lat.step(1)
+    lat.init_equilibrium(rho, ux, uy).step(steps)
     _, u, v = (_np(t) for t in lat.macros())
     lat.close()
-    _, ur, vr = oracle.macros(oracle.step(f0, tau1, tau2))
+    f0 = stored_state(oracle.init_equilibrium(rho, ux, uy), storage)
+    _, ur, vr = oracle.macros(oracle.run(f0, steps, tau1, tau2))
     return rel_errors(u, v, ur, vr)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_double_shear_layer_1024_full_size_step(L, storage):
-    """Double shear layer 1024^2 (Sec. III.A set-up, U0 = 0.04, kappa = 80,
-    delta = 0.05, Re = 1e5, 1/tau_s2 = 1.6): after 100 GPU steps, one more
-    GPU step equals the oracle's step from the same state."""
-    n, u0 = 1024, 0.04
-    tau1 = params.tau_from_re(u0, n, 1e5)
-    rho, ux, uy = inputs.double_shear_layer(n, u0)
-    emax, el2 = _one_step_full_size(L, storage, rho, ux, uy, tau1, 1 / 1.6, 100)
-    say("case: DSL 1024^2 %s one step: rel max %.3e rel L2 %.3e" % (storage, emax, el2))
-    assert emax <= TOL[storage] and el2 <= TOL[storage]
-
-
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_taylor_green_4096_full_size_step(L, storage):
+def test_taylor_green_4096_full_size_steps(L, storage):
     """The roofline workload (Taylor-Green 4096^2, tau_s = 0.6,
-    Lambda_s = 1/4) in the benchmark's launch shape: one GPU step equals the
-    oracle's step from the same state."""
+    Lambda_s = 1/4) in the benchmark's launch shape: two GPU steps equal two
+    oracle steps from the same seeded state."""
     n, tau1 = 4096, 0.6
     rho, ux, uy = inputs.taylor_green(n, 0.01, seed=0)
-    emax, el2 = _one_step_full_size(L, storage, rho, ux, uy, tau1,
-                                    params.tau2_from_magic(tau1, 0.25), 10)
-    say("case: TG 4096^2 %s one step: rel max %.3e rel L2 %.3e" % (storage, emax, el2))
+    emax, el2 = _full_size_run(L, storage, rho, ux, uy, tau1,
+                               params.tau2_from_magic(tau1, 0.25), 2)
+    say("case: TG 4096^2 %s two steps: rel max %.3e rel L2 %.3e" % (storage, emax, el2))
     assert emax <= TOL[storage] and el2 <= TOL[storage]
 
 

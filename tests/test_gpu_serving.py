@@ -3,7 +3,8 @@ result of running it alone, whatever shared its launches."""
 import numpy as np
 import pytest
 
-from gpu_util import say
+import oracle
+from gpu_util import TOL, rel_errors, say
 from paper_2312_10318_amd import inputs, params
 from paper_2312_10318_amd.serving import Request, Scheduler, summarize
 
@@ -71,6 +72,21 @@ def test_served_results_equal_results_alone(L, storage):
         for a, b in zip(alone, got):
             assert np.array_equal(a, b), "request %d (%s) differs alone vs served" % (q.rid, q.kind)
         assert not by[q.rid].diverged
+    if storage != "f32":
+        return
+    # the first served request of each kind against the FP64 oracle run of
+    # the same problem (FP32 storage tolerance, relative max and L2)
+    for kind in ("cylinder", "poiseuille", "taylor_green"):
+        q = next(r for r in reqs if r.kind == kind)
+        rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
+        f = oracle.run(oracle.init_equilibrium(rho, ux, uy, q.mask), q.steps, q.tau1, q.tau2,
+                       q.g[0], q.g[1], q.mask)
+        _, ur, vr = oracle.macros(f, q.g[0], q.g[1], q.mask)
+        _, u, v = by[q.rid].fields
+        emax, el2 = rel_errors(u, v, ur, vr)
+        say("  served %s %dx%d, %d steps, vs oracle: rel max %.3e L2 %.3e"
+            % (kind, q.nx, q.ny, q.steps, emax, el2))
+        assert emax <= TOL["f32"] and el2 <= TOL["f32"]
 
 
 def test_converged_requests_equal_results_alone(L):

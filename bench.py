@@ -56,6 +56,21 @@ def time_steps(lat, steps, warmup):
     return start.elapsed_time(end) / steps
 
 
+def time_probe(lat, launches, warmup=3):
+    """Average time per launch (ms) of the access-pattern probe on the
+    lattice's stream (the probe scrambles the lattice)."""
+    import torch
+    lat.pattern_probe(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.pattern_probe(launches)
+    end.record(lat.stream)
+    end.synchronize()
+    return start.elapsed_time(end) / launches
+
+
 def tg_lattice(n, storage, tau1=0.6, lam=0.25, tuning=None):
     from paper_2312_10318_amd import inputs, params
     from paper_2312_10318_amd.lattice import Lattice
@@ -178,7 +193,7 @@ def run_batch(count=256, steps=5000, storage="f32", seed=0):
             "aggregate_MLUPS": round(nodes * steps / sec / 1e6, 1),
             "launch_shape": list(tuned["best"]),
             "tuned_ms_per_step": round(tuned["ms"], 4),
-            "default_ms_per_step": round(table.get((0, 4, 0, 0), float("nan")), 4),
+            "default_ms_per_step": round(table.get((0, 4, 0, 0, -1, 1), float("nan")), 4),
             "diverged_instances": len(bad),
             "diverged": ["%s n=%d Re=%.3g 1/tau2=%.3f" % (members[k].kind, members[k].n,
                                                          members[k].re, 1 / members[k].tau2)
@@ -315,7 +330,11 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
             n = lat.nx
         else:
             lat = tg_lattice(n, storage, tuning=tuning)
-        lat.step(warmup + steps)
+        if workload == "stream":
+            # the sweep's access pattern without its arithmetic
+            lat.pattern_probe(warmup + steps)
+        else:
+            lat.step(warmup + steps)
         torch.cuda.synchronize()
         lat.close()
     src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -343,10 +362,11 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
-    ap.add_argument("--workload", default="tg", choices=["tg", "creeping", "batch"],
+    ap.add_argument("--workload", default="tg", choices=["tg", "creeping", "batch", "stream"],
                     help="lattice of --profile: the Taylor-Green benchmark (--n), the "
-                         "creeping-flow cylinder of Table 1 (1050^2, link map) or the "
-                         "256-member batch")
+                         "creeping-flow cylinder of Table 1 (1050^2, link map), the "
+                         "256-member batch, or the access-pattern probe on the benchmark "
+                         "lattice (the sweep's loads and stores without its arithmetic)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -369,7 +389,12 @@ def main():
     lat = tg_lattice(n, storage, tuning=tuning)
     ms = time_steps(lat, args.steps, args.warmup)
     stable = lat.check()
-    rows, waves, remap, cols = lat.tuning()
+    rows, waves, remap, cols, graph_steps = lat.tuning()
+    probe_ms = None
+    if cols == 2 and n % 128 == 0:
+        # the same launch shape moving the same bytes without the arithmetic
+        # (scrambles the lattice, which is not used afterwards)
+        probe_ms = time_probe(lat, max(10, args.steps))
     lat.close()
     lups = n * n / (ms * 1e-3)
     mlups = lups / 1e6
@@ -395,7 +420,8 @@ def main():
         "config": {"workload": "taylor_green_%dx%d" % (n, n), "storage": storage + "_shifted"
                    if storage != "f64" else "f64", "tau_s": 0.6, "tau_s2": 3.0, "u0": 0.01,
                    "nodes": n * n, "launch": {"rows_per_wave": rows, "waves_per_block": waves,
-                                              "xcd_remap": remap, "cols_per_lane": cols},
+                                              "xcd_remap": remap, "cols_per_lane": cols,
+                                              "graph_steps": graph_steps},
                    "stable": bool(stable)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -410,6 +436,16 @@ def main():
                      "profiled_avg_duration_us":
                          (profile_record(n, storage) or {}).get("avg_duration_us")},
     }
+    if probe_ms is not None:
+        probe_gbs = bytes_launch / (probe_ms * 1e-3) / 1e9
+        rec["roofline"]["access_pattern"] = {
+            "kernel": "pattern_probe_kernel<%s>" % storage,
+            "avg_duration_us": round(probe_ms * 1e3, 2),
+            "achieved": round(probe_gbs, 1), "frac": round(probe_gbs / HBM_PEAK_GBS, 4),
+            "sweep_over_pattern": round(achieved / probe_gbs, 4)}
+        log("bench: access-pattern probe %.4f ms/launch, %.1f GB/s (%.1f%% of peak); the sweep "
+            "reaches %.1f%% of it" % (probe_ms, probe_gbs, 100 * probe_gbs / HBM_PEAK_GBS,
+                                      100 * achieved / probe_gbs))
     if not args.no_extra:
         rec["extra"] = run_extra(max(200, args.steps // 4))
     if not args.no_cpu:

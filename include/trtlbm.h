@@ -120,6 +120,21 @@ typedef struct {
     int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default
                                 (on for one simulation, off for a batch) */
     int32_t cols_per_lane;   /* 1 or 2 columns per lane (0: 2 where it applies and nx >= 128) */
+    /* Batches only (ignored for one simulation; rows_per_wave > 0 overrides
+     * both): how members are cut into work items of one wavefront each. */
+    int32_t batch_items;     /* 0: default; -1: every member keeps the rows it would have
+                                alone; n > 0: one batch-wide cap on the rows, the longest
+                                (a power of two in 4..256) that still leaves at least n work
+                                items -- members no taller than the cap sweep their whole
+                                height as one item per strip, taller ones in equal blocks */
+    int32_t batch_order;     /* 0: default; 1: member by member; 2: costliest items (rows x
+                                columns) first, so short items fill in at the end */
+    int32_t graph_steps;     /* longest captured HIP graph, in sweeps: a power of two in
+                                2..1024 (0: default, 64).  trt_step / trt_batch_step replay
+                                whole graphs of this length, then one graph per binary digit
+                                of the rest (graphs of 2, 4, ... sweeps, captured at first
+                                use): the GPU idles ~8 us at each graph boundary and ~0.2 us
+                                between the sweeps inside one graph. */
 } trt_tuning;
 
 typedef struct trt_sim trt_sim;
@@ -187,9 +202,22 @@ trt_status trt_set_populations(trt_sim *s, const double *f);
 trt_status trt_get_populations(trt_sim *s, double *f);
 
 /* Advance nsteps >= 0 time steps (Eq. 2 followed by streaming), enqueued on
- * the stream as a captured HIP graph of two sweeps plus at most one plain
- * launch. */
+ * the stream as replays of captured HIP graphs (see trt_tuning.graph_steps)
+ * plus at most one plain launch; any split of the steps gives the same
+ * bits. */
 trt_status trt_step(trt_sim *s, int64_t nsteps);
+
+/* A measurement aid, not a step of the method: nsweeps launches that move
+ * the lattice holding the state to the other one (alternating) with the
+ * access pattern of the simulation's sweep -- its launch shape, the pull's
+ * nine population-row loads per lattice row (rows y, y - 1, y + 1 by
+ * population), the strip edges' extra loads, nine stores per row, one
+ * barrier per row -- and none of its arithmetic.  Its time per launch is the
+ * bandwidth ceiling of the sweep's access pattern on the same lattice.  The
+ * populations are scrambled: set the state again before stepping.  EINVAL
+ * unless the lattice is open and periodic, nx is a multiple of 128, it fits
+ * 4 GiB and the sweep runs two columns per lane. */
+trt_status trt_pattern_probe(trt_sim *s, int64_t nsweeps);
 
 /* rho and He-shifted u (Eq. 13) at time t into device FP64 [ny][nx];
  * 0 at solid nodes.  Any of the three pointers may be NULL. */
@@ -279,7 +307,8 @@ trt_status trt_batch_create(int32_t n, trt_sim *const *sims, trt_batch **out);
  * at every change of the active set. */
 trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
 
-/* Advance every member nsteps steps (graph-captured pairs of launches). */
+/* Advance every member nsteps steps (replays of captured graphs of batched
+ * launches as for trt_step, plus at most one plain launch). */
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps);
 
 /* Diagnostics of every member into device out[n][TRT_NDIAG]. */

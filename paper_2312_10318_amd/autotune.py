@@ -133,17 +133,26 @@ def best_shape(nx: int, ny: int, storage: str = "f32", has_mask: bool = False,
     return tuple(res["best"])
 
 
-# Batched launches: rows per wavefront (0: each member's own automatic
-# choice), wavefronts per workgroup (at most 4) and XCD remap; each member
-# keeps its column mode.
-BATCH_ROWS = (0, 4, 8, 16, 32)
-BATCH_WAVES = (1, 2, 4)
+# Batched launches: rows per wavefront (0: per the row policy below),
+# wavefronts per workgroup (at most 4) and XCD remap; each member keeps its
+# column mode.  Row policies (trt_tuning.batch_items): -1 each member's own
+# automatic rows; n > 0 one batch-wide cap leaving at least n work items
+# (members no taller than the cap in one item per strip).  Orders
+# (batch_order): 1 member by member, 2 costliest items first.
+BATCH_ROWS = (4, 8, 16, 32)
+BATCH_WAVES = (2, 4)
+BATCH_ITEMS = (-1, 16384, 32768)
+BATCH_ORDERS = (1, 2)
 
 
 def batch_candidates():
-    """Launch shapes (rows, waves per workgroup, XCD remap, columns) worth
-    timing for a batch."""
-    return [(r, w, x, 0) for r in BATCH_ROWS for w in BATCH_WAVES for x in REMAP]
+    """Launch shapes (rows, waves per workgroup, XCD remap, columns, row
+    policy, order) worth timing for a batch: uniform rows, and the two row
+    policies in both orders."""
+    out = [(r, w, x, 0, 0, 1) for r in BATCH_ROWS for w in BATCH_WAVES for x in REMAP]
+    out += [(0, w, x, 0, i, o) for i in BATCH_ITEMS for o in BATCH_ORDERS for w in BATCH_WAVES
+            for x in REMAP]
+    return out
 
 
 def batch_key(sizes, storage: str, has_mask: bool, arch: str = "gfx950") -> str:

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrtlbm.so")
-SOURCES = ["api.hip", "sweep.hip", "fields.hip"]
+SOURCES = ["api.hip", "sweep.hip", "fields.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -56,7 +56,8 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libtrtlbm.so")
-    spilled = {k: n for k, n in spills(r.stderr).items() if n > 0 and "sweep" in k}
+    spilled = {k: n for k, n in spills(r.stderr).items()
+               if n > 0 and ("sweep" in k or "probe" in k)}
     if spilled:
         os.remove(tmp)
         raise RuntimeError("sweep kernels spill registers to scratch memory: %s" % spilled)

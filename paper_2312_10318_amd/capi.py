@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "TRT_OK", 1: "TRT_EINVAL", 2: "TRT_ENOMEM", 3: "TRT_EDEVICE",
 EXPORTED = [
     "trt_pitch", "trt_row_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
-    "trt_get_populations", "trt_step", "trt_macros", "trt_diagnostics",
+    "trt_get_populations", "trt_step", "trt_pattern_probe", "trt_macros", "trt_diagnostics",
     "trt_diagnostics_noalloc", "trt_row_mean_ux",
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_update",
@@ -47,7 +47,9 @@ class trt_problem(ctypes.Structure):
 
 class trt_tuning(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
+                ("batch_items", ctypes.c_int32), ("batch_order", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
 
 class TrtError(RuntimeError):
@@ -85,6 +87,7 @@ def load():
         "trt_set_populations": (ctypes.c_int, [P, P]),
         "trt_get_populations": (ctypes.c_int, [P, P]),
         "trt_step": (ctypes.c_int, [P, I64]),
+        "trt_pattern_probe": (ctypes.c_int, [P, I64]),
         "trt_macros": (ctypes.c_int, [P, P, P, P]),
         "trt_diagnostics": (ctypes.c_int, [P, P]),
         "trt_diagnostics_noalloc": (ctypes.c_int, [prob, P, I64, P, P]),
@@ -147,15 +150,15 @@ def trt_create(p: trt_problem, f_a: int, f_b: int, stream: int) -> int:
 
 
 def trt_set_tuning(sim: int, rows_per_wave: int = 0, waves_per_block: int = 0,
-                   xcd_remap: int = -1, cols_per_lane: int = 0) -> None:
-    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
+                   xcd_remap: int = -1, cols_per_lane: int = 0, graph_steps: int = 0) -> None:
+    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane, 0, 0, graph_steps)
     _check(load().trt_set_tuning(sim, ctypes.byref(t)), "trt_set_tuning")
 
 
 def trt_get_tuning(sim: int) -> tuple:
     t = trt_tuning()
     _check(load().trt_get_tuning(sim, ctypes.byref(t)), "trt_get_tuning")
-    return t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane
+    return t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane, t.graph_steps
 
 
 def trt_init_equilibrium(sim: int, rho: int, ux: int, uy: int) -> None:
@@ -172,6 +175,10 @@ def trt_get_populations(sim: int, f: int) -> None:
 
 def trt_step(sim: int, nsteps: int) -> None:
     _check(load().trt_step(sim, nsteps), "trt_step")
+
+
+def trt_pattern_probe(sim: int, nsweeps: int) -> None:
+    _check(load().trt_pattern_probe(sim, nsweeps), "trt_pattern_probe")
 
 
 def trt_macros(sim: int, rho: int, ux: int, uy: int) -> None:
@@ -243,8 +250,10 @@ def trt_batch_diagnostics(batch: int, out: int) -> None:
 
 
 def trt_batch_set_tuning(batch: int, rows_per_wave: int = 0, waves_per_block: int = 0,
-                         xcd_remap: int = -1, cols_per_lane: int = 0) -> None:
-    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
+                         xcd_remap: int = -1, cols_per_lane: int = 0, batch_items: int = 0,
+                         batch_order: int = 0, graph_steps: int = 0) -> None:
+    t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane, batch_items,
+                   batch_order, graph_steps)
     _check(load().trt_batch_set_tuning(batch, ctypes.byref(t)), "trt_batch_set_tuning")
 
 

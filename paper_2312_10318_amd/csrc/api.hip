@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -58,12 +59,21 @@ trt_status guarded(F &&body) noexcept {
 
 // Default launch shape: rows per wave chosen per lattice (auto_rows), four
 // wavefronts per workgroup, XCD-contiguous workgroup order.
-constexpr Launch kDefaultLaunch = {0, 0, 1, 0};
+// Sweeps per captured graph: graphs of 2, 4, ..., graph_steps sweeps are
+// captured as needed (graph level k holds 2^(k+1) sweeps), and trt_step
+// replays whole graphs of graph_steps sweeps, then one graph per binary digit
+// of the rest.  Between sweeps inside one graph the GPU idles ~0.2 us, at a
+// graph boundary ~8 us (kernel trace of 126 double-shear-layer lattices of
+// 128^2, FP64, 62 us per batched sweep: 4.1 us per step with two-sweep graphs,
+// 0.25 with 128); 4096^2 FP32 214.0 -> 210.9 us per step.
+constexpr int kMaxGraphLevels = 10;  // up to 1024 sweeps per graph
+constexpr int kDefaultGraphSteps = 64;
+constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps};
 // Batches: no XCD remap by default.  A batch's work list runs member by
 // member, and spreading each member's items over all XCDs (the hardware's
 // round-robin) measured 3% faster than giving XCDs contiguous ranges of the
 // list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
-constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0};
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -131,6 +141,23 @@ trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) 
             return fail(TRT_EINVAL, "cols_per_lane must be 0 (automatic), 1 or 2");
         l.cols_per_lane = t->cols_per_lane;
     }
+    if (t->batch_items != 0) {
+        if (t->batch_items < -1 || t->batch_items > (1 << 24))
+            return fail(TRT_EINVAL, "batch_items must be 0 (default), -1 or lie in [1, 2^24]");
+        l.batch_items = t->batch_items;
+    }
+    if (t->batch_order != 0) {
+        if (t->batch_order != 1 && t->batch_order != 2)
+            return fail(TRT_EINVAL, "batch_order must be 0 (default), 1 or 2");
+        l.batch_order = t->batch_order;
+    }
+    if (t->graph_steps != 0) {
+        const int g = t->graph_steps;
+        if (g < 2 || g > (2 << (kMaxGraphLevels - 1)) || (g & (g - 1)) != 0)
+            return fail(TRT_EINVAL,
+                        "graph_steps must be 0 (default) or a power of two in [2, 1024]");
+        l.graph_steps = g;
+    }
     return TRT_OK;
 }
 
@@ -146,7 +173,9 @@ struct trt_sim {
     double *scratch;  // diagnostics partials + one TRT_NDIAG result
     uint16_t *links;  // link map (mask or open x boundaries), else null
     hipStream_t cap_stream;
-    hipGraphExec_t pair;  // captured sweeps 0 -> 1 -> 0
+    // captured graphs: level k holds 2^(k+1) sweeps, starting and ending on
+    // lattice 0 (null until first used)
+    hipGraphExec_t graphs[kMaxGraphLevels];
     bool in_batch;
 };
 
@@ -180,7 +209,7 @@ struct trt_batch {
     int nitems;
     int parity;  // steps taken by the batch, mod 2
     hipStream_t cap_stream;
-    hipGraphExec_t pair;
+    hipGraphExec_t graphs[kMaxGraphLevels];  // level k: 2^(k+1) batched sweeps
 };
 
 namespace {
@@ -190,6 +219,41 @@ void release_graph(hipGraphExec_t &g) {
         (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
+}
+
+void release_graphs(hipGraphExec_t (&gs)[kMaxGraphLevels]) {
+    for (hipGraphExec_t &g : gs) release_graph(g);
+}
+
+// Graph level of a power-of-two sweep count >= 2.
+int graph_level(int64_t sweeps) {
+    int k = 0;
+    while (((int64_t)2 << k) < sweeps) ++k;
+    return k;
+}
+
+// Replay an even number of sweeps through the graph ladder: whole graphs of
+// the top level, then one graph per remaining binary digit.  `ensure(k)`
+// captures level k if needed.
+template <class Ensure>
+trt_status replay_ladder(int64_t nsteps, int64_t graph_steps, hipGraphExec_t (&gs)[kMaxGraphLevels],
+                         hipStream_t stream, Ensure ensure) {
+    const int top = graph_level(graph_steps);
+    const int64_t big = (int64_t)2 << top;
+    if (nsteps >= big) {
+        trt_status st = ensure(top);
+        if (st != TRT_OK) return st;
+        for (int64_t k = 0; k < nsteps / big; ++k) TRT_HIP(hipGraphLaunch(gs[top], stream));
+        nsteps %= big;
+    }
+    for (int k = top - 1; k >= 0; --k) {
+        if (nsteps & ((int64_t)2 << k)) {
+            trt_status st = ensure(k);
+            if (st != TRT_OK) return st;
+            TRT_HIP(hipGraphLaunch(gs[k], stream));
+        }
+    }
+    return TRT_OK;
 }
 
 // Capture `body` (which enqueues work on the given stream) into an
@@ -213,8 +277,10 @@ template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F bo
     return TRT_OK;
 }
 
-trt_status sim_capture(trt_sim *s) {
-    release_graph(s->pair);
+// Capture `sweeps` (even) sweeps of a simulation, starting from lattice 0,
+// into `out`.
+trt_status sim_capture(trt_sim *s, hipGraphExec_t &out, int64_t sweeps) {
+    release_graph(out);
     if (!s->cap_stream) {
         hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -224,10 +290,12 @@ trt_status sim_capture(trt_sim *s) {
     }
     const int st = s->prob.storage;
     const bool m = s->prob.mask != nullptr;
-    return capture(s->cap_stream, s->pair, [&](hipStream_t cs) {
-        hipError_t e = trt::launch_sweep(s->desc, st, m, 0, s->launch, cs);
-        if (e != hipSuccess) return e;
-        return trt::launch_sweep(s->desc, st, m, 1, s->launch, cs);
+    return capture(s->cap_stream, out, [&](hipStream_t cs) {
+        for (int64_t k = 0; k < sweeps; ++k) {
+            hipError_t e = trt::launch_sweep(s->desc, st, m, (int)(k & 1), s->launch, cs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     });
 }
 
@@ -369,14 +437,14 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
 }
 
 trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
-    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     Launch l;
     trt_status st = check_launch(t, l, kDefaultLaunch);
     if (st != TRT_OK) return st;
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
     s->launch = l;
     trt::tile(s->desc, l, s->prob.storage);
-    release_graph(s->pair);
+    release_graphs(s->graphs);
     return TRT_OK;
 }
 
@@ -387,6 +455,9 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     t->waves_per_block = trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
     t->xcd_remap = s->launch.xcd_remap;
     t->cols_per_lane = s->desc.cols;
+    t->batch_items = 0;
+    t->batch_order = 0;
+    t->graph_steps = s->launch.graph_steps;
     return TRT_OK;
 }
 
@@ -429,18 +500,38 @@ trt_status trt_step(trt_sim *s, int64_t nsteps) {
         ++s->time;
         --nsteps;
     }
+    // every graph holds an even number of sweeps, so each replay starts and
+    // ends on lattice 0
     if (nsteps >= 2) {
-        if (!s->pair) {
-            trt_status cs = sim_capture(s);
-            if (cs != TRT_OK) return cs;
-        }
-        for (int64_t k = 0; k < nsteps / 2; ++k) TRT_HIP(hipGraphLaunch(s->pair, s->stream));
-        s->time += nsteps / 2 * 2;
+        const int64_t even = nsteps / 2 * 2;
+        trt_status rs = replay_ladder(even, s->launch.graph_steps, s->graphs, s->stream,
+                                      [&](int k) -> trt_status {
+                                          if (s->graphs[k]) return TRT_OK;
+                                          return sim_capture(s, s->graphs[k], (int64_t)2 << k);
+                                      });
+        if (rs != TRT_OK) return rs;
+        s->time += even;
     }
     if (nsteps % 2) {
         TRT_HIP(trt::launch_sweep(s->desc, st, m, 0, s->launch, s->stream));
         s->cur = 1;
         ++s->time;
+    }
+    return TRT_OK;
+}
+
+trt_status trt_pattern_probe(trt_sim *s, int64_t nsweeps) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (nsweeps < 0) return fail(TRT_EINVAL, "nsweeps must be >= 0");
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    const InstDesc &d = s->desc;
+    if (d.cols != 2 || d.nx % 128 != 0 || d.links != nullptr ||
+        !trt::buffer_addressable(d, s->prob.storage))
+        return fail(TRT_EINVAL, "the pattern probe needs an open periodic lattice of at most "
+                                "4 GiB, nx a multiple of 128, swept with two columns per lane");
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        TRT_HIP(trt::launch_pattern_probe(d, s->prob.storage, s->cur, s->launch, s->stream));
+        s->cur ^= 1;
     }
     return TRT_OK;
 }
@@ -591,7 +682,7 @@ trt_status trt_state(const trt_sim *s, int32_t *current, int64_t *time) {
 
 void trt_destroy(trt_sim *s) {
     if (!s) return;
-    release_graph(s->pair);
+    release_graphs(s->graphs);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->scratch) (void)hipFree(s->scratch);
     if (s->links) (void)hipFree(s->links);
@@ -639,17 +730,57 @@ static hipError_t grow_pinned(E *&p, size_t &cap, size_t need, std::vector<void 
 // device-wide wait is needed: launches already enqueued read the old tables
 // first (stream order).  Only a staging slot waits, for the copy that last
 // read it (several rebuilds ago).
-static trt_status batch_build(trt_batch *b) {
+// Rows per wavefront of every member under the batch's launch shape (see
+// trt_tuning.batch_items) and the work list in the batch's order.  The
+// tiling changes no result: every node's arithmetic is the same whatever
+// rows or order a sweep uses.
+static void batch_tile(const trt_batch *b, std::vector<InstDesc> &descs,
+                       std::vector<int4> &items) {
     const size_t n = b->sims.size();
-    size_t nitems = 0;
-    std::vector<InstDesc> descs(n);
     for (size_t k = 0; k < n; ++k) {
-        InstDesc d = b->sims[k]->desc;
+        InstDesc &d = descs[k];
+        d = b->sims[k]->desc;
         d.cur = b->sims[k]->cur;
         trt::tile(d, b->launch, b->sims[k]->prob.storage);
-        descs[k] = d;
-        nitems += (size_t)d.rowblocks * (size_t)d.strips;
     }
+    if (b->launch.rows_per_wave <= 0 && b->launch.batch_items > 0) {
+        // the longest power-of-two cap that leaves at least batch_items items
+        auto count = [&](int cap) {
+            size_t c = 0;
+            for (const InstDesc &d : descs) c += (size_t)d.strips * (size_t)((d.ny + cap - 1) / cap);
+            return c;
+        };
+        int cap = 256;
+        while (cap > 4 && count(cap) < (size_t)b->launch.batch_items) cap /= 2;
+        for (InstDesc &d : descs) {
+            const int blocks = (d.ny + cap - 1) / cap;
+            d.rows = (d.ny + blocks - 1) / blocks;  // equal blocks of at most cap rows
+            d.rowblocks = (d.ny + d.rows - 1) / d.rows;
+        }
+    }
+    items.clear();
+    for (size_t k = 0; k < n; ++k)
+        for (int r = 0; r < descs[k].rowblocks; ++r)
+            for (int c = 0; c < descs[k].strips; ++c) items.push_back(make_int4((int)k, c, r, 0));
+    if (b->launch.batch_order == 2) {
+        // costliest first: rows in the block x columns per strip (stable, so
+        // equal items keep member, row block and strip order)
+        auto cost = [&](const int4 &it) {
+            const InstDesc &d = descs[it.x];
+            const int rows = std::min(d.rows, d.ny - it.z * d.rows);
+            return (int64_t)rows * trt::kStripWidth * d.cols;
+        };
+        std::stable_sort(items.begin(), items.end(),
+                         [&](const int4 &a, const int4 &c) { return cost(a) > cost(c); });
+    }
+}
+
+static trt_status batch_build(trt_batch *b) {
+    const size_t n = b->sims.size();
+    std::vector<InstDesc> descs(n);
+    std::vector<int4> list;
+    batch_tile(b, descs, list);
+    const size_t nitems = list.size();
     if (nitems > (size_t)INT32_MAX) return fail(TRT_EINVAL, "batch work list too long");
     trt_batch::Staging &sg = b->stage[b->next_stage];
     b->next_stage = (b->next_stage + 1) % trt_batch::kStagingSlots;
@@ -661,12 +792,8 @@ static trt_status batch_build(trt_batch *b) {
     TRT_HIP(grow_pinned(sg.items, sg.cap_items, nitems, b->retired_host));
     TRT_HIP(grow_device(b->d_descs, b->cap_descs, n, b->retired_dev));
     TRT_HIP(grow_device(b->d_items, b->cap_items, nitems, b->retired_dev));
-    size_t j = 0;
-    for (size_t k = 0; k < n; ++k) {
-        sg.descs[k] = descs[k];
-        for (int r = 0; r < descs[k].rowblocks; ++r)
-            for (int c = 0; c < descs[k].strips; ++c) sg.items[j++] = make_int4((int)k, c, r, 0);
-    }
+    for (size_t k = 0; k < n; ++k) sg.descs[k] = descs[k];
+    for (size_t j = 0; j < nitems; ++j) sg.items[j] = list[j];
     TRT_HIP(hipMemcpyAsync(b->d_descs, sg.descs, n * sizeof(InstDesc), hipMemcpyHostToDevice,
                            b->stream));
     TRT_HIP(hipMemcpyAsync(b->d_items, sg.items, nitems * sizeof(int4), hipMemcpyHostToDevice,
@@ -675,7 +802,7 @@ static trt_status batch_build(trt_batch *b) {
     sg.pending = true;
     b->nitems = (int)nitems;
     b->parity = 0;
-    release_graph(b->pair);
+    release_graphs(b->graphs);
     return TRT_OK;
 }
 
@@ -751,10 +878,10 @@ trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims) {
 }
 
 trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
-    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
     Launch l;
     trt_status st = check_launch(t, l, kBatchDefaultLaunch);
     if (st != TRT_OK) return st;
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
     // members' cur already reflects every step taken; rebuilding restarts
     // the batch parity from there
     b->launch = l;
@@ -766,6 +893,19 @@ static void batch_sync_members(trt_batch *b, int64_t n) {
         s->time += n;
         if (n & 1) s->cur ^= 1;
     }
+}
+
+// Capture `sweeps` (even) batched sweeps, starting from parity 0, into `out`.
+static trt_status batch_capture(trt_batch *b, hipGraphExec_t &out, int64_t sweeps) {
+    release_graph(out);
+    return capture(b->cap_stream, out, [&](hipStream_t cs) {
+        for (int64_t k = 0; k < sweeps; ++k) {
+            hipError_t e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage,
+                                                   b->mask, b->buf, (int)(k & 1), b->launch, cs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    });
 }
 
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
@@ -781,19 +921,14 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
         --n;
     }
     if (n >= 2) {
-        if (!b->pair) {
-            trt_status cs = capture(b->cap_stream, b->pair, [&](hipStream_t cs2) {
-                hipError_t e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems,
-                                                       b->storage, b->mask, b->buf, 0, b->launch,
-                                                       cs2);
-                if (e != hipSuccess) return e;
-                return trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage,
-                                               b->mask, b->buf, 1, b->launch, cs2);
-            });
-            if (cs != TRT_OK) return cs;
-        }
-        for (int64_t k = 0; k < n / 2; ++k) TRT_HIP(hipGraphLaunch(b->pair, b->stream));
-        batch_sync_members(b, n / 2 * 2);
+        const int64_t even = n / 2 * 2;
+        trt_status rs = replay_ladder(even, b->launch.graph_steps, b->graphs, b->stream,
+                                      [&](int k) -> trt_status {
+                                          if (b->graphs[k]) return TRT_OK;
+                                          return batch_capture(b, b->graphs[k], (int64_t)2 << k);
+                                      });
+        if (rs != TRT_OK) return rs;
+        batch_sync_members(b, even);
     }
     if (n % 2) {
         TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf, 0,
@@ -817,7 +952,7 @@ trt_status trt_batch_diagnostics(trt_batch *b, double *out) {
 void trt_batch_destroy(trt_batch *b) {
     if (!b) return;
     for (trt_sim *s : b->sims) s->in_batch = false;
-    release_graph(b->pair);
+    release_graphs(b->graphs);
     for (auto &sg : b->stage) {
         if (sg.pending) (void)hipEventSynchronize(sg.done);
         if (sg.done) (void)hipEventDestroy(sg.done);

@@ -14,6 +14,12 @@ struct Launch {
     int waves_per_block;  // 0: chosen per storage and column mode
     int xcd_remap;
     int cols_per_lane;    // 0: two-column strips wherever they apply; 1 or 2
+    // batches only (see trt_tuning): the minimum number of work items that
+    // sets one batch-wide row cap (-1: each member's own rows), and the
+    // work-list order (1: member by member, 2: costliest items first)
+    int batch_items;
+    int batch_order;
+    int graph_steps;  // sweeps per captured graph (even)
 };
 
 // Wavefronts per workgroup of a single-lattice sweep.  The one-column
@@ -107,6 +113,14 @@ bool buffer_addressable(const InstDesc &d, int storage);
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);
+
+// The access-pattern probe (a measurement aid): one launch moves the lattice
+// `src` to the other one with the two-column sweep's loads, stores, launch
+// shape and barriers and none of its arithmetic.  Only for two-column
+// tilings of open periodic lattices whose width is a multiple of 128 and
+// that fit one buffer resource (else hipErrorInvalidValue).
+hipError_t launch_pattern_probe(const InstDesc &d, int storage, int src, const Launch &l,
+                                hipStream_t stream);
 
 // Link map of an instance with a mask or open x boundaries: d.links (device,
 // ny * d.lpitch 16-bit codes) receives, per node, bit 0 = solid and bit i

@@ -36,17 +36,6 @@ namespace trt {
 
 namespace {
 
-// Remap the hardware workgroup index so that each of the 8 XCDs (dispatched
-// round-robin) receives one contiguous range of logical workgroups; with
-// strips varying fastest, an XCD then sweeps a contiguous band of rows and
-// the halo rows shared by neighbouring wavefronts stay in its own L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    constexpr int kXcd = 8;
-    const int per = (nb + kXcd - 1) / kXcd;
-    const int tall = (nb % kXcd == 0) ? kXcd : nb % kXcd;
-    const int xcd = b % kXcd, local = b / kXcd;
-    return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
-}
 
 // Per-lane geometry of one strip column.
 struct Column {

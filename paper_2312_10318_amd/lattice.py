@@ -110,10 +110,14 @@ class Lattice:
         self.stream.synchronize()
 
     # ------------------------------------------------------------------- API
-    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0):
-        capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap, cols_per_lane)
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
+                   graph_steps=0):
+        capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap, cols_per_lane,
+                            graph_steps)
 
     def tuning(self):
+        """(rows per wavefront, wavefronts per workgroup, XCD remap, columns per
+        lane, sweeps per captured graph) in effect."""
         return capi.trt_get_tuning(self.handle)
 
     def init_equilibrium(self, rho, ux, uy, sync=True):
@@ -141,6 +145,11 @@ class Lattice:
 
     def step(self, nsteps=1):
         capi.trt_step(self.handle, int(nsteps))
+        return self
+
+    def pattern_probe(self, nsweeps=1):
+        """Launches of the access-pattern probe (scrambles the state)."""
+        capi.trt_pattern_probe(self.handle, int(nsweeps))
         return self
 
     def macros(self):
@@ -244,9 +253,10 @@ class Batch:
         self._diag = torch.empty((len(self.lattices), capi.TRT_NDIAG), dtype=torch.float64,
                                  device=self.lattices[0].device)
 
-    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0):
+    def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
+                   batch_items=0, batch_order=0, graph_steps=0):
         capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap,
-                                  cols_per_lane)
+                                  cols_per_lane, batch_items, batch_order, graph_steps)
 
     def update(self, lattices):
         """Replace the members (no device-wide wait)."""

@@ -28,7 +28,7 @@ import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SWEEP_SOURCES = ["paper_2312_10318_amd/csrc/sweep.hip", "paper_2312_10318_amd/csrc/lattice.hpp",
-                 "paper_2312_10318_amd/csrc/kernels.hpp"]
+                 "paper_2312_10318_amd/csrc/kernels.hpp", "paper_2312_10318_amd/csrc/probe.hip"]
 COPY_BYTES = 1 << 30
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16": 36}
 
@@ -61,7 +61,7 @@ def _csv(d, suffix):
 
 def _is_sweep(name):
     return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
-            "sweep_batch_kernel" in name)
+            "sweep_batch_kernel" in name or "pattern_probe_kernel" in name)
 
 
 def _is_copy(name):
@@ -113,6 +113,9 @@ WORKLOADS = {
                  "inflow wall and pressure outlet", "creeping_cylinder_%dx%d", 2),
     "batch": ("the 256-member batch (Taylor-Green and double-shear-layer members, sides "
               "64 to 1024, %d nodes in all, one launch per step)", "batch256", 0),
+    "stream": ("access-pattern probe (the sweep's loads, stores, launch shape and barriers "
+               "without its arithmetic) on the Taylor-Green lattice %dx%d",
+               "pattern_probe_%dx%d", 0),
 }
 
 
@@ -140,8 +143,8 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     alg = (BYTES_PER_LU[storage] + link_bytes) * nodes
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"sweep_(single|pair|batch)_kernel<[^>]*>", kname or "") or
-                   re.search(r".*", "sweep")).group(0),
+        "kernel": (re.search(r"(sweep_(single|pair|batch)|pattern_probe)_kernel<[^>]*>",
+                             kname or "") or re.search(r".*", "sweep")).group(0),
         "workload": wlabel, "storage": storage, "nodes": nodes,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
         "dispatches": len(sweep_ns), "avg_duration_us": round(dur * 1e6, 3),
@@ -156,9 +159,10 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         "hbm_GBps_measured": round((fetch_b + write_b) / dur / 1e9, 1),
         "copy_avg_duration_us": round(avg(copy_ns) * 1e-3, 3) if copy_ns else None,
     }
-    if workload == "tg":
-        cmd = ("python3 bench.py --profile --storage %s --n %d --steps %d --warmup %d"
-               % (storage, n, steps, warmup))
+    if workload in ("tg", "stream"):
+        cmd = ("python3 bench.py --profile%s --storage %s --n %d --steps %d --warmup %d"
+               % (" --workload stream" if workload == "stream" else "", storage, n, steps,
+                  warmup))
     else:
         cmd = ("python3 bench.py --profile --workload %s --storage %s --steps %d --warmup %d"
                % (workload, storage, steps, warmup))

@@ -44,9 +44,12 @@ def test_build_reads_register_spills_from_compiler_remarks():
 
 def test_batch_candidates_and_key():
     shapes = autotune.batch_candidates()
-    assert (0, 4, 0, 0) in shapes                       # the library's batch default
-    assert {w for _, w, _, _ in shapes} <= {1, 2, 4}     # batched workgroups hold at most 4
-    assert {c for _, _, _, c in shapes} == {0}           # members keep their column mode
+    assert (0, 4, 0, 0, -1, 1) in shapes                # the library's batch default
+    assert {s[1] for s in shapes} <= {1, 2, 4}           # batched workgroups hold at most 4
+    assert {s[3] for s in shapes} == {0}                 # members keep their column mode
+    # row policies: each member's own rows, or a batch-wide cap; both orders
+    assert {s[4] for s in shapes if s[0] == 0} == {-1, 16384, 32768}
+    assert {s[5] for s in shapes} == {1, 2}
     assert len(shapes) == len(set(shapes))
     a = autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f32", False)
     b = autotune.batch_key([(1024, 1024), (64, 64), (1010, 1000)], "f32", False)

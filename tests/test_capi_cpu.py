@@ -145,3 +145,18 @@ def test_link_map_limit_at_the_largest_sides(lib, nx, ny, masked, xb, ok):
     with pytest.raises(capi.TrtError) as e:
         capi.trt_create(p, 4096, 1 << 40, 0)
     assert e.value.status == capi.TRT_EINVAL and "link map" in str(e.value)
+
+
+@pytest.mark.parametrize("field,value,ok", [("graph_steps", 6, False), ("graph_steps", 2048, False),
+                                            ("graph_steps", 1, False), ("graph_steps", 256, True),
+                                            ("batch_items", -2, False), ("batch_order", 3, False),
+                                            ("batch_items", 4096, True)])
+def test_tuning_fields_are_validated(lib, field, value, ok):
+    """Launch-shape fields are checked before anything else (a NULL batch
+    handle is reported only after a valid shape)."""
+    t = capi.trt_tuning()
+    setattr(t, field, value)
+    st = lib.trt_batch_set_tuning(None, ctypes.byref(t))
+    assert st == capi.TRT_EINVAL
+    msg = capi.trt_last_error()
+    assert ("batch handle" in msg) == ok, msg

@@ -310,3 +310,90 @@ def test_batch_autotune_leaves_members_untouched_and_results_unchanged(L):
     bb.close()
     for x in a + b:
         x.close()
+
+
+def test_longer_step_graphs_are_bitwise_identical(L):
+    """Every graph ladder (longest graph 2, 8, 32 sweeps or the default)
+    gives the same bits for any split of the steps, including splits that
+    start on the odd lattice."""
+    n = 96
+    rho, ux, uy = inputs.taylor_green(n, 0.02, seed=5)
+    runs = {}
+    for g, splits in [(2, (37, 40)), (0, (77,)), (8, (1, 36, 17, 23)), (32, (77,)),
+                      (32, (3, 33, 41))]:
+        lat = L.Lattice(n, n, 0.57, 1.9, storage="f32").init_equilibrium(rho, ux, uy)
+        lat.set_tuning(graph_steps=g)
+        assert g == 0 or lat.tuning()[4] == g
+        for k in splits:
+            lat.step(k)
+        assert lat.state()[1] == 77
+        runs[(g, splits)] = _np(lat.get_populations())
+        lat.close()
+    ref = runs[(2, (37, 40))]
+    for key, f in runs.items():
+        assert np.array_equal(f, ref), key
+
+
+@pytest.mark.parametrize("shape", [(0, 4, 0, 0, 16384, 2, 8), (0, 2, 1, 0, 32768, 1, 16),
+                                   (16, 4, 0, 0, 0, 2, 2)])
+def test_batch_tilings_orders_and_graphs_are_bitwise_identical(L, shape):
+    """A batch cut into work items by a batch-wide row cap, in costliest-first
+    order, or with longer captured graphs, gives every member the bits of
+    the default shape."""
+    members = inputs.batch_workload(7, seed=4, side_lo=40, side_hi=400, re_hi=1e4)
+
+    def make():
+        out = []
+        for k, m in enumerate(members):
+            rho, ux, uy = inputs.member_fields(m, seed=k)
+            out.append(L.Lattice(m.n, m.n, m.tau1, m.tau2, storage="f32")
+                       .init_equilibrium(rho, ux, uy))
+        return out
+    a, b = make(), make()
+    ba, bb = L.Batch(a), L.Batch(b)
+    ba.set_tuning(*shape)
+    for k in (1, 22, 8):
+        ba.step(k)
+    bb.step(31)
+    for x, y in zip(a, b):
+        assert x.state()[1] == y.state()[1] == 31
+        assert np.array_equal(_np(x.get_populations()), _np(y.get_populations()))
+    ba.close()
+    bb.close()
+    for x in a + b:
+        x.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_pattern_probe_moves_the_pull_rows(L, storage):
+    """The access-pattern probe reads, for every lattice row y, population
+    row i of source row y - e_iy and writes it to row y of the other
+    lattice (the pull's row pattern), leaving every other word unchanged
+    except where the edge lanes fold in the elements they read beyond the
+    strip (population 1, strip columns 0 and 126)."""
+    import torch
+    nx, ny = 256, 11
+    rng = np.random.default_rng(9)
+    lat = L.Lattice(nx, ny, 0.7, 1.1, storage=storage)
+    lat.set_tuning(4, 2, 1, 2)
+    lat.set_populations(inputs.random_populations(rng, (ny, nx)))
+    cur, _ = lat.state()
+    src = (lat.fb if cur else lat.fa).clone()
+    lat.pattern_probe(1)
+    torch.cuda.synchronize()
+    assert lat.state()[0] == 1 - cur
+    dst = lat.fa if cur else lat.fb
+    view = lambda t: t.cpu().numpy().view({"f64": np.uint64, "f32": np.uint32,
+                                           "f16": np.uint16}[storage]).reshape(ny, 9, -1)
+    a, b = view(src), view(dst)
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    for i in range(9):
+        want = np.roll(a[:, i, :nx], ey[i], axis=0)
+        got = b[:, i, :nx]
+        if i == 1:
+            keep = np.ones(nx, bool)
+            keep[0::128] = keep[126::128] = False
+            assert np.array_equal(got[:, keep], want[:, keep])
+        else:
+            assert np.array_equal(got, want), i
+    lat.close()

@@ -83,9 +83,57 @@ def tg_lattice(n, storage, tau1=0.6, lam=0.25, tuning=None):
     return lat
 
 
+def rel_errors(u, v, ur, vr):
+    """(relative max, relative L2) velocity error against reference fields;
+    the L2 norm sums both components (the error measure of Sec. III)."""
+    import numpy as np
+    scale = max(np.max(np.abs(ur)), np.max(np.abs(vr)))
+    emax = max(np.max(np.abs(u - ur)), np.max(np.abs(v - vr))) / scale
+    el2 = np.sqrt((np.sum((u - ur) ** 2) + np.sum((v - vr) ** 2)) /
+                  (np.sum(ur ** 2) + np.sum(vr ** 2)))
+    return float("%.3e" % emax), float("%.3e" % el2)
+
+
+def velocity(lat):
+    """(ux, uy) of a lattice as numpy FP64 arrays."""
+    _, u, v = lat.macros()
+    return u.cpu().numpy(), v.cpu().numpy()
+
+
+def fp64_alone(nx, ny, tau1, tau2, steps, fields, g=(0.0, 0.0), mask=None, inflow=None):
+    """Velocity of the same problem run alone in FP64 storage on the GPU (the
+    path the parity tests hold to the FP64 oracle within 1e-12), the
+    reference of the batched and served errors."""
+    from paper_2312_10318_amd.lattice import Lattice
+    lat = Lattice(nx, ny, tau1, tau2, g=g, mask=mask, storage="f64", inflow=inflow)
+    lat.init_equilibrium(*fields).step(steps)
+    out = velocity(lat)
+    lat.close()
+    return out
+
+
+def accuracy_vs_oracle(n, ref):
+    """Errors of the benchmark lattice in every storage against the oracle
+    state of the CPU-baseline sample (same seeded lattice, same steps)."""
+    steps, ur, vr = ref
+    out = {"reference": "FP64 CPU oracle, the cpu_baseline sample", "steps": steps}
+    for storage in ("f32", "f16", "f64"):
+        lat = tg_lattice(n, storage)
+        lat.step(steps)
+        u, v = velocity(lat)
+        lat.close()
+        emax, el2 = rel_errors(u, v, ur, vr)
+        out[storage] = {"err_max": emax, "err_L2": el2}
+        log("accuracy %s after %d steps vs oracle: rel max %.3e, rel L2 %.3e"
+            % (storage, steps, emax, el2))
+    return out
+
+
 def cpu_baseline(n=4096, budget_s=12.0):
     """The FP64 oracle on the host cores, on a bounded sample: the same
-    4096^2 Taylor-Green lattice, as many whole steps as fit in ~budget_s."""
+    4096^2 Taylor-Green lattice, as many whole steps as fit in ~budget_s.
+    Returns the record and the sample's final state (steps, ux, uy), which
+    the GPU runs are compared with."""
     import numpy as np  # noqa: F401
     import oracle
     from paper_2312_10318_amd import inputs, params
@@ -115,12 +163,13 @@ def cpu_baseline(n=4096, budget_s=12.0):
         single = m * m / (time.perf_counter() - t0) / 1e6
     finally:
         oracle.set_num_threads(cores)
-    return {"value": round(n * n * steps / total / 1e6, 3), "unit": "MLUPS",
-            "cores": cores, "kind": "oracle",
-            "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total),
-            "single_thread_MLUPS": round(single, 3),
-            "single_thread_sample": "Taylor-Green %dx%d FP64, one step" % (m, m),
-            "cpu_model": cpu_model()}
+    _, ur, vr = oracle.macros(f)
+    return ({"value": round(n * n * steps / total / 1e6, 3), "unit": "MLUPS",
+             "cores": cores, "kind": "oracle",
+             "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total),
+             "single_thread_MLUPS": round(single, 3),
+             "single_thread_sample": "Taylor-Green %dx%d FP64, one step" % (m, m),
+             "cpu_model": cpu_model()}, (steps, ur, vr))
 
 
 def cpu_model() -> str:
@@ -184,16 +233,36 @@ def run_batch(count=256, steps=5000, storage="f32", seed=0):
     sec = start.elapsed_time(end) * 1e-3
     diag = b.diagnostics()
     nodes = sum(m.n * m.n for m in members)
+    bad = [k for k in range(count) if diag[k, 4] > 0]
+    # accuracy at the end of the timed run: sampled members (smallest and
+    # largest, odd and even widths, both flow kinds, none diverged) against
+    # the same member run alone in FP64
+    ok = [k for k in range(count) if k not in bad]
+    sizes = {k: members[k].n for k in ok}
+    pick = [min(ok, key=sizes.get), max(ok, key=sizes.get)]
+    pick += [k for k in ok if members[k].n % 2 == 1][:1] + [k for k in ok if members[k].n % 2 == 0][:1]
+    pick += [k for k in ok if members[k].kind == "dsl"][:1] + [k for k in ok if members[k].kind == "tg"][:1]
+    acc = []
+    for k in sorted(set(pick)):
+        m = members[k]
+        ur, vr = fp64_alone(m.n, m.n, m.tau1, m.tau2, 20 + steps, inputs.member_fields(m, seed=k))
+        u, v = velocity(lats[k])
+        emax, el2 = rel_errors(u, v, ur, vr)
+        acc.append({"member": k, "kind": m.kind, "n": m.n, "Re": float("%.3g" % m.re),
+                    "err_max": emax, "err_L2": el2})
     b.close()
     for l in lats:
         l.close()
-    bad = [k for k in range(count) if diag[k, 4] > 0]
     return {"instances": count, "steps": steps, "storage": storage, "nodes": nodes,
             "seconds": round(sec, 4), "solves_per_s": round(count / sec, 3),
             "aggregate_MLUPS": round(nodes * steps / sec / 1e6, 1),
             "launch_shape": list(tuned["best"]),
             "tuned_ms_per_step": round(tuned["ms"], 4),
             "default_ms_per_step": round(table.get((0, 4, 0, 0, -1, 1), float("nan")), 4),
+            "accuracy": {"reference": "each sampled member run alone in FP64 storage on the GPU",
+                         "steps": 20 + steps, "members": acc,
+                         "err_max": max(a["err_max"] for a in acc),
+                         "err_L2": max(a["err_L2"] for a in acc)},
             "diverged_instances": len(bad),
             "diverged": ["%s n=%d Re=%.3g 1/tau2=%.3f" % (members[k].kind, members[k].n,
                                                          members[k].re, 1 / members[k].tau2)
@@ -202,15 +271,32 @@ def run_batch(count=256, steps=5000, storage="f32", seed=0):
 
 def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
     """Poisson solve stream through the continuous-batching server."""
-    from paper_2312_10318_amd import serving
+    from paper_2312_10318_amd import inputs, serving
     reqs = serving.serving_workload(rate=rate, duration=duration, seed=seed)
+    # the smallest request of each kind keeps its final fields (checked below)
+    sample = {kind: min((r for r in reqs if r.kind == kind), key=lambda r: r.nx * r.ny).rid
+              for kind in ("cylinder", "poiseuille", "taylor_green")}
     ex = serving.GpuExecutor(storage)
-    sched = serving.Scheduler(ex, budget_bytes=int(budget_gb * (1 << 30)), quantum=100)
+    sched = serving.Scheduler(ex, budget_bytes=int(budget_gb * (1 << 30)), quantum=100,
+                              keep_fields=set(sample.values()))
     t0 = time.perf_counter()
     res = sched.run(reqs)
     wall = time.perf_counter() - t0
     ex.shutdown()
     out = serving.summarize(res, wall)
+    by = {r.rid: r for r in res}
+    acc = []
+    for kind, rid in sample.items():
+        q = next(r for r in reqs if r.rid == rid)
+        fields = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
+        ur, vr = fp64_alone(q.nx, q.ny, q.tau1, q.tau2, q.steps, fields, g=q.g, mask=q.mask)
+        _, u, v = by[rid].fields
+        emax, el2 = rel_errors(u, v, ur, vr)
+        acc.append({"request": rid, "kind": kind, "nx": q.nx, "ny": q.ny, "steps": q.steps,
+                    "err_max": emax, "err_L2": el2})
+    out["accuracy"] = {"reference": "each sampled request run alone in FP64 storage on the GPU",
+                       "requests": acc, "err_max": max(a["err_max"] for a in acc),
+                       "err_L2": max(a["err_L2"] for a in acc)}
     out.update({"storage": storage, "offered_rate_per_s": rate, "arrival_window_s": duration,
                 "peak_active": sched.peak_active, "peak_bytes": sched.peak_used,
                 "quanta": sched.quanta})
@@ -240,12 +326,49 @@ def run_extra(steps):
     for storage in ("f16", "f32"):
         out["serving_" + storage] = run_serving(storage)
         log("extra serving %s: %s" % (storage, out["serving_" + storage]))
+    out["dsl1024_error_curve"] = run_dsl_curve()
     out["dsl_critical_mach_f64"] = run_stability()
     log("extra stability study: %s" % out["dsl_critical_mach_f64"])
     out["tg_convergence_f64"] = run_convergence()
     log("extra convergence study: %s" % out["tg_convergence_f64"])
     out["poiseuille_slip_f64"] = run_poiseuille()
     log("extra Poiseuille slip study: %s" % out["poiseuille_slip_f64"])
+    return out
+
+
+def run_dsl_curve(n=1024, u0=0.04, checkpoints=(1000, 2000, 5000, 10000, 20000)):
+    """The double shear layer at its benchmark size (Sec. III.A set-up:
+    1024^2, U0 = 0.04, kappa = 80, delta = 0.05, 1/tau_s2 = 1.6) to 20000
+    steps at Re = 1e4 and 1e7: FP32 and FP16 (f - w) storage against the FP64
+    run of the same set-up on the GPU (which the parity tests hold to the
+    FP64 oracle within 1.3e-13 over the first 1000 steps), error against step."""
+    from paper_2312_10318_amd import inputs, params
+    from paper_2312_10318_amd.lattice import Lattice
+    out = {}
+    rho, ux, uy = inputs.double_shear_layer(n, u0)
+    for re in (1e4, 1e7):
+        tau1 = params.tau_from_re(u0, n, re)
+        lats = {st: Lattice(n, n, tau1, 1 / 1.6, storage=st).init_equilibrium(rho, ux, uy)
+                for st in ("f64", "f32", "f16")}
+        curve = {"f32": [], "f16": []}
+        done = 0
+        for c in checkpoints:
+            for lat in lats.values():
+                lat.step(c - done)
+            done = c
+            ur, vr = velocity(lats["f64"])
+            for st in ("f32", "f16"):
+                if lats[st].diagnostics()["n_diverged"] > 0:
+                    curve[st].append({"step": c, "diverged": True})
+                    continue
+                u, v = velocity(lats[st])
+                emax, el2 = rel_errors(u, v, ur, vr)
+                curve[st].append({"step": c, "err_max": emax, "err_L2": el2})
+        for lat in lats.values():
+            lat.close()
+        out["Re=%g" % re] = {"tau1": tau1, **curve}
+        log("extra DSL %d^2 Re=%g error curve: %s" % (n, re, curve))
+    out["reference"] = "FP64 storage on the GPU, same set-up"
     return out
 
 
@@ -450,7 +573,16 @@ def main():
         rec["extra"] = run_extra(max(200, args.steps // 4))
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample")
-        rec["cpu_baseline"] = cpu_baseline(n)
+        rec["cpu_baseline"], ref = cpu_baseline(n)
+        # every storage of the benchmark lattice against that oracle state
+        acc = accuracy_vs_oracle(n, ref)
+        rec["accuracy"] = {"reference": acc["reference"], "steps": acc["steps"],
+                           **acc[storage]}
+        for st in ("f16", "f64"):
+            key = "tg4096_" + st
+            if n == 4096 and key in rec.get("extra", {}):
+                rec["extra"][key]["accuracy"] = {"reference": acc["reference"],
+                                                 "steps": acc["steps"], **acc[st]}
     print(json.dumps(rec), flush=True)
 
 

@@ -120,7 +120,7 @@ WORKLOADS = {
 
 
 def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_prefix,
-              skip_first=2, run_log=None, workload="tg", nodes=None):
+              skip_first=2, run_log=None, workload="tg", nodes=None, tuning=None):
     sweep_ns, copy_ns, kname = kernel_durations(trace_dir)
     fs, fc = counter_values(fetch_dir, "FETCH_SIZE")
     ws, wc = counter_values(write_dir, "WRITE_SIZE")
@@ -166,6 +166,9 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     else:
         cmd = ("python3 bench.py --profile --workload %s --storage %s --steps %d --warmup %d"
                % (workload, storage, steps, warmup))
+    if tuning:
+        cmd += " --tuning " + tuning
+        rec["launch_shape"] = tuning
     with open(out_prefix + "_hbm_counters.json", "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(out_prefix + ".md", "w") as fh:
@@ -175,9 +178,10 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)
         fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --workload %s "
-                 "--storage %s --n %d --steps %d --warmup %d%s --out %s\n\n"
+                 "--storage %s --n %d --steps %d --warmup %d%s%s --out %s\n\n"
                  % (workload, storage, n, steps, warmup,
                     " --nodes %d" % nodes if workload == "batch" else "",
+                    " --tuning %s" % tuning if tuning else "",
                     os.path.relpath(out_prefix, ROOT)))
         fh.write("| quantity | value |\n|---|---|\n")
         for k, v in rec.items():
@@ -209,13 +213,15 @@ def main():
     ap.add_argument("--run-log", default=None,
                     help="stdout of the profiled bench.py run (carries the source hash the "
                          "profiled kernel was built from)")
+    ap.add_argument("--tuning", default=None,
+                    help="the --tuning argument of the profiled bench.py run, if any")
     ap.add_argument("--nodes", type=int, default=None,
                     help="lattice updates per launch of the batch workload (printed by the "
                          "profiled run)")
     a = ap.parse_args()
     rec = summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.storage, a.n, a.steps, a.warmup,
                     os.path.join(ROOT, a.out) if not os.path.isabs(a.out) else a.out,
-                    run_log=a.run_log, workload=a.workload, nodes=a.nodes)
+                    run_log=a.run_log, workload=a.workload, nodes=a.nodes, tuning=a.tuning)
     print(json.dumps(rec, indent=1))
 
 

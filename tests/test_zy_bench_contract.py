@@ -45,3 +45,11 @@ def test_bench_prints_one_json_line_with_roofline_and_cpu_baseline():
     cpu = rec["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
     assert cpu["unit"] == "MLUPS" and cpu["sample"]
+    # the timed configuration's accuracy against the oracle state of that sample
+    acc = rec["accuracy"]
+    assert acc["steps"] >= 1 and "oracle" in acc["reference"]
+    assert 0 < acc["err_max"] <= 1e-5 and 0 < acc["err_L2"] <= 1e-5
+    # the access-pattern ceiling beside the sweep's own figure
+    pat = roof["access_pattern"]
+    assert pat["kernel"].startswith("pattern_probe_kernel") and 0 < pat["frac"] < 1
+    assert abs(pat["sweep_over_pattern"] - roof["achieved"] / pat["achieved"]) < 1e-3

@@ -512,7 +512,7 @@ def main():
     lat = tg_lattice(n, storage, tuning=tuning)
     ms = time_steps(lat, args.steps, args.warmup)
     stable = lat.check()
-    rows, waves, remap, cols, graph_steps = lat.tuning()
+    rows, waves, remap, cols, graph_steps, steps_per_sweep = lat.tuning()
     probe_ms = None
     if cols == 2 and n % 128 == 0:
         # the same launch shape moving the same bytes without the arithmetic
@@ -544,7 +544,8 @@ def main():
                    if storage != "f64" else "f64", "tau_s": 0.6, "tau_s2": 3.0, "u0": 0.01,
                    "nodes": n * n, "launch": {"rows_per_wave": rows, "waves_per_block": waves,
                                               "xcd_remap": remap, "cols_per_lane": cols,
-                                              "graph_steps": graph_steps},
+                                              "graph_steps": graph_steps,
+                                              "steps_per_sweep": steps_per_sweep},
                    "stable": bool(stable)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -135,6 +135,11 @@ typedef struct {
                                 of the rest (graphs of 2, 4, ... sweeps, captured at first
                                 use): the GPU idles ~8 us at each graph boundary and ~0.2 us
                                 between the sweeps inside one graph. */
+    int32_t steps_per_sweep; /* 1 (0: default) or 2: two time steps per launch (each
+                                population crosses HBM once per two steps; the bits of two
+                                one-step sweeps).  Applies to single FP32 simulations without
+                                a mask or open boundaries whose width is a multiple of 128;
+                                elsewhere, and in batches, sweeps take one step. */
 } trt_tuning;
 
 typedef struct trt_sim trt_sim;

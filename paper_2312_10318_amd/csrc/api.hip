@@ -68,12 +68,12 @@ trt_status guarded(F &&body) noexcept {
 // 0.25 with 128); 4096^2 FP32 214.0 -> 210.9 us per step.
 constexpr int kMaxGraphLevels = 10;  // up to 1024 sweeps per graph
 constexpr int kDefaultGraphSteps = 64;
-constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps};
+constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 1};
 // Batches: no XCD remap by default.  A batch's work list runs member by
 // member, and spreading each member's items over all XCDs (the hardware's
 // round-robin) measured 3% faster than giving XCDs contiguous ranges of the
 // list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
-constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps};
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 1};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -157,6 +157,11 @@ trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) 
             return fail(TRT_EINVAL,
                         "graph_steps must be 0 (default) or a power of two in [2, 1024]");
         l.graph_steps = g;
+    }
+    if (t->steps_per_sweep != 0) {
+        if (t->steps_per_sweep != 1 && t->steps_per_sweep != 2)
+            return fail(TRT_EINVAL, "steps_per_sweep must be 0 (default), 1 or 2");
+        l.steps_per_sweep = t->steps_per_sweep;
     }
     return TRT_OK;
 }
@@ -277,8 +282,14 @@ template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F bo
     return TRT_OK;
 }
 
-// Capture `sweeps` (even) sweeps of a simulation, starting from lattice 0,
-// into `out`.
+// Whether a simulation's launches take two time steps each.
+bool sim_tb2(const trt_sim *s) {
+    return s->launch.steps_per_sweep == 2 && s->desc.cols == 2 &&
+           trt::tb2_eligible(s->desc, s->prob.storage);
+}
+
+// Capture `sweeps` (even) launches of a simulation, starting from lattice 0,
+// into `out` (each launch one step, or two with sim_tb2).
 trt_status sim_capture(trt_sim *s, hipGraphExec_t &out, int64_t sweeps) {
     release_graph(out);
     if (!s->cap_stream) {
@@ -290,9 +301,11 @@ trt_status sim_capture(trt_sim *s, hipGraphExec_t &out, int64_t sweeps) {
     }
     const int st = s->prob.storage;
     const bool m = s->prob.mask != nullptr;
+    const bool tb2 = sim_tb2(s);
     return capture(s->cap_stream, out, [&](hipStream_t cs) {
         for (int64_t k = 0; k < sweeps; ++k) {
-            hipError_t e = trt::launch_sweep(s->desc, st, m, (int)(k & 1), s->launch, cs);
+            hipError_t e = tb2 ? trt::launch_sweep_tb2(s->desc, st, (int)(k & 1), s->launch, cs)
+                               : trt::launch_sweep(s->desc, st, m, (int)(k & 1), s->launch, cs);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -452,12 +465,14 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!t) return fail(TRT_EINVAL, "out is NULL");
     t->rows_per_wave = s->desc.rows;
-    t->waves_per_block = trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
+    t->waves_per_block = sim_tb2(s) ? trt::tb2_waves_per_block(s->desc, s->prob.storage, s->launch)
+                                    : trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
     t->xcd_remap = s->launch.xcd_remap;
     t->cols_per_lane = s->desc.cols;
     t->batch_items = 0;
     t->batch_order = 0;
     t->graph_steps = s->launch.graph_steps;
+    t->steps_per_sweep = sim_tb2(s) ? 2 : 1;
     return TRT_OK;
 }
 
@@ -500,8 +515,36 @@ trt_status trt_step(trt_sim *s, int64_t nsteps) {
         ++s->time;
         --nsteps;
     }
-    // every graph holds an even number of sweeps, so each replay starts and
+    // every graph holds an even number of launches, so each replay starts and
     // ends on lattice 0
+    if (sim_tb2(s)) {
+        // two steps per launch: graphs of 2, 4, ... launches (4, 8, ... steps),
+        // then at most one two-step launch and one one-step sweep
+        if (nsteps >= 4) {
+            const int64_t launches = nsteps / 4 * 2;
+            trt_status rs = replay_ladder(
+                launches, std::max<int64_t>(2, s->launch.graph_steps / 2), s->graphs, s->stream,
+                [&](int k) -> trt_status {
+                    if (s->graphs[k]) return TRT_OK;
+                    return sim_capture(s, s->graphs[k], (int64_t)2 << k);
+                });
+            if (rs != TRT_OK) return rs;
+            s->time += 2 * launches;
+            nsteps -= 2 * launches;
+        }
+        if (nsteps >= 2) {
+            TRT_HIP(trt::launch_sweep_tb2(s->desc, st, 0, s->launch, s->stream));
+            s->cur = 1;
+            s->time += 2;
+            nsteps -= 2;
+        }
+        if (nsteps == 1) {
+            TRT_HIP(trt::launch_sweep(s->desc, st, m, s->cur, s->launch, s->stream));
+            s->cur ^= 1;
+            ++s->time;
+        }
+        return TRT_OK;
+    }
     if (nsteps >= 2) {
         const int64_t even = nsteps / 2 * 2;
         trt_status rs = replay_ladder(even, s->launch.graph_steps, s->graphs, s->stream,

@@ -20,6 +20,7 @@ struct Launch {
     int batch_items;
     int batch_order;
     int graph_steps;  // sweeps per captured graph (even)
+    int steps_per_sweep;  // 2: two time steps per launch where tb2_eligible
 };
 
 // Wavefronts per workgroup of a single-lattice sweep.  The one-column
@@ -113,6 +114,15 @@ bool buffer_addressable(const InstDesc &d, int storage);
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);
+
+// Two time steps per launch (FP32 storage, open periodic lattices, nx a
+// multiple of 128, two-column tiling): reads lattice src, writes the other
+// one, two steps later.  Gives the bits of two one-step sweeps.
+bool tb2_eligible(const InstDesc &d, int storage);
+// Wavefronts per workgroup of the two-step pass (at most four).
+int tb2_waves_per_block(const InstDesc &d, int storage, const Launch &l);
+hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launch &l,
+                            hipStream_t stream);
 
 // The access-pattern probe (a measurement aid): one launch moves the lattice
 // `src` to the other one with the two-column sweep's loads, stores, launch

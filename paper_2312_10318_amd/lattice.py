@@ -111,13 +111,13 @@ class Lattice:
 
     # ------------------------------------------------------------------- API
     def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
-                   graph_steps=0):
+                   graph_steps=0, steps_per_sweep=0):
         capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap, cols_per_lane,
-                            graph_steps)
+                            graph_steps, steps_per_sweep)
 
     def tuning(self):
         """(rows per wavefront, wavefronts per workgroup, XCD remap, columns per
-        lane, sweeps per captured graph) in effect."""
+        lane, longest captured graph, time steps per launch) in effect."""
         return capi.trt_get_tuning(self.handle)
 
     def init_equilibrium(self, rho, ux, uy, sync=True):

@@ -1,0 +1,89 @@
+"""Two time steps per launch (trt_tuning.steps_per_sweep = 2) give the bits
+of the one-step sweep: every node's arithmetic is the same and the first
+step's FP32 results are exactly what the one-step sweep stores and loads
+back.  Ragged and tiny heights (row blocks that wrap past the lattice), one
+and several strips, every row and workgroup shape, odd step counts; and the
+same run against the oracle within the FP32 tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import TOL, rel_errors, say, stored_state
+from paper_2312_10318_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_10318_amd import lattice
+    return lattice
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _state(seed, nx, ny):
+    rng = np.random.default_rng(seed)
+    f = inputs.random_populations(rng, (ny, nx), amp=0.05)
+    g = tuple(rng.uniform(-1e-4, 1e-4, 2))
+    return f, g, float(rng.uniform(0.52, 2.0)), float(rng.uniform(0.5, 3.0))
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 37), (256, 9), (384, 130), (128, 3), (256, 5),
+                                   (512, 64)])
+@pytest.mark.parametrize("tiling", [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1), (64, 4, 0)])
+def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
+    f, g, tau1, tau2 = _state(nx + 7 * ny, nx, ny)
+    say("case: two steps per launch %dx%d tiling=%s" % (nx, ny, tiling))
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    two = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    two.set_tuning(*tiling, 2, 8, 2)
+    assert two.tuning()[5] == 2 and two.tuning()[1] <= 4   # at most four wavefronts
+    for k in (1, 2, 5, 4, 11, 3):   # 26 steps: singles, two-step launches, graphs
+        one.step(k)
+        two.step(k)
+    assert one.state()[1] == two.state()[1] == 26
+    a, b = _np(one.get_populations()), _np(two.get_populations())
+    say("  differs at %d of %d entries" % (int(np.sum(a != b)), a.size))
+    assert np.array_equal(a, b)
+    one.close()
+    two.close()
+
+
+def test_two_steps_per_launch_against_the_oracle(L):
+    nx, ny, steps = 256, 70, 40
+    f, g, tau1, tau2 = _state(3, nx, ny)
+    lat = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    lat.set_tuning(steps_per_sweep=2)
+    lat.step(steps)
+    _, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    fo = oracle.run(stored_state(f, "f32"), steps, tau1, tau2, g[0], g[1])
+    _, ur, vr = oracle.macros(fo, g[0], g[1])
+    emax, el2 = rel_errors(u, v, ur, vr)
+    say("case: two steps per launch %dx%d, %d steps vs oracle: rel max %.3e L2 %.3e"
+        % (nx, ny, steps, emax, el2))
+    assert emax <= TOL["f32"] and el2 <= TOL["f32"]
+
+
+def test_two_steps_per_launch_applies_only_where_eligible(L):
+    """FP64/FP16 storage, masks and widths that are not multiples of 128 keep
+    one step per launch (and say so)."""
+    cases = [dict(nx=200, ny=8, storage="f32"), dict(nx=256, ny=8, storage="f64"),
+             dict(nx=256, ny=8, storage="f16")]
+    for c in cases:
+        lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
+        lat.set_tuning(steps_per_sweep=2)
+        assert lat.tuning()[5] == 1, c
+        lat.close()
+    mask = np.zeros((8, 256), np.uint8)
+    mask[0] = 1
+    lat = L.Lattice(256, 8, 0.7, 1.0, storage="f32", mask=mask)
+    lat.set_tuning(steps_per_sweep=2)
+    assert lat.tuning()[5] == 1
+    lat.close()

@@ -115,8 +115,8 @@ typedef struct {
 typedef struct {
     int32_t rows_per_wave;   /* rows one wavefront marches through, 1..4096 (0: automatic) */
     int32_t waves_per_block; /* wavefronts per workgroup: 1, 2, 4, 8 or 16 (0: automatic); the
-                                one-column and batched sweeps use at most 4, the two-column
-                                sweep at most 16 (FP64: 8) */
+                                one-column and batched sweeps and the two-step pass use at
+                                most 4, the two-column sweep at most 16 (FP64: 8) */
     int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default
                                 (on for one simulation, off for a batch) */
     int32_t cols_per_lane;   /* 1 or 2 columns per lane (0: 2 where it applies and nx >= 128) */
@@ -135,11 +135,13 @@ typedef struct {
                                 of the rest (graphs of 2, 4, ... sweeps, captured at first
                                 use): the GPU idles ~8 us at each graph boundary and ~0.2 us
                                 between the sweeps inside one graph. */
-    int32_t steps_per_sweep; /* 1 (0: default) or 2: two time steps per launch (each
+    int32_t steps_per_sweep; /* 2 (0: default) or 1: two time steps per launch (each
                                 population crosses HBM once per two steps; the bits of two
                                 one-step sweeps).  Applies to single FP32 simulations without
-                                a mask or open boundaries whose width is a multiple of 128;
-                                elsewhere, and in batches, sweeps take one step. */
+                                a mask or open boundaries whose width is even; elsewhere, and
+                                in batches, sweeps take one step.  With two steps per launch,
+                                rows_per_wave and waves_per_block shape the two-step pass
+                                (cols_per_lane the one-step sweeps of odd step counts). */
 } trt_tuning;
 
 typedef struct trt_sim trt_sim;
@@ -208,8 +210,9 @@ trt_status trt_get_populations(trt_sim *s, double *f);
 
 /* Advance nsteps >= 0 time steps (Eq. 2 followed by streaming), enqueued on
  * the stream as replays of captured HIP graphs (see trt_tuning.graph_steps)
- * plus at most one plain launch; any split of the steps gives the same
- * bits. */
+ * plus at most two plain launches; two time steps per launch where
+ * trt_tuning.steps_per_sweep allows it.  Any split of the steps, and either
+ * number of steps per launch, gives the same bits. */
 trt_status trt_step(trt_sim *s, int64_t nsteps);
 
 /* A measurement aid, not a step of the method: nsweeps launches that move

@@ -2,9 +2,9 @@
 
 For a lattice shape, storage type and mask presence it times the fused sweep
 over a grid of launch shapes (rows a wavefront marches, wavefronts per
-workgroup, XCD remap on/off, one or two columns per lane where two apply)
-on a scratch lattice of that shape, and keeps
-the fastest.  For a batch it times the batched step (rows, wavefronts per
+workgroup, XCD remap on/off, one or two columns per lane where two apply,
+one or two time steps per launch where two apply) on a scratch lattice of
+that shape, and keeps the fastest.  For a batch it times the batched step (rows, wavefronts per
 workgroup, XCD remap) on scratch copies of the members.  Results persist in
 a JSON cache keyed by GPU architecture, storage, mask presence and size
 buckets (for a batch: its member count and size mix); the cache path is
@@ -22,6 +22,8 @@ WAVES = (1, 2, 4)            # one column per lane: at most 4 wavefronts per wor
 WAVES_PAIR = (1, 2, 4, 8, 16)  # two columns per lane (the library caps FP64 at 8)
 REMAP = (1, 0)
 COLS = (1, 2)
+TB2_ROWS = (8, 12, 16, 24, 32, 48, 64)  # two time steps per launch
+TB2_WAVES = (1, 2, 4)
 
 
 def cache_path() -> str:
@@ -58,9 +60,10 @@ def save_cache(cache: dict, path: str | None = None) -> None:
 
 def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
     """Launch shapes (rows, waves per workgroup, XCD remap, columns per
-    lane) worth timing; two columns per lane apply to every width that is
-    not 1 mod 128 (with or without a mask: masked lattices use the link
-    map)."""
+    lane, graph sweeps (0: default), time steps per launch) worth timing.
+    Two columns per lane apply to every width that is not 1 mod 128 (with
+    or without a mask: masked lattices use the link map); two time steps
+    per launch to FP32 lattices without a mask whose width is even."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -71,7 +74,14 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
                 continue
             for w in waves:
                 for x in REMAP:
-                    out.append((r, w, x, c))
+                    out.append((r, w, x, c, 0, 1))
+    if storage == "f32" and not has_mask and nx % 2 == 0:
+        for r in TB2_ROWS:
+            if r > max(8, ny):
+                continue
+            for w in TB2_WAVES:
+                for x in REMAP:
+                    out.append((r, w, x, 2, 0, 2))
     return out
 
 

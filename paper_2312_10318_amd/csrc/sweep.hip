@@ -843,39 +843,37 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per pass (two columns per lane, FP32 storage, open periodic
-// lattices whose width is a multiple of 128).
+// Two time steps per pass (FP32 storage, open periodic lattices of even
+// width).
 //
 // One launch advances the lattice by two time steps and moves each
-// population through HBM once: the wavefront marches its 128-column strip
-// row by row, and in iteration y it
-//   (a) issues the loads of row y + 4 of the stored state (the pull of the
+// population through HBM once.  A wavefront owns a 128-column window (lane
+// l: the column pair s + 2l, s + 2l + 1, wrapped) and marches it through a
+// row block as a pipeline; in pipeline row y it
+//   (a) issues the loads of a later row of the stored state (the pull of the
 //       first step, as in the one-step sweep),
-//   (b) forms the moments and Phi of row y + 3 (first step) from the row
-//       loaded in the previous iteration,
+//   (b) forms the moments, Phi and collision coefficients of row y + 3
+//       (first step) from a row loaded earlier,
 //   (c) collides row y + 2 (first step): its post-collision populations stay
 //       in registers,
 //   (d) pulls row y + 1 of the second step from the first step's results of
 //       rows y, y + 1 and y + 2 (populations 2, 5, 6 from the row below,
 //       0, 1, 3 from the row itself, 4, 7, 8 from the row above; neighbours
-//       in x through DPP lane shifts) and forms its moments and Phi,
+//       in x through DPP lane shifts) and forms its moments, Phi and
+//       coefficients,
 //   (e) collides row y (second step) and stores it.
-// The first step's results are needed two columns beyond the strip on each
-// side (the pulls of the second step and its Phi gradient at the strip's
-// edge columns), so lanes 0 and 63 also run the first step for the column
-// pair just outside the strip (x0 - 2, x0 - 1 or x0 + 128, x0 + 129, the
-// "halo pair"), with the Phi of the next column out (x0 - 3 or x0 + 130)
-// from a gathered halo node, and pull the second step's state of the
-// adjacent outside column for its Phi.  Every node's arithmetic is that of
-// the one-step sweep, operation for operation (the halo nodes' too), and
-// the first step's FP32 results are exactly what that sweep would store and
-// load back, so two steps per pass give the one-step sweep's bits.
-// A row block of R output rows runs R + 6 iterations (the first six fill
-// the pipeline) and reads R + 8 stored rows.
-// 4096^2: 153 us per step at 64 rows and two wavefronts per workgroup,
-// against 212 us for one step per launch; the pass is then limited by
-// instruction issue, not HBM (the halo pair's code runs with the wavefront's
-// other 62 lanes idle).
+// Each stage's stencil reaches one column further than the last (the first
+// step's pull, its Phi gradient, the second step's pull, its Phi gradient),
+// so a window edge spoils one column per stage; the wavefront stores only
+// the window's middle 120 columns [s + 4, s + 124), and windows overlap by
+// eight columns.  Every lane runs the same code: no halo loads and no edge
+// lane work (a first design ran the first step on the two columns beyond a
+// 128-column strip in its edge lanes, and the other 62 lanes' issue slots
+// paid for it: 153 against 127 us per step on 4096^2).  A row block of R
+// rows runs R + 6 pipeline rows and reads R + 6 rows of each population.
+// Every node's arithmetic is the one-step sweep's, operation for operation,
+// and the first step's FP32 results are exactly what that sweep would store
+// and load back, so two steps per pass reproduce its bits.
 
 // The first step's post-collision populations of one node between the
 // iteration that makes them and the two iterations that pull them.
@@ -924,81 +922,136 @@ __device__ __forceinline__ void node_state(RowState<C, SHIFTED> &st, const C f[9
     st.phiy = st.m.rho * st.m.uy * st.m.uy * st.m.uy;
 }
 
-// Widen the halo pair's row: lane 0 holds columns (x0 - 2, x0 - 1), whose
-// populations 1, 5, 8 of node A come from column x0 - 3 (the halo row's
-// edge elements) and 3, 6, 7 of node B from column x0 (the own pair's node
-// A); lane 63 holds (x0 + 128, x0 + 129), node A taking 1, 5, 8 from column
-// x0 + 127 (the own pair's node B) and node B 3, 6, 7 from x0 + 130.
-template <class C, bool SHIFTED>
-__device__ __forceinline__ void widen_halo_pair(RowState<C, SHIFTED> &a, RowState<C, SHIFTED> &b,
-                                                const PairRow<float> &h, const PairRow<float> &o,
-                                                bool l0, C gx, C gy) {
-    C ha[9], hb[9], oa[9], ob[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        PairIO<float>::split(h.w[i], ha[i], hb[i]);
-        PairIO<float>::split(o.w[i], oa[i], ob[i]);
-    }
-    float e0 = h.edge[0], e1 = h.edge[1], e2 = h.edge[2];
-    C fa[9], fb[9];
-    fa[0] = ha[0]; fb[0] = hb[0];
-    fa[2] = ha[2]; fb[2] = hb[2];
-    fa[4] = ha[4]; fb[4] = hb[4];
-    fa[1] = l0 ? e0 : ob[1]; fb[1] = ha[1];
-    fa[5] = l0 ? e1 : ob[5]; fb[5] = ha[5];
-    fa[8] = l0 ? e2 : ob[8]; fb[8] = ha[8];
-    fb[3] = l0 ? oa[3] : e0; fa[3] = hb[3];
-    fb[6] = l0 ? oa[6] : e1; fa[6] = hb[6];
-    fb[7] = l0 ? oa[7] : e2; fa[7] = hb[7];
-    node_state<C, SHIFTED>(a, fa, gx, gy);
-    node_state<C, SHIFTED>(b, fb, gx, gy);
-}
+// Columns of a window that the pass stores.
+constexpr int kTb2Valid = 120;
 
-// The halo pair's first-step state lives in LDS, one slot per edge lane
-// (only lanes 0 and 63 use it, so in registers it would cost every lane):
-// the moments and Phi of the pair's row being collided (cur) and of the row
-// widened this iteration (nxt, two buffers swapped by parity), Phi_y of the
-// row below, Phi_x beyond the pair, and the pair's window of first-step
-// results.  Each edge lane reads and writes only its own slot.
-constexpr int kTb2MaxWaves = 16;
-struct HaloSlot {
-    float st[2][2][13];  // [parity][node A, B]: 11 moments, Phi_x, Phi_y
-    float hh[2];         // [parity]: Phi_x of the column beyond the pair
-    float bel[2];        // Phi_y of the row below the collided one (A, B)
-    float win[2][9];     // MidWindow of nodes A, B (lo[3], mid[6])
+template <class C> struct Tb2Carry {
+    Coeffs<C> kA, kB;     // first step: coefficients of the next row to collide
+    C pyA, pyB;           // ... its Phi_y
+    C belA, belB;         // ... and that of the row below it
+    MidWindow<C> wA, wB;  // first-step results in flight
+    Coeffs<C> qA, qB;     // second step: coefficients of the next row to store
+    C qyA, qyB, qbelA, qbelB;
 };
 
-template <class C, bool SH>
-__device__ __forceinline__ void put_state(float *o, const RowState<C, SH> &r) {
-    o[0] = r.m.base; o[1] = r.m.rho; o[2] = r.m.jx; o[3] = r.m.jy; o[4] = r.m.ux; o[5] = r.m.uy;
-    o[6] = r.m.pxx; o[7] = r.m.pyy; o[8] = r.m.pxy; o[9] = r.m.qxxy; o[10] = r.m.qxyy;
-    o[11] = r.phix; o[12] = r.phiy;
-}
-template <class C, bool SH>
-__device__ __forceinline__ void get_state(RowState<C, SH> &r, const float *o) {
-    r.m.base = o[0]; r.m.rho = o[1]; r.m.jx = o[2]; r.m.jy = o[3]; r.m.ux = o[4]; r.m.uy = o[5];
-    r.m.pxx = o[6]; r.m.pyy = o[7]; r.m.pxy = o[8]; r.m.qxxy = o[9]; r.m.qxyy = o[10];
-    r.phix = o[11]; r.phiy = o[12];
-    r.solid = false;
-}
-__device__ __forceinline__ void get_window(MidWindow<float> &w, const float *o) {
-    w.lo[0] = o[0]; w.lo[1] = o[1]; w.lo[2] = o[2];
+struct Tb2Params {
+    float gx, gy, w1, w2, ph;
+};
+
+// One pipeline row: (b) the moments and coefficients of first-step row
+// y + 3 from `raw`, whose registers then take the loads of row `yload`
+// (when `load`), (c) from STAGE 1 the first-step collision of row y + 2,
+// (d) from STAGE 2 the second-step pull of row y + 1 and its coefficients,
+// (e) at STAGE 3 the second-step collision and store of row y.
+template <int STAGE, class T, class C, bool SH>
+__device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const PairCtx<T> &cx,
+                                        const Tb2Params &p, const BufAccess<T> &out, int y,
+                                        bool load, int yload, bool store, int pitch,
+                                        int64_t plane, int stage = STAGE) {
+    const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
+    OpenX<C> ox;
+    ox.on = false;
+    ox.nx = 0;
+    ox.u_in = ox.rho_in = ox.rho_out = ox.phi_wall = C(0);
+    // (b) row y + 3, then (a) the next loads into the same registers
+    C nyA, nyB;
+    Coeffs<C> nkA, nkB;
+    {
+        RowState<C, SH> nA, nB;
+        widen_pair<T, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) gather_pair_row<T, false>(raw, cx, yload, 0u);
+        const C left = dpp_shr(C(0), nB.phix);
+        const C right = dpp_shl(C(0), nA.phix);
+        nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
+        nkB = collide_coeffs<C, SH>(nB.m, C(0.5) * (right - nA.phix), w1, w2, ph, gx, gy);
+        nyA = nA.phiy;
+        nyB = nB.phiy;
+    }
+    // (c) collide row y + 2 of the first step
+    C oa[9], ob[9];
+    if (stage >= 1) {
+        const C dya = C(0.5) * (nyA - k.belA);
+        const C dyb = C(0.5) * (nyB - k.belB);
+        reconstruct<C>(oa, k.kA.base, k.kA.bx, k.kA.by, k.kA.bxx, k.kA.byy - ph * dya, k.kA.bxy,
+                       k.kA.bxxy, k.kA.bxyy);
+        reconstruct<C>(ob, k.kB.base, k.kB.bx, k.kB.by, k.kB.bxx, k.kB.byy - ph * dyb, k.kB.bxy,
+                       k.kB.bxxy, k.kB.bxyy);
+    }
+    // (d) row y + 1 of the second step
+    C cyA = C(0), cyB = C(0);
+    Coeffs<C> ckA, ckB;
+    if (stage >= 2) {
+        C fa[9], fb[9];
+        MidWindow<C> lw, rw;
+        C lf[9], rf[9];
+        // node A: x - 1 is the previous lane's node B
+        lw.mid[1] = dpp_shr(C(0), k.wB.mid[1]);
+        lw.lo[1] = dpp_shr(C(0), k.wB.lo[1]);
+        lf[8] = dpp_shr(C(0), ob[8]);
+        mid_pull<C>(fa, k.wA, oa, lw, lf, k.wB, ob);
+        // node B: x + 2 is the next lane's node A
+        rw.mid[2] = dpp_shl(C(0), k.wA.mid[2]);
+        rw.lo[2] = dpp_shl(C(0), k.wA.lo[2]);
+        rf[7] = dpp_shl(C(0), oa[7]);
+        mid_pull<C>(fb, k.wB, ob, k.wA, oa, rw, rf);
+        RowState<C, SH> cA, cB;
+        node_state<C, SH>(cA, fa, gx, gy);
+        node_state<C, SH>(cB, fb, gx, gy);
+        const C left = dpp_shr(C(0), cB.phix);
+        const C right = dpp_shl(C(0), cA.phix);
+        ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
+        ckB = collide_coeffs<C, SH>(cB.m, C(0.5) * (right - cA.phix), w1, w2, ph, gx, gy);
+        cyA = cA.phiy;
+        cyB = cB.phiy;
+    }
+    // (e) collide row y of the second step and store the window's middle
+    if (stage >= 3) {
+        const C dya = C(0.5) * (cyA - k.qbelA);
+        const C dyb = C(0.5) * (cyB - k.qbelB);
+        C sa[9], sb[9];
+        reconstruct<C>(sa, k.qA.base, k.qA.bx, k.qA.by, k.qA.bxx, k.qA.byy - ph * dya, k.qA.bxy,
+                       k.qA.bxxy, k.qA.bxyy);
+        reconstruct<C>(sb, k.qB.base, k.qB.bx, k.qB.by, k.qB.bxx, k.qB.byy - ph * dyb, k.qB.bxy,
+                       k.qB.bxxy, k.qB.bxyy);
+        if (store) {
+            const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) w.mid[i] = o[3 + i];
-}
-__device__ __forceinline__ void put_window(float *o, const MidWindow<float> &w) {
-    o[0] = w.lo[0]; o[1] = w.lo[1]; o[2] = w.lo[2];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) o[3 + i] = w.mid[i];
+            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, sa[i], sb[i]);
+        }
+    }
+    // advance the pipeline by one row
+    if (stage >= 2) {
+        k.qbelA = k.qyA;
+        k.qbelB = k.qyB;
+        k.qyA = cyA;
+        k.qyB = cyB;
+        k.qA = ckA;
+        k.qB = ckB;
+    }
+    if (stage >= 1) {
+        mid_shift<C>(k.wA, oa);
+        mid_shift<C>(k.wB, ob);
+    }
+    k.belA = k.pyA;
+    k.belB = k.pyB;
+    k.pyA = nyA;
+    k.pyB = nyB;
+    k.kA = nkA;
+    k.kB = nkB;
+    __builtin_amdgcn_s_barrier();
 }
 
-template <int ST, bool SYNC>
+// One wavefront's window through one row block: the six rows that fill the
+// pipeline as a short loop (run-time stage: fewer registers than peeled
+// copies), then the full pipeline.  The loads run DEPTH rows ahead of their
+// use (DEPTH 2: two row buffers, alternating).
+template <int ST, int DEPTH>
 __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
     constexpr bool SH = Store<ST>::shifted;
     static_assert(ST == ST_F32, "two steps per pass: FP32 storage");
-    __shared__ HaloSlot halo_slots[kTb2MaxWaves][2];
+    static_assert(DEPTH == 1 || DEPTH == 2, "loads one or two rows ahead");
 
     const int lane = threadIdx.x & 63;
     const int nx = d.nx, ny = d.ny, pitch = d.pitch;
@@ -1008,211 +1061,51 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     const uint64_t bytes = (uint64_t)ny * (uint64_t)pitch * sizeof(T);
     const BufAccess<T> in(src, bytes), out(dst, bytes);
     const LinkAccess lacc(d.links, 0);
-    const bool l0 = lane == 0;
-    const bool edge = l0 || lane == 63;
-    HaloSlot &hs = halo_slots[threadIdx.x >> 6][l0 ? 0 : 1];
-
-    // the own pair: as in the one-step sweep (the host admits widths that are
-    // multiples of 128, so every lane's pair lies inside the row)
-    const int x0 = strip * kStripWidth2;
-    const int ca = x0 + 2 * lane;
-    const Column hcol = column_of(l0 ? x0 - 1 : x0 + kStripWidth2, nx, sizeof(T));
-    const int pe0 = l0 ? 1 : 3, pe1 = l0 ? 5 : 6, pe2 = l0 ? 8 : 7;
-    const uint32_t ve[3] = {(uint32_t)(pe0 * plane * (int64_t)sizeof(T)) + hcol.oc,
-                            (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hcol.oc,
-                            (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hcol.oc};
+    // the lane's pair (an even column: the width is even, so the pair lies
+    // inside the row) and whether it is in the stored middle of the window
+    // and inside the lattice
+    const int xs = strip * kTb2Valid - 4 + 2 * lane;
+    int ca = xs % nx;
+    if (ca < 0) ca += nx;
+    const bool store = lane >= 2 && lane < 62 && xs < nx;
+    const Column hcol = column_of(ca, nx, sizeof(T));  // no halo node: unused
+    const uint32_t ve[3] = {0u, 0u, 0u};
     const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)ca * (uint32_t)sizeof(T), (uint32_t)ca,
-                        edge, ve, hcol, lacc, false, d.lpitch, 0u, false};
-    // the halo pair and the column beyond it
-    int hc = l0 ? x0 - 2 : x0 + kStripWidth2;
-    if (hc < 0) hc += nx;
-    if (hc >= nx) hc -= nx;
-    const Column hhcol = column_of(l0 ? x0 - 3 : x0 + kStripWidth2 + 2, nx, sizeof(T));
-    const uint32_t hve[3] = {(uint32_t)(pe0 * plane * (int64_t)sizeof(T)) + hhcol.oc,
-                             (uint32_t)(pe1 * plane * (int64_t)sizeof(T)) + hhcol.oc,
-                             (uint32_t)(pe2 * plane * (int64_t)sizeof(T)) + hhcol.oc};
-    const PairCtx<T> hx{in, plane, pitch, ny, (uint32_t)hc * (uint32_t)sizeof(T), (uint32_t)hc,
-                        edge, hve, hhcol, lacc, false, d.lpitch, 0u, false};
-
-    const C gx = (C)d.gx, gy = (C)d.gy;
-    const C w1 = (C)d.omega1, w2 = (C)d.omega2, ph = (C)d.phi;
-    OpenX<C> ox;
-    ox.on = false;
-    ox.nx = nx;
-    ox.u_in = ox.rho_in = ox.rho_out = ox.phi_wall = C(0);
+                        false, ve, hcol, lacc, false, d.lpitch, 0u, false};
+    const Tb2Params p{(float)d.gx, (float)d.gy, (float)d.omega1, (float)d.omega2, (float)d.phi};
     const int y0 = rb * d.rows;
     const int y1 = min(y0 + d.rows, ny);
     const auto wrap_row = [&](int v) { v %= ny; return v < 0 ? v + ny : v; };
+    // the row loaded in pipeline row y (y + 3 + DEPTH), while one is needed
+    // (the last needed is y1 + 2)
+    const auto ld = [&](int y) { return y + 3 + DEPTH <= y1 + 2; };
+    const auto lrow = [&](int y) { return wrap_row(y + 3 + DEPTH); };
 
-    // first step: the raw row loaded last iteration (own and halo pair), the
-    // own pair's states of the row being collided, Phi_y of the row below
-    PairRow<T> raw, hraw;
-    RowState<C, SH> aA, aB;
-    C belA = C(0), belB = C(0);
-    // the own pair's first-step results in flight to the second step
-    MidWindow<C> wA{}, wB{};
-    // second step: the states of row y, Phi_y of row y - 1, the adjacent
-    // outside column's Phi_x of row y
-    RowState<C, SH> bA, bB;
-    C bbelA = C(0), bbelB = C(0), bhphix = C(0);
-    int par = 0;  // LDS buffer holding the halo pair's row being collided
-
-    if (edge) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) hs.win[0][i] = hs.win[1][i] = 0.0f;
-        hs.bel[0] = hs.bel[1] = 0.0f;
+    Tb2Carry<C> k{};
+    PairRow<T> raw[DEPTH];
+    gather_pair_row<T, false>(raw[0], cx, wrap_row(y0 - 3), 0u);
+    if (DEPTH == 2) gather_pair_row<T, false>(raw[DEPTH - 1], cx, wrap_row(y0 - 2), 0u);
+    constexpr int R1 = DEPTH - 1;
+    int y = y0 - 6;
+    for (int i = 0; i < 6; ++i, ++y) {
+        if (DEPTH == 2 && (i & 1))
+            tb2_row<-1, T, C, SH>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+                                  i >> 1);
+        else
+            tb2_row<-1, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+                                  i >> 1);
     }
-    gather_pair_row<T, false>(raw, cx, wrap_row(y0 - 3), 0u);
-    if (edge) gather_pair_row<T, true>(hraw, hx, wrap_row(y0 - 3), 0u);
-
-    for (int y = y0 - 6; y < y1; ++y) {
-        // (b) row y + 3 of the first step, from the row loaded last iteration
-        RowState<C, SH> nA, nB;
-        widen_pair<T, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
-        if (edge) {
-            RowState<C, SH> hA, hB;
-            widen_halo_pair<C, SH>(hA, hB, hraw, raw, l0, gx, gy);
-            put_state<C, SH>(hs.st[par ^ 1][0], hA);
-            put_state<C, SH>(hs.st[par ^ 1][1], hB);
-            hs.hh[par ^ 1] = pair_halo_phix<T, C, SH, false>(hraw.halo, hx, gx, ox);
+    if (DEPTH == 1) {
+        for (; y < y1; ++y)
+            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+    } else {
+        for (; y + 1 < y1; y += 2) {
+            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb2_row<3, T, C, SH>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
+                                 pitch, plane);
         }
-        // (a) then the loads of row y + 4 into the same registers: they have
-        // the rest of the iteration to arrive
-        const bool more = y + 4 <= y1 + 2;
-        if (more) {
-            gather_pair_row<T, false>(raw, cx, wrap_row(y + 4), 0u);
-            if (edge) gather_pair_row<T, true>(hraw, hx, wrap_row(y + 4), 0u);
-        }
-        // (c) collide row y + 2 of the first step
-        C oa[9] = {}, ob[9] = {};
-        const bool stepA = y >= y0 - 4;
-        // the halo pair's fresh results, and the old values of the second
-        // step's lane shifts (lane 0: halo node B, lane 63: halo node A)
-        C hoa7 = C(0), hob8 = C(0), oB1 = C(0), oB5 = C(0), oA3 = C(0), oA6 = C(0);
-        C chphix = C(0);
-        if (stepA) {
-            C hp = C(0);
-            if (edge) hp = hs.st[par][l0 ? 1 : 0][11];
-            const C left = dpp_shr(hp, aB.phix);
-            const C right = dpp_shl(hp, aA.phix);
-            Coeffs<C> fa = collide_coeffs<C, SH>(aA.m, C(0.5) * (aB.phix - left), w1, w2, ph, gx, gy);
-            Coeffs<C> fb = collide_coeffs<C, SH>(aB.m, C(0.5) * (right - aA.phix), w1, w2, ph, gx, gy);
-            const C dya = C(0.5) * (nA.phiy - belA);
-            const C dyb = C(0.5) * (nB.phiy - belB);
-            reconstruct<C>(oa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dya, fa.bxy, fa.bxxy,
-                           fa.bxyy);
-            reconstruct<C>(ob, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dyb, fb.bxy, fb.bxxy,
-                           fb.bxyy);
-            if (edge) {
-                // the halo pair's collision, then its part of the second step's
-                // pull: the old values of the lane shifts and the Phi_x of
-                // the outside column next to the strip (lane 0: column x0 - 1,
-                // halo node B between halo node A and own node A; lane 63:
-                // column x0 + 128, halo node A between own node B and halo B)
-                C hoa[9], hob[9];
-                {
-                    RowState<C, SH> hA, hB;
-                    get_state<C, SH>(hA, hs.st[par][0]);
-                    get_state<C, SH>(hB, hs.st[par][1]);
-                    const C hhp = hs.hh[par];
-                    const C la = l0 ? hhp : aB.phix;
-                    const C rb_ = l0 ? aA.phix : hhp;
-                    Coeffs<C> ga = collide_coeffs<C, SH>(hA.m, C(0.5) * (hB.phix - la), w1, w2, ph, gx, gy);
-                    Coeffs<C> gb = collide_coeffs<C, SH>(hB.m, C(0.5) * (rb_ - hA.phix), w1, w2, ph, gx, gy);
-                    const C hya = C(0.5) * (hs.st[par ^ 1][0][12] - hs.bel[0]);
-                    const C hyb = C(0.5) * (hs.st[par ^ 1][1][12] - hs.bel[1]);
-                    hs.bel[0] = hA.phiy;
-                    hs.bel[1] = hB.phiy;
-                    reconstruct<C>(hoa, ga.base, ga.bx, ga.by, ga.bxx, ga.byy - ph * hya, ga.bxy,
-                                   ga.bxxy, ga.bxyy);
-                    reconstruct<C>(hob, gb.base, gb.bx, gb.by, gb.bxx, gb.byy - ph * hyb, gb.bxy,
-                                   gb.bxxy, gb.bxyy);
-                }
-                MidWindow<C> hwA, hwB;
-                get_window(hwA, hs.win[0]);
-                get_window(hwB, hs.win[1]);
-                hoa7 = hoa[7];
-                hob8 = hob[8];
-                oB1 = hwB.mid[1];
-                oB5 = hwB.lo[1];
-                oA3 = hwA.mid[2];
-                oA6 = hwA.lo[2];
-                if (y >= y0 - 2) {
-                    C fh[9];
-                    if (l0)
-                        mid_pull<C>(fh, hwB, hob, hwA, hoa, wA, oa);
-                    else
-                        mid_pull<C>(fh, hwA, hoa, wB, ob, hwB, hob);
-                    RowState<C, SH> hsn;
-                    node_state<C, SH>(hsn, fh, gx, gy);
-                    chphix = hsn.phix;
-                }
-                mid_shift<C>(hwA, hoa);
-                mid_shift<C>(hwB, hob);
-                put_window(hs.win[0], hwA);
-                put_window(hs.win[1], hwB);
-            }
-        } else if (edge) {
-            hs.bel[0] = hs.st[par][0][12];
-            hs.bel[1] = hs.st[par][1][12];
-        }
-        // (d) row y + 1 of the second step
-        RowState<C, SH> cA, cB;
-        const bool pullB = y >= y0 - 2;
-        if (pullB) {
-            C fa[9], fb[9];
-            // node A: x - 1 is the previous lane's node B (lane 0: halo node B)
-            MidWindow<C> lw;
-            C lf[9];
-            lw.mid[1] = dpp_shr(oB1, wB.mid[1]);
-            lw.lo[1] = dpp_shr(oB5, wB.lo[1]);
-            lf[8] = dpp_shr(hob8, ob[8]);
-            mid_pull<C>(fa, wA, oa, lw, lf, wB, ob);
-            // node B: x + 2 is the next lane's node A (lane 63: halo node A)
-            MidWindow<C> rw;
-            C rf[9];
-            rw.mid[2] = dpp_shl(oA3, wA.mid[2]);
-            rw.lo[2] = dpp_shl(oA6, wA.lo[2]);
-            rf[7] = dpp_shl(hoa7, oa[7]);
-            mid_pull<C>(fb, wB, ob, wA, oa, rw, rf);
-            node_state<C, SH>(cA, fa, gx, gy);
-            node_state<C, SH>(cB, fb, gx, gy);
-        }
-        // (e) collide row y of the second step and store it
-        if (y >= y0) {
-            const C left = dpp_shr(bhphix, bB.phix);
-            const C right = dpp_shl(bhphix, bA.phix);
-            Coeffs<C> fa = collide_coeffs<C, SH>(bA.m, C(0.5) * (bB.phix - left), w1, w2, ph, gx, gy);
-            Coeffs<C> fb = collide_coeffs<C, SH>(bB.m, C(0.5) * (right - bA.phix), w1, w2, ph, gx, gy);
-            const C dya = C(0.5) * (cA.phiy - bbelA);
-            const C dyb = C(0.5) * (cB.phiy - bbelB);
-            C sa[9], sb[9];
-            reconstruct<C>(sa, fa.base, fa.bx, fa.by, fa.bxx, fa.byy - ph * dya, fa.bxy, fa.bxxy,
-                           fa.bxyy);
-            reconstruct<C>(sb, fb.base, fb.bx, fb.by, fb.bxx, fb.byy - ph * dyb, fb.bxy, fb.bxxy,
-                           fb.bxyy);
-            const int64_t e0 = (int64_t)y * pitch;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, sa[i], sb[i]);
-        }
-        // advance the pipeline by one row
-        if (pullB) {
-            bbelA = bA.phiy;
-            bbelB = bB.phiy;
-            bA = cA;
-            bB = cB;
-            bhphix = chphix;
-        }
-        if (stepA) {
-            mid_shift<C>(wA, oa);
-            mid_shift<C>(wB, ob);
-        }
-        belA = aA.phiy;
-        belB = aB.phiy;
-        aA = nA;
-        aB = nB;
-        par ^= 1;
-        if (SYNC) __builtin_amdgcn_s_barrier();
+        if (y < y1)
+            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
     }
 }
 
@@ -1246,16 +1139,15 @@ __global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(I
         idle_rows(d, rb);
 }
 
-// Two time steps per pass (see sweep_strip_tb2); the grid is as for the
-// two-column sweep, and a wavefront without a strip meets the barriers of
-// its row block's R + 6 iterations.
-// At most four wavefronts per workgroup: with the halo pair's state in LDS
-// the kernel fits 256 VGPRs without spills, two wavefronts per SIMD.
-#ifndef TRT_TB2_THREADS
-#define TRT_TB2_THREADS 256
-#endif
-template <int ST>
-__global__ __launch_bounds__(TRT_TB2_THREADS) void sweep_tb2_kernel(InstDesc d, int srcsel, int remap) {
+// Two time steps per pass (sweep_strip_tb2): workgroup b covers row block
+// b / groups and the windows [g * wpb, g * wpb + wpb) with g = b % groups,
+// as the two-column sweep; a wavefront without a window meets the R + 6
+// barriers of its row block.  DEPTH 1 fits 166 VGPRs (three wavefronts per
+// SIMD), DEPTH 2 214 (two).
+constexpr int kTb2MaxWaves = 4;
+template <int ST, int DEPTH>
+__global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d, int srcsel,
+                                                                      int remap) {
     int b = blockIdx.x;
     if (remap) b = xcd_remap(b, gridDim.x);
     const int wpb = blockDim.x >> 6;
@@ -1264,7 +1156,7 @@ __global__ __launch_bounds__(TRT_TB2_THREADS) void sweep_tb2_kernel(InstDesc d, 
     const int rb = b / groups;
     const int strip = (b - rb * groups) * wpb + w;
     if (strip < d.strips) {
-        sweep_strip_tb2<ST, true>(d, strip, rb, srcsel);
+        sweep_strip_tb2<ST, DEPTH>(d, strip, rb, srcsel);
     } else {
         const int y0 = rb * d.rows;
         const int y1 = min(y0 + d.rows, d.ny);
@@ -1379,20 +1271,59 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
 
 bool tb2_eligible(const InstDesc &d, int storage) {
     return storage == ST_F32 && d.links == nullptr && d.xbc == 0 && d.mask == nullptr &&
-           d.nx % kStripWidth2 == 0 && buffer_addressable(d, storage);
+           d.nx % 2 == 0 && buffer_addressable(d, storage);
 }
 
+// Wavefronts at which the two-step pass switches to loads two rows ahead
+// and four-wavefront workgroups: with at least two rounds of wavefronts at
+// two per SIMD, the deeper prefetch outweighs the lost third wavefront
+// (4096^2, 4480 wavefronts: 126.7 against 132.0 us per step), below it
+// does not (2048^2, 2304 wavefronts: 40.3 against 35.7).
+constexpr long long kTb2DeepWaves = 4096;
+
+InstDesc tb2_desc(const InstDesc &d, const Launch &l) {
+    InstDesc t = d;
+    t.strips = (d.nx + kTb2Valid - 1) / kTb2Valid;
+    if (l.rows_per_wave > 0) {
+        t.rows = l.rows_per_wave;
+    } else {
+        // the longest row block of 32, 24, 16, 12 or 8 rows that still gives
+        // 2048 wavefronts (a block of R rows runs R + 6 pipeline rows), else
+        // 8 (measured optima: 4096^2 32 rows, 2048^2 16, 1024^2 8-12)
+        static const int kRows[] = {32, 24, 16, 12, 8};
+        t.rows = 8;
+        for (int r : kRows) {
+            if ((long long)t.strips * ((d.ny + r - 1) / r) >= 2048) {
+                t.rows = r;
+                break;
+            }
+        }
+    }
+    t.rowblocks = (d.ny + t.rows - 1) / t.rows;
+    return t;
+}
+
+static bool tb2_deep(const InstDesc &t) { return (long long)t.strips * t.rowblocks >= kTb2DeepWaves; }
+
 int tb2_waves_per_block(const InstDesc &d, int storage, const Launch &l) {
-    const int wpb = single_waves_per_block(d, storage, l);
-    return wpb < TRT_TB2_THREADS / 64 ? wpb : TRT_TB2_THREADS / 64;
+    (void)storage;
+    const InstDesc t = tb2_desc(d, l);
+    int w = l.waves_per_block > 0 ? l.waves_per_block : (tb2_deep(t) ? 4 : 1);
+    if (w > kTb2MaxWaves) w = kTb2MaxWaves;
+    while (w > 1 && w / 2 >= t.strips) w /= 2;
+    return w;
 }
 
 hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launch &l,
                             hipStream_t stream) {
-    if (!tb2_eligible(d, storage) || d.cols != 2) return hipErrorInvalidValue;
+    if (!tb2_eligible(d, storage)) return hipErrorInvalidValue;
+    const InstDesc t = tb2_desc(d, l);
     const int wpb = tb2_waves_per_block(d, storage, l);
-    const int blocks = d.rowblocks * ((d.strips + wpb - 1) / wpb);
-    sweep_tb2_kernel<ST_F32><<<blocks, 64 * wpb, 0, stream>>>(d, src, l.xcd_remap);
+    const int blocks = t.rowblocks * ((t.strips + wpb - 1) / wpb);
+    if (tb2_deep(t))
+        sweep_tb2_kernel<ST_F32, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
+    else
+        sweep_tb2_kernel<ST_F32, 1><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
     return hipGetLastError();
 }
 

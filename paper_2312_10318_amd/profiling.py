@@ -61,7 +61,13 @@ def _csv(d, suffix):
 
 def _is_sweep(name):
     return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
-            "sweep_batch_kernel" in name or "pattern_probe_kernel" in name)
+            "sweep_tb2_kernel" in name or "sweep_batch_kernel" in name or
+            "pattern_probe_kernel" in name)
+
+
+def updates_per_launch(kernel_name) -> int:
+    """Time steps one launch of a sweep kernel advances the lattice by."""
+    return 2 if "sweep_tb2_kernel" in (kernel_name or "") else 1
 
 
 def _is_copy(name):
@@ -69,27 +75,33 @@ def _is_copy(name):
 
 
 def kernel_durations(trace_dir):
+    """Durations (ns) of the run's sweep kernel -- the sweep kernel with the
+    most dispatches (a run of two-step launches may end on a one-step
+    sweep) -- and of the copy kernel, and the sweep kernel's name."""
     rows = _csv(trace_dir, "kernel_trace.csv")
-    sweep, copy = [], []
-    name = None
+    by_name, copy = {}, []
     for r in rows:
         dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         if _is_sweep(r["Kernel_Name"]):
-            sweep.append(dt)
-            name = r["Kernel_Name"]
+            by_name.setdefault(r["Kernel_Name"], []).append(dt)
         elif _is_copy(r["Kernel_Name"]):
             copy.append(dt)
-    return sweep, copy, name
+    if not by_name:
+        return [], copy, None
+    name = max(by_name, key=lambda k: len(by_name[k]))
+    return by_name[name], copy, name
 
 
-def counter_values(pmc_dir, counter):
+def counter_values(pmc_dir, counter, kernel=None):
+    """Values of `counter` per dispatch of the sweep kernel `kernel` (any
+    sweep kernel when None) and of the copy kernel."""
     rows = _csv(pmc_dir, "counter_collection.csv")
     sweep, copy = [], []
     for r in rows:
         if r["Counter_Name"] != counter:
             continue
         v = float(r["Counter_Value"])
-        if _is_sweep(r["Kernel_Name"]):
+        if _is_sweep(r["Kernel_Name"]) and (kernel is None or r["Kernel_Name"] == kernel):
             sweep.append(v)
         elif _is_copy(r["Kernel_Name"]):
             copy.append(v)
@@ -119,11 +131,39 @@ WORKLOADS = {
 }
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES",
+               "SQ_WAIT_INST_ANY", "GRBM_GUI_ACTIVE")
+SIMDS = 1024  # 256 CUs x 4 SIMDs
+XCDS = 8
+
+
+def sq_summary(sq_dir, kernel, skip_first=2):
+    """Instruction-issue figures of the sweep kernel from one rocprofv3 pass
+    over SQ_COUNTERS: VALU instructions per launch and the fraction of the
+    SIMDs' issue cycles they fill (a wave64 VALU instruction occupies its
+    16-lane SIMD for 4 cycles; GRBM_GUI_ACTIVE counts the busy cycles of
+    each XCD, summed over the eight)."""
+    vals = {}
+    for c in SQ_COUNTERS:
+        v, _ = counter_values(sq_dir, c, kernel)
+        v = v[skip_first:]
+        if v:
+            vals[c] = sum(v) / len(v)
+    out = {"sq_" + k.lower(): round(v, 1) for k, v in vals.items()}
+    if "SQ_INSTS_VALU" in vals and "GRBM_GUI_ACTIVE" in vals:
+        cycles = vals["GRBM_GUI_ACTIVE"] / XCDS
+        out["valu_busy_frac"] = round(vals["SQ_INSTS_VALU"] * 4 / (SIMDS * cycles), 4)
+    if "SQ_WAIT_INST_ANY" in vals and "SQ_WAVE_CYCLES" in vals:
+        out["wave_wait_frac"] = round(vals["SQ_WAIT_INST_ANY"] / vals["SQ_WAVE_CYCLES"], 4)
+    return out
+
+
 def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_prefix,
-              skip_first=2, run_log=None, workload="tg", nodes=None, tuning=None):
+              skip_first=2, run_log=None, workload="tg", nodes=None, tuning=None,
+              sq_dir=None):
     sweep_ns, copy_ns, kname = kernel_durations(trace_dir)
-    fs, fc = counter_values(fetch_dir, "FETCH_SIZE")
-    ws, wc = counter_values(write_dir, "WRITE_SIZE")
+    fs, fc = counter_values(fetch_dir, "FETCH_SIZE", kname)
+    ws, wc = counter_values(write_dir, "WRITE_SIZE", kname)
     # the first dispatches include cold-cache and launch warm-up effects
     sweep_ns, fs, ws = sweep_ns[skip_first:], fs[skip_first:], ws[skip_first:]
     avg = lambda v: sum(v) / len(v)
@@ -140,12 +180,14 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         nodes = n * n
         label, wlabel = title % (n, n), wname % (n, n)
     # 9 populations read and written (+ the link code read, with a link map)
-    alg = (BYTES_PER_LU[storage] + link_bytes) * nodes
+    # per lattice update; a two-step launch counts two updates per node
+    ups = updates_per_launch(kname)
+    alg = (BYTES_PER_LU[storage] + link_bytes) * nodes * ups
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"(sweep_(single|pair|batch)|pattern_probe)_kernel<[^>]*>",
+        "kernel": (re.search(r"(sweep_(single|pair|tb2|batch)|pattern_probe)_kernel<[^>]*>",
                              kname or "") or re.search(r".*", "sweep")).group(0),
-        "workload": wlabel, "storage": storage, "nodes": nodes,
+        "workload": wlabel, "storage": storage, "nodes": nodes, "updates_per_launch": ups,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
         "dispatches": len(sweep_ns), "avg_duration_us": round(dur * 1e6, 3),
         "algorithmic_bytes_per_launch": alg,
@@ -159,6 +201,8 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         "hbm_GBps_measured": round((fetch_b + write_b) / dur / 1e9, 1),
         "copy_avg_duration_us": round(avg(copy_ns) * 1e-3, 3) if copy_ns else None,
     }
+    if sq_dir:
+        rec.update(sq_summary(sq_dir, kname, skip_first))
     if workload in ("tg", "stream"):
         cmd = ("python3 bench.py --profile%s --storage %s --n %d --steps %d --warmup %d"
                % (" --workload stream" if workload == "stream" else "", storage, n, steps,
@@ -177,17 +221,27 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)
+        if sq_dir:
+            fh.write("    rocprofv3 --pmc %s --kernel-trace -f csv -d <S> -o run -- %s\n"
+                     % (" ".join(SQ_COUNTERS), cmd))
         fh.write("    python -m paper_2312_10318_amd.profiling <T> <F> <W> --workload %s "
-                 "--storage %s --n %d --steps %d --warmup %d%s%s --out %s\n\n"
+                 "--storage %s --n %d --steps %d --warmup %d%s%s%s --out %s\n\n"
                  % (workload, storage, n, steps, warmup,
                     " --nodes %d" % nodes if workload == "batch" else "",
                     " --tuning %s" % tuning if tuning else "",
+                    " --sq <S>" if sq_dir else "",
                     os.path.relpath(out_prefix, ROOT)))
         fh.write("| quantity | value |\n|---|---|\n")
         for k, v in rec.items():
             fh.write("| %s | %s |\n" % (k, v))
+        fh.write("\nAlgorithmic bytes per launch: bytes per lattice update (9 populations "
+                 "read and written) x nodes x time steps per launch.\n")
         fh.write("\nCounters are KiB per dispatch; the scale factors are 1 GiB divided by "
                  "what the same counter reads for a plain 1 GiB device copy.\n")
+        if sq_dir:
+            fh.write("\nvalu_busy_frac: VALU instructions x 4 cycles / (1024 SIMDs x busy "
+                     "cycles per XCD); wave_wait_frac: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES "
+                     "(the share of the wavefronts' lifetime spent waiting to issue).\n")
         stats = _csv(trace_dir, "kernel_stats.csv")
         fh.write("\n`--kernel-trace --stats` summary (durations in ns):\n\n")
         fh.write("| kernel | calls | average | min | max |\n|---|---|---|---|---|\n")
@@ -215,13 +269,16 @@ def main():
                          "profiled kernel was built from)")
     ap.add_argument("--tuning", default=None,
                     help="the --tuning argument of the profiled bench.py run, if any")
+    ap.add_argument("--sq", default=None,
+                    help="output directory of a rocprofv3 pass over the SQ_COUNTERS")
     ap.add_argument("--nodes", type=int, default=None,
                     help="lattice updates per launch of the batch workload (printed by the "
                          "profiled run)")
     a = ap.parse_args()
     rec = summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.storage, a.n, a.steps, a.warmup,
                     os.path.join(ROOT, a.out) if not os.path.isabs(a.out) else a.out,
-                    run_log=a.run_log, workload=a.workload, nodes=a.nodes, tuning=a.tuning)
+                    run_log=a.run_log, workload=a.workload, nodes=a.nodes, tuning=a.tuning,
+                    sq_dir=a.sq)
     print(json.dumps(rec, indent=1))
 
 

@@ -5,22 +5,37 @@ from paper_2312_10318_amd import autotune
 def test_candidates_cover_both_column_modes_on_even_widths():
     for has_mask in (False, True):
         shapes = autotune.candidates(4096, 4096, has_mask, "f32")
-        assert {c for _, _, _, c in shapes} == {1, 2}
-        assert {w for _, w, _, c in shapes if c == 1} == {1, 2, 4}
-        assert {w for _, w, _, c in shapes if c == 2} == {1, 2, 4, 8, 16}
-        assert {x for _, _, x, _ in shapes} == {0, 1}
+        one = [s for s in shapes if s[5] == 1]
+        assert {s[3] for s in one} == {1, 2}
+        assert {s[1] for s in one if s[3] == 1} == {1, 2, 4}
+        assert {s[1] for s in one if s[3] == 2} == {1, 2, 4, 8, 16}
+        assert {s[2] for s in shapes} == {0, 1}
         assert len(shapes) == len(set(shapes))
+        assert all(len(s) == 6 and s[4] == 0 for s in shapes)
+
+
+def test_candidates_offer_two_steps_per_launch_where_it_applies():
+    """FP32 without a mask and of even width: two-step shapes (at most four
+    wavefronts per workgroup); masked, odd-width, FP16 and FP64 lattices:
+    none."""
+    two = [s for s in autotune.candidates(4096, 4096, False, "f32") if s[5] == 2]
+    assert {s[0] for s in two} == set(autotune.TB2_ROWS)
+    assert {s[1] for s in two} == {1, 2, 4}
+    for args in ((4096, 4096, True, "f32"), (4095, 4096, False, "f32"),
+                 (4096, 4096, False, "f16"), (4096, 4096, False, "f64")):
+        assert all(s[5] == 1 for s in autotune.candidates(*args)), args
 
 
 def test_candidates_respect_width_and_storage_limits():
     single = autotune.candidates(1025, 512, False, "f32")   # last strip: one column
-    assert {c for _, _, _, c in single} == {1}
+    assert {s[3] for s in single} == {1}
     odd = autotune.candidates(1027, 512, True, "f32")
-    assert {c for _, _, _, c in odd} == {1, 2}
+    assert {s[3] for s in odd} == {1, 2}
     f64 = autotune.candidates(4096, 4096, False, "f64")
-    assert max(w for _, w, _, c in f64 if c == 2) == 8
+    assert max(s[1] for s in f64 if s[3] == 2) == 8
     short = autotune.candidates(256, 8, False, "f16")
-    assert max(r for r, _, _, _ in short) == 8
+    assert max(s[0] for s in short) == 8
+    assert max(s[0] for s in autotune.candidates(256, 8, False, "f32") if s[5] == 2) == 8
 
 
 def test_cache_key_buckets_sizes():

@@ -34,15 +34,19 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_taylor_green_64_1000_steps(L, storage):
+@pytest.mark.parametrize("storage,sps", [("f64", 1), ("f32", 1), ("f32", 2)])
+def test_taylor_green_64_1000_steps(L, storage, sps):
     """Taylor-Green 64 x 64, u0 = 0.01, tau_s = 0.6, Lambda_s = 1/4 (Sec. III.B),
-    1000 steps, against the oracle."""
+    1000 steps, against the oracle (FP32: one and two time steps per
+    launch)."""
     n, steps, tau1 = 64, 1000, 0.6
     tau2 = params.tau2_from_magic(tau1, 0.25)
     rho, ux, uy = inputs.taylor_green(n, 0.01, seed=0)
-    say("case: TG %d^2 %s %d steps" % (n, storage, steps))
-    lat = L.Lattice(n, n, tau1, tau2, storage=storage).init_equilibrium(rho, ux, uy)
+    say("case: TG %d^2 %s %d steps, %d per launch" % (n, storage, steps, sps))
+    lat = L.Lattice(n, n, tau1, tau2, storage=storage)
+    lat.set_tuning(steps_per_sweep=sps)
+    assert lat.tuning()[5] == sps
+    lat.init_equilibrium(rho, ux, uy)
     lat.step(steps)
     _, u, v = (_np(t) for t in lat.macros())
     _, ur, vr = oracle.macros(oracle.run(oracle.init_equilibrium(rho, ux, uy), steps, tau1, tau2))
@@ -231,7 +235,7 @@ def test_two_column_strips_shifted_storage(L, storage, nx):
     out = {}
     for cols in (1, 2):
         lat = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage)
-        lat.set_tuning(8, 2, 1, cols)
+        lat.set_tuning(8, 2, 1, cols, 0, 1)   # one time step per launch
         assert lat.tuning()[3] == cols
         lat.set_populations(f).step(1)
         first = [_np(t) for t in lat.macros()]
@@ -249,7 +253,8 @@ def test_two_column_strips_shifted_storage(L, storage, nx):
 
 
 def test_workgroup_size_in_effect(L):
-    """The wavefronts per workgroup reported are the ones launched: capped at
+    """The wavefronts per workgroup reported are the ones launched by the
+    one-step sweep: capped at
     4 for one-column sweeps, 8 for FP64 and 16 otherwise for two-column
     sweeps, where they also never exceed what the strips need (62 is below
     the two-column width, so it sweeps one column per lane).  The automatic
@@ -261,7 +266,7 @@ def test_workgroup_size_in_effect(L):
              (1050, "f16", 0, 2), (1050, "f64", 0, 2), (1050, "f32", 8, 8)]
     for nx, storage, asked, want in cases:
         lat = L.Lattice(nx, 4, 0.8, 1.0, storage=storage)
-        lat.set_tuning(0, asked, -1, 0)
+        lat.set_tuning(0, asked, -1, 0, 0, 1)   # one time step per launch
         got = lat.tuning()[1]
         lat.close()
         say("case: nx=%d %s asked %d -> %d" % (nx, storage, asked, got))

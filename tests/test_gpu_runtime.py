@@ -152,7 +152,9 @@ def test_batch_matches_instances_alone_bitwise(L):
     for a in alone:
         a.step(25)
     for a, m in zip(alone, members):
-        assert a.state() == m.state()
+        # same time step and bits; which of its two lattices holds the state
+        # may differ (alone, FP32 lattices take two steps per launch)
+        assert a.state()[1] == m.state()[1]
         assert np.array_equal(_np(a.get_populations()), _np(m.get_populations()))
     assert [m.tuning()[3] for m in members] == [1, 2, 1, 2, 2, 1]  # odd 131: two columns
     dg = batch.diagnostics()
@@ -195,7 +197,7 @@ def test_batch_update_changes_members_without_changing_results(L):
         a.step(n)
     batch.close()
     for a, m in zip(alone, members):
-        assert a.state() == m.state()
+        assert a.state()[1] == m.state()[1]
         assert np.array_equal(_np(a.get_populations()), _np(m.get_populations()))
     for x in alone + members:
         x.close()
@@ -312,18 +314,20 @@ def test_batch_autotune_leaves_members_untouched_and_results_unchanged(L):
         x.close()
 
 
-def test_longer_step_graphs_are_bitwise_identical(L):
+@pytest.mark.parametrize("sps", [1, 2])
+def test_longer_step_graphs_are_bitwise_identical(L, sps):
     """Every graph ladder (longest graph 2, 8, 32 sweeps or the default)
     gives the same bits for any split of the steps, including splits that
-    start on the odd lattice."""
+    start on the odd lattice, with one or two time steps per launch."""
     n = 96
     rho, ux, uy = inputs.taylor_green(n, 0.02, seed=5)
     runs = {}
     for g, splits in [(2, (37, 40)), (0, (77,)), (8, (1, 36, 17, 23)), (32, (77,)),
                       (32, (3, 33, 41))]:
         lat = L.Lattice(n, n, 0.57, 1.9, storage="f32").init_equilibrium(rho, ux, uy)
-        lat.set_tuning(graph_steps=g)
+        lat.set_tuning(graph_steps=g, steps_per_sweep=sps)
         assert g == 0 or lat.tuning()[4] == g
+        assert lat.tuning()[5] == sps
         for k in splits:
             lat.step(k)
         assert lat.state()[1] == 77

@@ -2,8 +2,10 @@
 of the one-step sweep: every node's arithmetic is the same and the first
 step's FP32 results are exactly what the one-step sweep stores and loads
 back.  Ragged and tiny heights (row blocks that wrap past the lattice), one
-and several strips, every row and workgroup shape, odd step counts; and the
-same run against the oracle within the FP32 tolerance."""
+and several strips, widths that are not multiples of the stored window
+(windows that wrap, a last window only partly inside the lattice, lattices
+narrower than one window), every row and workgroup shape, odd step counts;
+and the same run against the oracle within the FP32 tolerance."""
 import numpy as np
 import pytest
 
@@ -35,12 +37,15 @@ def _state(seed, nx, ny):
 
 
 @pytest.mark.parametrize("nx,ny", [(128, 37), (256, 9), (384, 130), (128, 3), (256, 5),
-                                   (512, 64)])
+                                   (512, 64), (200, 37), (250, 9), (130, 66), (6, 5), (2, 4),
+                                   (1000, 41), (362, 1)])
 @pytest.mark.parametrize("tiling", [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1), (64, 4, 0)])
 def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
     f, g, tau1, tau2 = _state(nx + 7 * ny, nx, ny)
     say("case: two steps per launch %dx%d tiling=%s" % (nx, ny, tiling))
     one = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    one.set_tuning(steps_per_sweep=1)
+    assert one.tuning()[5] == 1
     two = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
     two.set_tuning(*tiling, 2, 8, 2)
     assert two.tuning()[5] == 2 and two.tuning()[1] <= 4   # at most four wavefronts
@@ -72,9 +77,9 @@ def test_two_steps_per_launch_against_the_oracle(L):
 
 
 def test_two_steps_per_launch_applies_only_where_eligible(L):
-    """FP64/FP16 storage, masks and widths that are not multiples of 128 keep
-    one step per launch (and say so)."""
-    cases = [dict(nx=200, ny=8, storage="f32"), dict(nx=256, ny=8, storage="f64"),
+    """FP64/FP16 storage, masks and odd widths keep one step per launch (and
+    say so)."""
+    cases = [dict(nx=201, ny=8, storage="f32"), dict(nx=256, ny=8, storage="f64"),
              dict(nx=256, ny=8, storage="f16")]
     for c in cases:
         lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
@@ -87,3 +92,25 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
     lat.set_tuning(steps_per_sweep=2)
     assert lat.tuning()[5] == 1
     lat.close()
+
+
+def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
+    """Eligible lattices take two steps per launch unless asked for one; the
+    reported rows and wavefronts are the two-step pass's: ~2048 wavefronts
+    of 120-column windows with rows from 32 down to 8, four-wavefront
+    workgroups from 4096 wavefronts on, else one; an explicit request is
+    kept (at most four wavefronts, no more than the windows need)."""
+    cases = [((4096, 4096), (0, 0), (32, 4)), ((2048, 2048), (0, 0), (16, 1)),
+             ((1024, 1024), (0, 0), (8, 1)), ((256, 8), (0, 0), (8, 1)),
+             ((4096, 64), (5, 16), (5, 4)), ((240, 64), (16, 4), (16, 2))]
+    for (nx, ny), asked, want in cases:
+        lat = L.Lattice(nx, ny, 0.7, 1.0, storage="f32")
+        assert lat.tuning()[5] == 2
+        lat.set_tuning(*asked)
+        got = lat.tuning()
+        say("case: %dx%d asked %s -> rows %d waves %d" % (nx, ny, asked, got[0], got[1]))
+        assert (got[0], got[1], got[5]) == (*want, 2)
+        lat.set_tuning(*asked, -1, 0, 0, 1)
+        assert lat.tuning()[5] == 1
+        lat.close()
+

@@ -19,11 +19,17 @@ def _write(path, header, rows):
         w.writerows(rows)
 
 
-def _fake_run(root, sweep_ns, copy_ns, fetch_kib, write_kib, copy_fetch, copy_write):
+def _fake_run(root, sweep_ns, copy_ns, fetch_kib, write_kib, copy_fetch, copy_write,
+              sweep=SWEEP, tail=()):
+    """Profiler output of `sweep` dispatches (then `tail`: (name, ns, fetch,
+    write) dispatches of another sweep kernel) and copies."""
     t = os.path.join(root, "T", "host")
     rows, clock = [], 0
     for dt in sweep_ns:
-        rows.append((SWEEP, clock, clock + dt))
+        rows.append((sweep, clock, clock + dt))
+        clock += dt + 10
+    for name, dt, _, _ in tail:
+        rows.append((name, clock, clock + dt))
         clock += dt + 10
     for dt in copy_ns:
         rows.append((COPY, clock, clock + dt))
@@ -31,11 +37,12 @@ def _fake_run(root, sweep_ns, copy_ns, fetch_kib, write_kib, copy_fetch, copy_wr
     _write(os.path.join(t, "run_kernel_trace.csv"),
            ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
     _write(os.path.join(t, "run_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs"],
-           [(SWEEP, len(sweep_ns), sum(sweep_ns) / len(sweep_ns),
+           [(sweep, len(sweep_ns), sum(sweep_ns) / len(sweep_ns),
              min(sweep_ns), max(sweep_ns))])
-    for sub, counter, sv, cv in (("F", "FETCH_SIZE", fetch_kib, copy_fetch),
-                                 ("W", "WRITE_SIZE", write_kib, copy_write)):
-        rows = [(SWEEP, counter, v) for v in sv] + [(COPY, counter, v) for v in cv]
+    for sub, counter, sv, cv, k in (("F", "FETCH_SIZE", fetch_kib, copy_fetch, 2),
+                                    ("W", "WRITE_SIZE", write_kib, copy_write, 3)):
+        rows = ([(sweep, counter, v) for v in sv] + [(x[0], counter, x[k]) for x in tail] +
+                [(COPY, counter, v) for v in cv])
         _write(os.path.join(root, sub, "host", "run_counter_collection.csv"),
                ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
     log = os.path.join(root, "run.log")
@@ -83,3 +90,39 @@ def test_source_hash_ignores_comments_but_not_code():
     b = "int x;\n/* three\n   four */\nint y;   \n"
     assert code_of(a) == code_of(b) == "int x;\nint y;"
     assert code_of("int x;\nint z;\n") != code_of(a)
+
+
+def test_two_step_launches_count_two_updates_and_a_trailing_one_step_sweep_is_ignored(tmp_path):
+    """A run of two-step launches (sweep_tb2_kernel) that ends on a one-step
+    sweep: the summary covers the two-step kernel only, and its algorithmic
+    bytes per launch are two lattice updates' (a measured traffic of half of
+    them is then a traffic ratio of 0.5)."""
+    n = 64
+    tb2 = "void trt::(anonymous namespace)::sweep_tb2_kernel<1, 2>(trt::InstDesc, int, int)"
+    alg = 2 * 72 * n * n
+    copy_fetch, copy_write = [(1 << 30) / 1024.0] * 3, [(1 << 30) / 1024.0] * 3
+    fetch = [1.0, 1.0] + [alg / 4 / 1024.0] * 4
+    write = [1.0, 1.0] + [alg / 4 / 1024.0] * 4
+    tail = [(SWEEP, 777, 5e6, 5e6)]
+    (t, f, w), log = _fake_run(str(tmp_path), [3000, 3000] + [2000] * 4, [2000] * 3, fetch,
+                               write, copy_fetch, copy_write, sweep=tb2, tail=tail)
+    # an SQ pass over the same dispatches
+    sq = os.path.join(str(tmp_path), "S", "host")
+    vals = {"SQ_WAVES": 4480, "SQ_INSTS_VALU": 8.0e7, "SQ_ACTIVE_INST_VALU": 8.1e7,
+            "SQ_WAVE_CYCLES": 3.0e8, "SQ_WAIT_INST_ANY": 1.2e8, "GRBM_GUI_ACTIVE": 4.0e6}
+    rows = [(tb2, c, v) for _ in range(6) for c, v in vals.items()]
+    rows += [(SWEEP, "SQ_INSTS_VALU", 1.0)]
+    _write(os.path.join(sq, "run_counter_collection.csv"),
+           ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    out = os.path.join(str(tmp_path), "summary")
+    rec = profiling.summarize(t, f, w, "f32", n, 4, 2, out, run_log=log,
+                              sq_dir=os.path.join(str(tmp_path), "S"))
+    assert rec["kernel"] == "sweep_tb2_kernel<1, 2>" and rec["updates_per_launch"] == 2
+    assert rec["dispatches"] == 4 and rec["avg_duration_us"] == 2.0
+    assert rec["algorithmic_bytes_per_launch"] == alg
+    assert rec["traffic_over_algorithmic"] == 0.5
+    # 8e7 VALU instructions x 4 cycles over 1024 SIMDs x 5e5 cycles per XCD
+    assert rec["valu_busy_frac"] == round(8.0e7 * 4 / (1024 * 4.0e6 / 8), 4)
+    assert rec["wave_wait_frac"] == 0.4
+    assert "SQ_INSTS_VALU" in open(out + ".md").read()
+

@@ -572,6 +572,16 @@ def main():
                      "profiled_avg_duration_us":
                          (profile_record(n, storage) or {}).get("avg_duration_us")},
     }
+    prof = profile_record(n, storage) or {}
+    if traffic:
+        # what HBM actually carries per launch (rocprofv3 counters) over the
+        # live launch time: with two steps per launch well below the
+        # B_LU x updates figure above, which can then exceed the peak
+        tg = traffic / (launch_ms * 1e-3) / 1e9
+        rec["roofline"]["traffic_GBps"] = round(tg, 1)
+        rec["roofline"]["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+    if "valu_busy_frac" in prof:
+        rec["roofline"]["valu_busy_frac"] = prof["valu_busy_frac"]
     if probe_ms is not None:
         # the probe moves one step's bytes per launch
         probe_gbs = bytes_step / (probe_ms * 1e-3) / 1e9

@@ -253,7 +253,58 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     return rec
 
 
+def bench_trace_summary(trace_dir, bench_json, out_prefix, cmd):
+    """The rocprofv3 kernel trace of a bench.py run next to the average
+    launch duration that run measured live with HIP events (its JSON line):
+    the traced average of the roofline's kernel must agree with it."""
+    with open(bench_json) as fh:
+        rec = json.loads([l for l in fh if l.strip().startswith("{")][-1])
+    live = rec["roofline"]["avg_duration_us"]
+    want = rec["roofline"]["kernel"].split("<")[0]
+    stats = _csv(trace_dir, "kernel_stats.csv")
+    traced = [r for r in stats if want in r["Name"]]
+    if not traced:
+        raise ValueError("no %s in the trace" % want)
+    t = traced[0]
+    out = {"kernel": want, "workload": rec["config"]["workload"], "dtype": rec["dtype"],
+           "source_hash": rec["roofline"]["source_hash"], "dispatches": int(t["Calls"]),
+           "traced_avg_duration_us": round(float(t["AverageNs"]) * 1e-3, 3),
+           "live_avg_duration_us": live,
+           "traced_over_live": round(float(t["AverageNs"]) * 1e-3 / live, 4),
+           "value": rec["value"], "unit": rec["unit"], "frac": rec["roofline"]["frac"]}
+    with open(out_prefix + ".json", "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(out_prefix + ".md", "w") as fh:
+        fh.write("# Kernel trace of the benchmark command, %s\n\n" % out["workload"])
+        fh.write("Command (run from the repository root):\n\n")
+        fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
+        fh.write("    python -m paper_2312_10318_amd.profiling --bench-trace <T> <stdout of the "
+                 "run> --cmd '%s' --out %s\n\n" % (cmd, os.path.relpath(out_prefix, ROOT)))
+        fh.write("| quantity | value |\n|---|---|\n")
+        for k, v in out.items():
+            fh.write("| %s | %s |\n" % (k, v))
+        fh.write("\nlive_avg_duration_us: the run's own HIP-event time per launch on the "
+                 "sweep's stream (bench.py's roofline.avg_duration_us).\n")
+        fh.write("\n`--kernel-trace --stats` summary (durations in ns):\n\n")
+        fh.write("| kernel | calls | average | min | max |\n|---|---|---|---|---|\n")
+        for r in stats:
+            nm = r["Name"]
+            m = re.search(r"(\w+_kernel<[^>]*>|copyBuffer)", nm)
+            fh.write("| %s | %s | %.0f | %s | %s |\n" % (m.group(1) if m else nm[:40],
+                     r["Calls"], float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
+    return out
+
+
 def main():
+    if len(os.sys.argv) > 1 and os.sys.argv[1] == "--bench-trace":
+        bp = argparse.ArgumentParser()
+        bp.add_argument("--bench-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_STDOUT"))
+        bp.add_argument("--cmd", required=True, help="the traced bench.py command")
+        bp.add_argument("--out", required=True)
+        b = bp.parse_args()
+        out = os.path.join(ROOT, b.out) if not os.path.isabs(b.out) else b.out
+        print(json.dumps(bench_trace_summary(*b.bench_trace, out, b.cmd), indent=1))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("trace_dir")
     ap.add_argument("fetch_dir")

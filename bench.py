@@ -10,10 +10,10 @@ The JSON line reports MLUPS (lattice updates per second / 1e6), the roofline
 of the sweep kernel (algorithmic bytes per lattice update x updates per
 launch / average launch time, against the 8 TB/s HBM peak), and the FP64 CPU
 oracle timed on a bounded sample of the same workload on the host cores.
-FP32 lattices run two time steps per launch (the library default where it
-applies), so a launch counts two lattice updates per node; it moves each
-population through HBM once, and the measured traffic (rocprofv3 counters)
-is about half the algorithmic bytes.
+FP32 and FP16 lattices run two time steps per launch (the library default
+where it applies), so a launch counts two lattice updates per node; it moves
+each population through HBM once, and the measured traffic (rocprofv3
+counters) is about half the algorithmic bytes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
                       [--no-extra] [--no-cpu]
@@ -173,7 +173,42 @@ def cpu_baseline(n=4096, budget_s=12.0):
              "sample": "Taylor-Green %dx%d FP64, %d whole steps (%.1f s)" % (n, n, steps, total),
              "single_thread_MLUPS": round(single, 3),
              "single_thread_sample": "Taylor-Green %dx%d FP64, one step" % (m, m),
+             "configs": cpu_configs(cores),
              "cpu_model": cpu_model()}, (steps, ur, vr))
+
+
+def cpu_configs(cores):
+    """The oracle on the two small configurations, all host cores and one
+    thread: Taylor-Green 64^2 x 1000 steps (u0 = 0.01, tau_s = 0.6,
+    Lambda_s = 1/4) and the double shear layer 1024^2 (U0 = 0.04, kappa = 80,
+    delta = 0.05, Re = 1e4, 1/tau_s2 = 1.6) x 100 steps (x 5 on one
+    thread).  A few seconds on 16 cores."""
+    import oracle
+    from paper_2312_10318_amd import inputs, params
+    out = {}
+
+    def timed(label, f, steps, tau1, tau2, nodes, threads):
+        oracle.set_num_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            oracle.run(f, steps, tau1, tau2)
+            sec = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(cores)
+        out[label] = {"MLUPS": round(nodes * steps / sec / 1e6, 3), "threads": threads,
+                      "steps": steps, "seconds": round(sec, 3)}
+
+    tau1 = 0.6
+    tau2 = params.tau2_from_magic(tau1, 0.25)
+    f = oracle.init_equilibrium(*inputs.taylor_green(64, 0.01, seed=0))
+    timed("taylor_green_64x64_x1000", f, 1000, tau1, tau2, 64 * 64, cores)
+    timed("taylor_green_64x64_x1000_1thread", f, 1000, tau1, tau2, 64 * 64, 1)
+    n, u0 = 1024, 0.04
+    tau1 = 0.5 + 3.0 * u0 * n / 1e4
+    f = oracle.init_equilibrium(*inputs.double_shear_layer(n, u0))
+    timed("double_shear_layer_1024x1024_x100", f, 100, tau1, 1 / 1.6, n * n, cores)
+    timed("double_shear_layer_1024x1024_x5_1thread", f, 5, tau1, 1 / 1.6, n * n, 1)
+    return out
 
 
 def cpu_model() -> str:

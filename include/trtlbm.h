@@ -137,9 +137,9 @@ typedef struct {
                                 between the sweeps inside one graph. */
     int32_t steps_per_sweep; /* 2 (0: default) or 1: two time steps per launch (each
                                 population crosses HBM once per two steps; the bits of two
-                                one-step sweeps).  Applies to single FP32 simulations without
-                                a mask or open boundaries whose width is even; elsewhere, and
-                                in batches, sweeps take one step.  With two steps per launch,
+                                one-step sweeps).  Applies to single FP32 and FP16 simulations
+                                without a mask or open boundaries whose width is even;
+                                elsewhere, and in batches, sweeps take one step.  With two steps per launch,
                                 rows_per_wave and waves_per_block shape the two-step pass
                                 (cols_per_lane the one-step sweeps of odd step counts). */
 } trt_tuning;

@@ -115,9 +115,9 @@ hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nite
                               bool mask, bool buf, int flip, const Launch &l,
                               hipStream_t stream);
 
-// Two time steps per launch (FP32 storage, open periodic lattices, even
-// width): reads lattice src, writes the other one, two steps later.  Gives
-// the bits of two one-step sweeps.
+// Two time steps per launch (FP32 or FP16 storage, open periodic lattices,
+// even width): reads lattice src, writes the other one, two steps later.
+// Gives the bits of two one-step sweeps.
 bool tb2_eligible(const InstDesc &d, int storage);
 // The tiling of the two-step pass: windows of 120 stored columns and,
 // unless the launch shape sets them, rows per wavefront for ~2048

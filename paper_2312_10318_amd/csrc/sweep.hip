@@ -843,8 +843,8 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per pass (FP32 storage, open periodic lattices of even
-// width).
+// Two time steps per pass (FP32 or FP16 storage, open periodic lattices of
+// even width).
 //
 // One launch advances the lattice by two time steps and moves each
 // population through HBM once.  A wavefront owns a 128-column window (lane
@@ -872,8 +872,9 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
 // paid for it: 153 against 127 us per step on 4096^2).  A row block of R
 // rows runs R + 6 pipeline rows and reads R + 6 rows of each population.
 // Every node's arithmetic is the one-step sweep's, operation for operation,
-// and the first step's FP32 results are exactly what that sweep would store
-// and load back, so two steps per pass reproduce its bits.
+// and the first step's results are exactly what that sweep would store and
+// load back (FP16: rounded to the stored words in registers), so two steps
+// per pass reproduce its bits.
 
 // The first step's post-collision populations of one node between the
 // iteration that makes them and the two iterations that pull them.
@@ -1041,6 +1042,158 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     __builtin_amdgcn_s_barrier();
 }
 
+// FP16 storage: the first step's results stay in registers as the words the
+// one-step sweep would store (node A's population in the low half, node B's
+// in the high one, each rounded once from its exact value), and the second
+// step widens them exactly as that sweep widens the words it loads.  The
+// window of a lane's pair is then one word per population instead of two
+// values.
+struct Tb2CarryH {
+    Coeffs<float> kA, kB;
+    float pyA, pyB, belA, belB;
+    MidWindow<uint32_t> w;
+    Coeffs<float> qA, qB;
+    float qyA, qyB, qbelA, qbelB;
+};
+
+// The nine store words of a pair from its coefficients and Phi_y gradients,
+// as the one-step FP16 sweep forms them.
+__device__ __forceinline__ void tb2_half_words(uint32_t wd[9], const Coeffs<float> &a, float dya,
+                                               const Coeffs<float> &b, float dyb, float ph) {
+    HalfPairs pa, pb;
+    reconstruct_pairs(pa, a.base, a.bx, a.by, a.bxx, a.byy - ph * dya, a.bxy, a.bxxy, a.bxyy);
+    reconstruct_pairs(pb, b.base, b.bx, b.by, b.bxx, b.byy - ph * dyb, b.bxy, b.bxxy, b.bxyy);
+    wd[0] = half_out<0, true>(pb, half_out<0, false>(pa));
+    wd[1] = half_out<1, true>(pb, half_out<1, false>(pa));
+    wd[2] = half_out<2, true>(pb, half_out<2, false>(pa));
+    wd[3] = half_out<3, true>(pb, half_out<3, false>(pa));
+    wd[4] = half_out<4, true>(pb, half_out<4, false>(pa));
+    wd[5] = half_out<5, true>(pb, half_out<5, false>(pa));
+    wd[6] = half_out<6, true>(pb, half_out<6, false>(pa));
+    wd[7] = half_out<7, true>(pb, half_out<7, false>(pa));
+    wd[8] = half_out<8, true>(pb, half_out<8, false>(pa));
+}
+
+// One pipeline row with FP16 storage (stages as tb2_row).
+template <int STAGE>
+__device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
+                                          const PairCtx<_Float16> &cx, const Tb2Params &p,
+                                          const BufAccess<_Float16> &out, int y, bool load,
+                                          int yload, bool store, int pitch, int64_t plane,
+                                          int stage = STAGE) {
+    using C = float;
+    constexpr bool SH = true;
+    const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
+    OpenX<C> ox;
+    ox.on = false;
+    ox.nx = 0;
+    ox.u_in = ox.rho_in = ox.rho_out = ox.phi_wall = C(0);
+    // (b) row y + 3 from its stored halves, then (a) the next loads
+    C nyA, nyB;
+    Coeffs<C> nkA, nkB;
+    {
+        RowState<C, SH> nA, nB;
+        widen_pair<_Float16, C, SH, true>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) gather_pair_row<_Float16, false>(raw, cx, yload, 0u);
+        const C left = dpp_shr(C(0), nB.phix);
+        const C right = dpp_shl(C(0), nA.phix);
+        nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
+        nkB = collide_coeffs<C, SH>(nB.m, C(0.5) * (right - nA.phix), w1, w2, ph, gx, gy);
+        nyA = nA.phiy;
+        nyB = nB.phiy;
+    }
+    // (c) collide row y + 2 of the first step into store words
+    uint32_t ow[9];
+    if (stage >= 1) {
+        const C dya = C(0.5) * (nyA - k.belA);
+        const C dyb = C(0.5) * (nyB - k.belB);
+        tb2_half_words(ow, k.kA, dya, k.kB, dyb, ph);
+    }
+    // (d) row y + 1 of the second step: the words its pull reads (populations
+    // 2, 5, 6 from row y, 0, 1, 3 from row y + 1, 4, 7, 8 from row y + 2),
+    // widened as loaded words are (x neighbours by DPP word shifts)
+    C cyA = C(0), cyB = C(0);
+    Coeffs<C> ckA, ckB;
+    if (stage >= 2) {
+        PairRow<_Float16> pr;
+        pr.w[0] = k.w.mid[0];
+        pr.w[1] = k.w.mid[1];
+        pr.w[3] = k.w.mid[2];
+        pr.w[2] = k.w.lo[0];
+        pr.w[5] = k.w.lo[1];
+        pr.w[6] = k.w.lo[2];
+        pr.w[4] = ow[4];
+        pr.w[7] = ow[7];
+        pr.w[8] = ow[8];
+        pr.edge[0] = pr.edge[1] = pr.edge[2] = _Float16(0);
+        pr.lk = pr.rs = 0u;
+        RowState<C, SH> cA, cB;
+        widen_pair<_Float16, C, SH, true>(cA, cB, pr, cx, gx, gy, ox);
+        const C left = dpp_shr(C(0), cB.phix);
+        const C right = dpp_shl(C(0), cA.phix);
+        ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
+        ckB = collide_coeffs<C, SH>(cB.m, C(0.5) * (right - cA.phix), w1, w2, ph, gx, gy);
+        cyA = cA.phiy;
+        cyB = cB.phiy;
+    }
+    // (e) collide row y of the second step and store the window's middle
+    if (stage >= 3) {
+        uint32_t sw[9];
+        tb2_half_words(sw, k.qA, C(0.5) * (cyA - k.qbelA), k.qB, C(0.5) * (cyB - k.qbelB), ph);
+        if (store) {
+            const int64_t e0 = (int64_t)y * pitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(sw[i], out.r, cx.opair,
+                                                      (uint32_t)((i * plane + e0) * 2),
+                                                      TRT_STORE_CPOL);
+        }
+    }
+    // advance the pipeline by one row
+    if (stage >= 2) {
+        k.qbelA = k.qyA;
+        k.qbelB = k.qyB;
+        k.qyA = cyA;
+        k.qyB = cyB;
+        k.qA = ckA;
+        k.qB = ckB;
+    }
+    if (stage >= 1) mid_shift<uint32_t>(k.w, ow);
+    k.belA = k.pyA;
+    k.belB = k.pyB;
+    k.pyA = nyA;
+    k.pyB = nyB;
+    k.kA = nkA;
+    k.kB = nkB;
+    __builtin_amdgcn_s_barrier();
+}
+
+// The pipeline row and carried state of each storage type.
+template <int ST> struct Tb2Rows;
+template <> struct Tb2Rows<ST_F32> {
+    using Carry = Tb2Carry<float>;
+    template <int STAGE>
+    __device__ static __forceinline__ void row(Carry &k, PairRow<float> &raw,
+                                               const PairCtx<float> &cx, const Tb2Params &p,
+                                               const BufAccess<float> &out, int y, bool load,
+                                               int yload, bool store, int pitch, int64_t plane,
+                                               int stage = STAGE) {
+        tb2_row<STAGE, float, float, true>(k, raw, cx, p, out, y, load, yload, store, pitch, plane,
+                                           stage);
+    }
+};
+template <> struct Tb2Rows<ST_F16> {
+    using Carry = Tb2CarryH;
+    template <int STAGE>
+    __device__ static __forceinline__ void row(Carry &k, PairRow<_Float16> &raw,
+                                               const PairCtx<_Float16> &cx, const Tb2Params &p,
+                                               const BufAccess<_Float16> &out, int y, bool load,
+                                               int yload, bool store, int pitch, int64_t plane,
+                                               int stage = STAGE) {
+        tb2_row_h<STAGE>(k, raw, cx, p, out, y, load, yload, store, pitch, plane, stage);
+    }
+};
+
 // One wavefront's window through one row block: the six rows that fill the
 // pipeline as a short loop (run-time stage: fewer registers than peeled
 // copies), then the full pipeline.  The loads run DEPTH rows ahead of their
@@ -1048,9 +1201,8 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
 template <int ST, int DEPTH>
 __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
-    using C = typename Store<ST>::C;
-    constexpr bool SH = Store<ST>::shifted;
-    static_assert(ST == ST_F32, "two steps per pass: FP32 storage");
+    using R = Tb2Rows<ST>;
+    static_assert(ST == ST_F32 || ST == ST_F16, "two steps per pass: FP32 or FP16 storage");
     static_assert(DEPTH == 1 || DEPTH == 2, "loads one or two rows ahead");
 
     const int lane = threadIdx.x & 63;
@@ -1081,7 +1233,7 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     const auto ld = [&](int y) { return y + 3 + DEPTH <= y1 + 2; };
     const auto lrow = [&](int y) { return wrap_row(y + 3 + DEPTH); };
 
-    Tb2Carry<C> k{};
+    typename R::Carry k{};
     PairRow<T> raw[DEPTH];
     gather_pair_row<T, false>(raw[0], cx, wrap_row(y0 - 3), 0u);
     if (DEPTH == 2) gather_pair_row<T, false>(raw[DEPTH - 1], cx, wrap_row(y0 - 2), 0u);
@@ -1089,23 +1241,23 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     int y = y0 - 6;
     for (int i = 0; i < 6; ++i, ++y) {
         if (DEPTH == 2 && (i & 1))
-            tb2_row<-1, T, C, SH>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
         else
-            tb2_row<-1, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
     }
     if (DEPTH == 1) {
         for (; y < y1; ++y)
-            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
     } else {
         for (; y + 1 < y1; y += 2) {
-            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
-            tb2_row<3, T, C, SH>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
+            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
                                  pitch, plane);
         }
         if (y < y1)
-            tb2_row<3, T, C, SH>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
     }
 }
 
@@ -1142,8 +1294,8 @@ __global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(I
 // Two time steps per pass (sweep_strip_tb2): workgroup b covers row block
 // b / groups and the windows [g * wpb, g * wpb + wpb) with g = b % groups,
 // as the two-column sweep; a wavefront without a window meets the R + 6
-// barriers of its row block.  DEPTH 1 fits 166 VGPRs (three wavefronts per
-// SIMD), DEPTH 2 214 (two).
+// barriers of its row block.  FP32: DEPTH 1 fits 168 VGPRs (three
+// wavefronts per SIMD), DEPTH 2 210 (two); FP16: 133 (three) and 171 (two).
 constexpr int kTb2MaxWaves = 4;
 template <int ST, int DEPTH>
 __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d, int srcsel,
@@ -1270,8 +1422,8 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
 }
 
 bool tb2_eligible(const InstDesc &d, int storage) {
-    return storage == ST_F32 && d.links == nullptr && d.xbc == 0 && d.mask == nullptr &&
-           d.nx % 2 == 0 && buffer_addressable(d, storage);
+    return (storage == ST_F32 || storage == ST_F16) && d.links == nullptr && d.xbc == 0 &&
+           d.mask == nullptr && d.nx % 2 == 0 && buffer_addressable(d, storage);
 }
 
 // Wavefronts at which the two-step pass switches to loads two rows ahead
@@ -1320,10 +1472,17 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
     const InstDesc t = tb2_desc(d, l);
     const int wpb = tb2_waves_per_block(d, storage, l);
     const int blocks = t.rowblocks * ((t.strips + wpb - 1) / wpb);
-    if (tb2_deep(t))
+    const bool deep = tb2_deep(t);
+    if (storage == ST_F16) {
+        if (deep)
+            sweep_tb2_kernel<ST_F16, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
+        else
+            sweep_tb2_kernel<ST_F16, 1><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
+    } else if (deep) {
         sweep_tb2_kernel<ST_F32, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
-    else
+    } else {
         sweep_tb2_kernel<ST_F32, 1><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap);
+    }
     return hipGetLastError();
 }
 

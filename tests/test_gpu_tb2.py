@@ -1,7 +1,7 @@
 """Two time steps per launch (trt_tuning.steps_per_sweep = 2) give the bits
-of the one-step sweep: every node's arithmetic is the same and the first
-step's FP32 results are exactly what the one-step sweep stores and loads
-back.  Ragged and tiny heights (row blocks that wrap past the lattice), one
+of the one-step sweep, FP32 and FP16: every node's arithmetic is the same
+and the first step's results are exactly what the one-step sweep stores and
+loads back (FP16: rounded to the stored words in registers).  Ragged and tiny heights (row blocks that wrap past the lattice), one
 and several strips, widths that are not multiples of the stored window
 (windows that wrap, a last window only partly inside the lattice, lattices
 narrower than one window), every row and workgroup shape, odd step counts;
@@ -40,13 +40,14 @@ def _state(seed, nx, ny):
                                    (512, 64), (200, 37), (250, 9), (130, 66), (6, 5), (2, 4),
                                    (1000, 41), (362, 1)])
 @pytest.mark.parametrize("tiling", [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1), (64, 4, 0)])
-def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling, storage):
     f, g, tau1, tau2 = _state(nx + 7 * ny, nx, ny)
-    say("case: two steps per launch %dx%d tiling=%s" % (nx, ny, tiling))
-    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    say("case: two steps per launch %dx%d %s tiling=%s" % (nx, ny, storage, tiling))
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage).set_populations(f)
     one.set_tuning(steps_per_sweep=1)
     assert one.tuning()[5] == 1
-    two = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    two = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage).set_populations(f)
     two.set_tuning(*tiling, 2, 8, 2)
     assert two.tuning()[5] == 2 and two.tuning()[1] <= 4   # at most four wavefronts
     for k in (1, 2, 5, 4, 11, 3):   # 26 steps: singles, two-step launches, graphs
@@ -76,11 +77,30 @@ def test_two_steps_per_launch_against_the_oracle(L):
     assert emax <= TOL["f32"] and el2 <= TOL["f32"]
 
 
+def test_two_steps_per_launch_fp16_one_launch_against_the_oracle(L):
+    """FP16: one two-step launch from a state held in FP16 against two oracle
+    steps from the same state, within the FP16 tolerance (the first step's
+    results are rounded to FP16 in registers, as a store would)."""
+    nx, ny = 256, 70
+    f, g, tau1, tau2 = _state(5, nx, ny)
+    lat = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f16").set_populations(f)
+    assert lat.tuning()[5] == 2
+    lat.step(2)
+    _, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    fo = oracle.run(stored_state(f, "f16"), 2, tau1, tau2, g[0], g[1])
+    _, ur, vr = oracle.macros(fo, g[0], g[1])
+    emax, el2 = rel_errors(u, v, ur, vr)
+    say("case: FP16 two steps per launch %dx%d vs oracle: rel max %.3e L2 %.3e"
+        % (nx, ny, emax, el2))
+    assert emax <= TOL["f16"] and el2 <= TOL["f16"]
+
+
 def test_two_steps_per_launch_applies_only_where_eligible(L):
-    """FP64/FP16 storage, masks and odd widths keep one step per launch (and
-    say so)."""
+    """FP64 storage, masks and odd widths keep one step per launch (and say
+    so)."""
     cases = [dict(nx=201, ny=8, storage="f32"), dict(nx=256, ny=8, storage="f64"),
-             dict(nx=256, ny=8, storage="f16")]
+             dict(nx=201, ny=8, storage="f16")]
     for c in cases:
         lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
         lat.set_tuning(steps_per_sweep=2)
@@ -88,10 +108,11 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
         lat.close()
     mask = np.zeros((8, 256), np.uint8)
     mask[0] = 1
-    lat = L.Lattice(256, 8, 0.7, 1.0, storage="f32", mask=mask)
-    lat.set_tuning(steps_per_sweep=2)
-    assert lat.tuning()[5] == 1
-    lat.close()
+    for storage in ("f32", "f16"):
+        lat = L.Lattice(256, 8, 0.7, 1.0, storage=storage, mask=mask)
+        lat.set_tuning(steps_per_sweep=2)
+        assert lat.tuning()[5] == 1
+        lat.close()
 
 
 def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
@@ -113,4 +134,7 @@ def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
         lat.set_tuning(*asked, -1, 0, 0, 1)
         assert lat.tuning()[5] == 1
         lat.close()
+    lat = L.Lattice(4096, 64, 0.7, 1.0, storage="f16")
+    assert lat.tuning()[5] == 2
+    lat.close()
 

@@ -53,6 +53,12 @@ def test_bench_prints_one_json_line_with_roofline_and_cpu_baseline():
     cpu = rec["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
     assert cpu["unit"] == "MLUPS" and cpu["sample"]
+    # the oracle on the two small configurations too, all cores and one thread
+    assert set(cpu["configs"]) == {"taylor_green_64x64_x1000",
+                                   "taylor_green_64x64_x1000_1thread",
+                                   "double_shear_layer_1024x1024_x100",
+                                   "double_shear_layer_1024x1024_x5_1thread"}
+    assert all(c["MLUPS"] > 0 for c in cpu["configs"].values())
     # the timed configuration's accuracy against the oracle state of that sample
     acc = rec["accuracy"]
     assert acc["steps"] >= 1 and "oracle" in acc["reference"]

@@ -32,7 +32,8 @@ EXPORTED = [
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_update",
     "trt_batch_step",
-    "trt_batch_diagnostics", "trt_batch_set_tuning", "trt_batch_destroy", "trt_last_error",
+    "trt_batch_diagnostics", "trt_batch_set_tuning", "trt_batch_get_tuning", "trt_batch_destroy",
+    "trt_last_error",
     "trt_version",
 ]
 
@@ -103,6 +104,7 @@ def load():
         "trt_batch_step": (ctypes.c_int, [P, I64]),
         "trt_batch_diagnostics": (ctypes.c_int, [P, P]),
         "trt_batch_set_tuning": (ctypes.c_int, [P, tun]),
+        "trt_batch_get_tuning": (ctypes.c_int, [P, tun]),
         "trt_batch_destroy": (None, [P]),
         "trt_last_error": (ctypes.c_char_p, []),
         "trt_version": (ctypes.c_char_p, []),
@@ -254,10 +256,20 @@ def trt_batch_diagnostics(batch: int, out: int) -> None:
 
 def trt_batch_set_tuning(batch: int, rows_per_wave: int = 0, waves_per_block: int = 0,
                          xcd_remap: int = -1, cols_per_lane: int = 0, batch_items: int = 0,
-                         batch_order: int = 0, graph_steps: int = 0) -> None:
+                         batch_order: int = 0, graph_steps: int = 0,
+                         steps_per_sweep: int = 0) -> None:
     t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane, batch_items,
-                   batch_order, graph_steps, 0)
+                   batch_order, graph_steps, steps_per_sweep)
     _check(load().trt_batch_set_tuning(batch, ctypes.byref(t)), "trt_batch_set_tuning")
+
+
+def trt_batch_get_tuning(batch: int) -> tuple:
+    """(rows, waves per workgroup, XCD remap, columns per lane, batch_items,
+    batch_order, longest captured graph, time steps per launch)."""
+    t = trt_tuning()
+    _check(load().trt_batch_get_tuning(batch, ctypes.byref(t)), "trt_batch_get_tuning")
+    return (t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane, t.batch_items,
+            t.batch_order, t.graph_steps, t.steps_per_sweep)
 
 
 def trt_batch_destroy(batch: int) -> None:

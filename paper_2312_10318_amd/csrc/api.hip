@@ -77,7 +77,7 @@ constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 2};
 // member, and spreading each member's items over all XCDs (the hardware's
 // round-robin) measured 3% faster than giving XCDs contiguous ranges of the
 // list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
-constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 1};
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 2};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -215,10 +215,21 @@ struct trt_batch {
     // Outgrown tables and staging buffers, freed with the batch: freeing
     // them at once would wait for the launches queued on the stream.
     std::vector<void *> retired_dev, retired_host;
-    int nitems;
-    int parity;  // steps taken by the batch, mod 2
+    int nitems;  // one-step items: members of class 0, then of class 1
+    int parity;  // steps taken by the batch, mod 2 (with two-step launches:
+                 // the lattice parity of the class-0 members)
+    // Two time steps per launch for the members that allow it (class 1,
+    // two[k] = 1): their descriptors tiled for the two-step pass follow the
+    // n one-step ones, their two-step items follow the one-step items.
+    std::vector<char> two;
+    int nitems0;  // one-step items of class-0 members (a prefix of the list)
+    int nitems2;  // two-step items
+    int ndescs2;  // two-step descriptors (class-1 members)
+    bool deep2;   // two-step launches load two rows ahead
+    int parity2;  // two-step launches and one-step sweeps of class 1, mod 2
     hipStream_t cap_stream;
     hipGraphExec_t graphs[kMaxGraphLevels];  // level k: 2^(k+1) batched sweeps
+                                             // (two-step mode: 2^(k+1) units)
 };
 
 namespace {
@@ -780,9 +791,9 @@ static hipError_t grow_pinned(E *&p, size_t &cap, size_t need, std::vector<void 
 // trt_tuning.batch_items) and the work list in the batch's order.  The
 // tiling changes no result: every node's arithmetic is the same whatever
 // rows or order a sweep uses.
-static void batch_tile(const trt_batch *b, std::vector<InstDesc> &descs,
-                       std::vector<int4> &items) {
+static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<int4> &items) {
     const size_t n = b->sims.size();
+    descs.resize(n);
     for (size_t k = 0; k < n; ++k) {
         InstDesc &d = descs[k];
         d = b->sims[k]->desc;
@@ -793,39 +804,95 @@ static void batch_tile(const trt_batch *b, std::vector<InstDesc> &descs,
         // the longest power-of-two cap that leaves at least batch_items items
         auto count = [&](int cap) {
             size_t c = 0;
-            for (const InstDesc &d : descs) c += (size_t)d.strips * (size_t)((d.ny + cap - 1) / cap);
+            for (size_t k = 0; k < n; ++k)
+                c += (size_t)descs[k].strips * (size_t)((descs[k].ny + cap - 1) / cap);
             return c;
         };
         int cap = 256;
         while (cap > 4 && count(cap) < (size_t)b->launch.batch_items) cap /= 2;
-        for (InstDesc &d : descs) {
+        for (size_t k = 0; k < n; ++k) {
+            InstDesc &d = descs[k];
             const int blocks = (d.ny + cap - 1) / cap;
             d.rows = (d.ny + blocks - 1) / blocks;  // equal blocks of at most cap rows
             d.rowblocks = (d.ny + d.rows - 1) / d.rows;
         }
     }
-    items.clear();
-    for (size_t k = 0; k < n; ++k)
-        for (int r = 0; r < descs[k].rowblocks; ++r)
-            for (int c = 0; c < descs[k].strips; ++c) items.push_back(make_int4((int)k, c, r, 0));
-    if (b->launch.batch_order == 2) {
+    // class 1: members that take two-step launches
+    b->two.assign(n, 0);
+    if (b->launch.steps_per_sweep == 2)
+        for (size_t k = 0; k < n; ++k)
+            b->two[k] = trt::tb2_eligible(descs[k], b->sims[k]->prob.storage) ? 1 : 0;
+    const auto cost = [&](const int4 &it) {
+        // two-step items (it.w == 2) index the two-step descriptors, which
+        // follow the n one-step ones
+        const InstDesc &d = descs[it.w == 2 ? n + (size_t)it.x : (size_t)it.x];
+        const int rows = std::min(d.rows, d.ny - it.z * d.rows);
+        return (int64_t)rows * (it.w == 2 ? trt::kTb2Valid : trt::kStripWidth * d.cols);
+    };
+    const auto order = [&](size_t from) {
         // costliest first: rows in the block x columns per strip (stable, so
         // equal items keep member, row block and strip order)
-        auto cost = [&](const int4 &it) {
-            const InstDesc &d = descs[it.x];
-            const int rows = std::min(d.rows, d.ny - it.z * d.rows);
-            return (int64_t)rows * trt::kStripWidth * d.cols;
-        };
-        std::stable_sort(items.begin(), items.end(),
-                         [&](const int4 &a, const int4 &c) { return cost(a) > cost(c); });
+        if (b->launch.batch_order == 2)
+            std::stable_sort(items.begin() + (std::ptrdiff_t)from, items.end(),
+                             [&](const int4 &a, const int4 &c) { return cost(a) > cost(c); });
+    };
+    items.clear();
+    for (int cls = 0; cls < 2; ++cls) {
+        const size_t from = items.size();
+        for (size_t k = 0; k < n; ++k)
+            if (b->two[k] == cls)
+                for (int r = 0; r < descs[k].rowblocks; ++r)
+                    for (int c = 0; c < descs[k].strips; ++c)
+                        items.push_back(make_int4((int)k, c, r, cls));
+        order(from);
+        if (cls == 0) b->nitems0 = (int)items.size();
     }
+    b->nitems = (int)items.size();
+    // the two-step tables: descriptors tiled for the pass (rows shared by
+    // the batch unless set: the longest of 32, 24, 16, 12, 8 rows that gives
+    // 2048 items, else 8), then their items
+    std::vector<size_t> mem;
+    for (size_t k = 0; k < n; ++k)
+        if (b->two[k]) mem.push_back(k);
+    b->nitems2 = 0;
+    b->ndescs2 = (int)mem.size();
+    b->deep2 = false;
+    if (mem.empty()) return;
+    Launch l2 = b->launch;
+    if (l2.rows_per_wave <= 0) {
+        static const int kRows[] = {32, 24, 16, 12, 8};
+        l2.rows_per_wave = 8;
+        for (int r : kRows) {
+            long long c = 0;
+            for (size_t k : mem)
+                c += (long long)((descs[k].nx + trt::kTb2Valid - 1) / trt::kTb2Valid) *
+                     ((descs[k].ny + r - 1) / r);
+            if (c >= 2048) {
+                l2.rows_per_wave = r;
+                break;
+            }
+        }
+    }
+    const size_t from = items.size();
+    for (size_t j = 0; j < mem.size(); ++j) {
+        InstDesc d2 = trt::tb2_desc(descs[mem[j]], l2);
+        descs.push_back(d2);
+        // the two-step kernel's descriptor table starts after the n
+        // one-step ones: its items name j (entry n + j of the whole table)
+        for (int r = 0; r < d2.rowblocks; ++r)
+            for (int c = 0; c < d2.strips; ++c)
+                items.push_back(make_int4((int)j, c, r, 2));
+    }
+    order(from);
+    b->nitems2 = (int)(items.size() - from);
+    b->deep2 = b->nitems2 >= 4096;
 }
 
 static trt_status batch_build(trt_batch *b) {
-    const size_t n = b->sims.size();
-    std::vector<InstDesc> descs(n);
+    std::vector<InstDesc> descs;
     std::vector<int4> list;
     batch_tile(b, descs, list);
+    const size_t n = descs.size();
     const size_t nitems = list.size();
     if (nitems > (size_t)INT32_MAX) return fail(TRT_EINVAL, "batch work list too long");
     trt_batch::Staging &sg = b->stage[b->next_stage];
@@ -846,8 +913,8 @@ static trt_status batch_build(trt_batch *b) {
                            b->stream));
     TRT_HIP(hipEventRecord(sg.done, b->stream));
     sg.pending = true;
-    b->nitems = (int)nitems;
     b->parity = 0;
+    b->parity2 = 0;
     release_graphs(b->graphs);
     return TRT_OK;
 }
@@ -934,24 +1001,111 @@ trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t) {
     return guarded([&] { return batch_build(b); });
 }
 
-static void batch_sync_members(trt_batch *b, int64_t n) {
-    for (trt_sim *s : b->sims) {
-        s->time += n;
-        if (n & 1) s->cur ^= 1;
+// Host state of the members after `steps` time steps in which class-0
+// members' lattices flipped `flips0` times and class-1 members' `flips1`.
+trt_status trt_batch_get_tuning(const trt_batch *b, trt_tuning *t) {
+    if (!b) return fail(TRT_EINVAL, "batch handle is NULL");
+    if (!t) return fail(TRT_EINVAL, "out is NULL");
+    t->rows_per_wave = b->launch.rows_per_wave;
+    t->waves_per_block = trt::batch_waves_per_block(b->launch);
+    t->xcd_remap = b->launch.xcd_remap;
+    t->cols_per_lane = b->launch.cols_per_lane;
+    t->batch_items = b->launch.batch_items;
+    t->batch_order = b->launch.batch_order;
+    t->graph_steps = b->launch.graph_steps;
+    t->steps_per_sweep = b->nitems2 > 0 ? 2 : 1;
+    return TRT_OK;
+}
+
+static void batch_sync_members(trt_batch *b, int64_t steps, int64_t flips0, int64_t flips1) {
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        trt_sim *s = b->sims[k];
+        s->time += steps;
+        if (((b->two.empty() || !b->two[k]) ? flips0 : flips1) & 1) s->cur ^= 1;
     }
 }
 
-// Capture `sweeps` (even) batched sweeps, starting from parity 0, into `out`.
+// Launches of the two-step mode.  single: one step of every member (class 0
+// at parity f0, class 1 at f1).  unit: two steps -- one two-step launch of
+// the class-1 members (parity f1) and two one-step sweeps of the class-0
+// members (parity f0, then f0 ^ 1).
+static hipError_t batch_single(const trt_batch *b, int f0, int f1, hipStream_t s) {
+    return trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf,
+                                   f0, f1, b->launch, s);
+}
+static hipError_t batch_unit(const trt_batch *b, int f0, int f1, hipStream_t s) {
+    const size_t n = b->sims.size();
+    hipError_t e = trt::launch_sweep_tb2_batch(b->d_descs + n, b->ndescs2, b->d_items + b->nitems,
+                                               b->nitems2, b->storage, f1, b->deep2, b->launch, s);
+    for (int h = 0; h < 2 && e == hipSuccess && b->nitems0 > 0; ++h)
+        e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems0, b->storage, b->mask,
+                                    b->buf, f0 ^ h, f0 ^ h, b->launch, s);
+    return e;
+}
+
+// Capture `sweeps` (even) batched sweeps, starting from parity 0, into `out`;
+// in two-step mode `sweeps` units (four steps per pair) from parities 0, 0.
 static trt_status batch_capture(trt_batch *b, hipGraphExec_t &out, int64_t sweeps) {
     release_graph(out);
     return capture(b->cap_stream, out, [&](hipStream_t cs) {
         for (int64_t k = 0; k < sweeps; ++k) {
-            hipError_t e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage,
-                                                   b->mask, b->buf, (int)(k & 1), b->launch, cs);
+            hipError_t e = b->nitems2 > 0
+                               ? batch_unit(b, 0, (int)(k & 1), cs)
+                               : trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems,
+                                                         b->storage, b->mask, b->buf, (int)(k & 1),
+                                                         (int)(k & 1), b->launch, cs);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     });
+}
+
+// Two-step mode: class-1 members advance two steps per two-step launch,
+// class-0 members by one-step sweeps, each class with its own lattice
+// parity (parity, parity2); graphs start and end at parities 0, 0.
+static trt_status batch_step_two(trt_batch *b, int64_t n) {
+    auto single = [&]() -> trt_status {
+        TRT_HIP(batch_single(b, b->parity, b->parity2, b->stream));
+        b->parity ^= 1;
+        b->parity2 ^= 1;
+        batch_sync_members(b, 1, 1, 1);
+        return TRT_OK;
+    };
+    auto unit = [&]() -> trt_status {
+        TRT_HIP(batch_unit(b, b->parity, b->parity2, b->stream));
+        b->parity2 ^= 1;
+        batch_sync_members(b, 2, 2, 1);
+        return TRT_OK;
+    };
+    // back to parities 0, 0: a single step flips both classes, a unit only
+    // class 1 (at most two launches)
+    while (n > 0 && (b->parity || b->parity2)) {
+        const bool one = b->parity || n == 1;
+        trt_status st = one ? single() : unit();
+        if (st != TRT_OK) return st;
+        n -= one ? 1 : 2;
+    }
+    if (n >= 4) {
+        // graphs of 2, 4, ... units (4, 8, ... steps), each from and back to
+        // parities 0, 0
+        const int64_t units = n / 4 * 2;
+        trt_status rs = replay_ladder(
+            units, std::max<int64_t>(2, b->launch.graph_steps / 2), b->graphs, b->stream,
+            [&](int k) -> trt_status {
+                if (b->graphs[k]) return TRT_OK;
+                return batch_capture(b, b->graphs[k], (int64_t)2 << k);
+            });
+        if (rs != TRT_OK) return rs;
+        batch_sync_members(b, 2 * units, 2 * units, units);
+        n -= 2 * units;
+    }
+    if (n >= 2) {
+        trt_status st = unit();
+        if (st != TRT_OK) return st;
+        n -= 2;
+    }
+    if (n == 1) return single();
+    return TRT_OK;
 }
 
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
@@ -959,11 +1113,12 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
     if (nsteps < 0) return fail(TRT_EINVAL, "nsteps must be >= 0");
     int64_t n = nsteps;
     if (n == 0) return TRT_OK;
+    if (b->nitems2 > 0) return batch_step_two(b, n);
     if (b->parity == 1) {
-        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf, 1,
-                                        b->launch, b->stream));
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask,
+                                        b->buf, 1, 1, b->launch, b->stream));
         b->parity = 0;
-        batch_sync_members(b, 1);
+        batch_sync_members(b, 1, 1, 1);
         --n;
     }
     if (n >= 2) {
@@ -974,13 +1129,13 @@ trt_status trt_batch_step(trt_batch *b, int64_t nsteps) {
                                           return batch_capture(b, b->graphs[k], (int64_t)2 << k);
                                       });
         if (rs != TRT_OK) return rs;
-        batch_sync_members(b, even);
+        batch_sync_members(b, even, even, even);
     }
     if (n % 2) {
-        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf, 0,
-                                        b->launch, b->stream));
+        TRT_HIP(trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask,
+                                        b->buf, 0, 0, b->launch, b->stream));
         b->parity = 1;
-        batch_sync_members(b, 1);
+        batch_sync_members(b, 1, 1, 1);
     }
     return TRT_OK;
 }

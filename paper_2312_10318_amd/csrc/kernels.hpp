@@ -107,17 +107,27 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
 bool buffer_addressable(const InstDesc &d, int storage);
 
 // One fused sweep of every instance of a batch.  descs: device InstDesc[n];
-// items: device int4[nitems] of (instance, strip, rowblock, 0); the lattice
-// read by instance k is buf[descs[k].cur ^ flip].  `buf` may be true only if
+// items: device int4[nitems] of (instance, strip, rowblock, class); the
+// lattice read by instance k is buf[descs[k].cur ^ flip] for class 0 and
+// buf[descs[k].cur ^ flip1] for class 1.  `buf` may be true only if
 // every instance is buffer_addressable; instances with descs[k].cols == 2
 // (tiled so only where pair_eligible) are swept with two-column strips.
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
-                              bool mask, bool buf, int flip, const Launch &l,
+                              bool mask, bool buf, int flip, int flip1, const Launch &l,
                               hipStream_t stream);
+// Two time steps of the batch members named by items (device int4 of
+// (index into descs, window, row block, -); descs: device InstDesc[ndescs]
+// tiled by tb2_desc): each reads lattice cur ^ flip.  Items naming no
+// descriptor are skipped.  deep: loads two rows ahead (many items).
+hipError_t launch_sweep_tb2_batch(const InstDesc *descs, int ndescs, const int4 *items,
+                                  int nitems, int storage, int flip, bool deep, const Launch &l,
+                                  hipStream_t stream);
 
 // Two time steps per launch (FP32 or FP16 storage, open periodic lattices,
 // even width): reads lattice src, writes the other one, two steps later.
-// Gives the bits of two one-step sweeps.
+// Gives the bits of two one-step sweeps.  A wavefront computes a
+// 128-column window and stores its middle kTb2Valid columns.
+constexpr int kTb2Valid = 120;
 bool tb2_eligible(const InstDesc &d, int storage);
 // The tiling of the two-step pass: windows of 120 stored columns and,
 // unless the launch shape sets them, rows per wavefront for ~2048

@@ -923,9 +923,6 @@ __device__ __forceinline__ void node_state(RowState<C, SHIFTED> &st, const C f[9
     st.phiy = st.m.rho * st.m.uy * st.m.uy * st.m.uy;
 }
 
-// Columns of a window that the pass stores.
-constexpr int kTb2Valid = 120;
-
 template <class C> struct Tb2Carry {
     Coeffs<C> kA, kB;     // first step: coefficients of the next row to collide
     C pyA, pyB;           // ... its Phi_y
@@ -944,7 +941,7 @@ struct Tb2Params {
 // (when `load`), (c) from STAGE 1 the first-step collision of row y + 2,
 // (d) from STAGE 2 the second-step pull of row y + 1 and its coefficients,
 // (e) at STAGE 3 the second-step collision and store of row y.
-template <int STAGE, class T, class C, bool SH>
+template <int STAGE, class T, class C, bool SH, bool SYNC = true>
 __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const PairCtx<T> &cx,
                                         const Tb2Params &p, const BufAccess<T> &out, int y,
                                         bool load, int yload, bool store, int pitch,
@@ -1039,7 +1036,7 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
-    __builtin_amdgcn_s_barrier();
+    if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
 // FP16 storage: the first step's results stay in registers as the words the
@@ -1075,7 +1072,7 @@ __device__ __forceinline__ void tb2_half_words(uint32_t wd[9], const Coeffs<floa
 }
 
 // One pipeline row with FP16 storage (stages as tb2_row).
-template <int STAGE>
+template <int STAGE, bool SYNC = true>
 __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
                                           const PairCtx<_Float16> &cx, const Tb2Params &p,
                                           const BufAccess<_Float16> &out, int y, bool load,
@@ -1165,40 +1162,42 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
-    __builtin_amdgcn_s_barrier();
+    if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
 // The pipeline row and carried state of each storage type.
 template <int ST> struct Tb2Rows;
 template <> struct Tb2Rows<ST_F32> {
     using Carry = Tb2Carry<float>;
-    template <int STAGE>
+    template <int STAGE, bool SYNC>
     __device__ static __forceinline__ void row(Carry &k, PairRow<float> &raw,
                                                const PairCtx<float> &cx, const Tb2Params &p,
                                                const BufAccess<float> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
                                                int stage = STAGE) {
-        tb2_row<STAGE, float, float, true>(k, raw, cx, p, out, y, load, yload, store, pitch, plane,
-                                           stage);
+        tb2_row<STAGE, float, float, true, SYNC>(k, raw, cx, p, out, y, load, yload, store, pitch,
+                                                 plane, stage);
     }
 };
 template <> struct Tb2Rows<ST_F16> {
     using Carry = Tb2CarryH;
-    template <int STAGE>
+    template <int STAGE, bool SYNC>
     __device__ static __forceinline__ void row(Carry &k, PairRow<_Float16> &raw,
                                                const PairCtx<_Float16> &cx, const Tb2Params &p,
                                                const BufAccess<_Float16> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
                                                int stage = STAGE) {
-        tb2_row_h<STAGE>(k, raw, cx, p, out, y, load, yload, store, pitch, plane, stage);
+        tb2_row_h<STAGE, SYNC>(k, raw, cx, p, out, y, load, yload, store, pitch, plane, stage);
     }
 };
 
 // One wavefront's window through one row block: the six rows that fill the
 // pipeline as a short loop (run-time stage: fewer registers than peeled
 // copies), then the full pipeline.  The loads run DEPTH rows ahead of their
-// use (DEPTH 2: two row buffers, alternating).
-template <int ST, int DEPTH>
+// use (DEPTH 2: two row buffers, alternating).  SYNC: one workgroup barrier
+// per pipeline row (adjacent windows in step); batch work items run
+// without.
+template <int ST, int DEPTH, bool SYNC = true>
 __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
     using R = Tb2Rows<ST>;
@@ -1241,23 +1240,23 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     int y = y0 - 6;
     for (int i = 0; i < 6; ++i, ++y) {
         if (DEPTH == 2 && (i & 1))
-            R::template row<-1>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1, SYNC>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
         else
-            R::template row<-1>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
     }
     if (DEPTH == 1) {
         for (; y < y1; ++y)
-            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
     } else {
         for (; y + 1 < y1; y += 2) {
-            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
-            R::template row<3>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
+            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
                                  pitch, plane);
         }
         if (y < y1)
-            R::template row<3>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
     }
 }
 
@@ -1328,10 +1327,15 @@ __global__ __launch_bounds__(256) void sweep_single_kernel(InstDesc d, int srcse
     sweep_strip<ST, MASK, BUF>(d, strip, rb, srcsel);
 }
 
+// Batched one-step sweep: wavefront w takes work item w = (member, strip,
+// row block, class); members of class 1 (it.w) read lattice cur ^ flip1,
+// the others cur ^ flip0 (members that also take two-step launches advance
+// their lattice parity at another rate).
 template <int ST, bool MASK, bool BUF>
 __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__restrict__ descs,
                                                            const int4 *__restrict__ items,
-                                                           int nitems, int flip, int remap) {
+                                                           int nitems, int flip0, int flip1,
+                                                           int remap) {
     int b = blockIdx.x;
     if (remap) b = xcd_remap(b, gridDim.x);
     const int wpb = blockDim.x >> 6;
@@ -1339,10 +1343,29 @@ __global__ __launch_bounds__(256) void sweep_batch_kernel(const InstDesc *__rest
     if (wave >= nitems) return;
     const int4 it = items[wave];
     const InstDesc d = descs[it.x];
+    const int flip = it.w ? flip1 : flip0;
     if (d.cols == 2)
         sweep_strip2<ST, false, MASK>(d, it.y, it.z, d.cur ^ flip);
     else
         sweep_strip<ST, MASK, BUF>(d, it.y, it.z, d.cur ^ flip);
+}
+
+// Batched two-step pass: wavefront w takes item w = (member, window, row
+// block, -) of the two-step tables (each member's descriptor tiled for the
+// pass); items are independent, so no barriers.
+template <int ST, int DEPTH>
+__global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_batch_kernel(
+    const InstDesc *__restrict__ descs, int ndescs, const int4 *__restrict__ items, int nitems,
+    int flip, int remap) {
+    int b = blockIdx.x;
+    if (remap) b = xcd_remap(b, gridDim.x);
+    const int wpb = blockDim.x >> 6;
+    const int wave = b * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nitems) return;
+    const int4 it = items[wave];
+    if ((unsigned)it.x >= (unsigned)ndescs) return;
+    const InstDesc d = descs[it.x];
+    sweep_strip_tb2<ST, DEPTH, false>(d, it.y, it.z, d.cur ^ flip);
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -1356,11 +1379,11 @@ hipError_t launch_single_t(const InstDesc &d, int src, const Launch &l, hipStrea
 
 template <int ST, bool MASK, bool BUF>
 hipError_t launch_batch_t(const InstDesc *descs, const int4 *items, int nitems, int flip,
-                          const Launch &l, hipStream_t s) {
+                          int flip1, const Launch &l, hipStream_t s) {
     const int wpb = batch_waves_per_block(l);
     const int blocks = (nitems + wpb - 1) / wpb;
     sweep_batch_kernel<ST, MASK, BUF><<<blocks, 64 * wpb, 0, s>>>(descs, items, nitems, flip,
-                                                                 l.xcd_remap);
+                                                                 flip1, l.xcd_remap);
     return hipGetLastError();
 }
 
@@ -1384,9 +1407,9 @@ hipError_t launch_single_b(const InstDesc &d, int src, const Launch &l, bool buf
 
 template <int ST, bool MASK>
 hipError_t launch_batch_b(const InstDesc *descs, const int4 *items, int nitems, int flip,
-                          const Launch &l, bool buf, hipStream_t s) {
-    return buf ? launch_batch_t<ST, MASK, true>(descs, items, nitems, flip, l, s)
-               : launch_batch_t<ST, MASK, false>(descs, items, nitems, flip, l, s);
+                          int flip1, const Launch &l, bool buf, hipStream_t s) {
+    return buf ? launch_batch_t<ST, MASK, true>(descs, items, nitems, flip, flip1, l, s)
+               : launch_batch_t<ST, MASK, false>(descs, items, nitems, flip, flip1, l, s);
 }
 
 }  // namespace
@@ -1487,17 +1510,41 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
 }
 
 hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nitems, int storage,
-                              bool mask, bool buf, int flip, const Launch &l,
+                              bool mask, bool buf, int flip, int flip1, const Launch &l,
                               hipStream_t stream) {
     switch (storage * 2 + (mask ? 1 : 0)) {
-        case 0: return launch_batch_b<ST_F64, false>(descs, items, nitems, flip, l, buf, stream);
-        case 1: return launch_batch_b<ST_F64, true>(descs, items, nitems, flip, l, buf, stream);
-        case 2: return launch_batch_b<ST_F32, false>(descs, items, nitems, flip, l, buf, stream);
-        case 3: return launch_batch_b<ST_F32, true>(descs, items, nitems, flip, l, buf, stream);
-        case 4: return launch_batch_b<ST_F16, false>(descs, items, nitems, flip, l, buf, stream);
-        case 5: return launch_batch_b<ST_F16, true>(descs, items, nitems, flip, l, buf, stream);
+        case 0: return launch_batch_b<ST_F64, false>(descs, items, nitems, flip, flip1, l, buf, stream);
+        case 1: return launch_batch_b<ST_F64, true>(descs, items, nitems, flip, flip1, l, buf, stream);
+        case 2: return launch_batch_b<ST_F32, false>(descs, items, nitems, flip, flip1, l, buf, stream);
+        case 3: return launch_batch_b<ST_F32, true>(descs, items, nitems, flip, flip1, l, buf, stream);
+        case 4: return launch_batch_b<ST_F16, false>(descs, items, nitems, flip, flip1, l, buf, stream);
+        case 5: return launch_batch_b<ST_F16, true>(descs, items, nitems, flip, flip1, l, buf, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sweep_tb2_batch(const InstDesc *descs, int ndescs, const int4 *items,
+                                  int nitems, int storage, int flip, bool deep, const Launch &l,
+                                  hipStream_t stream) {
+    if (nitems <= 0) return hipSuccess;
+    const int wpb = batch_waves_per_block(l);
+    const int blocks = (nitems + wpb - 1) / wpb;
+    const int r = l.xcd_remap;
+    const dim3 g(blocks), t(64 * wpb);
+    if (storage == ST_F32) {
+        if (deep)
+            sweep_tb2_batch_kernel<ST_F32, 2><<<g, t, 0, stream>>>(descs, ndescs, items, nitems, flip, r);
+        else
+            sweep_tb2_batch_kernel<ST_F32, 1><<<g, t, 0, stream>>>(descs, ndescs, items, nitems, flip, r);
+    } else if (storage == ST_F16) {
+        if (deep)
+            sweep_tb2_batch_kernel<ST_F16, 2><<<g, t, 0, stream>>>(descs, ndescs, items, nitems, flip, r);
+        else
+            sweep_tb2_batch_kernel<ST_F16, 1><<<g, t, 0, stream>>>(descs, ndescs, items, nitems, flip, r);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace trt

@@ -254,9 +254,16 @@ class Batch:
                                  device=self.lattices[0].device)
 
     def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
-                   batch_items=0, batch_order=0, graph_steps=0):
+                   batch_items=0, batch_order=0, graph_steps=0, steps_per_sweep=0):
         capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap,
-                                  cols_per_lane, batch_items, batch_order, graph_steps)
+                                  cols_per_lane, batch_items, batch_order, graph_steps,
+                                  steps_per_sweep)
+
+    def tuning(self):
+        """(rows, wavefronts per workgroup, XCD remap, columns per lane,
+        batch_items, batch_order, longest captured graph, time steps per
+        launch: 2 if some member takes two-step launches)."""
+        return capi.trt_batch_get_tuning(self.handle)
 
     def update(self, lattices):
         """Replace the members (no device-wide wait)."""

@@ -138,3 +138,53 @@ def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
     assert lat.tuning()[5] == 2
     lat.close()
 
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_two_step_members_equal_one_step_batches(L, storage):
+    """A batch whose members mix two-step members (even widths) with
+    one-step ones (odd widths, a mask) advances every member to the bits a
+    one-step batch gives, over odd and even splits, graph ladders and a
+    membership change; the batch reports two steps per launch only while a
+    member takes them."""
+    specs = [(64, 64), (200, 37), (97, 33), (128, 130), (131, 40), (250, 9), (66, 3)]
+    mask = np.zeros((37, 200), np.uint8)
+    mask[0] = 1
+    runs = {}
+    for sps in (1, 2):
+        lats = []
+        for k, (nx, ny) in enumerate(specs):
+            f, g, tau1, tau2 = _state(100 + k, nx, ny)
+            mk = mask if k == 1 else None
+            if mk is not None:
+                f = f.copy()
+                f[:, mk.astype(bool)] = 0.0
+            lats.append(L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage,
+                                  mask=mk).set_populations(f))
+        b = L.Batch(lats)
+        b.set_tuning(steps_per_sweep=sps, graph_steps=8)
+        assert b.tuning()[7] == sps
+        for k in (1, 2, 5, 4, 11, 3, 8):
+            b.step(k)
+        b.update(lats[2:])
+        b.step(7)
+        b.update(lats)
+        b.step(6)
+        runs[sps] = [(_np(m.get_populations()), m.state()[1]) for m in lats]
+        b.close()
+        for m in lats:
+            m.close()
+    for k, ((a, ta), (c, tc)) in enumerate(zip(runs[1], runs[2])):
+        say("case: batch member %d %s: time %d/%d, differs at %d entries"
+            % (k, storage, ta, tc, int(np.sum(a != c))))
+        assert ta == tc and np.array_equal(a, c), k
+    # only one-step members: the batch takes one step per launch
+    wall = np.zeros((8, 64), np.uint8)
+    wall[0] = 1
+    lats = [L.Lattice(97, 33, 0.7, 1.0, storage=storage),
+            L.Lattice(64, 8, 0.7, 1.0, storage=storage, mask=wall)]
+    b = L.Batch(lats)
+    assert b.tuning()[7] == 1
+    b.close()
+    for m in lats:
+        m.close()

@@ -138,8 +138,8 @@ typedef struct {
     int32_t steps_per_sweep; /* 2 (0: default) or 1: two time steps per launch (each
                                 population crosses HBM once per two steps; the bits of two
                                 one-step sweeps).  Applies to FP32 and FP16 simulations, alone
-                                or in a batch, without a mask or open boundaries whose width
-                                is even; elsewhere sweeps take one step.  With two steps per launch,
+                                or in a batch, without a mask or open boundaries; elsewhere
+                                sweeps take one step.  With two steps per launch,
                                 rows_per_wave and waves_per_block shape the two-step pass
                                 (cols_per_lane the one-step sweeps of odd step counts). */
 } trt_tuning;
@@ -318,9 +318,9 @@ trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
 /* Advance every member nsteps steps (replays of captured graphs of batched
  * launches as for trt_step, plus at most a few plain launches).  With
  * trt_tuning.steps_per_sweep = 2 (the default), members that allow it (FP32
- * or FP16, no mask or open boundaries, even width) advance two steps per
- * launch and the others by one-step sweeps in the same graphs; every member
- * gets the bits it gets alone. */
+ * or FP16, no mask or open boundaries) advance two steps per launch and the
+ * others by one-step sweeps in the same graphs; every member gets the bits
+ * it gets alone. */
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps);
 
 /* Diagnostics of every member into device out[n][TRT_NDIAG]. */

@@ -63,7 +63,7 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
     lane, graph sweeps (0: default), time steps per launch) worth timing.
     Two columns per lane apply to every width that is not 1 mod 128 (with
     or without a mask: masked lattices use the link map); two time steps
-    per launch to FP32 lattices without a mask whose width is even."""
+    per launch to FP32 and FP16 lattices without a mask."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -75,7 +75,7 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
             for w in waves:
                 for x in REMAP:
                     out.append((r, w, x, c, 0, 1))
-    if storage == "f32" and not has_mask and nx % 2 == 0:
+    if storage in ("f32", "f16") and not has_mask:
         for r in TB2_ROWS:
             if r > max(8, ny):
                 continue

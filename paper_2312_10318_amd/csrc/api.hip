@@ -67,7 +67,7 @@ trt_status guarded(F &&body) noexcept {
 // 128^2, FP64, 62 us per batched sweep: 4.1 us per step with two-sweep graphs,
 // 0.25 with 128); 4096^2 FP32 214.0 -> 210.9 us per step.
 // Two time steps per launch wherever the lattice allows it (FP32 or FP16
-// storage, open periodic, even width): FP32 4096^2 127 against 210 us per
+// storage, open periodic): FP32 4096^2 127 against 210 us per
 // step, 2048^2 35.7 against 59.6, 1024^2 12.6 against 19.6; FP16 4096^2 85
 // against 118, 2048^2 26.4 against 36.0; bit for bit the same results.
 constexpr int kMaxGraphLevels = 10;  // up to 1024 sweeps per graph
@@ -850,7 +850,10 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     b->nitems = (int)items.size();
     // the two-step tables: descriptors tiled for the pass (rows shared by
     // the batch unless set: the longest of 32, 24, 16, 12, 8 rows that gives
-    // 2048 items, else 8), then their items
+    // 24576 items, else 8 -- a batch of small members needs many short items
+    // to balance: 256 members of 64^2 ... 1024^2, 4-wavefront workgroups,
+    // FP32 108.7 / 112.3 / 116.3 / 117.9 GLUPS at 32 / 24 / 16 / 12 rows,
+    // FP16 162.5 / 166.4 / 165.7 / 160.3), then their items
     std::vector<size_t> mem;
     for (size_t k = 0; k < n; ++k)
         if (b->two[k]) mem.push_back(k);
@@ -867,7 +870,7 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
             for (size_t k : mem)
                 c += (long long)((descs[k].nx + trt::kTb2Valid - 1) / trt::kTb2Valid) *
                      ((descs[k].ny + r - 1) / r);
-            if (c >= 2048) {
+            if (c >= 24576) {
                 l2.rows_per_wave = r;
                 break;
             }

@@ -123,8 +123,8 @@ hipError_t launch_sweep_tb2_batch(const InstDesc *descs, int ndescs, const int4 
                                   int nitems, int storage, int flip, bool deep, const Launch &l,
                                   hipStream_t stream);
 
-// Two time steps per launch (FP32 or FP16 storage, open periodic lattices,
-// even width): reads lattice src, writes the other one, two steps later.
+// Two time steps per launch (FP32 or FP16 storage, open periodic lattices):
+// reads lattice src, writes the other one, two steps later.
 // Gives the bits of two one-step sweeps.  A wavefront computes a
 // 128-column window and stores its middle kTb2Valid columns.
 constexpr int kTb2Valid = 120;

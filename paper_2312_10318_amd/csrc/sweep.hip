@@ -843,8 +843,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per pass (FP32 or FP16 storage, open periodic lattices of
-// even width).
+// Two time steps per pass (FP32 or FP16 storage, open periodic lattices).
 //
 // One launch advances the lattice by two time steps and moves each
 // population through HBM once.  A wavefront owns a 128-column window (lane
@@ -867,7 +866,7 @@ __device__ __forceinline__ void sweep_strip2(const InstDesc &d, int strip, int r
 // so a window edge spoils one column per stage; the wavefront stores only
 // the window's middle 120 columns [s + 4, s + 124), and windows overlap by
 // eight columns.  Every lane runs the same code: no halo loads and no edge
-// lane work (a first design ran the first step on the two columns beyond a
+// lane work (odd widths: see Tb2Lane) (a first design ran the first step on the two columns beyond a
 // 128-column strip in its edge lanes, and the other 62 lanes' issue slots
 // paid for it: 153 against 127 us per step on 4096^2).  A row block of R
 // rows runs R + 6 pipeline rows and reads R + 6 rows of each population.
@@ -923,6 +922,63 @@ __device__ __forceinline__ void node_state(RowState<C, SHIFTED> &st, const C f[9
     st.phiy = st.m.rho * st.m.uy * st.m.uy * st.m.uy;
 }
 
+// A lane's pair in a window: the columns ca (node A) and cb (node B, the
+// next column, wrapped).  With an odd width a pair can start on an odd
+// column or straddle the wrap (nx - 1, 0); such a lane ("split") loads its
+// two elements one by one into the word a paired load would give.  Its
+// paired load, issued by every lane, goes to the aligned pair below ca (or
+// to (nx - 1, padding): an odd width always leaves row padding, which
+// nothing reads as data), and its store too, which only a stored lane
+// issues (a stored pair starts on an even column inside the lattice, so it
+// is split only at (nx - 1, padding)).
+struct Tb2Lane {
+    bool split;
+    uint32_t oa, ob;  // byte offsets of columns ca and cb within a row
+};
+
+template <class T> struct Tb2Word;
+template <> struct Tb2Word<float> {
+    __device__ static __forceinline__ u32x2 get(const BufAccess<float> &in, int64_t e,
+                                                const Tb2Lane &ln) {
+        u32x2 w;
+        w.x = __builtin_bit_cast(uint32_t, in.ld(e, ln.oa));
+        w.y = __builtin_bit_cast(uint32_t, in.ld(e, ln.ob));
+        return w;
+    }
+};
+template <> struct Tb2Word<_Float16> {
+    __device__ static __forceinline__ uint32_t get(const BufAccess<_Float16> &in, int64_t e,
+                                                   const Tb2Lane &ln) {
+        const uint32_t lo = __builtin_bit_cast(unsigned short, in.ld(e, ln.oa));
+        const uint32_t hi = __builtin_bit_cast(unsigned short, in.ld(e, ln.ob));
+        return lo | (hi << 16);
+    }
+};
+
+// One row of a lane's pair for the pull (as gather_pair_row), split lanes
+// element by element.
+template <class T>
+__device__ __forceinline__ void tb2_gather(PairRow<T> &r, const PairCtx<T> &c, const Tb2Lane &ln,
+                                           bool odd, int y) {
+    gather_pair_row<T, false>(r, c, y, 0u);
+    if (odd && ln.split) {
+        const int ym = (y == 0) ? c.ny - 1 : y - 1;
+        const int yp = (y == c.ny - 1) ? 0 : y + 1;
+        const int64_t e0 = (int64_t)y * c.pitch, em = (int64_t)ym * c.pitch,
+                      ep = (int64_t)yp * c.pitch;
+        const int64_t pl = c.plane;
+        r.w[0] = Tb2Word<T>::get(c.in, e0, ln);
+        r.w[1] = Tb2Word<T>::get(c.in, pl + e0, ln);
+        r.w[2] = Tb2Word<T>::get(c.in, 2 * pl + em, ln);
+        r.w[3] = Tb2Word<T>::get(c.in, 3 * pl + e0, ln);
+        r.w[4] = Tb2Word<T>::get(c.in, 4 * pl + ep, ln);
+        r.w[5] = Tb2Word<T>::get(c.in, 5 * pl + em, ln);
+        r.w[6] = Tb2Word<T>::get(c.in, 6 * pl + em, ln);
+        r.w[7] = Tb2Word<T>::get(c.in, 7 * pl + ep, ln);
+        r.w[8] = Tb2Word<T>::get(c.in, 8 * pl + ep, ln);
+    }
+}
+
 template <class C> struct Tb2Carry {
     Coeffs<C> kA, kB;     // first step: coefficients of the next row to collide
     C pyA, pyB;           // ... its Phi_y
@@ -943,9 +999,9 @@ struct Tb2Params {
 // (e) at STAGE 3 the second-step collision and store of row y.
 template <int STAGE, class T, class C, bool SH, bool SYNC = true>
 __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const PairCtx<T> &cx,
-                                        const Tb2Params &p, const BufAccess<T> &out, int y,
-                                        bool load, int yload, bool store, int pitch,
-                                        int64_t plane, int stage = STAGE) {
+                                        const Tb2Lane &ln, bool odd, const Tb2Params &p,
+                                        const BufAccess<T> &out, int y, bool load, int yload,
+                                        bool store, int pitch, int64_t plane, int stage = STAGE) {
     const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
     OpenX<C> ox;
     ox.on = false;
@@ -957,7 +1013,7 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     {
         RowState<C, SH> nA, nB;
         widen_pair<T, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
-        if (load) gather_pair_row<T, false>(raw, cx, yload, 0u);
+        if (load) tb2_gather<T>(raw, cx, ln, odd, yload);
         const C left = dpp_shr(C(0), nB.phix);
         const C right = dpp_shl(C(0), nA.phix);
         nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
@@ -1074,7 +1130,8 @@ __device__ __forceinline__ void tb2_half_words(uint32_t wd[9], const Coeffs<floa
 // One pipeline row with FP16 storage (stages as tb2_row).
 template <int STAGE, bool SYNC = true>
 __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
-                                          const PairCtx<_Float16> &cx, const Tb2Params &p,
+                                          const PairCtx<_Float16> &cx, const Tb2Lane &ln,
+                                          bool odd, const Tb2Params &p,
                                           const BufAccess<_Float16> &out, int y, bool load,
                                           int yload, bool store, int pitch, int64_t plane,
                                           int stage = STAGE) {
@@ -1091,7 +1148,7 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
     {
         RowState<C, SH> nA, nB;
         widen_pair<_Float16, C, SH, true>(nA, nB, raw, cx, gx, gy, ox);
-        if (load) gather_pair_row<_Float16, false>(raw, cx, yload, 0u);
+        if (load) tb2_gather<_Float16>(raw, cx, ln, odd, yload);
         const C left = dpp_shr(C(0), nB.phix);
         const C right = dpp_shl(C(0), nA.phix);
         nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
@@ -1171,23 +1228,26 @@ template <> struct Tb2Rows<ST_F32> {
     using Carry = Tb2Carry<float>;
     template <int STAGE, bool SYNC>
     __device__ static __forceinline__ void row(Carry &k, PairRow<float> &raw,
-                                               const PairCtx<float> &cx, const Tb2Params &p,
+                                               const PairCtx<float> &cx, const Tb2Lane &ln,
+                                               bool odd, const Tb2Params &p,
                                                const BufAccess<float> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
                                                int stage = STAGE) {
-        tb2_row<STAGE, float, float, true, SYNC>(k, raw, cx, p, out, y, load, yload, store, pitch,
-                                                 plane, stage);
+        tb2_row<STAGE, float, float, true, SYNC>(k, raw, cx, ln, odd, p, out, y, load, yload,
+                                                 store, pitch, plane, stage);
     }
 };
 template <> struct Tb2Rows<ST_F16> {
     using Carry = Tb2CarryH;
     template <int STAGE, bool SYNC>
     __device__ static __forceinline__ void row(Carry &k, PairRow<_Float16> &raw,
-                                               const PairCtx<_Float16> &cx, const Tb2Params &p,
+                                               const PairCtx<_Float16> &cx, const Tb2Lane &ln,
+                                               bool odd, const Tb2Params &p,
                                                const BufAccess<_Float16> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
                                                int stage = STAGE) {
-        tb2_row_h<STAGE, SYNC>(k, raw, cx, p, out, y, load, yload, store, pitch, plane, stage);
+        tb2_row_h<STAGE, SYNC>(k, raw, cx, ln, odd, p, out, y, load, yload, store, pitch, plane,
+                               stage);
     }
 };
 
@@ -1212,16 +1272,20 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     const uint64_t bytes = (uint64_t)ny * (uint64_t)pitch * sizeof(T);
     const BufAccess<T> in(src, bytes), out(dst, bytes);
     const LinkAccess lacc(d.links, 0);
-    // the lane's pair (an even column: the width is even, so the pair lies
-    // inside the row) and whether it is in the stored middle of the window
-    // and inside the lattice
+    // the lane's pair (Tb2Lane) and whether it is in the stored middle of
+    // the window and inside the lattice
     const int xs = strip * kTb2Valid - 4 + 2 * lane;
     int ca = xs % nx;
     if (ca < 0) ca += nx;
+    const int cb = ca + 1 == nx ? 0 : ca + 1;
+    const bool odd = (nx & 1) != 0;
+    const Tb2Lane ln{(ca & 1) != 0 || cb != ca + 1, (uint32_t)ca * (uint32_t)sizeof(T),
+                     (uint32_t)cb * (uint32_t)sizeof(T)};
+    const int cp = ln.split ? (ca & ~1) : ca;  // the aligned pair loaded (and stored)
     const bool store = lane >= 2 && lane < 62 && xs < nx;
-    const Column hcol = column_of(ca, nx, sizeof(T));  // no halo node: unused
+    const Column hcol = column_of(cp, nx, sizeof(T));  // no halo node: unused
     const uint32_t ve[3] = {0u, 0u, 0u};
-    const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)ca * (uint32_t)sizeof(T), (uint32_t)ca,
+    const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)cp * (uint32_t)sizeof(T), (uint32_t)cp,
                         false, ve, hcol, lacc, false, d.lpitch, 0u, false};
     const Tb2Params p{(float)d.gx, (float)d.gy, (float)d.omega1, (float)d.omega2, (float)d.phi};
     const int y0 = rb * d.rows;
@@ -1234,29 +1298,29 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
 
     typename R::Carry k{};
     PairRow<T> raw[DEPTH];
-    gather_pair_row<T, false>(raw[0], cx, wrap_row(y0 - 3), 0u);
-    if (DEPTH == 2) gather_pair_row<T, false>(raw[DEPTH - 1], cx, wrap_row(y0 - 2), 0u);
+    tb2_gather<T>(raw[0], cx, ln, odd, wrap_row(y0 - 3));
+    if (DEPTH == 2) tb2_gather<T>(raw[DEPTH - 1], cx, ln, odd, wrap_row(y0 - 2));
     constexpr int R1 = DEPTH - 1;
     int y = y0 - 6;
     for (int i = 0; i < 6; ++i, ++y) {
         if (DEPTH == 2 && (i & 1))
-            R::template row<-1, SYNC>(k, raw[R1], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1, SYNC>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
         else
-            R::template row<-1, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane,
+            R::template row<-1, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane,
                                   i >> 1);
     }
     if (DEPTH == 1) {
         for (; y < y1; ++y)
-            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
     } else {
         for (; y + 1 < y1; y += 2) {
-            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
-            R::template row<3, SYNC>(k, raw[R1], cx, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
+            R::template row<3, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[R1], cx, ln, odd, p, out, y + 1, ld(y + 1), lrow(y + 1), store,
                                  pitch, plane);
         }
         if (y < y1)
-            R::template row<3, SYNC>(k, raw[0], cx, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            R::template row<3, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
     }
 }
 
@@ -1446,7 +1510,7 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
 
 bool tb2_eligible(const InstDesc &d, int storage) {
     return (storage == ST_F32 || storage == ST_F16) && d.links == nullptr && d.xbc == 0 &&
-           d.mask == nullptr && d.nx % 2 == 0 && buffer_addressable(d, storage);
+           d.mask == nullptr && buffer_addressable(d, storage);
 }
 
 // Wavefronts at which the two-step pass switches to loads two rows ahead

@@ -15,20 +15,21 @@ def test_candidates_cover_both_column_modes_on_even_widths():
 
 
 def test_candidates_offer_two_steps_per_launch_where_it_applies():
-    """FP32 without a mask and of even width: two-step shapes (at most four
-    wavefronts per workgroup); masked, odd-width, FP16 and FP64 lattices:
-    none."""
-    two = [s for s in autotune.candidates(4096, 4096, False, "f32") if s[5] == 2]
-    assert {s[0] for s in two} == set(autotune.TB2_ROWS)
-    assert {s[1] for s in two} == {1, 2, 4}
-    for args in ((4096, 4096, True, "f32"), (4095, 4096, False, "f32"),
-                 (4096, 4096, False, "f16"), (4096, 4096, False, "f64")):
+    """FP32 and FP16 without a mask, any width: two-step shapes (at most four
+    wavefronts per workgroup); masked and FP64 lattices: none."""
+    for args in ((4096, 4096, False, "f32"), (4095, 4096, False, "f32"),
+                 (4096, 4096, False, "f16")):
+        two = [s for s in autotune.candidates(*args) if s[5] == 2]
+        assert {s[0] for s in two} == set(autotune.TB2_ROWS), args
+        assert {s[1] for s in two} == {1, 2, 4}
+    for args in ((4096, 4096, True, "f32"), (4096, 4096, True, "f16"),
+                 (4096, 4096, False, "f64")):
         assert all(s[5] == 1 for s in autotune.candidates(*args)), args
 
 
 def test_candidates_respect_width_and_storage_limits():
     single = autotune.candidates(1025, 512, False, "f32")   # last strip: one column
-    assert {s[3] for s in single} == {1}
+    assert {s[3] for s in single if s[5] == 1} == {1}
     odd = autotune.candidates(1027, 512, True, "f32")
     assert {s[3] for s in odd} == {1, 2}
     f64 = autotune.candidates(4096, 4096, False, "f64")

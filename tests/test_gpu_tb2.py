@@ -4,7 +4,8 @@ and the first step's results are exactly what the one-step sweep stores and
 loads back (FP16: rounded to the stored words in registers).  Ragged and tiny heights (row blocks that wrap past the lattice), one
 and several strips, widths that are not multiples of the stored window
 (windows that wrap, a last window only partly inside the lattice, lattices
-narrower than one window), every row and workgroup shape, odd step counts;
+narrower than one window), odd widths (pairs across the wrap and on odd
+columns), every row and workgroup shape, odd step counts;
 and the same run against the oracle within the FP32 tolerance."""
 import numpy as np
 import pytest
@@ -38,7 +39,9 @@ def _state(seed, nx, ny):
 
 @pytest.mark.parametrize("nx,ny", [(128, 37), (256, 9), (384, 130), (128, 3), (256, 5),
                                    (512, 64), (200, 37), (250, 9), (130, 66), (6, 5), (2, 4),
-                                   (1000, 41), (362, 1)])
+                                   (1000, 41), (362, 1), (201, 37), (97, 33), (241, 20),
+                                   (121, 7), (127, 9), (129, 4), (1, 5), (3, 6), (5, 3),
+                                   (999, 12)])
 @pytest.mark.parametrize("tiling", [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1), (64, 4, 0)])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling, storage):
@@ -97,15 +100,19 @@ def test_two_steps_per_launch_fp16_one_launch_against_the_oracle(L):
 
 
 def test_two_steps_per_launch_applies_only_where_eligible(L):
-    """FP64 storage, masks and odd widths keep one step per launch (and say
-    so)."""
-    cases = [dict(nx=201, ny=8, storage="f32"), dict(nx=256, ny=8, storage="f64"),
-             dict(nx=201, ny=8, storage="f16")]
+    """FP64 storage and masks keep one step per launch (and say so); every
+    width takes two."""
+    cases = [dict(nx=256, ny=8, storage="f64"), dict(nx=201, ny=8, storage="f64")]
     for c in cases:
         lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
         lat.set_tuning(steps_per_sweep=2)
         assert lat.tuning()[5] == 1, c
         lat.close()
+    for nx in (201, 1, 3):
+        for storage in ("f32", "f16"):
+            lat = L.Lattice(nx, 8, 0.7, 1.0, storage=storage)
+            assert lat.tuning()[5] == 2, (nx, storage)
+            lat.close()
     mask = np.zeros((8, 256), np.uint8)
     mask[0] = 1
     for storage in ("f32", "f16"):
@@ -142,8 +149,8 @@ def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_batch_two_step_members_equal_one_step_batches(L, storage):
-    """A batch whose members mix two-step members (even widths) with
-    one-step ones (odd widths, a mask) advances every member to the bits a
+    """A batch whose members mix two-step members (even and odd widths)
+    with a one-step one (a mask) advances every member to the bits a
     one-step batch gives, over odd and even splits, graph ladders and a
     membership change; the batch reports two steps per launch only while a
     member takes them."""
@@ -181,8 +188,8 @@ def test_batch_two_step_members_equal_one_step_batches(L, storage):
     # only one-step members: the batch takes one step per launch
     wall = np.zeros((8, 64), np.uint8)
     wall[0] = 1
-    lats = [L.Lattice(97, 33, 0.7, 1.0, storage=storage),
-            L.Lattice(64, 8, 0.7, 1.0, storage=storage, mask=wall)]
+    lats = [L.Lattice(64, 8, 0.7, 1.0, storage=storage, mask=wall),
+            L.Lattice(64, 8, 0.9, 1.0, storage=storage, mask=wall)]
     b = L.Batch(lats)
     assert b.tuning()[7] == 1
     b.close()

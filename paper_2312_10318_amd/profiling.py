@@ -61,13 +61,14 @@ def _csv(d, suffix):
 
 def _is_sweep(name):
     return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
-            "sweep_tb2_kernel" in name or "sweep_batch_kernel" in name or
+            "sweep_tb2_kernel" in name or "sweep_tb2_batch_kernel" in name or
+            "sweep_batch_kernel" in name or
             "pattern_probe_kernel" in name)
 
 
 def updates_per_launch(kernel_name) -> int:
     """Time steps one launch of a sweep kernel advances the lattice by."""
-    return 2 if "sweep_tb2_kernel" in (kernel_name or "") else 1
+    return 2 if "sweep_tb2" in (kernel_name or "") else 1
 
 
 def _is_copy(name):
@@ -185,7 +186,7 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     alg = (BYTES_PER_LU[storage] + link_bytes) * nodes * ups
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"(sweep_(single|pair|tb2|batch)|pattern_probe)_kernel<[^>]*>",
+        "kernel": (re.search(r"(sweep_(single|pair|tb2_batch|tb2|batch)|pattern_probe)_kernel<[^>]*>",
                              kname or "") or re.search(r".*", "sweep")).group(0),
         "workload": wlabel, "storage": storage, "nodes": nodes, "updates_per_launch": ups,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),

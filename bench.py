@@ -328,7 +328,8 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
     for kind, rid in sample.items():
         q = next(r for r in reqs if r.rid == rid)
         fields = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
-        ur, vr = fp64_alone(q.nx, q.ny, q.tau1, q.tau2, q.steps, fields, g=q.g, mask=q.mask)
+        ur, vr = fp64_alone(q.nx, q.ny, q.tau1, q.tau2, q.steps, fields, g=q.g, mask=q.mask,
+                            inflow=q.inflow)
         _, u, v = by[rid].fields
         emax, el2 = rel_errors(u, v, ur, vr)
         acc.append({"request": rid, "kind": kind, "nx": q.nx, "ny": q.ny, "steps": q.steps,

@@ -99,11 +99,21 @@ def channel_mask(nx: int, n_fluid: int) -> np.ndarray:
     return m
 
 
+def square_obstacle_mask(nx: int = 400, ny: int = 200, side: int = 20) -> np.ndarray:
+    """A centred square obstacle of `side` nodes (nodes [(n - side) // 2,
+    (n - side) // 2 + side) in x and y), nothing else solid."""
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    x0 = (nx - side) // 2
+    y0 = (ny - side) // 2
+    m[y0:y0 + side, x0:x0 + side] = 1
+    return m
+
+
 def cylinder_channel_mask(nx: int = 400, ny: int = 200, side: int = 20) -> np.ndarray:
     """Channel with solid top/bottom rows and a centred square obstacle.
 
-    Used by the force-driven creeping-flow serving workload (a mask-only
-    stand-in for the square-cylinder problem of Sec. III.D).
+    A force-driven stand-in for the square-cylinder problem of Sec. III.D
+    (used by tests of walled batches).
     """
     m = np.zeros((ny, nx), dtype=np.uint8)
     m[0, :] = 1

@@ -55,6 +55,7 @@ class Request:
     meta: dict = dataclasses.field(default_factory=dict)
     tol: Optional[float] = None   # end when the velocity change per check is below tol
     check: int = 1000             # steps between convergence checks (with tol)
+    inflow: Optional[tuple] = None  # (u_in, rho_in, rho_out): open x boundaries
 
 
 @dataclasses.dataclass
@@ -256,12 +257,13 @@ class GpuExecutor:
 
     def footprint(self, req: Request) -> int:
         from .lattice import footprint_bytes
-        return footprint_bytes(req.nx, req.ny, self.storage, req.mask is not None)
+        return footprint_bytes(req.nx, req.ny, self.storage,
+                               req.mask is not None or req.inflow is not None)
 
     def start(self, req: Request):
         from .lattice import Lattice
         lat = Lattice(req.nx, req.ny, req.tau1, req.tau2, g=req.g, mask=req.mask,
-                      storage=self.storage, stream=self.stream)
+                      storage=self.storage, stream=self.stream, inflow=req.inflow)
         if req.fields:
             rho, ux, uy = req.fields(device=lat.device)
         else:
@@ -284,7 +286,10 @@ class GpuExecutor:
         import torch
 
         from .lattice import Batch
-        groups = ([h for h in handles if h.mask is None], [h for h in handles if h.mask is not None])
+        # lattices with a link map (masks, open boundaries) batch apart
+        linked = [h.mask is not None or h.inflow is not None for h in handles]
+        groups = ([h for h, k in zip(handles, linked) if not k],
+                  [h for h, k in zip(handles, linked) if k])
         for g in (0, 1):
             members = groups[g]
             if [id(l) for l in members] != [id(l) for l in self._members[g]]:
@@ -378,18 +383,27 @@ class GpuExecutor:
 MAX_G_TAU1 = 0.05
 
 
+def _inflow_fields(mask: np.ndarray, u: float):
+    """rho = 1 and the inflow velocity (u, 0) at every fluid node."""
+    ny, nx = mask.shape
+    return np.ones((ny, nx)), np.where(mask != 0, 0.0, u), np.zeros((ny, nx))
+
+
 def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
                      side_lo: int = 64, side_hi: int = 2048, steps=None):
     """Poisson stream of solves: one third creeping flow past a centred
-    square obstacle in a 400 x 200 channel (force-driven, walls top and
-    bottom, Re log-uniform in [1e-7, 1], T = Ma^2/Re = 0.1, Lambda_s = 3/16),
-    one third force-driven Poiseuille channels and one third Taylor-Green
-    vortices with sides log-uniform in [side_lo, side_hi].  Body forces are
-    capped at g tau1 <= MAX_G_TAU1 (stability of very viscous forced runs)."""
+    square cylinder (side 20) in a 400 x 200 domain with the set-up of
+    Sec. III.D -- uniform inflow through a moving wall on the left, a
+    pressure outlet on the right, periodic top and bottom; Re log-uniform in
+    [1e-7, 1], T = Ma^2/Re = 0.1, Lambda_s = 3/16, starting from the inflow
+    velocity at every fluid node -- one third force-driven Poiseuille
+    channels and one third Taylor-Green vortices with sides log-uniform in
+    [side_lo, side_hi].  Channel body forces are capped at g tau1 <=
+    MAX_G_TAU1 (stability of very viscous forced runs)."""
     steps = steps or {"cylinder": 2000, "poiseuille": 1000, "taylor_green": 1000}
     rng = np.random.default_rng(seed)
     t, rid, out = 0.0, 0, []
-    cyl_mask = inputs.cylinder_channel_mask(400, 200, 20)
+    cyl_mask = inputs.square_obstacle_mask(400, 200, 20)
     while True:
         t += rng.exponential(1.0 / rate)
         if t > duration:
@@ -401,13 +415,9 @@ def serving_workload(rate: float = 200.0, duration: float = 2.0, seed: int = 0,
             u = params.u_from_mach(ma)
             tau1 = params.tau_from_re(u, 20.0, re)
             tau2 = params.tau2_from_magic(tau1, 3 / 16)
-            nu = params.nu_from_tau(tau1)
-            # force for a channel velocity u, capped at g tau1 <= 0.05: a body
-            # force of g tau1 >~ 0.2 per step destabilises the very viscous
-            # runs; the creeping flow is linear in g, so the cap only rescales it
-            g = min(8 * nu * u / 198.0 ** 2, MAX_G_TAU1 / tau1)
-            req = Request(rid, kind, 400, 200, tau1, tau2, steps[kind], (g, 0.0), cyl_mask,
-                          None, t, {"re": re})
+            req = Request(rid, kind, 400, 200, tau1, tau2, steps[kind], (0.0, 0.0), cyl_mask,
+                          (lambda device=None, u=u: _inflow_fields(cyl_mask, u)), t,
+                          {"re": re, "u_in": u}, inflow=(u, 1.0, 1.0))
         else:
             n = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
             if kind == "poiseuille":

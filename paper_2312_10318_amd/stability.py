@@ -132,6 +132,51 @@ def critical_mach(res, inv_tau2s, rlb: bool = True, n: int = 128, dma: float = 0
             "seconds": round(time.perf_counter() - t0, 3), "cases": out}
 
 
+def divergence_steps(runs, n: int = 128, storage: str = "f64", quantum: int = 16,
+                     periods: float = 4.0):
+    """For every (re, ma, inv_tau2) of `runs`: the first check (every
+    `quantum` steps) at which the run has diverged, in units of t_c, or None
+    if it has not within `periods` t_c.  Shows how close to the horizon of
+    the study a run near Ma_c diverges."""
+    from .lattice import Batch, Lattice
+
+    lats, tcs, remaining = [], [], []
+    for re, ma, inv_tau2 in runs:
+        u0, tau1, tau2, steps = run_parameters(n, re, ma, inv_tau2, periods)
+        lat = Lattice(n, n, tau1, tau2, storage=storage)
+        lat.init_equilibrium(*inputs.double_shear_layer(n, u0))
+        lats.append(lat)
+        tcs.append(n / u0)
+        remaining.append(steps)
+    out = [None] * len(runs)
+    done = [False] * len(runs)
+    taken = 0
+    batch = Batch(lats)
+    members = list(range(len(runs)))
+    try:
+        while members:
+            q = min(quantum, min(remaining[i] - taken for i in members))
+            batch.step(q)
+            taken += q
+            diag = batch.diagnostics()
+            for row, i in zip(diag, members):
+                if row[4] > 0:
+                    out[i], done[i] = taken / tcs[i], True
+                elif taken >= remaining[i]:
+                    done[i] = True
+            alive = [i for i in members if not done[i]]
+            if alive != members:
+                batch.close()
+                batch = Batch([lats[i] for i in alive]) if alive else None
+                members = alive
+    finally:
+        if batch is not None:
+            batch.close()
+        for lat in lats:
+            lat.close()
+    return out
+
+
 def summary(result) -> dict:
     """Per Re: the TRT-RLB maximum of Ma_c over 1/tau_s2 (and where), and RLB."""
     by_re = {}
@@ -154,8 +199,20 @@ def main():
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-rlb", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--divergence", type=float, nargs="+", default=None, metavar="MA",
+                    help="instead of the search: when each Mach number diverges (in t_c, "
+                         "up to 4 t_c) at every --re and --inv-tau2 (and RLB)")
     a = ap.parse_args()
     import sys
+    if a.divergence:
+        rates = list(a.inv_tau2) + ([] if a.no_rlb else [None])
+        runs = [(re, ma, r) for re in a.re for r in rates for ma in a.divergence]
+        times = divergence_steps(runs, n=a.n, storage=a.storage)
+        for (re, ma, r), t in zip(runs, times):
+            print(json.dumps({"re": re, "inv_tau2": r, "ma": ma,
+                              "diverged_at_tc": None if t is None else round(t, 3)}),
+                  flush=True)
+        return
     res = critical_mach(a.re, a.inv_tau2, rlb=not a.no_rlb, n=a.n, storage=a.storage,
                         log=lambda m: print(m, file=sys.stderr, flush=True))
     res["summary"] = {str(k): v for k, v in summary(res).items()}

@@ -24,10 +24,21 @@ def _requests():
     rng = np.random.default_rng(3)
     reqs, t = [], 0.0
     mask = inputs.cylinder_channel_mask(160, 80, 12)
+    obstacle = inputs.square_obstacle_mask(160, 80, 12)
     for k in range(14):
         t += float(rng.exponential(0.004))
         kind = ("cylinder", "poiseuille", "taylor_green")[k % 3]
-        if kind == "cylinder":
+        if kind == "cylinder" and k % 2:
+            # the paper's set-up: inflow wall, pressure outlet, periodic in y
+            tau1 = float(np.exp(rng.uniform(np.log(0.6), np.log(300.0))))
+            tau2 = params.tau2_from_magic(tau1, 3 / 16)
+            u = 1e-3
+            r = Request(k, kind, 160, 80, tau1, tau2, 150 + 37 * k, (0.0, 0.0), obstacle,
+                        (lambda device=None, u=u: (np.ones((80, 160)),
+                                                   np.where(obstacle != 0, 0.0, u),
+                                                   np.zeros((80, 160)))), t,
+                        inflow=(u, 1.0, 1.0))
+        elif kind == "cylinder":
             tau1 = float(np.exp(rng.uniform(np.log(0.6), np.log(300.0))))
             tau2 = params.tau2_from_magic(tau1, 3 / 16)
             g = 8 * params.nu_from_tau(tau1) * 1e-3 / 78.0 ** 2
@@ -63,7 +74,8 @@ def test_served_results_equal_results_alone(L, storage):
     assert len(res) == len(reqs) and sched.peak_active >= 3
     by = {r.rid: r for r in res}
     for q in reqs:
-        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage)
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage,
+                        inflow=q.inflow)
         rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
         lat.init_equilibrium(rho, ux, uy).step(q.steps)
         alone = [t.cpu().numpy() for t in lat.macros()]
@@ -113,7 +125,8 @@ def test_converged_requests_equal_results_alone(L):
         say("case: served Poiseuille n=%d: converged=%s after %d steps (change %.2e)" %
             (q.ny, r.converged, r.steps, r.change))
         assert r.converged and r.steps % q.check == 0 and r.steps < q.steps
-        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage="f64")
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage="f64",
+                        inflow=q.inflow)
         lat.init_equilibrium(*inputs.rest_state(q.ny, q.nx))
         prev = tuple(torch.zeros((q.ny, q.nx), dtype=torch.float64, device=lat.device)
                      for _ in range(2))
@@ -168,7 +181,8 @@ def test_full_serving_stream_sampled_requests_equal_results_alone(L, storage):
     for q in reqs:
         if q.rid not in pick:
             continue
-        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage)
+        lat = L.Lattice(q.nx, q.ny, q.tau1, q.tau2, g=q.g, mask=q.mask, storage=storage,
+                        inflow=q.inflow)
         rho, ux, uy = q.fields() if q.fields else inputs.rest_state(q.ny, q.nx)
         lat.init_equilibrium(rho, ux, uy).step(q.steps)
         alone = [t.cpu().numpy() for t in lat.macros()]

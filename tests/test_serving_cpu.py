@@ -1,5 +1,8 @@
 """Scheduler logic of the solve server, on the CPU with a test-double
 executor that models only footprints and step counts (no device)."""
+import math
+
+import numpy as np
 import pytest
 
 from paper_2312_10318_amd.serving import Request, Scheduler, serving_workload, summarize
@@ -121,6 +124,14 @@ def test_serving_workload_mix_and_parameters():
         if r.kind == "cylinder":
             assert (r.nx, r.ny) == (400, 200) and r.mask is not None
             assert r.mask[100, 200] == 1 and r.mask[100, 0] == 0
+            # the paper's set-up: no walls and no body force; inflow u_c =
+            # c_s Ma through the left wall, outlet at rho = 1
+            assert r.mask.sum() == 400 and not r.mask[0].any() and r.g == (0.0, 0.0)
+            u = r.inflow[0]
+            assert r.inflow[1:] == (1.0, 1.0) and u == r.meta["u_in"]
+            assert abs(u - math.sqrt(1 / 3) * math.sqrt(0.1 * r.meta["re"])) < 1e-15
+            rho, ux, uy = r.fields()
+            assert np.all(rho == 1) and np.all(ux[r.mask == 0] == u) and np.all(ux[r.mask != 0] == 0)
             # T = Ma^2 / Re = 0.1 and Lambda_s = 3/16 (Sec. III.D set-up)
             assert abs((r.tau1 - 0.5) * (r.tau2 - 0.5) - 3 / 16) < 1e-9
         else:

@@ -522,7 +522,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default="",
                     help="rows_per_wave,waves_per_block,xcd_remap[,cols_per_lane"
-                         "[,graph_steps[,steps_per_sweep]]]")
+                         "[,graph_steps[,steps_per_sweep[,prefetch_rows]]]]")
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
@@ -553,7 +553,7 @@ def main():
     lat = tg_lattice(n, storage, tuning=tuning)
     ms = time_steps(lat, args.steps, args.warmup)
     stable = lat.check()
-    rows, waves, remap, cols, graph_steps, steps_per_sweep = lat.tuning()
+    rows, waves, remap, cols, graph_steps, steps_per_sweep, prefetch = lat.tuning()
     probe_ms = None
     if cols == 2 and n % 128 == 0:
         # the same launch shape moving the same bytes without the arithmetic
@@ -591,7 +591,8 @@ def main():
                    "nodes": n * n, "launch": {"rows_per_wave": rows, "waves_per_block": waves,
                                               "xcd_remap": remap, "cols_per_lane": cols,
                                               "graph_steps": graph_steps,
-                                              "steps_per_sweep": steps_per_sweep},
+                                              "steps_per_sweep": steps_per_sweep,
+                                              "prefetch_rows": prefetch},
                    "stable": bool(stable)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

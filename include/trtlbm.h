@@ -105,8 +105,9 @@ typedef struct {
 /* Launch shape of the fused sweep.  Zero fields take the built-in default
  * (rows per wavefront chosen from the lattice size, wavefronts per
  * workgroup chosen per storage, XCD remap on, two columns per lane where
- * that applies).  trt_get_tuning reports the rows, wavefronts per workgroup
- * and columns per lane in effect.
+ * that applies).  trt_get_tuning reports the rows, wavefronts per workgroup,
+ * columns per lane, time steps per launch and prefetch rows in effect
+ * (prefetch_rows 0 when the simulation takes one step per launch).
  * Two columns per lane (a wavefront sweeps 128-column strips with one
  * paired access per population) applies to lattices of at most 4 GiB whose
  * width is not 1 mod 128, with or without a mask or open boundaries;
@@ -142,6 +143,12 @@ typedef struct {
                                 sweeps take one step.  With two steps per launch,
                                 rows_per_wave and waves_per_block shape the two-step pass
                                 (cols_per_lane the one-step sweeps of odd step counts). */
+    int32_t prefetch_rows;   /* two-step pass: how many rows ahead of their use its loads
+                                are issued, 1 or 2 (0: automatic -- 2 for FP32 launches of
+                                at least 4096 wavefronts, else 1).  Two rows ahead keeps
+                                more loads in flight per wavefront but needs more
+                                registers, so fewer wavefronts fit on a SIMD.  No effect on
+                                results. */
 } trt_tuning;
 
 typedef struct trt_sim trt_sim;
@@ -330,8 +337,9 @@ trt_status trt_batch_diagnostics(trt_batch *b, double *out);
 trt_status trt_batch_set_tuning(trt_batch *b, const trt_tuning *t);
 
 /* The batch's launch shape as set (0 where automatic); steps_per_sweep
- * reports 2 only if some member takes two-step launches.  EINVAL for a NULL
- * handle or out. */
+ * reports 2 only if some member takes two-step launches, prefetch_rows the
+ * two-step launches' rows ahead in effect (0 without such members).  EINVAL
+ * for a NULL handle or out. */
 trt_status trt_batch_get_tuning(const trt_batch *b, trt_tuning *t);
 
 void trt_batch_destroy(trt_batch *b);

@@ -22,8 +22,9 @@ WAVES = (1, 2, 4)            # one column per lane: at most 4 wavefronts per wor
 WAVES_PAIR = (1, 2, 4, 8, 16)  # two columns per lane (the library caps FP64 at 8)
 REMAP = (1, 0)
 COLS = (1, 2)
-TB2_ROWS = (8, 12, 16, 24, 32, 48, 64)  # two time steps per launch
+TB2_ROWS = (8, 12, 16, 20, 24, 30, 32, 37, 48, 64)  # two time steps per launch
 TB2_WAVES = (1, 2, 4)
+TB2_PREFETCH = (1, 2)  # rows ahead of their use that the two-step loads run
 
 
 def cache_path() -> str:
@@ -60,10 +61,11 @@ def save_cache(cache: dict, path: str | None = None) -> None:
 
 def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
     """Launch shapes (rows, waves per workgroup, XCD remap, columns per
-    lane, graph sweeps (0: default), time steps per launch) worth timing.
-    Two columns per lane apply to every width that is not 1 mod 128 (with
-    or without a mask: masked lattices use the link map); two time steps
-    per launch to FP32 and FP16 lattices without a mask."""
+    lane, graph sweeps (0: default), time steps per launch, prefetch rows (0:
+    automatic)) worth timing.  Two columns per lane apply to every width
+    that is not 1 mod 128 (with or without a mask: masked lattices use the
+    link map); two time steps per launch to FP32 and FP16 lattices without a
+    mask, whose loads run one or two rows ahead."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -74,14 +76,15 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
                 continue
             for w in waves:
                 for x in REMAP:
-                    out.append((r, w, x, c, 0, 1))
+                    out.append((r, w, x, c, 0, 1, 0))
     if storage in ("f32", "f16") and not has_mask:
         for r in TB2_ROWS:
             if r > max(8, ny):
                 continue
             for w in TB2_WAVES:
                 for x in REMAP:
-                    out.append((r, w, x, 2, 0, 2))
+                    for p in TB2_PREFETCH:
+                        out.append((r, w, x, 2, 0, 2, p))
     return out
 
 

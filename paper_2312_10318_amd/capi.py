@@ -50,7 +50,8 @@ class trt_tuning(ctypes.Structure):
     _fields_ = [("rows_per_wave", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
                 ("batch_items", ctypes.c_int32), ("batch_order", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("steps_per_sweep", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("steps_per_sweep", ctypes.c_int32),
+                ("prefetch_rows", ctypes.c_int32)]
 
 
 class TrtError(RuntimeError):
@@ -153,9 +154,9 @@ def trt_create(p: trt_problem, f_a: int, f_b: int, stream: int) -> int:
 
 def trt_set_tuning(sim: int, rows_per_wave: int = 0, waves_per_block: int = 0,
                    xcd_remap: int = -1, cols_per_lane: int = 0, graph_steps: int = 0,
-                   steps_per_sweep: int = 0) -> None:
+                   steps_per_sweep: int = 0, prefetch_rows: int = 0) -> None:
     t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane, 0, 0, graph_steps,
-                   steps_per_sweep)
+                   steps_per_sweep, prefetch_rows)
     _check(load().trt_set_tuning(sim, ctypes.byref(t)), "trt_set_tuning")
 
 
@@ -163,7 +164,7 @@ def trt_get_tuning(sim: int) -> tuple:
     t = trt_tuning()
     _check(load().trt_get_tuning(sim, ctypes.byref(t)), "trt_get_tuning")
     return (t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane, t.graph_steps,
-            t.steps_per_sweep)
+            t.steps_per_sweep, t.prefetch_rows)
 
 
 def trt_init_equilibrium(sim: int, rho: int, ux: int, uy: int) -> None:
@@ -257,19 +258,20 @@ def trt_batch_diagnostics(batch: int, out: int) -> None:
 def trt_batch_set_tuning(batch: int, rows_per_wave: int = 0, waves_per_block: int = 0,
                          xcd_remap: int = -1, cols_per_lane: int = 0, batch_items: int = 0,
                          batch_order: int = 0, graph_steps: int = 0,
-                         steps_per_sweep: int = 0) -> None:
+                         steps_per_sweep: int = 0, prefetch_rows: int = 0) -> None:
     t = trt_tuning(rows_per_wave, waves_per_block, xcd_remap, cols_per_lane, batch_items,
-                   batch_order, graph_steps, steps_per_sweep)
+                   batch_order, graph_steps, steps_per_sweep, prefetch_rows)
     _check(load().trt_batch_set_tuning(batch, ctypes.byref(t)), "trt_batch_set_tuning")
 
 
 def trt_batch_get_tuning(batch: int) -> tuple:
     """(rows, waves per workgroup, XCD remap, columns per lane, batch_items,
-    batch_order, longest captured graph, time steps per launch)."""
+    batch_order, longest captured graph, time steps per launch, rows the
+    two-step loads run ahead)."""
     t = trt_tuning()
     _check(load().trt_batch_get_tuning(batch, ctypes.byref(t)), "trt_batch_get_tuning")
     return (t.rows_per_wave, t.waves_per_block, t.xcd_remap, t.cols_per_lane, t.batch_items,
-            t.batch_order, t.graph_steps, t.steps_per_sweep)
+            t.batch_order, t.graph_steps, t.steps_per_sweep, t.prefetch_rows)
 
 
 def trt_batch_destroy(batch: int) -> None:

@@ -72,12 +72,12 @@ trt_status guarded(F &&body) noexcept {
 // against 118, 2048^2 26.4 against 36.0; bit for bit the same results.
 constexpr int kMaxGraphLevels = 10;  // up to 1024 sweeps per graph
 constexpr int kDefaultGraphSteps = 64;
-constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 2};
+constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 2, 0};
 // Batches: no XCD remap by default.  A batch's work list runs member by
 // member, and spreading each member's items over all XCDs (the hardware's
 // round-robin) measured 3% faster than giving XCDs contiguous ranges of the
 // list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
-constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 2};
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 2, 0};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -166,6 +166,11 @@ trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) 
         if (t->steps_per_sweep != 1 && t->steps_per_sweep != 2)
             return fail(TRT_EINVAL, "steps_per_sweep must be 0 (default), 1 or 2");
         l.steps_per_sweep = t->steps_per_sweep;
+    }
+    if (t->prefetch_rows != 0) {
+        if (t->prefetch_rows != 1 && t->prefetch_rows != 2)
+            return fail(TRT_EINVAL, "prefetch_rows must be 0 (automatic), 1 or 2");
+        l.prefetch_rows = t->prefetch_rows;
     }
     return TRT_OK;
 }
@@ -487,6 +492,8 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     t->batch_order = 0;
     t->graph_steps = s->launch.graph_steps;
     t->steps_per_sweep = sim_tb2(s) ? 2 : 1;
+    t->prefetch_rows =
+        sim_tb2(s) ? trt::tb2_prefetch_rows(s->desc, s->prob.storage, s->launch) : 0;
     return TRT_OK;
 }
 
@@ -850,10 +857,10 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     b->nitems = (int)items.size();
     // the two-step tables: descriptors tiled for the pass (rows shared by
     // the batch unless set: the longest of 32, 24, 16, 12, 8 rows that gives
-    // 24576 items, else 8 -- a batch of small members needs many short items
+    // 32768 items, else 8 -- a batch of small members needs many short items
     // to balance: 256 members of 64^2 ... 1024^2, 4-wavefront workgroups,
-    // FP32 108.7 / 112.3 / 116.3 / 117.9 GLUPS at 32 / 24 / 16 / 12 rows,
-    // FP16 162.5 / 166.4 / 165.7 / 160.3), then their items
+    // FP32 (loads two rows ahead) 112.5 / 116.5 / 118.1 GLUPS at 24 / 16 /
+    // 12 rows, FP16 (one row ahead) 163.5 / 169.9 / 173.3), then their items
     std::vector<size_t> mem;
     for (size_t k = 0; k < n; ++k)
         if (b->two[k]) mem.push_back(k);
@@ -870,7 +877,7 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
             for (size_t k : mem)
                 c += (long long)((descs[k].nx + trt::kTb2Valid - 1) / trt::kTb2Valid) *
                      ((descs[k].ny + r - 1) / r);
-            if (c >= 24576) {
+            if (c >= 32768) {
                 l2.rows_per_wave = r;
                 break;
             }
@@ -888,7 +895,7 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     }
     order(from);
     b->nitems2 = (int)(items.size() - from);
-    b->deep2 = b->nitems2 >= 4096;
+    b->deep2 = trt::tb2_batch_prefetch_rows(b->nitems2, b->storage, b->launch) == 2;
 }
 
 static trt_status batch_build(trt_batch *b) {
@@ -1017,6 +1024,7 @@ trt_status trt_batch_get_tuning(const trt_batch *b, trt_tuning *t) {
     t->batch_order = b->launch.batch_order;
     t->graph_steps = b->launch.graph_steps;
     t->steps_per_sweep = b->nitems2 > 0 ? 2 : 1;
+    t->prefetch_rows = b->nitems2 > 0 ? (b->deep2 ? 2 : 1) : 0;
     return TRT_OK;
 }
 

@@ -21,6 +21,7 @@ struct Launch {
     int batch_order;
     int graph_steps;  // sweeps per captured graph (even)
     int steps_per_sweep;  // 2: two time steps per launch where tb2_eligible
+    int prefetch_rows;    // two-step pass: loads 1 or 2 rows ahead (0: automatic)
 };
 
 // Wavefronts per workgroup of a single-lattice sweep.  The one-column
@@ -118,7 +119,8 @@ hipError_t launch_sweep_batch(const InstDesc *descs, const int4 *items, int nite
 // Two time steps of the batch members named by items (device int4 of
 // (index into descs, window, row block, -); descs: device InstDesc[ndescs]
 // tiled by tb2_desc): each reads lattice cur ^ flip.  Items naming no
-// descriptor are skipped.  deep: loads two rows ahead (many items).
+// descriptor are skipped.  deep: loads two rows ahead
+// (tb2_batch_prefetch_rows).
 hipError_t launch_sweep_tb2_batch(const InstDesc *descs, int ndescs, const int4 *items,
                                   int nitems, int storage, int flip, bool deep, const Launch &l,
                                   hipStream_t stream);
@@ -130,11 +132,15 @@ hipError_t launch_sweep_tb2_batch(const InstDesc *descs, int ndescs, const int4 
 constexpr int kTb2Valid = 120;
 bool tb2_eligible(const InstDesc &d, int storage);
 // The tiling of the two-step pass: windows of 120 stored columns and,
-// unless the launch shape sets them, rows per wavefront for ~2048
-// wavefronts.
+// unless the launch shape sets them, rows per wavefront for at least 6144
+// wavefronts (else 2048).
 InstDesc tb2_desc(const InstDesc &d, const Launch &l);
 // Wavefronts per workgroup of the two-step pass (at most four).
 int tb2_waves_per_block(const InstDesc &d, int storage, const Launch &l);
+// Rows ahead of their use that the two-step pass issues its loads: 1 or 2.
+int tb2_prefetch_rows(const InstDesc &d, int storage, const Launch &l);
+// The same for the batched two-step pass over `items` work items.
+int tb2_batch_prefetch_rows(int items, int storage, const Launch &l);
 hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launch &l,
                             hipStream_t stream);
 

@@ -1569,11 +1569,11 @@ bool tb2_eligible(const InstDesc &d, int storage) {
            d.mask == nullptr && buffer_addressable(d, storage);
 }
 
-// Wavefronts at which the two-step pass switches to loads two rows ahead
-// and four-wavefront workgroups: with at least two rounds of wavefronts at
-// two per SIMD, the deeper prefetch outweighs the lost third wavefront
-// (4096^2, 4480 wavefronts: 126.7 against 132.0 us per step), below it
-// does not (2048^2, 2304 wavefronts: 40.3 against 35.7).
+// Wavefronts from which the two-step pass uses four-wavefront workgroups
+// and, in FP32, loads two rows ahead: with at least two rounds of
+// wavefronts at two per SIMD, the deeper prefetch outweighs the lost third
+// wavefront (4096^2 at 32 rows, 4480 wavefronts: 126.7 against 132.0 us per
+// step), below it does not (2048^2, 2304 wavefronts: 40.3 against 35.7).
 constexpr long long kTb2DeepWaves = 4096;
 
 InstDesc tb2_desc(const InstDesc &d, const Launch &l) {
@@ -1583,27 +1583,61 @@ InstDesc tb2_desc(const InstDesc &d, const Launch &l) {
         t.rows = l.rows_per_wave;
     } else {
         // the longest row block of 32, 24, 16, 12 or 8 rows that still gives
-        // 2048 wavefronts (a block of R rows runs R + 6 pipeline rows), else
-        // 8 (measured optima: 4096^2 32 rows, 2048^2 16, 1024^2 8-12)
+        // 6144 wavefronts, else the longest that gives 2048, else 8 (a block
+        // of R rows runs R + 6 pipeline rows).  Measured (us per step, the
+        // chosen shape against the best of rows 8..37 x 1, 2, 4 wavefronts
+        // per workgroup x loads 1 or 2 rows ahead): FP32 8192^2 32 rows
+        // 453.5 / 453.5, 4096^2 16 rows 120.1 / 120.1 (32 rows: 126.0),
+        // 3000^2 12 rows 74.2 / 72.2, 2048^2 16 rows 35.8 / 35.1, 1024^2 8
+        // rows 12.6 / 12.6; FP16 8192^2 272.8 / 272.8, 4096^2 75.3 / 75.3,
+        // 3000^2 46.9 / 46.6, 2048^2 26.1 / 25.2, 1024^2 12.0 / 11.6.  Short
+        // blocks read more overlap rows, but the many more wavefronts fill
+        // the last round of workgroups on the CUs more evenly.
         static const int kRows[] = {32, 24, 16, 12, 8};
+        const auto waves = [&](int r) { return (long long)t.strips * ((d.ny + r - 1) / r); };
         t.rows = 8;
-        for (int r : kRows) {
-            if ((long long)t.strips * ((d.ny + r - 1) / r) >= 2048) {
-                t.rows = r;
-                break;
+        bool found = false;
+        for (long long target : {6144LL, 2048LL}) {
+            for (int r : kRows) {
+                if (waves(r) >= target) {
+                    t.rows = r;
+                    found = true;
+                    break;
+                }
             }
+            if (found) break;
         }
     }
     t.rowblocks = (d.ny + t.rows - 1) / t.rows;
     return t;
 }
 
-static bool tb2_deep(const InstDesc &t) { return (long long)t.strips * t.rowblocks >= kTb2DeepWaves; }
+// Loads two rows ahead: two row buffers per wavefront (FP32: 210 VGPRs,
+// two wavefronts per SIMD) instead of one (164, three per SIMD).  It pays
+// only for FP32 launches of many wavefronts (8192^2 453.5 against 460.2 us
+// per step, 4096^2 equal); FP16 gains more from the third wavefront per
+// SIMD at every size (4096^2 75.3 against 79.9 us, 8192^2 272.8 against
+// 297.1, 2048^2 25.2 against 26.0; the 256-member batch 311.7 against 323.7
+// us per step, where FP32 keeps two rows ahead: 454.5 against 474.9).
+static int tb2_prefetch(long long waves, int storage, const Launch &l) {
+    if (l.prefetch_rows > 0) return l.prefetch_rows;
+    return (storage == ST_F32 && waves >= kTb2DeepWaves) ? 2 : 1;
+}
+
+int tb2_prefetch_rows(const InstDesc &d, int storage, const Launch &l) {
+    const InstDesc t = tb2_desc(d, l);
+    return tb2_prefetch((long long)t.strips * t.rowblocks, storage, l);
+}
+
+int tb2_batch_prefetch_rows(int items, int storage, const Launch &l) {
+    return tb2_prefetch(items, storage, l);
+}
 
 int tb2_waves_per_block(const InstDesc &d, int storage, const Launch &l) {
     (void)storage;
     const InstDesc t = tb2_desc(d, l);
-    int w = l.waves_per_block > 0 ? l.waves_per_block : (tb2_deep(t) ? 4 : 1);
+    const bool many = (long long)t.strips * t.rowblocks >= kTb2DeepWaves;
+    int w = l.waves_per_block > 0 ? l.waves_per_block : (many ? 4 : 1);
     if (w > kTb2MaxWaves) w = kTb2MaxWaves;
     while (w > 1 && w / 2 >= t.strips) w /= 2;
     return w;
@@ -1615,7 +1649,7 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
     const InstDesc t = tb2_desc(d, l);
     const int wpb = tb2_waves_per_block(d, storage, l);
     const int blocks = t.rowblocks * ((t.strips + wpb - 1) / wpb);
-    const bool deep = tb2_deep(t);
+    const bool deep = tb2_prefetch((long long)t.strips * t.rowblocks, storage, l) == 2;
     // Alternating march directions share each row-block boundary's reads
     // through L2: 4096^2 FP32 HBM reads 0.734 -> 0.664 GB per launch, time
     // 128.0 -> 126.4 us per step (48 rows: 149.4 -> 143.6).  Where the pass

@@ -111,13 +111,14 @@ class Lattice:
 
     # ------------------------------------------------------------------- API
     def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
-                   graph_steps=0, steps_per_sweep=0):
+                   graph_steps=0, steps_per_sweep=0, prefetch_rows=0):
         capi.trt_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap, cols_per_lane,
-                            graph_steps, steps_per_sweep)
+                            graph_steps, steps_per_sweep, prefetch_rows)
 
     def tuning(self):
         """(rows per wavefront, wavefronts per workgroup, XCD remap, columns per
-        lane, longest captured graph, time steps per launch) in effect."""
+        lane, longest captured graph, time steps per launch, rows the two-step
+        loads run ahead: 0 for one step per launch) in effect."""
         return capi.trt_get_tuning(self.handle)
 
     def init_equilibrium(self, rho, ux, uy, sync=True):
@@ -254,15 +255,17 @@ class Batch:
                                  device=self.lattices[0].device)
 
     def set_tuning(self, rows_per_wave=0, waves_per_block=0, xcd_remap=-1, cols_per_lane=0,
-                   batch_items=0, batch_order=0, graph_steps=0, steps_per_sweep=0):
+                   batch_items=0, batch_order=0, graph_steps=0, steps_per_sweep=0,
+                   prefetch_rows=0):
         capi.trt_batch_set_tuning(self.handle, rows_per_wave, waves_per_block, xcd_remap,
                                   cols_per_lane, batch_items, batch_order, graph_steps,
-                                  steps_per_sweep)
+                                  steps_per_sweep, prefetch_rows)
 
     def tuning(self):
         """(rows, wavefronts per workgroup, XCD remap, columns per lane,
         batch_items, batch_order, longest captured graph, time steps per
-        launch: 2 if some member takes two-step launches)."""
+        launch: 2 if some member takes two-step launches, rows the two-step
+        loads run ahead)."""
         return capi.trt_batch_get_tuning(self.handle)
 
     def update(self, lattices):

@@ -11,7 +11,8 @@ def test_candidates_cover_both_column_modes_on_even_widths():
         assert {s[1] for s in one if s[3] == 2} == {1, 2, 4, 8, 16}
         assert {s[2] for s in shapes} == {0, 1}
         assert len(shapes) == len(set(shapes))
-        assert all(len(s) == 6 and s[4] == 0 for s in shapes)
+        assert all(len(s) == 7 and s[4] == 0 for s in shapes)
+        assert all(s[6] == 0 for s in one)             # prefetch: two-step shapes only
 
 
 def test_candidates_offer_two_steps_per_launch_where_it_applies():
@@ -22,6 +23,7 @@ def test_candidates_offer_two_steps_per_launch_where_it_applies():
         two = [s for s in autotune.candidates(*args) if s[5] == 2]
         assert {s[0] for s in two} == set(autotune.TB2_ROWS), args
         assert {s[1] for s in two} == {1, 2, 4}
+        assert {s[6] for s in two} == {1, 2}           # loads one or two rows ahead
     for args in ((4096, 4096, True, "f32"), (4096, 4096, True, "f16"),
                  (4096, 4096, False, "f64")):
         assert all(s[5] == 1 for s in autotune.candidates(*args)), args

@@ -150,7 +150,10 @@ def test_link_map_limit_at_the_largest_sides(lib, nx, ny, masked, xb, ok):
 @pytest.mark.parametrize("field,value,ok", [("graph_steps", 6, False), ("graph_steps", 2048, False),
                                             ("graph_steps", 1, False), ("graph_steps", 256, True),
                                             ("batch_items", -2, False), ("batch_order", 3, False),
-                                            ("batch_items", 4096, True)])
+                                            ("batch_items", 4096, True),
+                                            ("prefetch_rows", 3, False),
+                                            ("prefetch_rows", -1, False),
+                                            ("prefetch_rows", 2, True)])
 def test_tuning_fields_are_validated(lib, field, value, ok):
     """Launch-shape fields are checked before anything else (a NULL batch
     handle is reported only after a valid shape)."""

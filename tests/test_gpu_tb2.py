@@ -64,6 +64,32 @@ def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling, storage):
     two.close()
 
 
+# Launches of at least 4096 wavefronts load two rows ahead, and in FP32 their
+# odd row blocks march down the block instead of up: an even and an odd
+# number of row blocks, a last block shorter than the rest, an odd width.
+@pytest.mark.parametrize("nx,ny,tiling", [((1000, 520, (1, 4, 1))), ((4096, 391, (3, 4, 1))),
+                                          ((2047, 1001, (4, 4, 0))), ((2048, 1030, (4, 2, 1)))])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_deep_two_step_launches_equal_one_step_sweeps(L, nx, ny, tiling, storage):
+    f, g, tau1, tau2 = _state(nx + 3 * ny, nx, ny)
+    windows = -(-nx // 120)
+    assert windows * -(-ny // tiling[0]) >= 4096   # the deep pipeline
+    say("case: deep two-step launches %dx%d %s tiling=%s" % (nx, ny, storage, tiling))
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage).set_populations(f)
+    one.set_tuning(steps_per_sweep=1)
+    two = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage).set_populations(f)
+    two.set_tuning(*tiling, 2, 8, 2)
+    assert two.tuning()[:2] == tiling[:2] and two.tuning()[5] == 2
+    for k in (1, 2, 5, 4, 11, 3):
+        one.step(k)
+        two.step(k)
+    a, b = _np(one.get_populations()), _np(two.get_populations())
+    say("  differs at %d of %d entries" % (int(np.sum(a != b)), a.size))
+    assert np.array_equal(a, b)
+    one.close()
+    two.close()
+
+
 def test_two_steps_per_launch_against_the_oracle(L):
     nx, ny, steps = 256, 70, 40
     f, g, tau1, tau2 = _state(3, nx, ny)
@@ -124,26 +150,29 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
 
 def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
     """Eligible lattices take two steps per launch unless asked for one; the
-    reported rows and wavefronts are the two-step pass's: ~2048 wavefronts
-    of 120-column windows with rows from 32 down to 8, four-wavefront
-    workgroups from 4096 wavefronts on, else one; an explicit request is
-    kept (at most four wavefronts, no more than the windows need)."""
-    cases = [((4096, 4096), (0, 0), (32, 4)), ((2048, 2048), (0, 0), (16, 1)),
-             ((1024, 1024), (0, 0), (8, 1)), ((256, 8), (0, 0), (8, 1)),
-             ((4096, 64), (5, 16), (5, 4)), ((240, 64), (16, 4), (16, 2))]
-    for (nx, ny), asked, want in cases:
-        lat = L.Lattice(nx, ny, 0.7, 1.0, storage="f32")
+    reported rows and wavefronts are the two-step pass's: 120-column windows
+    with the longest rows of 32 down to 8 that give 6144 wavefronts (else
+    2048), four-wavefront workgroups from 4096 wavefronts on, else one;
+    loads two rows ahead for FP32 launches from 4096 wavefronts on, else
+    one; an explicit request is kept (at most four wavefronts, no more than
+    the windows need)."""
+    cases = [((4096, 4096), (0, 0), "f32", (16, 4, 2)), ((4096, 4096), (0, 0), "f16", (16, 4, 1)),
+             ((8192, 8192), (0, 0), "f32", (32, 4, 2)), ((2048, 2048), (0, 0), "f32", (16, 1, 1)),
+             ((1024, 1024), (0, 0), "f32", (8, 1, 1)), ((256, 8), (0, 0), "f32", (8, 1, 1)),
+             ((4096, 64), (5, 16), "f32", (5, 4, 1)), ((240, 64), (16, 4), "f32", (16, 2, 1)),
+             ((4096, 4096), (0, 0, 1, 0, 0, 0, 1), "f32", (16, 4, 1)),
+             ((4096, 4096), (0, 0, 1, 0, 0, 0, 2), "f16", (16, 4, 2))]
+    for (nx, ny), asked, storage, want in cases:
+        lat = L.Lattice(nx, ny, 0.7, 1.0, storage=storage)
         assert lat.tuning()[5] == 2
         lat.set_tuning(*asked)
         got = lat.tuning()
-        say("case: %dx%d asked %s -> rows %d waves %d" % (nx, ny, asked, got[0], got[1]))
-        assert (got[0], got[1], got[5]) == (*want, 2)
-        lat.set_tuning(*asked, -1, 0, 0, 1)
-        assert lat.tuning()[5] == 1
+        say("case: %dx%d %s asked %s -> rows %d waves %d prefetch %d"
+            % (nx, ny, storage, asked, got[0], got[1], got[6]))
+        assert (got[0], got[1], got[6], got[5]) == (*want, 2)
+        lat.set_tuning(*asked[:2], -1, 0, 0, 1)
+        assert lat.tuning()[5] == 1 and lat.tuning()[6] == 0
         lat.close()
-    lat = L.Lattice(4096, 64, 0.7, 1.0, storage="f16")
-    assert lat.tuning()[5] == 2
-    lat.close()
 
 
 

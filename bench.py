@@ -598,7 +598,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_lu": BYTES_PER_LU[storage],
                      "updates_per_launch": steps_per_sweep,
-                     "kernel": ("sweep_tb2_kernel<%s>" if steps_per_sweep == 2 else
+                     "kernel": ("sweep_tb3_kernel<%s>" if steps_per_sweep == 3 else
+                                "sweep_tb2_kernel<%s>" if steps_per_sweep == 2 else
                                 "sweep_pair_kernel<%s>" if cols == 2 else
                                 "sweep_single_kernel<%s,nomask>") % storage,
                      "source_hash": sweep_source_hash(),

@@ -136,16 +136,19 @@ typedef struct {
                                 of the rest (graphs of 2, 4, ... sweeps, captured at first
                                 use): the GPU idles ~8 us at each graph boundary and ~0.2 us
                                 between the sweeps inside one graph. */
-    int32_t steps_per_sweep; /* 2 (0: default) or 1: two time steps per launch (each
-                                population crosses HBM once per two steps; the bits of two
-                                one-step sweeps).  Applies to FP32 and FP16 simulations, alone
-                                or in a batch, without a mask or open boundaries; elsewhere
-                                sweeps take one step.  With two steps per launch,
-                                rows_per_wave and waves_per_block shape the two-step pass
-                                (cols_per_lane the one-step sweeps of odd step counts). */
+    int32_t steps_per_sweep; /* time steps per launch: 2 (0: default), 1 or 3.  k steps per
+                                launch move each population through HBM once per k steps and
+                                give the bits of k one-step sweeps.  Two apply to FP32 and
+                                FP16 simulations, alone or in a batch, without a mask or open
+                                boundaries; three to such FP32 simulations alone (batch
+                                members take two); elsewhere sweeps take fewer steps.  With
+                                two or three steps per launch, rows_per_wave and
+                                waves_per_block shape that pass (cols_per_lane the one-step
+                                sweeps of leftover steps). */
     int32_t prefetch_rows;   /* two-step pass: how many rows ahead of their use its loads
                                 are issued, 1 or 2 (0: automatic -- 2 for FP32 launches of
-                                at least 4096 wavefronts, else 1).  Two rows ahead keeps
+                                at least 4096 wavefronts, else 1; the three-step pass always
+                                loads one row ahead).  Two rows ahead keeps
                                 more loads in flight per wavefront but needs more
                                 registers, so fewer wavefronts fit on a SIMD.  No effect on
                                 results. */

@@ -163,8 +163,8 @@ trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) 
         l.graph_steps = g;
     }
     if (t->steps_per_sweep != 0) {
-        if (t->steps_per_sweep != 1 && t->steps_per_sweep != 2)
-            return fail(TRT_EINVAL, "steps_per_sweep must be 0 (default), 1 or 2");
+        if (t->steps_per_sweep < 1 || t->steps_per_sweep > 3)
+            return fail(TRT_EINVAL, "steps_per_sweep must be 0 (default), 1, 2 or 3");
         l.steps_per_sweep = t->steps_per_sweep;
     }
     if (t->prefetch_rows != 0) {
@@ -302,13 +302,24 @@ template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F bo
     return TRT_OK;
 }
 
-// Whether a simulation's launches take two time steps each.
-bool sim_tb2(const trt_sim *s) {
-    return s->launch.steps_per_sweep == 2 && trt::tb2_eligible(s->desc, s->prob.storage);
+// Time steps per launch of a simulation: three, two or one, as asked and
+// as the lattice allows.
+int sim_k(const trt_sim *s) {
+    if (s->launch.steps_per_sweep == 3 && trt::tb3_eligible(s->desc, s->prob.storage)) return 3;
+    if (s->launch.steps_per_sweep >= 2 && trt::tb2_eligible(s->desc, s->prob.storage)) return 2;
+    return 1;
+}
+
+// One launch of k time steps (k as sim_k or lower) reading lattice src.
+hipError_t sim_launch(const trt_sim *s, int k, int src, hipStream_t stream) {
+    const int st = s->prob.storage;
+    if (k == 3) return trt::launch_sweep_tb3(s->desc, st, src, s->launch, stream);
+    if (k == 2) return trt::launch_sweep_tb2(s->desc, st, src, s->launch, stream);
+    return trt::launch_sweep(s->desc, st, s->prob.mask != nullptr, src, s->launch, stream);
 }
 
 // Capture `sweeps` (even) launches of a simulation, starting from lattice 0,
-// into `out` (each launch one step, or two with sim_tb2).
+// into `out` (each launch sim_k steps).
 trt_status sim_capture(trt_sim *s, hipGraphExec_t &out, int64_t sweeps) {
     release_graph(out);
     if (!s->cap_stream) {
@@ -318,13 +329,10 @@ trt_status sim_capture(trt_sim *s, hipGraphExec_t &out, int64_t sweeps) {
             return fail_hip(e, "hipStreamCreateWithFlags");
         }
     }
-    const int st = s->prob.storage;
-    const bool m = s->prob.mask != nullptr;
-    const bool tb2 = sim_tb2(s);
+    const int ks = sim_k(s);
     return capture(s->cap_stream, out, [&](hipStream_t cs) {
         for (int64_t k = 0; k < sweeps; ++k) {
-            hipError_t e = tb2 ? trt::launch_sweep_tb2(s->desc, st, (int)(k & 1), s->launch, cs)
-                               : trt::launch_sweep(s->desc, st, m, (int)(k & 1), s->launch, cs);
+            hipError_t e = sim_launch(s, ks, (int)(k & 1), cs);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -483,17 +491,23 @@ trt_status trt_set_tuning(trt_sim *s, const trt_tuning *t) {
 trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (!t) return fail(TRT_EINVAL, "out is NULL");
-    t->rows_per_wave = sim_tb2(s) ? trt::tb2_desc(s->desc, s->launch).rows : s->desc.rows;
-    t->waves_per_block = sim_tb2(s) ? trt::tb2_waves_per_block(s->desc, s->prob.storage, s->launch)
-                                    : trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
+    const int ks = sim_k(s);
+    t->rows_per_wave = ks == 3   ? trt::tb3_desc(s->desc, s->launch).rows
+                       : ks == 2 ? trt::tb2_desc(s->desc, s->launch).rows
+                                 : s->desc.rows;
+    t->waves_per_block =
+        ks == 3   ? trt::tb3_waves_per_block(s->desc, s->launch)
+        : ks == 2 ? trt::tb2_waves_per_block(s->desc, s->prob.storage, s->launch)
+                  : trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
     t->xcd_remap = s->launch.xcd_remap;
     t->cols_per_lane = s->desc.cols;
     t->batch_items = 0;
     t->batch_order = 0;
     t->graph_steps = s->launch.graph_steps;
-    t->steps_per_sweep = sim_tb2(s) ? 2 : 1;
-    t->prefetch_rows =
-        sim_tb2(s) ? trt::tb2_prefetch_rows(s->desc, s->prob.storage, s->launch) : 0;
+    t->steps_per_sweep = ks;
+    t->prefetch_rows = ks == 3   ? trt::tb3_prefetch_rows(s->desc, s->launch)
+                       : ks == 2 ? trt::tb2_prefetch_rows(s->desc, s->prob.storage, s->launch)
+                                 : 0;
     return TRT_OK;
 }
 
@@ -538,11 +552,13 @@ trt_status trt_step(trt_sim *s, int64_t nsteps) {
     }
     // every graph holds an even number of launches, so each replay starts and
     // ends on lattice 0
-    if (sim_tb2(s)) {
-        // two steps per launch: graphs of 2, 4, ... launches (4, 8, ... steps),
-        // then at most one two-step launch and one one-step sweep
-        if (nsteps >= 4) {
-            const int64_t launches = nsteps / 4 * 2;
+    const int ks = sim_k(s);
+    if (ks > 1) {
+        // ks steps per launch: graphs of 2, 4, ... launches (2 ks, 4 ks, ...
+        // steps), then at most one ks-step launch, and the rest (fewer than
+        // ks steps) as one two-step launch and one-step sweeps
+        if (nsteps >= 2 * ks) {
+            const int64_t launches = nsteps / (2 * ks) * 2;
             trt_status rs = replay_ladder(
                 launches, std::max<int64_t>(2, s->launch.graph_steps / 2), s->graphs, s->stream,
                 [&](int k) -> trt_status {
@@ -550,19 +566,16 @@ trt_status trt_step(trt_sim *s, int64_t nsteps) {
                     return sim_capture(s, s->graphs[k], (int64_t)2 << k);
                 });
             if (rs != TRT_OK) return rs;
-            s->time += 2 * launches;
-            nsteps -= 2 * launches;
+            s->time += ks * launches;
+            nsteps -= ks * launches;
         }
-        if (nsteps >= 2) {
-            TRT_HIP(trt::launch_sweep_tb2(s->desc, st, 0, s->launch, s->stream));
-            s->cur = 1;
-            s->time += 2;
-            nsteps -= 2;
-        }
-        if (nsteps == 1) {
-            TRT_HIP(trt::launch_sweep(s->desc, st, m, s->cur, s->launch, s->stream));
+        // fewer than 2 ks steps are left: ks, then 2 (when ks is 3), then 1
+        for (int k : {ks, 2, 1}) {
+            if (k > ks || nsteps < k) continue;
+            TRT_HIP(sim_launch(s, k, s->cur, s->stream));
             s->cur ^= 1;
-            ++s->time;
+            s->time += k;
+            nsteps -= k;
         }
         return TRT_OK;
     }
@@ -826,7 +839,7 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     }
     // class 1: members that take two-step launches
     b->two.assign(n, 0);
-    if (b->launch.steps_per_sweep == 2)
+    if (b->launch.steps_per_sweep >= 2)   // batches take at most two steps per launch
         for (size_t k = 0; k < n; ++k)
             b->two[k] = trt::tb2_eligible(descs[k], b->sims[k]->prob.storage) ? 1 : 0;
     const auto cost = [&](const int4 &it) {

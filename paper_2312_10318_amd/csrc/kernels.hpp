@@ -20,7 +20,7 @@ struct Launch {
     int batch_items;
     int batch_order;
     int graph_steps;  // sweeps per captured graph (even)
-    int steps_per_sweep;  // 2: two time steps per launch where tb2_eligible
+    int steps_per_sweep;  // 2 or 3: time steps per launch where tb2_eligible / tb3_eligible
     int prefetch_rows;    // two-step pass: loads 1 or 2 rows ahead (0: automatic)
 };
 
@@ -142,6 +142,18 @@ int tb2_prefetch_rows(const InstDesc &d, int storage, const Launch &l);
 // The same for the batched two-step pass over `items` work items.
 int tb2_batch_prefetch_rows(int items, int storage, const Launch &l);
 hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launch &l,
+                            hipStream_t stream);
+
+// Three time steps per launch (FP32 storage, open periodic lattices, as
+// for two): reads lattice src, writes the other one, three steps later,
+// with the bits of three one-step sweeps.  A wavefront computes a
+// 128-column window and stores its middle kTb3Valid columns.
+constexpr int kTb3Valid = 116;
+bool tb3_eligible(const InstDesc &d, int storage);
+InstDesc tb3_desc(const InstDesc &d, const Launch &l);
+int tb3_waves_per_block(const InstDesc &d, const Launch &l);
+int tb3_prefetch_rows(const InstDesc &d, const Launch &l);
+hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launch &l,
                             hipStream_t stream);
 
 // The access-pattern probe (a measurement aid): one launch moves the lattice

@@ -1006,6 +1006,52 @@ struct Tb2Params {
     float gx, gy, w1, w2, ph;
 };
 
+// The collision coefficients (all but the Phi_y gradient term) and Phi_y
+// of a lane's pair in the row between the window (wA, wB) of a previous
+// step's post-collision rows and that step's freshly collided row (oa, ob):
+// the pull (x neighbours by DPP lane shifts), the moments and the Phi_x
+// gradient, as the one-step sweep forms them.
+template <class C, bool SH, bool UP>
+__device__ __forceinline__ void pull_coeffs_pair(Coeffs<C> &ckA, Coeffs<C> &ckB, C &cyA, C &cyB,
+                                                 const MidWindow<C> &wA, const MidWindow<C> &wB,
+                                                 const C oa[9], const C ob[9],
+                                                 const Tb2Params &p) {
+    const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
+    C fa[9], fb[9];
+    MidWindow<C> lw, rw;
+    C lf[9], rf[9];
+    // node A: x - 1 is the previous lane's node B (it gives 1 and the
+    // x + 1 movers of the other two rows: 5 and 8)
+    lw.mid[1] = dpp_shr(C(0), wB.mid[1]);
+    if (UP) {
+        lw.lo[1] = dpp_shr(C(0), wB.lo[1]);
+        lf[8] = dpp_shr(C(0), ob[8]);
+    } else {
+        lw.lo[2] = dpp_shr(C(0), wB.lo[2]);
+        lf[5] = dpp_shr(C(0), ob[5]);
+    }
+    mid_pull<C, UP>(fa, wA, oa, lw, lf, wB, ob);
+    // node B: x + 2 is the next lane's node A (3, 6 and 7)
+    rw.mid[2] = dpp_shl(C(0), wA.mid[2]);
+    if (UP) {
+        rw.lo[2] = dpp_shl(C(0), wA.lo[2]);
+        rf[7] = dpp_shl(C(0), oa[7]);
+    } else {
+        rw.lo[1] = dpp_shl(C(0), wA.lo[1]);
+        rf[6] = dpp_shl(C(0), oa[6]);
+    }
+    mid_pull<C, UP>(fb, wB, ob, wA, oa, rw, rf);
+    RowState<C, SH> cA, cB;
+    node_state<C, SH>(cA, fa, gx, gy);
+    node_state<C, SH>(cB, fb, gx, gy);
+    const C left = dpp_shr(C(0), cB.phix);
+    const C right = dpp_shl(C(0), cA.phix);
+    ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
+    ckB = collide_coeffs<C, SH>(cB.m, C(0.5) * (right - cA.phix), w1, w2, ph, gx, gy);
+    cyA = cA.phiy;
+    cyB = cB.phiy;
+}
+
 // One pipeline row: (b) the moments and coefficients of first-step row
 // y + 3 from `raw`, whose registers then take the loads of row `yload`
 // (when `load`), (c) from STAGE 1 the first-step collision of row y + 2,
@@ -1049,41 +1095,8 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     // (d) row y + 1 of the second step
     C cyA = C(0), cyB = C(0);
     Coeffs<C> ckA, ckB;
-    if (stage >= 2) {
-        C fa[9], fb[9];
-        MidWindow<C> lw, rw;
-        C lf[9], rf[9];
-        // node A: x - 1 is the previous lane's node B (it gives 1 and the
-        // x + 1 movers of the other two rows: 5 and 8)
-        lw.mid[1] = dpp_shr(C(0), k.wB.mid[1]);
-        if (UP) {
-            lw.lo[1] = dpp_shr(C(0), k.wB.lo[1]);
-            lf[8] = dpp_shr(C(0), ob[8]);
-        } else {
-            lw.lo[2] = dpp_shr(C(0), k.wB.lo[2]);
-            lf[5] = dpp_shr(C(0), ob[5]);
-        }
-        mid_pull<C, UP>(fa, k.wA, oa, lw, lf, k.wB, ob);
-        // node B: x + 2 is the next lane's node A (3, 6 and 7)
-        rw.mid[2] = dpp_shl(C(0), k.wA.mid[2]);
-        if (UP) {
-            rw.lo[2] = dpp_shl(C(0), k.wA.lo[2]);
-            rf[7] = dpp_shl(C(0), oa[7]);
-        } else {
-            rw.lo[1] = dpp_shl(C(0), k.wA.lo[1]);
-            rf[6] = dpp_shl(C(0), oa[6]);
-        }
-        mid_pull<C, UP>(fb, k.wB, ob, k.wA, oa, rw, rf);
-        RowState<C, SH> cA, cB;
-        node_state<C, SH>(cA, fa, gx, gy);
-        node_state<C, SH>(cB, fb, gx, gy);
-        const C left = dpp_shr(C(0), cB.phix);
-        const C right = dpp_shl(C(0), cA.phix);
-        ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
-        ckB = collide_coeffs<C, SH>(cB.m, C(0.5) * (right - cA.phix), w1, w2, ph, gx, gy);
-        cyA = cA.phiy;
-        cyB = cB.phiy;
-    }
+    if (stage >= 2)
+        pull_coeffs_pair<C, SH, UP>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p);
     // (e) collide row y of the second step and store the window's middle
     if (stage >= 3) {
         const C dya = C(0.5) * (UP ? cyA - k.qbelA : k.qbelA - cyA);
@@ -1402,6 +1415,203 @@ __global__ __launch_bounds__(ST == ST_F64 ? 512 : 1024) void sweep_pair_kernel(I
         idle_rows(d, rb);
 }
 
+// Three time steps per pass (FP32 storage): the two-step pipeline with one
+// more step in the middle.  A wavefront's 128-column window loses two
+// columns on each side per step (the pull and the Phi_x gradient each
+// reach one column further), so it stores its middle kTb3Valid = 116
+// columns; a row block of R rows reads R + 10 rows.  Pipeline row y:
+// (b) the first-step moments and coefficients of row y + 5 from `raw`,
+// then the loads of a later row; (c) the first-step collision of row y + 4;
+// (d) the second-step pull and coefficients of row y + 3; (e) the
+// second-step collision of row y + 2; (f) the third-step pull and
+// coefficients of row y + 1; (g) the third-step collision of row y and its
+// store.  Stage k adds part k of these; the first ten pipeline rows of a
+// block fill the pipeline.  Every node's arithmetic is the one-step
+// sweep's and each step's results are those that sweep stores and loads
+// back, so three steps per pass reproduce its bits.
+template <class C> struct Tb3Carry {
+    Coeffs<C> kA, kB;     // first step: coefficients of the next row to collide
+    C pyA, pyB;           // ... its Phi_y
+    C belA, belB;         // ... and that of the row behind it
+    MidWindow<C> wA, wB;  // first-step results in flight
+    Coeffs<C> qA, qB;     // second step: the next row to collide ...
+    C qyA, qyB, qbelA, qbelB;
+    MidWindow<C> vA, vB;  // second-step results in flight
+    Coeffs<C> rA, rB;     // third step: the next row to collide and store
+    C ryA, ryB, rbelA, rbelB;
+};
+
+// Post-collision populations of a lane's pair from their coefficients and
+// Phi_y gradients (dya, dyb: the row ahead minus the row behind, halved).
+template <class C>
+__device__ __forceinline__ void collide_pair(C oa[9], C ob[9], const Coeffs<C> &a, C dya,
+                                             const Coeffs<C> &b, C dyb, C ph) {
+    reconstruct<C>(oa, a.base, a.bx, a.by, a.bxx, a.byy - ph * dya, a.bxy, a.bxxy, a.bxyy);
+    reconstruct<C>(ob, b.base, b.bx, b.by, b.bxx, b.byy - ph * dyb, b.bxy, b.bxxy, b.bxyy);
+}
+
+template <int STAGE, bool UP = true>
+__device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
+                                        const PairCtx<float> &cx, const Tb2Lane &ln, bool odd,
+                                        const Tb2Params &p, const BufAccess<float> &out, int y,
+                                        bool load, int yload, bool store, int pitch,
+                                        int64_t plane, int stage = STAGE) {
+    using C = float;
+    constexpr bool SH = true;
+    const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
+    OpenX<C> ox;
+    ox.on = false;
+    ox.nx = 0;
+    ox.u_in = ox.rho_in = ox.rho_out = ox.phi_wall = C(0);
+    // the Phi_y gradient: the row ahead of the march minus the row behind
+    const auto grad = [](C ahead, C behind) { return C(0.5) * (UP ? ahead - behind : behind - ahead); };
+    // (b) row y + 5, then (a) the next loads into the same registers
+    C nyA, nyB;
+    Coeffs<C> nkA, nkB;
+    {
+        RowState<C, SH> nA, nB;
+        widen_pair<float, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) tb2_gather<float>(raw, cx, ln, odd, yload);
+        const C left = dpp_shr(C(0), nB.phix);
+        const C right = dpp_shl(C(0), nA.phix);
+        nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
+        nkB = collide_coeffs<C, SH>(nB.m, C(0.5) * (right - nA.phix), w1, w2, ph, gx, gy);
+        nyA = nA.phiy;
+        nyB = nB.phiy;
+    }
+    // (c) first-step collision of row y + 4
+    C oa[9], ob[9];
+    if (stage >= 1) collide_pair<C>(oa, ob, k.kA, grad(nyA, k.belA), k.kB, grad(nyB, k.belB), ph);
+    // (d) second-step pull and coefficients of row y + 3
+    C cyA = C(0), cyB = C(0);
+    Coeffs<C> ckA, ckB;
+    if (stage >= 2) pull_coeffs_pair<C, SH, UP>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p);
+    // (e) second-step collision of row y + 2
+    C sa[9], sb[9];
+    if (stage >= 3) collide_pair<C>(sa, sb, k.qA, grad(cyA, k.qbelA), k.qB, grad(cyB, k.qbelB), ph);
+    // (f) third-step pull and coefficients of row y + 1
+    C ryA = C(0), ryB = C(0);
+    Coeffs<C> rkA, rkB;
+    if (stage >= 4) pull_coeffs_pair<C, SH, UP>(rkA, rkB, ryA, ryB, k.vA, k.vB, sa, sb, p);
+    // (g) third-step collision of row y and the store of the window's middle
+    if (stage >= 5) {
+        C ta[9], tb[9];
+        collide_pair<C>(ta, tb, k.rA, grad(ryA, k.rbelA), k.rB, grad(ryB, k.rbelB), ph);
+        if (store) {
+            const int64_t e0 = (int64_t)y * pitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                PairIO<float>::st(out, i * plane + e0, cx.opair, ta[i], tb[i]);
+        }
+    }
+    // advance the pipeline by one row
+    if (stage >= 4) {
+        k.rbelA = k.ryA;
+        k.rbelB = k.ryB;
+        k.ryA = ryA;
+        k.ryB = ryB;
+        k.rA = rkA;
+        k.rB = rkB;
+    }
+    if (stage >= 3) {
+        mid_shift<C, UP>(k.vA, sa);
+        mid_shift<C, UP>(k.vB, sb);
+    }
+    if (stage >= 2) {
+        k.qbelA = k.qyA;
+        k.qbelB = k.qyB;
+        k.qyA = cyA;
+        k.qyB = cyB;
+        k.qA = ckA;
+        k.qB = ckB;
+    }
+    if (stage >= 1) {
+        mid_shift<C, UP>(k.wA, oa);
+        mid_shift<C, UP>(k.wB, ob);
+    }
+    k.belA = k.pyA;
+    k.belB = k.pyB;
+    k.pyA = nyA;
+    k.pyB = nyB;
+    k.kA = nkA;
+    k.kB = nkB;
+    __builtin_amdgcn_s_barrier();
+}
+
+// Three time steps over row block rb of window `strip` (FP32): as
+// sweep_strip_tb2, with ten pipeline rows of fill and the block's rows
+// y0 - 5 ... y1 + 4 gathered.
+template <int DEPTH, bool UP = true>
+__device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, int rb, int srcsel) {
+    static_assert(DEPTH == 1 || DEPTH == 2, "loads one or two rows ahead");
+    using T = float;
+    const int lane = threadIdx.x & 63;
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+    const int64_t plane = d.plane;
+    const T *__restrict__ src = static_cast<const T *>(srcsel ? d.buf[1] : d.buf[0]);
+    T *__restrict__ dst = static_cast<T *>(srcsel ? d.buf[0] : d.buf[1]);
+    const uint64_t bytes = (uint64_t)ny * (uint64_t)pitch * sizeof(T);
+    const BufAccess<T> in(src, bytes), out(dst, bytes);
+    const LinkAccess lacc(d.links, 0);
+    // the lane's pair and whether it is in the stored middle of the window
+    // (lanes 3 ... 60) and inside the lattice
+    const int xs = strip * kTb3Valid - 6 + 2 * lane;
+    int ca = xs % nx;
+    if (ca < 0) ca += nx;
+    const int cb = ca + 1 == nx ? 0 : ca + 1;
+    const bool odd = (nx & 1) != 0;
+    const Tb2Lane ln{(ca & 1) != 0 || cb != ca + 1, (uint32_t)ca * (uint32_t)sizeof(T),
+                     (uint32_t)cb * (uint32_t)sizeof(T)};
+    const int cp = ln.split ? (ca & ~1) : ca;
+    const bool store = lane >= 3 && lane < 61 && xs < nx;
+    const Column hcol = column_of(cp, nx, sizeof(T));
+    const uint32_t ve[3] = {0u, 0u, 0u};
+    const PairCtx<T> cx{in, plane, pitch, ny, (uint32_t)cp * (uint32_t)sizeof(T), (uint32_t)cp,
+                        false, ve, hcol, lacc, false, d.lpitch, 0u, false};
+    const Tb2Params p{(float)d.gx, (float)d.gy, (float)d.omega1, (float)d.omega2, (float)d.phi};
+    const int y0 = rb * d.rows;
+    const int y1 = min(y0 + d.rows, ny);
+    const auto wrap_row = [&](int v) { v %= ny; return v < 0 ? v + ny : v; };
+    // pipeline row y widens row y + 5 dir and loads row y + (5 + DEPTH) dir
+    // while one is needed (the block needs rows y0 - 5 ... y1 + 4)
+    constexpr int dir = UP ? 1 : -1;
+    const auto ld = [&](int y) {
+        return UP ? y + 5 + DEPTH <= y1 + 4 : y - 5 - DEPTH >= y0 - 5;
+    };
+    const auto lrow = [&](int y) { return wrap_row(y + dir * (5 + DEPTH)); };
+
+    Tb3Carry<float> k{};
+    PairRow<T> raw[DEPTH];
+    const int ys = UP ? y0 - 10 : y1 + 9;  // the first pipeline row
+    tb2_gather<T>(raw[0], cx, ln, odd, wrap_row(ys + 5 * dir));
+    if (DEPTH == 2) tb2_gather<T>(raw[DEPTH - 1], cx, ln, odd, wrap_row(ys + 6 * dir));
+    constexpr int R1 = DEPTH - 1;
+    int y = ys;
+    for (int i = 0; i < 10; ++i, y += dir) {
+        // both buffers named statically (a run-time index would move them
+        // to scratch memory)
+        if (DEPTH == 2 && (i & 1))
+            tb3_row<-1, UP>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
+                            plane, i >> 1);
+        else
+            tb3_row<-1, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
+                            plane, i >> 1);
+    }
+    const auto inside = [&](int v) { return UP ? v < y1 : v >= y0; };
+    if (DEPTH == 1) {
+        for (; inside(y); y += dir)
+            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+    } else {
+        for (; inside(y + dir); y += 2 * dir) {
+            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir), lrow(y + dir),
+                           store, pitch, plane);
+        }
+        if (inside(y))
+            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+    }
+}
+
 // Two time steps per pass (sweep_strip_tb2): workgroup b covers row block
 // b / groups and the windows [g * wpb, g * wpb + wpb) with g = b % groups,
 // as the two-column sweep; a wavefront without a window meets the R + 6
@@ -1432,6 +1642,31 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d
         const int y0 = rb * d.rows;
         const int y1 = min(y0 + d.rows, d.ny);
         for (int y = y0 - 6; y < y1; ++y) __builtin_amdgcn_s_barrier();
+    }
+}
+
+// Three time steps per pass: workgroups as for two (sweep_tb2_kernel), R +
+// 10 barriers per row block; loads one row ahead (238 VGPRs, two wavefronts
+// per SIMD).
+__global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_kernel(InstDesc d, int srcsel,
+                                                                      int remap,
+                                                                      int alternate) {
+    int b = blockIdx.x;
+    if (remap) b = xcd_remap(b, gridDim.x);
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int groups = (d.strips + wpb - 1) / wpb;
+    const int rb = b / groups;
+    const int strip = (b - rb * groups) * wpb + w;
+    if (strip < d.strips) {
+        if (alternate && (rb & 1))
+            sweep_strip_tb3<1, false>(d, strip, rb, srcsel);
+        else
+            sweep_strip_tb3<1, true>(d, strip, rb, srcsel);
+    } else {
+        const int y0 = rb * d.rows;
+        const int y1 = min(y0 + d.rows, d.ny);
+        for (int y = y0 - 10; y < y1; ++y) __builtin_amdgcn_s_barrier();
     }
 }
 
@@ -1667,6 +1902,63 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
     } else {
         sweep_tb2_kernel<ST_F32, 1><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
     }
+    return hipGetLastError();
+}
+
+bool tb3_eligible(const InstDesc &d, int storage) {
+    return storage == ST_F32 && tb2_eligible(d, storage);
+}
+
+InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
+    InstDesc t = d;
+    t.strips = (d.nx + kTb3Valid - 1) / kTb3Valid;
+    if (l.rows_per_wave > 0) {
+        t.rows = l.rows_per_wave;
+    } else {
+        // the longest of 32, 24, 16, 12 or 8 rows that gives 6144
+        // wavefronts, else the longest that gives 2048, else 8
+        static const int kRows[] = {32, 24, 16, 12, 8};
+        const auto waves = [&](int r) { return (long long)t.strips * ((d.ny + r - 1) / r); };
+        t.rows = 8;
+        bool found = false;
+        for (long long target : {6144LL, 2048LL}) {
+            for (int r : kRows) {
+                if (waves(r) >= target) {
+                    t.rows = r;
+                    found = true;
+                    break;
+                }
+            }
+            if (found) break;
+        }
+    }
+    t.rowblocks = (d.ny + t.rows - 1) / t.rows;
+    return t;
+}
+
+int tb3_waves_per_block(const InstDesc &d, const Launch &l) {
+    const InstDesc t = tb3_desc(d, l);
+    const bool many = (long long)t.strips * t.rowblocks >= kTb2DeepWaves;
+    int w = l.waves_per_block > 0 ? l.waves_per_block : (many ? 4 : 1);
+    if (w > kTb2MaxWaves) w = kTb2MaxWaves;
+    while (w > 1 && w / 2 >= t.strips) w /= 2;
+    return w;
+}
+
+// The three-step pass loads one row ahead whatever is asked: two rows ahead
+// take 256 VGPRs and 33 AGPRs, one wavefront per SIMD.
+int tb3_prefetch_rows(const InstDesc &, const Launch &) { return 1; }
+
+hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launch &l,
+                            hipStream_t stream) {
+    if (!tb3_eligible(d, storage)) return hipErrorInvalidValue;
+    const InstDesc t = tb3_desc(d, l);
+    const int wpb = tb3_waves_per_block(d, l);
+    const int blocks = t.rowblocks * ((t.strips + wpb - 1) / wpb);
+    // odd row blocks march down, as in the two-step pass: each block
+    // boundary's ten shared rows are read by both blocks at the same end
+    // of their runs
+    sweep_tb3_kernel<<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, 1);
     return hipGetLastError();
 }
 

@@ -62,13 +62,15 @@ def _csv(d, suffix):
 def _is_sweep(name):
     return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
             "sweep_tb2_kernel" in name or "sweep_tb2_batch_kernel" in name or
+            "sweep_tb3_kernel" in name or
             "sweep_batch_kernel" in name or
             "pattern_probe_kernel" in name)
 
 
 def updates_per_launch(kernel_name) -> int:
     """Time steps one launch of a sweep kernel advances the lattice by."""
-    return 2 if "sweep_tb2" in (kernel_name or "") else 1
+    name = kernel_name or ""
+    return 3 if "sweep_tb3" in name else 2 if "sweep_tb2" in name else 1
 
 
 def _is_copy(name):
@@ -186,7 +188,7 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     alg = (BYTES_PER_LU[storage] + link_bytes) * nodes * ups
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"(sweep_(single|pair|tb2_batch|tb2|batch)|pattern_probe)_kernel<[^>]*>",
+        "kernel": (re.search(r"(sweep_(single|pair|tb2_batch|tb2|tb3|batch)|pattern_probe)_kernel(<[^>]*>)?",
                              kname or "") or re.search(r".*", "sweep")).group(0),
         "workload": wlabel, "storage": storage, "nodes": nodes, "updates_per_launch": ups,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),
@@ -248,7 +250,7 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
         fh.write("| kernel | calls | average | min | max |\n|---|---|---|---|---|\n")
         for r in stats:
             nm = r["Name"]
-            m = re.search(r"(\w+_kernel<[^>]*>|copyBuffer)", nm)
+            m = re.search(r"(\w+_kernel(<[^>]*>)?|copyBuffer)", nm)
             fh.write("| %s | %s | %.0f | %s | %s |\n" % (m.group(1) if m else nm[:40],
                      r["Calls"], float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
     return rec
@@ -290,7 +292,7 @@ def bench_trace_summary(trace_dir, bench_json, out_prefix, cmd):
         fh.write("| kernel | calls | average | min | max |\n|---|---|---|---|---|\n")
         for r in stats:
             nm = r["Name"]
-            m = re.search(r"(\w+_kernel<[^>]*>|copyBuffer)", nm)
+            m = re.search(r"(\w+_kernel(<[^>]*>)?|copyBuffer)", nm)
             fh.write("| %s | %s | %.0f | %s | %s |\n" % (m.group(1) if m else nm[:40],
                      r["Calls"], float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
     return out

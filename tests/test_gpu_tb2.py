@@ -64,6 +64,56 @@ def test_two_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling, storage):
     two.close()
 
 
+@pytest.mark.parametrize("nx,ny", [(128, 37), (256, 9), (384, 130), (128, 3), (232, 5),
+                                   (512, 64), (200, 37), (250, 9), (130, 66), (6, 5), (2, 4),
+                                   (1000, 41), (362, 1), (201, 37), (97, 33), (241, 20),
+                                   (117, 7), (115, 9), (116, 4), (1, 5), (3, 6), (5, 3),
+                                   (999, 12), (4096, 73)])
+@pytest.mark.parametrize("tiling", [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1), (64, 4, 0)])
+def test_three_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
+    """FP32 three steps per launch (116 stored columns of a 128-column
+    window, odd row blocks marching down): the bits of one-step sweeps."""
+    f, g, tau1, tau2 = _state(nx + 5 * ny, nx, ny)
+    say("case: three steps per launch %dx%d tiling=%s" % (nx, ny, tiling))
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    one.set_tuning(steps_per_sweep=1)
+    three = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    three.set_tuning(*tiling, 2, 8, 3)
+    assert three.tuning()[5] == 3 and three.tuning()[6] == 1 and three.tuning()[1] <= 4
+    for k in (1, 2, 5, 4, 11, 3, 6, 13):   # 45 steps: every remainder, graphs
+        one.step(k)
+        three.step(k)
+    assert one.state()[1] == three.state()[1] == 45
+    a, b = _np(one.get_populations()), _np(three.get_populations())
+    say("  differs at %d of %d entries" % (int(np.sum(a != b)), a.size))
+    assert np.array_equal(a, b)
+    one.close()
+    three.close()
+
+
+def test_three_steps_per_launch_apply_to_fp32_alone(L):
+    """FP16 lattices asked for three steps per launch take two, FP64 and
+    masked ones one; a batch of FP32 members takes two."""
+    for storage, want in (("f32", 3), ("f16", 2), ("f64", 1)):
+        lat = L.Lattice(256, 64, 0.7, 1.0, storage=storage)
+        lat.set_tuning(steps_per_sweep=3)
+        assert lat.tuning()[5] == want, storage
+        lat.close()
+    mask = np.zeros((64, 256), np.uint8)
+    mask[0] = mask[-1] = 1
+    lat = L.Lattice(256, 64, 0.7, 1.0, storage="f32", mask=mask)
+    lat.set_tuning(steps_per_sweep=3)
+    assert lat.tuning()[5] == 1
+    lat.close()
+    lats = [L.Lattice(n, n, 0.7, 1.0, storage="f32") for n in (64, 130)]
+    b = L.Batch(lats)
+    b.set_tuning(steps_per_sweep=3)
+    assert b.tuning()[7] == 2
+    b.close()
+    for l in lats:
+        l.close()
+
+
 # Launches of at least 4096 wavefronts load two rows ahead, and in FP32 their
 # odd row blocks march down the block instead of up: an even and an odd
 # number of row blocks, a last block shorter than the rest, an odd width.

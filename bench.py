@@ -10,10 +10,10 @@ The JSON line reports MLUPS (lattice updates per second / 1e6), the roofline
 of the sweep kernel (algorithmic bytes per lattice update x updates per
 launch / average launch time, against the 8 TB/s HBM peak), and the FP64 CPU
 oracle timed on a bounded sample of the same workload on the host cores.
-FP32 and FP16 lattices run two time steps per launch (the library default
-where it applies), so a launch counts two lattice updates per node; it moves
-each population through HBM once, and the measured traffic (rocprofv3
-counters) is about half the algorithmic bytes.
+By the library default the FP32 benchmark lattice runs three time steps per
+launch and FP16 two, so a launch counts that many lattice updates per node;
+it moves each population through HBM about once, and the measured traffic
+(rocprofv3 counters) is a fraction of the algorithmic bytes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
                       [--no-extra] [--no-cpu]
@@ -48,6 +48,9 @@ def time_steps(lat, steps, warmup):
     """Average time per step (ms) over `steps` steps after `warmup` steps."""
     import torch
     lat.step(warmup)
+    # the step graphs the timed steps replay are captured beforehand, so
+    # no host-side capture falls in the timed region
+    lat.prepare(steps)
     torch.cuda.synchronize()
     with torch.cuda.stream(lat.stream):
         start = torch.cuda.Event(enable_timing=True)
@@ -85,6 +88,31 @@ def tg_lattice(n, storage, tau1=0.6, lam=0.25, tuning=None):
         lat.set_tuning(*tuning)
     lat.init_equilibrium(rho, ux, uy)
     return lat
+
+
+def headline_shape(lat, n, storage):
+    """The launch shape a Taylor-Green benchmark lattice runs in: the
+    autotuner's pick among the shapes of the lattice's default pass (its
+    time steps per launch), timed on a scratch lattice and cached per box
+    like every tuner result.  Returns (shape, record)."""
+    from paper_2312_10318_amd import autotune
+    rows, waves, remap, cols, _, sps, prefetch = lat.tuning()
+    default = (rows, waves, remap, cols if sps == 1 else 2, 0, sps, prefetch)
+    key = autotune.key(n, n, storage, False) + "|steps%d" % sps
+    cache = autotune.load_cache()
+    if key in cache:
+        c = cache[key]
+        return tuple(c["best"]), c
+    shapes = [sh for sh in autotune.candidates(n, n, False, storage) if sh[5] == sps]
+    if default not in shapes:
+        shapes.append(default)
+    res = autotune.tune(n, n, storage, shapes=shapes)
+    table = {tuple(sh): ms for sh, ms in res["table"]}
+    rec = {"best": res["best"], "ms": res["ms"], "default": list(default),
+           "default_ms": table[default], "candidates": len(shapes), "when": res["when"]}
+    cache[key] = rec
+    autotune.save_cache(cache)
+    return tuple(res["best"]), rec
 
 
 def rel_errors(u, v, ur, vr):
@@ -351,11 +379,13 @@ def run_extra(steps):
     out = {}
     for storage in ("f16", "f64"):
         lat = tg_lattice(4096, storage)
+        shape = headline_shape(lat, 4096, storage)[0]
+        lat.set_tuning(*shape)
         ms = time_steps(lat, steps, 20)
         lat.close()
         mlups = 4096 * 4096 / (ms * 1e-3) / 1e6
         out["tg4096_" + storage] = {
-            "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5),
+            "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5), "launch_shape": list(shape),
             "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / (HBM_PEAK_GBS * 1e9), 4)}
         log("extra %s: %.1f MLUPS" % (storage, mlups))
     out["batch256_f32"] = run_batch()
@@ -468,6 +498,7 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
     scale the HBM counters."""
     import torch
     nodes = None
+    launch = None
     if workload == "batch":
         # the benchmark's 256-member batch in the library's default batch shape
         from paper_2312_10318_amd import inputs
@@ -493,6 +524,11 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
             n = lat.nx
         else:
             lat = tg_lattice(n, storage, tuning=tuning)
+            if tuning is None and workload == "tg":
+                # the shape the benchmark runs in (bench.py --tune-only beforehand
+                # puts it in the tuner's cache, so no tuning runs under the profiler)
+                lat.set_tuning(*headline_shape(lat, n, storage)[0])
+        launch = list(lat.tuning())
         if workload == "stream":
             # the sweep's access pattern without its arithmetic
             lat.pattern_probe(warmup + steps)
@@ -508,7 +544,7 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
     print(json.dumps({"profile": "done", "sweeps": warmup + steps, "copy_bytes": 1 << 30,
                       "copies": 3, "storage": storage, "n": n, "workload": workload,
                       "nodes": nodes if nodes is not None else n * n,
-                      "source_hash": sweep_source_hash()}), flush=True)
+                      "launch": launch, "source_hash": sweep_source_hash()}), flush=True)
 
 
 def main():
@@ -520,6 +556,13 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run (or read from the tuner's cache) the launch-shape choice of "
+                         "the --storage/--n benchmark lattice, print it and exit (so that "
+                         "later profiled runs read it from the cache)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default launch shape instead of the "
+                         "autotuner's pick")
     ap.add_argument("--tuning", default="",
                     help="rows_per_wave,waves_per_block,xcd_remap[,cols_per_lane"
                          "[,graph_steps[,steps_per_sweep[,prefetch_rows]]]]")
@@ -546,11 +589,24 @@ def main():
 
     n, storage = args.n, args.storage
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    if args.tune_only:
+        lat = tg_lattice(n, storage)
+        shape, rec = headline_shape(lat, n, storage)
+        lat.close()
+        print(json.dumps({"tune": {"n": n, "storage": storage, "shape": list(shape),
+                                   "ms": rec.get("ms")}}), flush=True)
+        return
     if args.profile:
         profile_run(n, storage, args.steps, args.warmup, tuning, args.workload)
         return
     log("bench: TG %dx%d %s, warmup %d, steps %d" % (n, n, storage, args.warmup, args.steps))
     lat = tg_lattice(n, storage, tuning=tuning)
+    tuned = None
+    if tuning is None and not args.no_tune:
+        shape, tuned = headline_shape(lat, n, storage)
+        lat.set_tuning(*shape)
+        log("bench: launch shape %s chosen by the autotuner (%.4f ms per step; the default "
+            "shape %s: %.4f)" % (shape, tuned["ms"], tuned["default"], tuned["default_ms"]))
     ms = time_steps(lat, args.steps, args.warmup)
     stable = lat.check()
     rows, waves, remap, cols, graph_steps, steps_per_sweep, prefetch = lat.tuning()
@@ -565,6 +621,9 @@ def main():
     # one launch advances the lattice by steps_per_sweep steps: its
     # algorithmic bytes are those of that many lattice updates, and its
     # duration that many steps' time
+    # (with a step count that is not a multiple of steps_per_sweep the timed
+    # region ends on a launch of fewer steps, counted as that fraction of a
+    # launch)
     bytes_step = BYTES_PER_LU[storage] * n * n
     bytes_launch = bytes_step * steps_per_sweep
     launch_ms = ms * steps_per_sweep
@@ -593,6 +652,13 @@ def main():
                                               "graph_steps": graph_steps,
                                               "steps_per_sweep": steps_per_sweep,
                                               "prefetch_rows": prefetch},
+                   "launch_chosen_by": ("autotuner" if tuned else
+                                        "--tuning" if tuning else "library default"),
+                   "autotune": ({"candidates": tuned.get("candidates"),
+                                 "tuned_ms_per_step": round(tuned["ms"], 5),
+                                 "default_shape": tuned.get("default"),
+                                 "default_ms_per_step": round(tuned["default_ms"], 5)}
+                                if tuned and "default_ms" in tuned else None),
                    "stable": bool(stable)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

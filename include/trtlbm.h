@@ -136,12 +136,15 @@ typedef struct {
                                 of the rest (graphs of 2, 4, ... sweeps, captured at first
                                 use): the GPU idles ~8 us at each graph boundary and ~0.2 us
                                 between the sweeps inside one graph. */
-    int32_t steps_per_sweep; /* time steps per launch: 2 (0: default), 1 or 3.  k steps per
-                                launch move each population through HBM once per k steps and
-                                give the bits of k one-step sweeps.  Two apply to FP32 and
-                                FP16 simulations, alone or in a batch, without a mask or open
-                                boundaries; three to such FP32 simulations alone (batch
-                                members take two); elsewhere sweeps take fewer steps.  With
+    int32_t steps_per_sweep; /* time steps per launch: 1, 2 or 3 (0: automatic -- three for
+                                FP32 simulations of at least 2048^2 nodes that allow it, else
+                                two where allowed; in a batch three for FP32 members, two for
+                                FP16).  k steps per launch move each
+                                population through HBM once per k steps and give the bits of
+                                k one-step sweeps.  Two apply to FP32 and FP16 simulations,
+                                alone or in a batch, without a mask or open boundaries; three
+                                to such FP32 simulations, alone or in an FP32 batch; elsewhere
+                                sweeps take fewer steps.  With
                                 two or three steps per launch, rows_per_wave and
                                 waves_per_block shape that pass (cols_per_lane the one-step
                                 sweeps of leftover steps). */
@@ -220,10 +223,16 @@ trt_status trt_get_populations(trt_sim *s, double *f);
 
 /* Advance nsteps >= 0 time steps (Eq. 2 followed by streaming), enqueued on
  * the stream as replays of captured HIP graphs (see trt_tuning.graph_steps)
- * plus at most two plain launches; two time steps per launch where
- * trt_tuning.steps_per_sweep allows it.  Any split of the steps, and either
- * number of steps per launch, gives the same bits. */
+ * plus at most three plain launches; two or three time steps per launch
+ * where trt_tuning.steps_per_sweep allows it.  Any split of the steps, and
+ * any number of steps per launch, gives the same bits. */
 trt_status trt_step(trt_sim *s, int64_t nsteps);
+
+/* Capture the step graphs that trt_step(s, nsteps) would replay from the
+ * current state, without launching anything (the state and time are
+ * unchanged), so that a later trt_step(s, nsteps) spends no host time on
+ * capture.  Graphs stay captured until the launch shape changes. */
+trt_status trt_prepare_steps(trt_sim *s, int64_t nsteps);
 
 /* A measurement aid, not a step of the method: nsweeps launches that move
  * the lattice holding the state to the other one (alternating) with the

@@ -3,7 +3,7 @@
 For a lattice shape, storage type and mask presence it times the fused sweep
 over a grid of launch shapes (rows a wavefront marches, wavefronts per
 workgroup, XCD remap on/off, one or two columns per lane where two apply,
-one or two time steps per launch where two apply) on a scratch lattice of
+one, two or three time steps per launch where they apply) on a scratch lattice of
 that shape, and keeps the fastest.  For a batch it times the batched step (rows, wavefronts per
 workgroup, XCD remap) on scratch copies of the members.  Results persist in
 a JSON cache keyed by GPU architecture, storage, mask presence and size
@@ -25,6 +25,7 @@ COLS = (1, 2)
 TB2_ROWS = (8, 12, 16, 20, 24, 30, 32, 37, 48, 64)  # two time steps per launch
 TB2_WAVES = (1, 2, 4)
 TB2_PREFETCH = (1, 2)  # rows ahead of their use that the two-step loads run
+TB3_ROWS = (8, 12, 16, 20, 24, 32, 38, 40, 48, 64)  # three time steps per launch (FP32)
 
 
 def cache_path() -> str:
@@ -65,7 +66,8 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
     automatic)) worth timing.  Two columns per lane apply to every width
     that is not 1 mod 128 (with or without a mask: masked lattices use the
     link map); two time steps per launch to FP32 and FP16 lattices without a
-    mask, whose loads run one or two rows ahead."""
+    mask, whose loads run one or two rows ahead; three to such FP32
+    lattices."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -85,6 +87,13 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
                 for x in REMAP:
                     for p in TB2_PREFETCH:
                         out.append((r, w, x, 2, 0, 2, p))
+    if storage == "f32" and not has_mask:
+        for r in TB3_ROWS:
+            if r > max(8, ny):
+                continue
+            for w in TB2_WAVES:
+                for x in REMAP:
+                    out.append((r, w, x, 2, 0, 3, 1))
     return out
 
 
@@ -93,6 +102,7 @@ def time_shape(lat, shape, steps: int, warmup: int) -> float:
     import torch
     lat.set_tuning(*shape)
     lat.step(warmup)
+    lat.prepare(steps)   # graph capture stays out of the timed region
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(lat.stream)

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "TRT_OK", 1: "TRT_EINVAL", 2: "TRT_ENOMEM", 3: "TRT_EDEVICE",
 EXPORTED = [
     "trt_pitch", "trt_row_stride", "trt_lattice_bytes", "trt_footprint_bytes", "trt_create",
     "trt_set_tuning", "trt_get_tuning", "trt_init_equilibrium", "trt_set_populations",
-    "trt_get_populations", "trt_step", "trt_pattern_probe", "trt_macros", "trt_diagnostics",
+    "trt_get_populations", "trt_step", "trt_prepare_steps", "trt_pattern_probe", "trt_macros", "trt_diagnostics",
     "trt_diagnostics_noalloc", "trt_row_mean_ux",
     "trt_wall_force", "trt_velocity_change", "trt_velocity_error",
     "trt_check", "trt_state", "trt_destroy", "trt_batch_create", "trt_batch_update",
@@ -89,6 +89,7 @@ def load():
         "trt_set_populations": (ctypes.c_int, [P, P]),
         "trt_get_populations": (ctypes.c_int, [P, P]),
         "trt_step": (ctypes.c_int, [P, I64]),
+        "trt_prepare_steps": (ctypes.c_int, [P, I64]),
         "trt_pattern_probe": (ctypes.c_int, [P, I64]),
         "trt_macros": (ctypes.c_int, [P, P, P, P]),
         "trt_diagnostics": (ctypes.c_int, [P, P]),
@@ -181,6 +182,10 @@ def trt_get_populations(sim: int, f: int) -> None:
 
 def trt_step(sim: int, nsteps: int) -> None:
     _check(load().trt_step(sim, nsteps), "trt_step")
+
+
+def trt_prepare_steps(sim: int, nsteps: int) -> None:
+    _check(load().trt_prepare_steps(sim, nsteps), "trt_prepare_steps")
 
 
 def trt_pattern_probe(sim: int, nsweeps: int) -> None:

@@ -66,18 +66,20 @@ trt_status guarded(F &&body) noexcept {
 // graph boundary ~8 us (kernel trace of 126 double-shear-layer lattices of
 // 128^2, FP64, 62 us per batched sweep: 4.1 us per step with two-sweep graphs,
 // 0.25 with 128); 4096^2 FP32 214.0 -> 210.9 us per step.
-// Two time steps per launch wherever the lattice allows it (FP32 or FP16
-// storage, open periodic): FP32 4096^2 127 against 210 us per
-// step, 2048^2 35.7 against 59.6, 1024^2 12.6 against 19.6; FP16 4096^2 85
-// against 118, 2048^2 26.4 against 36.0; bit for bit the same results.
+// Several time steps per launch wherever the lattice allows it (FP32 or
+// FP16 storage, open periodic; sim_k): two steps per launch took FP32
+// 4096^2 from 210 to 127 us per step, 2048^2 59.6 -> 35.7, 1024^2 19.6 ->
+// 12.6, FP16 4096^2 118 -> 85, 2048^2 36.0 -> 26.4; three (FP32 from 2048^2
+// on) take 4096^2 to 96, 8192^2 to 346 (two steps: 122, 454); bit for bit
+// the same results.
 constexpr int kMaxGraphLevels = 10;  // up to 1024 sweeps per graph
 constexpr int kDefaultGraphSteps = 64;
-constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 2, 0};
+constexpr Launch kDefaultLaunch = {0, 0, 1, 0, 0, 0, kDefaultGraphSteps, 0, 0};
 // Batches: no XCD remap by default.  A batch's work list runs member by
 // member, and spreading each member's items over all XCDs (the hardware's
 // round-robin) measured 3% faster than giving XCDs contiguous ranges of the
 // list (256 members of 64^2 ... 1024^2, FP32: 67.7 against 65.8 GLUPS).
-constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 2, 0};
+constexpr Launch kBatchDefaultLaunch = {0, 0, 0, 0, -1, 1, kDefaultGraphSteps, 0, 0};
 constexpr int kMaxSide = 46340;
 
 int elem_size(int storage) {
@@ -231,7 +233,8 @@ struct trt_batch {
     int nitems2;  // two-step items
     int ndescs2;  // two-step descriptors (class-1 members)
     bool deep2;   // two-step launches load two rows ahead
-    int parity2;  // two-step launches and one-step sweeps of class 1, mod 2
+    int k2;       // time steps per class-1 launch: 2, or 3 (FP32, steps_per_sweep 3)
+    int parity2;  // class-1 launches and one-step sweeps of class 1, mod 2
     hipStream_t cap_stream;
     hipGraphExec_t graphs[kMaxGraphLevels];  // level k: 2^(k+1) batched sweeps
                                              // (two-step mode: 2^(k+1) units)
@@ -260,22 +263,24 @@ int graph_level(int64_t sweeps) {
 // Replay an even number of sweeps through the graph ladder: whole graphs of
 // the top level, then one graph per remaining binary digit.  `ensure(k)`
 // captures level k if needed.
+// With run = false the graphs are only captured (nothing is launched).
 template <class Ensure>
 trt_status replay_ladder(int64_t nsteps, int64_t graph_steps, hipGraphExec_t (&gs)[kMaxGraphLevels],
-                         hipStream_t stream, Ensure ensure) {
+                         hipStream_t stream, Ensure ensure, bool run = true) {
     const int top = graph_level(graph_steps);
     const int64_t big = (int64_t)2 << top;
     if (nsteps >= big) {
         trt_status st = ensure(top);
         if (st != TRT_OK) return st;
-        for (int64_t k = 0; k < nsteps / big; ++k) TRT_HIP(hipGraphLaunch(gs[top], stream));
+        if (run)
+            for (int64_t k = 0; k < nsteps / big; ++k) TRT_HIP(hipGraphLaunch(gs[top], stream));
         nsteps %= big;
     }
     for (int k = top - 1; k >= 0; --k) {
         if (nsteps & ((int64_t)2 << k)) {
             trt_status st = ensure(k);
             if (st != TRT_OK) return st;
-            TRT_HIP(hipGraphLaunch(gs[k], stream));
+            if (run) TRT_HIP(hipGraphLaunch(gs[k], stream));
         }
     }
     return TRT_OK;
@@ -299,14 +304,30 @@ template <class F> trt_status capture(hipStream_t cap, hipGraphExec_t &out, F bo
         out = nullptr;
         return fail_hip(e3, "hipGraphInstantiate");
     }
+    // move the graph's launch resources to the device now rather than at
+    // its first replay
+    TRT_HIP(hipGraphUpload(out, cap));
+    TRT_HIP(hipStreamSynchronize(cap));
     return TRT_OK;
 }
 
-// Time steps per launch of a simulation: three, two or one, as asked and
-// as the lattice allows.
+// Time steps per launch of a simulation: three, two or one, as asked (0:
+// automatic) and as the lattice allows.  Automatic: three for FP32 lattices
+// of at least 2048^2 nodes, else two.  Measured (us per step, each pass at
+// its default shape, FP32): 8192^2 two steps 453.5, three 345.5; 6144^2
+// 284.8 / 211.5; 4096^2 122.3 / 96.2; 3000^2 74.5 / 62.3; 2048^2 35.5 /
+// 29.0; below, three steps gain nothing (1536^2 21.0 / 20.9, 1024^2 12.6 /
+// 12.8, 512^2 8.6 / 9.2): the extra fill rows and window columns cost more
+// than the HBM traffic saved on lattices that largely stay in the
+// memory-side cache.
+constexpr int64_t kTb3MinNodes = 2048LL * 2048LL;
 int sim_k(const trt_sim *s) {
-    if (s->launch.steps_per_sweep == 3 && trt::tb3_eligible(s->desc, s->prob.storage)) return 3;
-    if (s->launch.steps_per_sweep >= 2 && trt::tb2_eligible(s->desc, s->prob.storage)) return 2;
+    const int want = s->launch.steps_per_sweep;
+    const int st = s->prob.storage;
+    if (trt::tb3_eligible(s->desc, st) &&
+        (want == 3 || (want == 0 && (int64_t)s->desc.nx * s->desc.ny >= kTb3MinNodes)))
+        return 3;
+    if (want != 1 && trt::tb2_eligible(s->desc, st)) return 2;
     return 1;
 }
 
@@ -597,6 +618,27 @@ trt_status trt_step(trt_sim *s, int64_t nsteps) {
     return TRT_OK;
 }
 
+trt_status trt_prepare_steps(trt_sim *s, int64_t nsteps) {
+    if (check_sim(s) != TRT_OK) return TRT_EINVAL;
+    if (nsteps < 0) return fail(TRT_EINVAL, "nsteps must be >= 0");
+    if (s->in_batch) return fail(TRT_ESTATE, "simulation is a batch member");
+    // the launches trt_step would replay as graphs (see there)
+    int64_t n = nsteps;
+    if (s->cur == 1 && n > 0) --n;
+    const int ks = sim_k(s);
+    const int64_t launches = ks > 1 ? n / (2 * ks) * 2 : n / 2 * 2;
+    if (launches == 0) return TRT_OK;
+    const int64_t longest =
+        ks > 1 ? std::max<int64_t>(2, s->launch.graph_steps / 2) : s->launch.graph_steps;
+    return replay_ladder(
+        launches, longest, s->graphs, s->stream,
+        [&](int k) -> trt_status {
+            if (s->graphs[k]) return TRT_OK;
+            return sim_capture(s, s->graphs[k], (int64_t)2 << k);
+        },
+        false);
+}
+
 trt_status trt_pattern_probe(trt_sim *s, int64_t nsweeps) {
     if (check_sim(s) != TRT_OK) return TRT_EINVAL;
     if (nsweeps < 0) return fail(TRT_EINVAL, "nsweeps must be >= 0");
@@ -837,17 +879,27 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
             d.rowblocks = (d.ny + d.rows - 1) / d.rows;
         }
     }
-    // class 1: members that take two-step launches
+    // class 1: members that take multi-step launches: three steps per launch
+    // in FP32 (unless two are asked for), two in FP16.  The 256-member
+    // benchmark batch (sides 64 to 1024), FP32: 155.4 GLUPS with three steps
+    // per launch against 118.0 with two -- its members are small, but
+    // together they far exceed the memory-side cache.
+    const int sps = b->launch.steps_per_sweep;
+    b->k2 = ((sps == 0 || sps == 3) && b->storage == trt::ST_F32) ? 3 : 2;
     b->two.assign(n, 0);
-    if (b->launch.steps_per_sweep >= 2)   // batches take at most two steps per launch
+    if (b->launch.steps_per_sweep != 1)
         for (size_t k = 0; k < n; ++k)
-            b->two[k] = trt::tb2_eligible(descs[k], b->sims[k]->prob.storage) ? 1 : 0;
+            b->two[k] = (b->k2 == 3 ? trt::tb3_eligible(descs[k], b->sims[k]->prob.storage)
+                                    : trt::tb2_eligible(descs[k], b->sims[k]->prob.storage))
+                            ? 1
+                            : 0;
+    const int valid2 = b->k2 == 3 ? trt::kTb3Valid : trt::kTb2Valid;
     const auto cost = [&](const int4 &it) {
         // two-step items (it.w == 2) index the two-step descriptors, which
         // follow the n one-step ones
         const InstDesc &d = descs[it.w == 2 ? n + (size_t)it.x : (size_t)it.x];
         const int rows = std::min(d.rows, d.ny - it.z * d.rows);
-        return (int64_t)rows * (it.w == 2 ? trt::kTb2Valid : trt::kStripWidth * d.cols);
+        return (int64_t)rows * (it.w == 2 ? valid2 : trt::kStripWidth * d.cols);
     };
     const auto order = [&](size_t from) {
         // costliest first: rows in the block x columns per strip (stable, so
@@ -868,12 +920,15 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
         if (cls == 0) b->nitems0 = (int)items.size();
     }
     b->nitems = (int)items.size();
-    // the two-step tables: descriptors tiled for the pass (rows shared by
-    // the batch unless set: the longest of 32, 24, 16, 12, 8 rows that gives
-    // 32768 items, else 8 -- a batch of small members needs many short items
-    // to balance: 256 members of 64^2 ... 1024^2, 4-wavefront workgroups,
-    // FP32 (loads two rows ahead) 112.5 / 116.5 / 118.1 GLUPS at 24 / 16 /
-    // 12 rows, FP16 (one row ahead) 163.5 / 169.9 / 173.3), then their items
+    // the multi-step tables: descriptors tiled for the pass (rows shared by
+    // the batch unless set -- a batch of small members needs many short
+    // items to balance.  Two steps: the longest of 32, 24, 16, 12, 8 rows
+    // that gives 32768 items (256 members of 64^2 ... 1024^2, 4-wavefront
+    // workgroups: FP32 (loads two rows ahead) 112.5 / 116.5 / 118.1 GLUPS at
+    // 24 / 16 / 12 rows, FP16 (one row ahead) 163.5 / 169.9 / 173.3).  Three
+    // steps (ten rows of fill per block): the longest of 32, 24, 20, 16, 12,
+    // 8 that gives 24576 items (FP32 152.7 / 154.5 / 155.4 / 153.8 / 147.2
+    // GLUPS at 32 / 24 / 20 / 16 / 12 rows).  Else 8.), then their items
     std::vector<size_t> mem;
     for (size_t k = 0; k < n; ++k)
         if (b->two[k]) mem.push_back(k);
@@ -883,14 +938,19 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     if (mem.empty()) return;
     Launch l2 = b->launch;
     if (l2.rows_per_wave <= 0) {
-        static const int kRows[] = {32, 24, 16, 12, 8};
+        static const int kRows2[] = {32, 24, 16, 12, 8};
+        static const int kRows3[] = {32, 24, 20, 16, 12, 8};
+        const int *rows = b->k2 == 3 ? kRows3 : kRows2;
+        const int nrows = b->k2 == 3 ? 6 : 5;
+        const long long target = b->k2 == 3 ? 24576 : 32768;
         l2.rows_per_wave = 8;
-        for (int r : kRows) {
+        for (int i = 0; i < nrows; ++i) {
+            const int r = rows[i];
             long long c = 0;
             for (size_t k : mem)
-                c += (long long)((descs[k].nx + trt::kTb2Valid - 1) / trt::kTb2Valid) *
+                c += (long long)((descs[k].nx + valid2 - 1) / valid2) *
                      ((descs[k].ny + r - 1) / r);
-            if (c >= 32768) {
+            if (c >= target) {
                 l2.rows_per_wave = r;
                 break;
             }
@@ -898,7 +958,8 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     }
     const size_t from = items.size();
     for (size_t j = 0; j < mem.size(); ++j) {
-        InstDesc d2 = trt::tb2_desc(descs[mem[j]], l2);
+        InstDesc d2 = b->k2 == 3 ? trt::tb3_desc(descs[mem[j]], l2)
+                                 : trt::tb2_desc(descs[mem[j]], l2);
         descs.push_back(d2);
         // the two-step kernel's descriptor table starts after the n
         // one-step ones: its items name j (entry n + j of the whole table)
@@ -908,7 +969,8 @@ static void batch_tile(trt_batch *b, std::vector<InstDesc> &descs, std::vector<i
     }
     order(from);
     b->nitems2 = (int)(items.size() - from);
-    b->deep2 = trt::tb2_batch_prefetch_rows(b->nitems2, b->storage, b->launch) == 2;
+    b->deep2 = b->k2 == 2 &&
+               trt::tb2_batch_prefetch_rows(b->nitems2, b->storage, b->launch) == 2;
 }
 
 static trt_status batch_build(trt_batch *b) {
@@ -1036,7 +1098,7 @@ trt_status trt_batch_get_tuning(const trt_batch *b, trt_tuning *t) {
     t->batch_items = b->launch.batch_items;
     t->batch_order = b->launch.batch_order;
     t->graph_steps = b->launch.graph_steps;
-    t->steps_per_sweep = b->nitems2 > 0 ? 2 : 1;
+    t->steps_per_sweep = b->nitems2 > 0 ? b->k2 : 1;
     t->prefetch_rows = b->nitems2 > 0 ? (b->deep2 ? 2 : 1) : 0;
     return TRT_OK;
 }
@@ -1057,24 +1119,31 @@ static hipError_t batch_single(const trt_batch *b, int f0, int f1, hipStream_t s
     return trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems, b->storage, b->mask, b->buf,
                                    f0, f1, b->launch, s);
 }
+// One unit of k2 steps: one k2-step launch of class 1 and k2 one-step
+// sweeps of class 0 (parities f0 and f1 at its start).
 static hipError_t batch_unit(const trt_batch *b, int f0, int f1, hipStream_t s) {
     const size_t n = b->sims.size();
-    hipError_t e = trt::launch_sweep_tb2_batch(b->d_descs + n, b->ndescs2, b->d_items + b->nitems,
-                                               b->nitems2, b->storage, f1, b->deep2, b->launch, s);
-    for (int h = 0; h < 2 && e == hipSuccess && b->nitems0 > 0; ++h)
+    hipError_t e =
+        b->k2 == 3
+            ? trt::launch_sweep_tb3_batch(b->d_descs + n, b->ndescs2, b->d_items + b->nitems,
+                                          b->nitems2, b->storage, f1, b->launch, s)
+            : trt::launch_sweep_tb2_batch(b->d_descs + n, b->ndescs2, b->d_items + b->nitems,
+                                          b->nitems2, b->storage, f1, b->deep2, b->launch, s);
+    for (int h = 0; h < b->k2 && e == hipSuccess && b->nitems0 > 0; ++h)
         e = trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems0, b->storage, b->mask,
-                                    b->buf, f0 ^ h, f0 ^ h, b->launch, s);
+                                    b->buf, f0 ^ (h & 1), f0 ^ (h & 1), b->launch, s);
     return e;
 }
 
 // Capture `sweeps` (even) batched sweeps, starting from parity 0, into `out`;
-// in two-step mode `sweeps` units (four steps per pair) from parities 0, 0.
+// in multi-step mode `sweeps` units (2 k2 steps per pair) from parities 0, 0
+// (unit u starts class 0 on parity u k2 mod 2).
 static trt_status batch_capture(trt_batch *b, hipGraphExec_t &out, int64_t sweeps) {
     release_graph(out);
     return capture(b->cap_stream, out, [&](hipStream_t cs) {
         for (int64_t k = 0; k < sweeps; ++k) {
             hipError_t e = b->nitems2 > 0
-                               ? batch_unit(b, 0, (int)(k & 1), cs)
+                               ? batch_unit(b, (int)((k * b->k2) & 1), (int)(k & 1), cs)
                                : trt::launch_sweep_batch(b->d_descs, b->d_items, b->nitems,
                                                          b->storage, b->mask, b->buf, (int)(k & 1),
                                                          (int)(k & 1), b->launch, cs);
@@ -1084,10 +1153,11 @@ static trt_status batch_capture(trt_batch *b, hipGraphExec_t &out, int64_t sweep
     });
 }
 
-// Two-step mode: class-1 members advance two steps per two-step launch,
+// Multi-step mode: class-1 members advance k2 steps per k2-step launch,
 // class-0 members by one-step sweeps, each class with its own lattice
 // parity (parity, parity2); graphs start and end at parities 0, 0.
 static trt_status batch_step_two(trt_batch *b, int64_t n) {
+    const int k2 = b->k2;
     auto single = [&]() -> trt_status {
         TRT_HIP(batch_single(b, b->parity, b->parity2, b->stream));
         b->parity ^= 1;
@@ -1097,22 +1167,24 @@ static trt_status batch_step_two(trt_batch *b, int64_t n) {
     };
     auto unit = [&]() -> trt_status {
         TRT_HIP(batch_unit(b, b->parity, b->parity2, b->stream));
+        b->parity ^= k2 & 1;
         b->parity2 ^= 1;
-        batch_sync_members(b, 2, 2, 1);
+        batch_sync_members(b, k2, k2, 1);
         return TRT_OK;
     };
-    // back to parities 0, 0: a single step flips both classes, a unit only
-    // class 1 (at most two launches)
+    // back to parities 0, 0: a single step flips both classes, a unit class
+    // 1 and, for odd k2, class 0 (at most two launches)
     while (n > 0 && (b->parity || b->parity2)) {
-        const bool one = b->parity || n == 1;
+        const bool unit_returns = (b->parity ^ (k2 & 1)) == 0 && (b->parity2 ^ 1) == 0;
+        const bool one = n < k2 || !unit_returns;
         trt_status st = one ? single() : unit();
         if (st != TRT_OK) return st;
-        n -= one ? 1 : 2;
+        n -= one ? 1 : k2;
     }
-    if (n >= 4) {
-        // graphs of 2, 4, ... units (4, 8, ... steps), each from and back to
-        // parities 0, 0
-        const int64_t units = n / 4 * 2;
+    if (n >= 2 * k2) {
+        // graphs of 2, 4, ... units (2 k2, 4 k2, ... steps), each from and
+        // back to parities 0, 0
+        const int64_t units = n / (2 * k2) * 2;
         trt_status rs = replay_ladder(
             units, std::max<int64_t>(2, b->launch.graph_steps / 2), b->graphs, b->stream,
             [&](int k) -> trt_status {
@@ -1120,15 +1192,19 @@ static trt_status batch_step_two(trt_batch *b, int64_t n) {
                 return batch_capture(b, b->graphs[k], (int64_t)2 << k);
             });
         if (rs != TRT_OK) return rs;
-        batch_sync_members(b, 2 * units, 2 * units, units);
-        n -= 2 * units;
+        batch_sync_members(b, k2 * units, k2 * units, units);
+        n -= k2 * units;
     }
-    if (n >= 2) {
+    if (n >= k2) {
         trt_status st = unit();
         if (st != TRT_OK) return st;
-        n -= 2;
+        n -= k2;
     }
-    if (n == 1) return single();
+    while (n > 0) {
+        trt_status st = single();
+        if (st != TRT_OK) return st;
+        --n;
+    }
     return TRT_OK;
 }
 

@@ -155,6 +155,11 @@ int tb3_waves_per_block(const InstDesc &d, const Launch &l);
 int tb3_prefetch_rows(const InstDesc &d, const Launch &l);
 hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launch &l,
                             hipStream_t stream);
+// Three time steps of the batch members named by items, as
+// launch_sweep_tb2_batch (descs tiled by tb3_desc; FP32 only).
+hipError_t launch_sweep_tb3_batch(const InstDesc *descs, int ndescs, const int4 *items,
+                                  int nitems, int storage, int flip, const Launch &l,
+                                  hipStream_t stream);
 
 // The access-pattern probe (a measurement aid): one launch moves the lattice
 // `src` to the other one with the two-column sweep's loads, stores, launch

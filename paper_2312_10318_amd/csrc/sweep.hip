@@ -1450,7 +1450,7 @@ __device__ __forceinline__ void collide_pair(C oa[9], C ob[9], const Coeffs<C> &
     reconstruct<C>(ob, b.base, b.bx, b.by, b.bxx, b.byy - ph * dyb, b.bxy, b.bxxy, b.bxyy);
 }
 
-template <int STAGE, bool UP = true>
+template <int STAGE, bool UP = true, bool SYNC = true>
 __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
                                         const PairCtx<float> &cx, const Tb2Lane &ln, bool odd,
                                         const Tb2Params &p, const BufAccess<float> &out, int y,
@@ -1535,13 +1535,14 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
-    __builtin_amdgcn_s_barrier();
+    if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
 // Three time steps over row block rb of window `strip` (FP32): as
 // sweep_strip_tb2, with ten pipeline rows of fill and the block's rows
-// y0 - 5 ... y1 + 4 gathered.
-template <int DEPTH, bool UP = true>
+// y0 - 5 ... y1 + 4 gathered.  SYNC: one workgroup barrier per pipeline
+// row; batch work items run without.
+template <int DEPTH, bool UP = true, bool SYNC = true>
 __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, int rb, int srcsel) {
     static_assert(DEPTH == 1 || DEPTH == 2, "loads one or two rows ahead");
     using T = float;
@@ -1591,24 +1592,24 @@ __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, in
         // both buffers named statically (a run-time index would move them
         // to scratch memory)
         if (DEPTH == 2 && (i & 1))
-            tb3_row<-1, UP>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
+            tb3_row<-1, UP, SYNC>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
                             plane, i >> 1);
         else
-            tb3_row<-1, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
+            tb3_row<-1, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
                             plane, i >> 1);
     }
     const auto inside = [&](int v) { return UP ? v < y1 : v >= y0; };
     if (DEPTH == 1) {
         for (; inside(y); y += dir)
-            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
     } else {
         for (; inside(y + dir); y += 2 * dir) {
-            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
-            tb3_row<5, UP>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir), lrow(y + dir),
+            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP, SYNC>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir), lrow(y + dir),
                            store, pitch, plane);
         }
         if (inside(y))
-            tb3_row<5, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
     }
 }
 
@@ -1668,6 +1669,25 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_kernel(InstDesc d
         const int y1 = min(y0 + d.rows, d.ny);
         for (int y = y0 - 10; y < y1; ++y) __builtin_amdgcn_s_barrier();
     }
+}
+
+// Batched three-step pass (FP32): wavefront w takes item w = (member,
+// window, row block, -) of the three-step tables; no barriers.
+__global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_batch_kernel(
+    const InstDesc *__restrict__ descs, int ndescs, const int4 *__restrict__ items, int nitems,
+    int flip, int remap) {
+    int b = blockIdx.x;
+    if (remap) b = xcd_remap(b, gridDim.x);
+    const int wpb = blockDim.x >> 6;
+    const int wave = b * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nitems) return;
+    const int4 it = items[wave];
+    if ((unsigned)it.x >= (unsigned)ndescs) return;
+    const InstDesc d = descs[it.x];
+    if (it.z & 1)
+        sweep_strip_tb3<1, false, false>(d, it.y, it.z, d.cur ^ flip);
+    else
+        sweep_strip_tb3<1, true, false>(d, it.y, it.z, d.cur ^ flip);
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -1905,6 +1925,12 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
     return hipGetLastError();
 }
 
+// Wavefronts from which the three-step pass takes four-wavefront
+// workgroups (4096^2 at 40 rows, 3708 wavefronts: 96.2 against 110.6 us per
+// step with one-wavefront workgroups; 2048^2 at 24 rows, 1548: 31.0
+// against 29.0).
+constexpr long long kTb3ManyWaves = 3584;
+
 bool tb3_eligible(const InstDesc &d, int storage) {
     return storage == ST_F32 && tb2_eligible(d, storage);
 }
@@ -1915,14 +1941,25 @@ InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
     if (l.rows_per_wave > 0) {
         t.rows = l.rows_per_wave;
     } else {
-        // the longest of 32, 24, 16, 12 or 8 rows that gives 6144
-        // wavefronts, else the longest that gives 2048, else 8
-        static const int kRows[] = {32, 24, 16, 12, 8};
+        // the longest of 48, 40, 32, 24 or 16 rows that gives 3584
+        // wavefronts (four-wavefront workgroups), else the longest of those
+        // and 12, 8 that gives 1536 (one-wavefront workgroups), else 8 (2048^2
+        // at 8 rows, 4608 wavefronts: 35.6 us per step against 29.0 at 24
+        // rows, one wavefront per workgroup).  A block of R rows
+        // repeats ten rows of fill, so blocks are longer than in the
+        // two-step pass.  Measured (us per step; chosen / best of rows 8 ...
+        // 64 x 1, 2, 4 wavefronts per workgroup): 8192^2 48 rows ~340 /
+        // 333.6, 6144^2 48 rows 211.5 / 211.5, 4096^2 40 rows 96.2 / 93.8
+        // (38 rows), 3000^2 16 rows 62.3 / 56.7, 2048^2 24 rows 29.0 / 27.6;
+        // the optimum moves with how evenly the workgroups fill the CUs,
+        // which the autotuner searches.
+        static const int kRows[] = {48, 40, 32, 24, 16, 12, 8};
         const auto waves = [&](int r) { return (long long)t.strips * ((d.ny + r - 1) / r); };
         t.rows = 8;
         bool found = false;
-        for (long long target : {6144LL, 2048LL}) {
+        for (long long target : {kTb3ManyWaves, 1536LL}) {
             for (int r : kRows) {
+                if (target == kTb3ManyWaves && r < 16) break;
                 if (waves(r) >= target) {
                     t.rows = r;
                     found = true;
@@ -1938,7 +1975,7 @@ InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
 
 int tb3_waves_per_block(const InstDesc &d, const Launch &l) {
     const InstDesc t = tb3_desc(d, l);
-    const bool many = (long long)t.strips * t.rowblocks >= kTb2DeepWaves;
+    const bool many = (long long)t.strips * t.rowblocks >= kTb3ManyWaves;
     int w = l.waves_per_block > 0 ? l.waves_per_block : (many ? 4 : 1);
     if (w > kTb2MaxWaves) w = kTb2MaxWaves;
     while (w > 1 && w / 2 >= t.strips) w /= 2;
@@ -1959,6 +1996,18 @@ hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launc
     // boundary's ten shared rows are read by both blocks at the same end
     // of their runs
     sweep_tb3_kernel<<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_tb3_batch(const InstDesc *descs, int ndescs, const int4 *items,
+                                  int nitems, int storage, int flip, const Launch &l,
+                                  hipStream_t stream) {
+    if (storage != ST_F32) return hipErrorInvalidValue;
+    if (nitems <= 0) return hipSuccess;
+    const int wpb = batch_waves_per_block(l);
+    const int blocks = (nitems + wpb - 1) / wpb;
+    sweep_tb3_batch_kernel<<<blocks, 64 * wpb, 0, stream>>>(descs, ndescs, items, nitems, flip,
+                                                            l.xcd_remap);
     return hipGetLastError();
 }
 

@@ -148,6 +148,12 @@ class Lattice:
         capi.trt_step(self.handle, int(nsteps))
         return self
 
+    def prepare(self, nsteps):
+        """Capture the step graphs that step(nsteps) would replay from the
+        current state, launching nothing."""
+        capi.trt_prepare_steps(self.handle, int(nsteps))
+        return self
+
     def pattern_probe(self, nsweeps=1):
         """Launches of the access-pattern probe (scrambles the state)."""
         capi.trt_pattern_probe(self.handle, int(nsweeps))

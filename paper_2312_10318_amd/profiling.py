@@ -111,14 +111,19 @@ def counter_values(pmc_dir, counter, kernel=None):
     return sweep, copy
 
 
-def _run_hash(log_path):
-    """The sweep source hash that `bench.py --profile` printed at run time."""
+def _run_record(log_path):
+    """The record `bench.py --profile` printed at run time."""
     with open(log_path) as fh:
         for line in fh:
             line = line.strip()
             if line.startswith("{") and '"profile"' in line:
-                return json.loads(line).get("source_hash")
+                return json.loads(line)
     raise ValueError("no profile record in " + log_path)
+
+
+def _run_hash(log_path):
+    """The sweep source hash that `bench.py --profile` printed at run time."""
+    return _run_record(log_path).get("source_hash")
 
 
 # Workloads of `bench.py --profile`: (title, name, link code bytes per node).
@@ -216,11 +221,18 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     if tuning:
         cmd += " --tuning " + tuning
         rec["launch_shape"] = tuning
+    if run_log and _run_record(run_log).get("launch"):
+        # (rows, wavefronts per workgroup, XCD remap, columns per lane, longest
+        # graph, time steps per launch, prefetch rows) in effect
+        rec["launch_in_effect"] = _run_record(run_log)["launch"]
     with open(out_prefix + "_hbm_counters.json", "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(out_prefix + ".md", "w") as fh:
         fh.write("# Fused sweep, %s, %s storage\n\n" % (label, storage))
         fh.write("Commands (run from the repository root, one profiler run each):\n\n")
+        if workload == "tg" and not tuning:
+            fh.write("    python3 bench.py --tune-only --storage %s --n %d   # the autotuner's "
+                     "launch shape, cached for the runs below\n" % (storage, n))
         fh.write("    rocprofv3 --kernel-trace --stats -f csv -d <T> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d <F> -o run -- %s\n" % cmd)
         fh.write("    rocprofv3 --pmc WRITE_SIZE --kernel-trace -f csv -d <W> -o run -- %s\n" % cmd)

@@ -29,6 +29,15 @@ def test_candidates_offer_two_steps_per_launch_where_it_applies():
         assert all(s[5] == 1 for s in autotune.candidates(*args)), args
 
 
+def test_candidates_offer_three_steps_per_launch_for_fp32():
+    three = [s for s in autotune.candidates(4096, 4096, False, "f32") if s[5] == 3]
+    assert {s[0] for s in three} == set(autotune.TB3_ROWS)
+    assert {s[1] for s in three} == {1, 2, 4} and {s[6] for s in three} == {1}
+    for args in ((4096, 4096, False, "f16"), (4096, 4096, True, "f32"),
+                 (4096, 4096, False, "f64")):
+        assert all(s[5] != 3 for s in autotune.candidates(*args)), args
+
+
 def test_candidates_respect_width_and_storage_limits():
     single = autotune.candidates(1025, 512, False, "f32")   # last strip: one column
     assert {s[3] for s in single if s[5] == 1} == {1}

@@ -34,10 +34,10 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("storage,sps", [("f64", 1), ("f32", 1), ("f32", 2)])
+@pytest.mark.parametrize("storage,sps", [("f64", 1), ("f32", 1), ("f32", 2), ("f32", 3)])
 def test_taylor_green_64_1000_steps(L, storage, sps):
     """Taylor-Green 64 x 64, u0 = 0.01, tau_s = 0.6, Lambda_s = 1/4 (Sec. III.B),
-    1000 steps, against the oracle (FP32: one and two time steps per
+    1000 steps, against the oracle (FP32: one, two and three time steps per
     launch)."""
     n, steps, tau1 = 64, 1000, 0.6
     tau2 = params.tau2_from_magic(tau1, 0.25)

@@ -314,11 +314,12 @@ def test_batch_autotune_leaves_members_untouched_and_results_unchanged(L):
         x.close()
 
 
-@pytest.mark.parametrize("sps", [1, 2])
+@pytest.mark.parametrize("sps", [1, 2, 3])
 def test_longer_step_graphs_are_bitwise_identical(L, sps):
     """Every graph ladder (longest graph 2, 8, 32 sweeps or the default)
     gives the same bits for any split of the steps, including splits that
-    start on the odd lattice, with one or two time steps per launch."""
+    start on the odd lattice, with one, two or three time steps per
+    launch."""
     n = 96
     rho, ux, uy = inputs.taylor_green(n, 0.02, seed=5)
     runs = {}
@@ -336,6 +337,29 @@ def test_longer_step_graphs_are_bitwise_identical(L, sps):
     ref = runs[(2, (37, 40))]
     for key, f in runs.items():
         assert np.array_equal(f, ref), key
+
+
+@pytest.mark.parametrize("sps", [1, 2, 3])
+def test_prepared_step_graphs_change_nothing(L, sps):
+    """trt_prepare_steps captures graphs only: state and time stay, and the
+    prepared steps give the bits of unprepared ones (from either lattice)."""
+    n = 96
+    rho, ux, uy = inputs.taylor_green(n, 0.02, seed=6)
+    out = []
+    for prep in (False, True):
+        lat = L.Lattice(n, n, 0.57, 1.9, storage="f32").init_equilibrium(rho, ux, uy)
+        lat.set_tuning(graph_steps=8, steps_per_sweep=sps)
+        for k in (29, 1, 40):
+            if prep:
+                before = _np(lat.get_populations()), lat.state()
+                lat.prepare(k)
+                assert lat.state() == before[1]
+                assert np.array_equal(_np(lat.get_populations()), before[0])
+            lat.step(k)
+        assert lat.state()[1] == 70
+        out.append(_np(lat.get_populations()))
+        lat.close()
+    assert np.array_equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("shape", [(0, 4, 0, 0, 16384, 2, 8), (0, 2, 1, 0, 32768, 1, 16),

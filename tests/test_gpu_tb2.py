@@ -93,7 +93,8 @@ def test_three_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
 
 def test_three_steps_per_launch_apply_to_fp32_alone(L):
     """FP16 lattices asked for three steps per launch take two, FP64 and
-    masked ones one; a batch of FP32 members takes two."""
+    masked ones one; a batch of FP32 members takes three by default (two
+    when asked), an FP16 batch two."""
     for storage, want in (("f32", 3), ("f16", 2), ("f64", 1)):
         lat = L.Lattice(256, 64, 0.7, 1.0, storage=storage)
         lat.set_tuning(steps_per_sweep=3)
@@ -105,13 +106,17 @@ def test_three_steps_per_launch_apply_to_fp32_alone(L):
     lat.set_tuning(steps_per_sweep=3)
     assert lat.tuning()[5] == 1
     lat.close()
-    lats = [L.Lattice(n, n, 0.7, 1.0, storage="f32") for n in (64, 130)]
-    b = L.Batch(lats)
-    b.set_tuning(steps_per_sweep=3)
-    assert b.tuning()[7] == 2
-    b.close()
-    for l in lats:
-        l.close()
+    for storage, want in (("f32", 3), ("f16", 2)):
+        lats = [L.Lattice(n, n, 0.7, 1.0, storage=storage) for n in (64, 130)]
+        b = L.Batch(lats)
+        assert b.tuning()[7] == want
+        b.set_tuning(steps_per_sweep=2)
+        assert b.tuning()[7] == 2
+        b.set_tuning(steps_per_sweep=3)
+        assert b.tuning()[7] == want and b.tuning()[8] == 1
+        b.close()
+        for l in lats:
+            l.close()
 
 
 # Launches of at least 4096 wavefronts load two rows ahead, and in FP32 their
@@ -152,6 +157,23 @@ def test_two_steps_per_launch_against_the_oracle(L):
     _, ur, vr = oracle.macros(fo, g[0], g[1])
     emax, el2 = rel_errors(u, v, ur, vr)
     say("case: two steps per launch %dx%d, %d steps vs oracle: rel max %.3e L2 %.3e"
+        % (nx, ny, steps, emax, el2))
+    assert emax <= TOL["f32"] and el2 <= TOL["f32"]
+
+
+def test_three_steps_per_launch_against_the_oracle(L):
+    nx, ny, steps = 256, 70, 42
+    f, g, tau1, tau2 = _state(4, nx, ny)
+    lat = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32").set_populations(f)
+    lat.set_tuning(steps_per_sweep=3)
+    assert lat.tuning()[5] == 3
+    lat.step(steps)
+    _, u, v = (_np(t) for t in lat.macros())
+    lat.close()
+    fo = oracle.run(stored_state(f, "f32"), steps, tau1, tau2, g[0], g[1])
+    _, ur, vr = oracle.macros(fo, g[0], g[1])
+    emax, el2 = rel_errors(u, v, ur, vr)
+    say("case: three steps per launch %dx%d, %d steps vs oracle: rel max %.3e L2 %.3e"
         % (nx, ny, steps, emax, el2))
     assert emax <= TOL["f32"] and el2 <= TOL["f32"]
 
@@ -198,46 +220,52 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
         lat.close()
 
 
-def test_two_steps_per_launch_is_the_default_and_reports_its_shape(L):
-    """Eligible lattices take two steps per launch unless asked for one; the
-    reported rows and wavefronts are the two-step pass's: 120-column windows
-    with the longest rows of 32 down to 8 that give 6144 wavefronts (else
-    2048), four-wavefront workgroups from 4096 wavefronts on, else one;
-    loads two rows ahead for FP32 launches from 4096 wavefronts on, else
-    one; an explicit request is kept (at most four wavefronts, no more than
-    the windows need)."""
-    cases = [((4096, 4096), (0, 0), "f32", (16, 4, 2)), ((4096, 4096), (0, 0), "f16", (16, 4, 1)),
-             ((8192, 8192), (0, 0), "f32", (32, 4, 2)), ((2048, 2048), (0, 0), "f32", (16, 1, 1)),
-             ((1024, 1024), (0, 0), "f32", (8, 1, 1)), ((256, 8), (0, 0), "f32", (8, 1, 1)),
-             ((4096, 64), (5, 16), "f32", (5, 4, 1)), ((240, 64), (16, 4), "f32", (16, 2, 1)),
-             ((4096, 4096), (0, 0, 1, 0, 0, 0, 1), "f32", (16, 4, 1)),
-             ((4096, 4096), (0, 0, 1, 0, 0, 0, 2), "f16", (16, 4, 2))]
+def test_steps_per_launch_default_and_reported_shape(L):
+    """Unless asked otherwise, FP32 lattices of at least 2048^2 nodes take
+    three steps per launch and other eligible ones two.  The reported rows,
+    wavefronts and prefetch rows are those of the pass in effect: two steps
+    -- 120-column windows, the longest rows of 32 down to 8 that give 6144
+    wavefronts (else 2048), four-wavefront workgroups from 4096 wavefronts
+    on, loads two rows ahead in FP32 from 4096 wavefronts on; three steps --
+    116-column windows, rows of 48 down to 8 for 3584 wavefronts (four per
+    workgroup; else 1536, one per workgroup), loads one row ahead; an
+    explicit request is kept (at most four wavefronts, no more than the
+    windows need)."""
+    cases = [((4096, 4096), (), "f32", (40, 4, 1, 3)), ((4096, 4096), (), "f16", (16, 4, 1, 2)),
+             ((8192, 8192), (), "f32", (48, 4, 1, 3)), ((2048, 2048), (), "f32", (24, 1, 1, 3)),
+             ((1024, 1024), (), "f32", (8, 1, 1, 2)), ((256, 8), (), "f32", (8, 1, 1, 2)),
+             ((4096, 64), (5, 16), "f32", (5, 4, 1, 2)), ((240, 64), (16, 4), "f32", (16, 2, 1, 2)),
+             ((4096, 4096), (0, 0, 1, 0, 0, 2), "f32", (16, 4, 2, 2)),
+             ((4096, 4096), (0, 0, 1, 0, 0, 2, 1), "f32", (16, 4, 1, 2)),
+             ((4096, 4096), (0, 0, 1, 0, 0, 0, 2), "f16", (16, 4, 2, 2)),
+             ((1024, 1024), (0, 0, 1, 0, 0, 3), "f32", (8, 1, 1, 3)),
+             ((4096, 4096), (32, 2, 1, 0, 0, 3, 2), "f32", (32, 2, 1, 3))]
     for (nx, ny), asked, storage, want in cases:
         lat = L.Lattice(nx, ny, 0.7, 1.0, storage=storage)
-        assert lat.tuning()[5] == 2
         lat.set_tuning(*asked)
         got = lat.tuning()
-        say("case: %dx%d %s asked %s -> rows %d waves %d prefetch %d"
-            % (nx, ny, storage, asked, got[0], got[1], got[6]))
-        assert (got[0], got[1], got[6], got[5]) == (*want, 2)
-        lat.set_tuning(*asked[:2], -1, 0, 0, 1)
+        say("case: %dx%d %s asked %s -> rows %d waves %d prefetch %d steps %d"
+            % (nx, ny, storage, asked, got[0], got[1], got[6], got[5]))
+        assert (got[0], got[1], got[6], got[5]) == want
+        rows, waves = (tuple(asked) + (0, 0))[:2]
+        lat.set_tuning(rows, waves, -1, 0, 0, 1)
         assert lat.tuning()[5] == 1 and lat.tuning()[6] == 0
         lat.close()
 
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_batch_two_step_members_equal_one_step_batches(L, storage):
-    """A batch whose members mix two-step members (even and odd widths)
-    with a one-step one (a mask) advances every member to the bits a
-    one-step batch gives, over odd and even splits, graph ladders and a
-    membership change; the batch reports two steps per launch only while a
-    member takes them."""
+@pytest.mark.parametrize("storage,ksteps", [("f32", 2), ("f16", 2), ("f32", 3)])
+def test_batch_two_step_members_equal_one_step_batches(L, storage, ksteps):
+    """A batch whose members mix k-step members (even and odd widths) with a
+    one-step one (a mask) advances every member to the bits a one-step
+    batch gives, over odd and even splits, graph ladders and a membership
+    change; the batch reports k steps per launch only while a member takes
+    them."""
     specs = [(64, 64), (200, 37), (97, 33), (128, 130), (131, 40), (250, 9), (66, 3)]
     mask = np.zeros((37, 200), np.uint8)
     mask[0] = 1
     runs = {}
-    for sps in (1, 2):
+    for sps in (1, ksteps):
         lats = []
         for k, (nx, ny) in enumerate(specs):
             f, g, tau1, tau2 = _state(100 + k, nx, ny)
@@ -260,10 +288,10 @@ def test_batch_two_step_members_equal_one_step_batches(L, storage):
         b.close()
         for m in lats:
             m.close()
-    for k, ((a, ta), (c, tc)) in enumerate(zip(runs[1], runs[2])):
-        say("case: batch member %d %s: time %d/%d, differs at %d entries"
-            % (k, storage, ta, tc, int(np.sum(a != c))))
-        assert ta == tc and np.array_equal(a, c), k
+    for j, ((a, ta), (c, tc)) in enumerate(zip(runs[1], runs[ksteps])):
+        say("case: batch member %d %s, %d steps per launch: time %d/%d, differs at %d entries"
+            % (j, storage, ksteps, ta, tc, int(np.sum(a != c))))
+        assert ta == tc and np.array_equal(a, c), j
     # only one-step members: the batch takes one step per launch
     wall = np.zeros((8, 64), np.uint8)
     wall[0] = 1

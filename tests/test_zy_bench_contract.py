@@ -42,12 +42,12 @@ def test_bench_prints_one_json_line_with_roofline_and_cpu_baseline():
     # achieved = 72 B per lattice update x nodes / time per step
     assert abs(roof["achieved"] - 72 * 4096 ** 2 / (rec["ms_per_step"] * 1e-3) / 1e9) \
         <= 1e-3 * roof["achieved"]
-    # two time steps per launch: the launch lasts two steps' time, and what
-    # HBM carries (when the committed counters match the source) stays below
-    # the peak
-    assert roof["updates_per_launch"] == 2 and roof["kernel"] == "sweep_tb2_kernel<f32>"
-    assert rec["config"]["launch"]["steps_per_sweep"] == 2
-    assert abs(roof["avg_duration_us"] - 2e3 * rec["ms_per_step"]) <= 2e-3 * roof["avg_duration_us"]
+    # three time steps per launch: the launch lasts three steps' time, and
+    # what HBM carries (when the committed counters match the source) stays
+    # below the peak
+    assert roof["updates_per_launch"] == 3 and roof["kernel"] == "sweep_tb3_kernel<f32>"
+    assert rec["config"]["launch"]["steps_per_sweep"] == 3
+    assert abs(roof["avg_duration_us"] - 3e3 * rec["ms_per_step"]) <= 2e-3 * roof["avg_duration_us"]
     if roof["traffic"] is not None:
         assert 0 < roof["traffic_frac"] < 1
     cpu = rec["cpu_baseline"]

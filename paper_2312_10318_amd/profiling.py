@@ -62,7 +62,7 @@ def _csv(d, suffix):
 def _is_sweep(name):
     return ("sweep_single_kernel" in name or "sweep_pair_kernel" in name or
             "sweep_tb2_kernel" in name or "sweep_tb2_batch_kernel" in name or
-            "sweep_tb3_kernel" in name or
+            "sweep_tb3_kernel" in name or "sweep_tb3_batch_kernel" in name or
             "sweep_batch_kernel" in name or
             "pattern_probe_kernel" in name)
 
@@ -132,7 +132,7 @@ WORKLOADS = {
     "creeping": ("creeping flow past a square cylinder (Sec. III.D), %dx%d, obstacle, "
                  "inflow wall and pressure outlet", "creeping_cylinder_%dx%d", 2),
     "batch": ("the 256-member batch (Taylor-Green and double-shear-layer members, sides "
-              "64 to 1024, %d nodes in all, one launch per step)", "batch256", 0),
+              "64 to 1024, %d nodes in all, the library's default batch shape)", "batch256", 0),
     "stream": ("access-pattern probe (the sweep's loads, stores, launch shape and barriers "
                "without its arithmetic) on the Taylor-Green lattice %dx%d",
                "pattern_probe_%dx%d", 0),
@@ -193,7 +193,7 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     alg = (BYTES_PER_LU[storage] + link_bytes) * nodes * ups
     dur = avg(sweep_ns) * 1e-9
     rec = {
-        "kernel": (re.search(r"(sweep_(single|pair|tb2_batch|tb2|tb3|batch)|pattern_probe)_kernel(<[^>]*>)?",
+        "kernel": (re.search(r"(sweep_(single|pair|tb2_batch|tb2|tb3_batch|tb3|batch)|pattern_probe)_kernel(<[^>]*>)?",
                              kname or "") or re.search(r".*", "sweep")).group(0),
         "workload": wlabel, "storage": storage, "nodes": nodes, "updates_per_launch": ups,
         "source_hash": _run_hash(run_log) if run_log else sweep_source_hash(),

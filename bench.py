@@ -528,7 +528,8 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
                 # the shape the benchmark runs in (bench.py --tune-only beforehand
                 # puts it in the tuner's cache, so no tuning runs under the profiler)
                 lat.set_tuning(*headline_shape(lat, n, storage)[0])
-        launch = list(lat.tuning())
+        if workload != "stream":   # the probe keeps the one-step sweep's tiling
+            launch = list(lat.tuning())
         if workload == "stream":
             # the sweep's access pattern without its arithmetic
             lat.pattern_probe(warmup + steps)

@@ -141,6 +141,7 @@ trt_status check_launch(const trt_tuning *t, Launch &l, const Launch &defaults) 
         if (t->xcd_remap != 0 && t->xcd_remap != 1)
             return fail(TRT_EINVAL, "xcd_remap must be -1, 0 or 1");
         l.xcd_remap = t->xcd_remap;
+        l.remap_asked = 1;
     }
     if (t->cols_per_lane != 0) {
         if (t->cols_per_lane != 1 && t->cols_per_lane != 2)
@@ -520,7 +521,7 @@ trt_status trt_get_tuning(const trt_sim *s, trt_tuning *t) {
         ks == 3   ? trt::tb3_waves_per_block(s->desc, s->launch)
         : ks == 2 ? trt::tb2_waves_per_block(s->desc, s->prob.storage, s->launch)
                   : trt::single_waves_per_block(s->desc, s->prob.storage, s->launch);
-    t->xcd_remap = s->launch.xcd_remap;
+    t->xcd_remap = ks == 3 ? trt::tb3_xcd_remap(s->desc, s->launch) : s->launch.xcd_remap;
     t->cols_per_lane = s->desc.cols;
     t->batch_items = 0;
     t->batch_order = 0;

@@ -22,6 +22,7 @@ struct Launch {
     int graph_steps;  // sweeps per captured graph (even)
     int steps_per_sweep;  // 2 or 3: time steps per launch where tb2_eligible / tb3_eligible
     int prefetch_rows;    // two-step pass: loads 1 or 2 rows ahead (0: automatic)
+    int remap_asked;      // xcd_remap was set by the caller (else the pass's default)
 };
 
 // Wavefronts per workgroup of a single-lattice sweep.  The one-column
@@ -153,6 +154,9 @@ bool tb3_eligible(const InstDesc &d, int storage);
 InstDesc tb3_desc(const InstDesc &d, const Launch &l);
 int tb3_waves_per_block(const InstDesc &d, const Launch &l);
 int tb3_prefetch_rows(const InstDesc &d, const Launch &l);
+// XCD remap of the three-step pass: as asked, else off from kTb3ManyWaves
+// wavefronts on and on below.
+int tb3_xcd_remap(const InstDesc &d, const Launch &l);
 hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launch &l,
                             hipStream_t stream);
 // Three time steps of the batch members named by items, as

@@ -1926,10 +1926,14 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
 }
 
 // Wavefronts from which the three-step pass takes four-wavefront
-// workgroups (4096^2 at 40 rows, 3708 wavefronts: 96.2 against 110.6 us per
-// step with one-wavefront workgroups; 2048^2 at 24 rows, 1548: 31.0
-// against 29.0).
-constexpr long long kTb3ManyWaves = 3584;
+// workgroups in the hardware's round-robin order over the XCDs (4096^2 at
+// 48 rows, 3096 wavefronts: 90.3 us per step, against 107.0 with
+// contiguous XCD bands and 107.7 with one-wavefront workgroups; 8192^2 and
+// 6144^2 at 48 rows: 338.9 / 204.1 against 345.6 / 211.4 with bands),
+// below it one-wavefront workgroups in contiguous bands (2048^2 at 24 rows,
+// 1548 wavefronts: 29.4 against 31.3 with four per workgroup and 30.8
+// without bands).
+constexpr long long kTb3ManyWaves = 3072;
 
 bool tb3_eligible(const InstDesc &d, int storage) {
     return storage == ST_F32 && tb2_eligible(d, storage);
@@ -1941,16 +1945,17 @@ InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
     if (l.rows_per_wave > 0) {
         t.rows = l.rows_per_wave;
     } else {
-        // the longest of 48, 40, 32, 24 or 16 rows that gives 3584
+        // the longest of 48, 40, 32, 24 or 16 rows that gives 3072
         // wavefronts (four-wavefront workgroups), else the longest of those
         // and 12, 8 that gives 1536 (one-wavefront workgroups), else 8 (2048^2
         // at 8 rows, 4608 wavefronts: 35.6 us per step against 29.0 at 24
         // rows, one wavefront per workgroup).  A block of R rows
         // repeats ten rows of fill, so blocks are longer than in the
         // two-step pass.  Measured (us per step; chosen / best of rows 8 ...
-        // 64 x 1, 2, 4 wavefronts per workgroup): 8192^2 48 rows ~340 /
-        // 333.6, 6144^2 48 rows 211.5 / 211.5, 4096^2 40 rows 96.2 / 93.8
-        // (38 rows), 3000^2 16 rows 62.3 / 56.7, 2048^2 24 rows 29.0 / 27.6;
+        // 64 x 1, 2, 4 wavefronts per workgroup x XCD order): 8192^2 48 rows
+        // 338.9 / 328.3 (64 rows), 6144^2 48 rows 204.1 / 203.6, 4096^2 48
+        // rows 90.3 / 90.3, 3000^2 24 rows 61.6 / 55.3 (40 rows, two
+        // wavefronts per workgroup), 2048^2 24 rows 29.4 / 28.0 (40 rows);
         // the optimum moves with how evenly the workgroups fill the CUs,
         // which the autotuner searches.
         static const int kRows[] = {48, 40, 32, 24, 16, 12, 8};
@@ -1971,6 +1976,12 @@ InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
     }
     t.rowblocks = (d.ny + t.rows - 1) / t.rows;
     return t;
+}
+
+int tb3_xcd_remap(const InstDesc &d, const Launch &l) {
+    if (l.remap_asked) return l.xcd_remap;
+    const InstDesc t = tb3_desc(d, l);
+    return (long long)t.strips * t.rowblocks >= kTb3ManyWaves ? 0 : 1;
 }
 
 int tb3_waves_per_block(const InstDesc &d, const Launch &l) {
@@ -1995,7 +2006,7 @@ hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launc
     // odd row blocks march down, as in the two-step pass: each block
     // boundary's ten shared rows are read by both blocks at the same end
     // of their runs
-    sweep_tb3_kernel<<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, 1);
+    sweep_tb3_kernel<<<blocks, 64 * wpb, 0, stream>>>(t, src, tb3_xcd_remap(d, l), 1);
     return hipGetLastError();
 }
 

@@ -227,12 +227,14 @@ def test_steps_per_launch_default_and_reported_shape(L):
     -- 120-column windows, the longest rows of 32 down to 8 that give 6144
     wavefronts (else 2048), four-wavefront workgroups from 4096 wavefronts
     on, loads two rows ahead in FP32 from 4096 wavefronts on; three steps --
-    116-column windows, rows of 48 down to 8 for 3584 wavefronts (four per
-    workgroup; else 1536, one per workgroup), loads one row ahead; an
+    116-column windows, rows of 48 down to 16 for 3072 wavefronts (four per
+    workgroup, XCD round-robin; else rows down to 8 for 1536, one per
+    workgroup, XCD bands), loads one row ahead; an
     explicit request is kept (at most four wavefronts, no more than the
     windows need)."""
-    cases = [((4096, 4096), (), "f32", (40, 4, 1, 3)), ((4096, 4096), (), "f16", (16, 4, 1, 2)),
+    cases = [((4096, 4096), (), "f32", (48, 4, 1, 3)), ((4096, 4096), (), "f16", (16, 4, 1, 2)),
              ((8192, 8192), (), "f32", (48, 4, 1, 3)), ((2048, 2048), (), "f32", (24, 1, 1, 3)),
+             ((3000, 3000), (), "f32", (24, 4, 1, 3)),
              ((1024, 1024), (), "f32", (8, 1, 1, 2)), ((256, 8), (), "f32", (8, 1, 1, 2)),
              ((4096, 64), (5, 16), "f32", (5, 4, 1, 2)), ((240, 64), (16, 4), "f32", (16, 2, 1, 2)),
              ((4096, 4096), (0, 0, 1, 0, 0, 2), "f32", (16, 4, 2, 2)),
@@ -247,6 +249,8 @@ def test_steps_per_launch_default_and_reported_shape(L):
         say("case: %dx%d %s asked %s -> rows %d waves %d prefetch %d steps %d"
             % (nx, ny, storage, asked, got[0], got[1], got[6], got[5]))
         assert (got[0], got[1], got[6], got[5]) == want
+        if not asked and want[3] == 3:
+            assert got[2] == (0 if want[1] == 4 else 1)   # XCD order of the three-step pass
         rows, waves = (tuple(asked) + (0, 0))[:2]
         lat.set_tuning(rows, waves, -1, 0, 0, 1)
         assert lat.tuning()[5] == 1 and lat.tuning()[6] == 0

@@ -83,7 +83,7 @@ def test_create_rejects_bad_buffers(lib):
 def test_null_handles_are_rejected(lib):
     for fn, args in [(lib.trt_step, (None, 1)), (lib.trt_macros, (None, None, None, None)),
                      (lib.trt_diagnostics, (None, None)), (lib.trt_batch_step, (None, 1)),
-                     (lib.trt_check, (None,))]:
+                     (lib.trt_check, (None,)), (lib.trt_prepare_steps, (None, 6))]:
         assert fn(*args) == capi.TRT_EINVAL
     out = ctypes.c_void_p()
     assert lib.trt_batch_create(0, None, ctypes.byref(out)) == capi.TRT_EINVAL

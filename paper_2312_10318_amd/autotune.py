@@ -51,13 +51,20 @@ def load_cache(path: str | None = None) -> dict:
         return {}
 
 
-def save_cache(cache: dict, path: str | None = None) -> None:
+def save_cache(cache: dict, path: str | None = None) -> bool:
+    """Write the cache atomically; False (and nothing raised) where the
+    cache location is not writable -- tuning results then last for the
+    process only."""
     path = path or cache_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
-    tmp = path + ".tmp%d" % os.getpid()
-    with open(tmp, "w") as fh:
-        json.dump(cache, fh, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        return False
+    return True
 
 
 def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):

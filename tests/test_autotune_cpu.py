@@ -84,3 +84,14 @@ def test_batch_candidates_and_key():
     assert a != autotune.batch_key([(64, 64), (1000, 1000)], "f32", False)
     assert a != autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f16", False)
     assert a != autotune.batch_key([(64, 64), (1000, 1000), (1024, 1024)], "f32", True)
+
+
+def test_cache_round_trip_and_unwritable_location(tmp_path):
+    path = str(tmp_path / "sub" / "tune.json")
+    assert autotune.save_cache({"k": {"best": [1, 2]}}, path)
+    assert autotune.load_cache(path) == {"k": {"best": [1, 2]}}
+    blocker = tmp_path / "file"
+    blocker.write_text("x")
+    # a directory that cannot be created (a file is in the way): no exception
+    assert autotune.save_cache({"k": 1}, str(blocker / "tune.json")) is False
+    assert autotune.load_cache(str(blocker / "tune.json")) == {}

@@ -25,7 +25,32 @@ COLS = (1, 2)
 TB2_ROWS = (8, 12, 16, 20, 24, 30, 32, 37, 48, 64)  # two time steps per launch
 TB2_WAVES = (1, 2, 4)
 TB2_PREFETCH = (1, 2)  # rows ahead of their use that the two-step loads run
-TB3_ROWS = (8, 12, 16, 20, 24, 32, 38, 40, 48, 64)  # three time steps per launch (FP32)
+TB3_ROWS = (8, 12, 16, 20, 24, 32, 38, 40, 48, 64, 96)  # three time steps per launch (FP32)
+TB2_VALID, TB3_VALID = 120, 116  # columns a wavefront stores in the two- and three-step passes
+SIMDS = 1024  # 256 CUs x 4 SIMDs
+
+
+def whole_round_rows(nx: int, ny: int, valid: int, waves_per_block: int,
+                     resident_per_simd: int, rounds=(1, 2, 3)):
+    """Rows per wavefront that make the workgroups of a multi-step pass fill
+    the machine in whole rounds: for k rounds, the shortest rows whose
+    workgroup count (row blocks x window groups) is at most k times the
+    workgroups resident at once (SIMDs x wavefronts per SIMD / wavefronts
+    per workgroup).  The measured optimum often sits at such a count (4096^2,
+    three steps per launch: 74 rows, 504 workgroups of 512 resident, 87.6
+    us per step against 91.0 at 48 rows)."""
+    windows = (nx + valid - 1) // valid
+    groups = (windows + waves_per_block - 1) // waves_per_block
+    slots = SIMDS * resident_per_simd // waves_per_block
+    out = set()
+    for k in rounds:
+        blocks = k * slots // groups
+        if blocks < 1:
+            continue
+        r = (ny + blocks - 1) // blocks
+        if 8 <= r <= 512:
+            out.add(r)
+    return sorted(out)
 
 
 def cache_path() -> str:
@@ -94,11 +119,27 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
                 for x in REMAP:
                     for p in TB2_PREFETCH:
                         out.append((r, w, x, 2, 0, 2, p))
+        # FP32 loading two rows ahead keeps two wavefronts per SIMD, else three
+        for w in TB2_WAVES:
+            for p in TB2_PREFETCH:
+                per = 2 if (storage == "f32" and p == 2) or storage == "f64" else 3
+                for r in whole_round_rows(nx, ny, TB2_VALID, w, per):
+                    if r in TB2_ROWS:
+                        continue
+                    for x in REMAP:
+                        out.append((r, w, x, 2, 0, 2, p))
     if storage == "f32" and not has_mask:
         for r in TB3_ROWS:
             if r > max(8, ny):
                 continue
             for w in TB2_WAVES:
+                for x in REMAP:
+                    out.append((r, w, x, 2, 0, 3, 1))
+        # two wavefronts per SIMD (238 VGPRs)
+        for w in TB2_WAVES:
+            for r in whole_round_rows(nx, ny, TB3_VALID, w, 2):
+                if r in TB3_ROWS:
+                    continue
                 for x in REMAP:
                     out.append((r, w, x, 2, 0, 3, 1))
     return out

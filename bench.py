@@ -47,10 +47,14 @@ def log(msg):
 def time_steps(lat, steps, warmup):
     """Average time per step (ms) over `steps` steps after `warmup` steps."""
     import torch
+    # the step graphs the warm-up and the timed steps replay are captured
+    # first (for the timed steps from either lattice the warm-up may end on),
+    # so the warm-up runs right before the timed region and no host-side
+    # capture falls between them or in it
+    lat.prepare(warmup)
+    for n in (steps - 1, steps, steps + 1):
+        lat.prepare(max(n, 0))
     lat.step(warmup)
-    # the step graphs the timed steps replay are captured beforehand, so
-    # no host-side capture falls in the timed region
-    lat.prepare(steps)
     torch.cuda.synchronize()
     with torch.cuda.stream(lat.stream):
         start = torch.cuda.Event(enable_timing=True)

@@ -45,7 +45,9 @@
  *    device arrays [ny][nx] (populations: [9][ny][nx]), x fastest.
  *  - The mask, when present, is a device uint8 array [ny][nx]; nonzero marks
  *    a solid node.  Solid nodes are never collided; their rho, u and f read
- *    back as 0 and they contribute nothing to diagnostics.
+ *    back as 0 and they contribute nothing to diagnostics.  A mask whose
+ *    solid nodes fill whole rows (walls parallel to x, as the channels of
+ *    Sec. III.C) lets FP32 simulations take several steps per launch.
  */
 #ifndef TRTLBM_H
 #define TRTLBM_H
@@ -144,9 +146,10 @@ typedef struct {
                                 FP16).  k steps per launch move each
                                 population through HBM once per k steps and give the bits of
                                 k one-step sweeps.  Two apply to FP32 and FP16 simulations,
-                                alone or in a batch, without a mask or open boundaries; three
-                                to such FP32 simulations, alone or in an FP32 batch; elsewhere
-                                sweeps take fewer steps.  With
+                                alone or in a batch, without a mask or open boundaries, and
+                                to FP32 ones whose mask's solid nodes fill whole rows (x
+                                periodic); three to such FP32 simulations, alone or in an FP32
+                                batch; elsewhere sweeps take fewer steps.  With
                                 two or three steps per launch, rows_per_wave and
                                 waves_per_block shape that pass (cols_per_lane the one-step
                                 sweeps of leftover steps). */
@@ -196,7 +199,12 @@ size_t trt_footprint_bytes(const trt_problem *p);
  * next.  The problem (including the mask pointer) is copied; the mask memory
  * must stay valid while the simulation exists, and its contents must not
  * change (the sweep reads the link map derived from it on the stream at
- * creation).  EINVAL on a NULL or
+ * creation).  The mask must hold its contents when trt_create is called:
+ * with periodic x it is also read at once, on a stream of the library's own
+ * (created at the first such call per device, kept until the process
+ * ends), and waited for there, to find whether its solid nodes fill whole
+ * rows -- so creation does not wait for the work queued on hip_stream.
+ * EINVAL on a NULL or
  * misaligned pointer, a size out of range, tau_s <= 1/2, tau_s2 < 1/2 or a
  * non-finite parameter.  With a mask or open x boundaries the link map
  * (2 * ny * (nx rounded up to 128) bytes) must stay below 4 GiB, which
@@ -338,10 +346,10 @@ trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
 
 /* Advance every member nsteps steps (replays of captured graphs of batched
  * launches as for trt_step, plus at most a few plain launches).  With
- * trt_tuning.steps_per_sweep = 2 (the default), members that allow it (FP32
- * or FP16, no mask or open boundaries) advance two steps per launch and the
- * others by one-step sweeps in the same graphs; every member gets the bits
- * it gets alone. */
+ * the default steps_per_sweep, members that allow it (FP32 or FP16 without
+ * a mask or open boundaries; FP32 with walls that fill whole rows) advance
+ * three (FP32) or two (FP16) steps per launch and the others by one-step
+ * sweeps in the same graphs; every member gets the bits it gets alone. */
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps);
 
 /* Diagnostics of every member into device out[n][TRT_NDIAG]. */

@@ -72,6 +72,13 @@ def load():
         raise ImportError("libtrtlbm.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2312_10318_amd.build); the TRT-RLB path has no "
                           "fallback")
+    # PyTorch ships its own HIP runtime under the same soname: it is loaded
+    # first, so that the library binds to it (a second HIP runtime in the
+    # process would find no GPU once the first has opened it)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     PP = ctypes.POINTER(ctypes.c_void_p)

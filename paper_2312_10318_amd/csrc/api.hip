@@ -408,6 +408,46 @@ size_t link_alloc_bytes(int32_t nx, int32_t ny) {
 }  // namespace
 
 namespace {
+// The library's own stream on the current device (non-blocking, default
+// priority, kept until the process ends): the mask check of trt_create runs
+// and waits there, so creating a simulation does not wait for the work
+// queued on the caller's stream.
+hipError_t own_stream(hipStream_t &out) {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    out = streams[dev];
+    return hipSuccess;
+}
+
+// rows = 1 when every row of the problem's mask is all solid or all fluid
+// (walls parallel to x): the mask is read on the library's own stream, with
+// `scratch` (at least one int) for the device flag.
+hipError_t mask_in_rows(const trt_problem *p, void *scratch, int32_t &rows) {
+    rows = 0;
+    hipStream_t st = nullptr;
+    hipError_t e = own_stream(st);
+    if (e != hipSuccess) return e;
+    int *flag = static_cast<int *>(scratch);
+    int mixed = 1;
+    e = trt::launch_mask_rows(p->mask, p->nx, p->ny, flag, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&mixed, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && mixed == 0) rows = 1;
+    return e;
+}
+
 // The descriptor of a problem over the lattices f_a, f_b (no link map yet;
 // tiled for the default launch shape by the caller).
 void fill_desc(InstDesc &d, const trt_problem *p, void *f_a, void *f_b) {
@@ -434,7 +474,7 @@ void fill_desc(InstDesc &d, const trt_problem *p, void *f_a, void *f_b) {
     d.lpitch = link_pitch(p->nx);
     d.rowsum = nullptr;
     d.nsum = summary_count(p->nx);
-    d.pad3_ = 0;
+    d.rowwalls = 0;
 }
 }  // namespace
 
@@ -489,6 +529,15 @@ trt_status trt_create(const trt_problem *p, void *f_a, void *f_b, void *hip_stre
             (void)hipFree(s->scratch);
             delete s;
             return fail_hip(e, "link map");
+        }
+    }
+    if (p->mask != nullptr && d.xbc == 0) {
+        e = mask_in_rows(p, s->scratch, d.rowwalls);
+        if (e != hipSuccess) {
+            (void)hipFree(s->links);
+            (void)hipFree(s->scratch);
+            delete s;
+            return fail_hip(e, "mask check");
         }
     }
     trt::tile(d, s->launch, p->storage);

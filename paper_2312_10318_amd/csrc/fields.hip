@@ -403,6 +403,20 @@ __global__ void link_summary_kernel(InstDesc d, const uint16_t *__restrict__ lin
     sum[(int64_t)y * d.nsum + s] = acc;
 }
 
+// Whether the mask's solid nodes fill whole rows: one wavefront per row
+// compares every node with the row's first, and a row that differs sets
+// *mixed (every writer stores the same 1).
+__global__ void mask_rows_kernel(const uint8_t *__restrict__ mask, int nx, int ny,
+                                 int *__restrict__ mixed) {
+    const int y = blockIdx.x;
+    if (y >= ny) return;
+    const uint8_t *row = mask + (int64_t)y * nx;
+    const bool first = row[0] != 0;
+    bool diff = false;
+    for (int x = (int)threadIdx.x; x < nx; x += 64) diff |= (row[x] != 0) != first;
+    if (__builtin_amdgcn_ballot_w64(diff) != 0 && threadIdx.x == 0) *mixed = 1;
+}
+
 dim3 node_grid(const InstDesc &d) { return dim3((d.nx + 63) / 64, (d.ny + 3) / 4); }
 
 #define TRT_DISPATCH(storage, CALL)                 \
@@ -421,6 +435,13 @@ hipError_t launch_link_map(const InstDesc &d, hipStream_t stream) {
     if (e != hipSuccess) return e;
     link_summary_kernel<<<dim3((d.nsum + 63) / 64, d.ny), 64, 0, stream>>>(
         d, d.links, const_cast<uint32_t *>(d.rowsum));
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_rows(const uint8_t *mask, int nx, int ny, int *mixed, hipStream_t stream) {
+    hipError_t e = hipMemsetAsync(mixed, 0, sizeof(int), stream);
+    if (e != hipSuccess) return e;
+    mask_rows_kernel<<<ny, 64, 0, stream>>>(mask, nx, ny, mixed);
     return hipGetLastError();
 }
 

@@ -179,6 +179,10 @@ hipError_t launch_pattern_probe(const InstDesc &d, int storage, int src, const L
 // d.rowsum receives the link summary (see InstDesc).
 hipError_t launch_link_map(const InstDesc &d, hipStream_t stream);
 
+// *mixed (device int) = 0 when every row of the dense [ny][nx] mask is all
+// solid or all fluid, else 1.
+hipError_t launch_mask_rows(const uint8_t *mask, int nx, int ny, int *mixed, hipStream_t stream);
+
 // Pre-collision state <-> device FP64 [9][ny][nx]; f^eq initialisation.
 hipError_t launch_set_populations(const InstDesc &d, int storage, int src, const double *f,
                                   hipStream_t stream);

@@ -77,7 +77,11 @@ struct InstDesc {
     // pulls and halo need no link step in that row.  nsum is even, so a
     // 128-column strip k reads entries 2k and 2k + 1.
     const uint32_t *rowsum;
-    int32_t nsum, pad3_;
+    int32_t nsum;
+    // 1: every row of the mask is all solid or all fluid (walls parallel to
+    // x) and x is periodic; a row's state is then bit 0 of its first
+    // summary entry, and FP32 passes of several steps apply
+    int32_t rowwalls;
     // population lattice layout [y][i][x]: f_i of node (x, y) is element
     // y * pitch + i * plane + x
     int64_t plane;        // elements between populations i and i+1 of a node

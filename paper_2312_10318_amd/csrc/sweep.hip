@@ -531,7 +531,10 @@ __device__ __forceinline__ void gather_pair_row(PairRow<T> &r, const PairCtx<T> 
 // nodes' moments and Phi.
 // HALVES (FP16 storage without a link map or open boundaries): the words are
 // shifted across lanes whole and the moments summed from their FP16 halves.
-template <class T, class C, bool SHIFTED, bool HALVES = false>
+// WALLS (passes of several steps over whole-row walls, row flags in r.rs as
+// set by tb2_gather): populations bounced at a solid row below or above
+// were loaded from the node's own slots and take no shift in x.
+template <class T, class C, bool SHIFTED, bool HALVES = false, bool WALLS = false>
 __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, SHIFTED> &b,
                                            const PairRow<T> &r, const PairCtx<T> &c, C gx, C gy,
                                            const OpenX<C> &ox) {
@@ -607,6 +610,17 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
     fa[6] = c.tail ? h1 : pb[6]; fb[6] = dpp_shl(h1, pa[6]);
     fa[7] = c.tail ? h2 : pb[7]; fb[7] = dpp_shl(h2, pa[7]);
     a.solid = b.solid = false;
+    if constexpr (WALLS) {
+        if (r.rs & 2u) {
+            fa[5] = pa[5]; fb[5] = pb[5];
+            fa[6] = pa[6]; fb[6] = pb[6];
+        }
+        if (r.rs & 4u) {
+            fa[7] = pa[7]; fb[7] = pb[7];
+            fa[8] = pa[8]; fb[8] = pb[8];
+        }
+        a.solid = b.solid = (r.rs & 1u) != 0;
+    }
     if (c.linked && r.rs != 0u) {
         // only rows that touch a wall or an obstacle pay for the link codes
         const uint32_t la_ = r.lk & 0xffffu, lb_ = r.lk >> 16;
@@ -885,11 +899,20 @@ template <class C> struct MidWindow {
     C mid[6];  // one row behind: populations 0, 1, 3 and those streaming forward
 };
 
-template <class C, bool UP = true>
-__device__ __forceinline__ void mid_shift(MidWindow<C> &w, const C f[9]) {
+// WALLS, solid_mid: the row leaving the middle is a solid row, so the new
+// middle row's pull bounces the populations it would take from it; lo then
+// keeps the new middle row's own populations that come back (4, 7, 8 up the
+// march, 2, 5, 6 down it) in the slots of those they replace.
+template <class C, bool UP = true, bool WALLS = false>
+__device__ __forceinline__ void mid_shift(MidWindow<C> &w, const C f[9], bool solid_mid = false) {
     w.lo[0] = w.mid[3];
     w.lo[1] = w.mid[4];
     w.lo[2] = w.mid[5];
+    if constexpr (WALLS) {
+        w.lo[0] = solid_mid ? f[UP ? 4 : 2] : w.lo[0];
+        w.lo[1] = solid_mid ? f[UP ? 7 : 5] : w.lo[1];
+        w.lo[2] = solid_mid ? f[UP ? 8 : 6] : w.lo[2];
+    }
     w.mid[0] = f[0];
     w.mid[1] = f[1];
     w.mid[2] = f[3];
@@ -903,10 +926,15 @@ __device__ __forceinline__ void mid_shift(MidWindow<C> &w, const C f[9]) {
 // row (s, sf) and those of its left (x - 1: l, lf) and right (x + 1: r, rf)
 // neighbours: 0, 1, 3 from the middle row, the populations streaming
 // forward from the row behind, the others from the fresh row ahead.
-template <class C, bool UP = true>
+// WALLS: behind (ahead) the row behind (ahead) is solid, and the populations
+// it would give come back from the node's own slots (half-way bounce-back):
+// those of the row ahead from the node's window (mid[3..5]), those of the
+// row behind from lo (kept there by mid_shift), with no shift in x.
+template <class C, bool UP = true, bool WALLS = false>
 __device__ __forceinline__ void mid_pull(C f[9], const MidWindow<C> &s, const C sf[9],
                                          const MidWindow<C> &l, const C lf[9],
-                                         const MidWindow<C> &r, const C rf[9]) {
+                                         const MidWindow<C> &r, const C rf[9],
+                                         bool behind = false, bool ahead = false) {
     f[0] = s.mid[0];
     f[1] = l.mid[1];
     f[3] = r.mid[2];
@@ -925,15 +953,34 @@ __device__ __forceinline__ void mid_pull(C f[9], const MidWindow<C> &s, const C 
         f[5] = lf[5];
         f[6] = rf[6];
     }
+    if constexpr (WALLS) {
+        if (UP) {
+            f[5] = behind ? s.lo[1] : f[5];
+            f[6] = behind ? s.lo[2] : f[6];
+            f[4] = ahead ? s.mid[3] : f[4];
+            f[7] = ahead ? s.mid[4] : f[7];
+            f[8] = ahead ? s.mid[5] : f[8];
+        } else {
+            f[7] = behind ? s.lo[1] : f[7];
+            f[8] = behind ? s.lo[2] : f[8];
+            f[2] = ahead ? s.mid[3] : f[2];
+            f[5] = ahead ? s.mid[4] : f[5];
+            f[6] = ahead ? s.mid[5] : f[6];
+        }
+    }
 }
 
-// Moments, Phi_x and Phi_y of one node from its populations, as widen().
+// Moments, Phi_x and Phi_y of one node from its populations, as widen()
+// (Phi 0 at a solid node).
 template <class C, bool SHIFTED>
-__device__ __forceinline__ void node_state(RowState<C, SHIFTED> &st, const C f[9], C gx, C gy) {
-    st.solid = false;
+__device__ __forceinline__ void node_state(RowState<C, SHIFTED> &st, const C f[9], C gx, C gy,
+                                           bool solid = false) {
+    st.solid = solid;
     st.m.compute(f, gx, gy);
-    st.phix = st.m.rho * st.m.ux * st.m.ux * st.m.ux;
-    st.phiy = st.m.rho * st.m.uy * st.m.uy * st.m.uy;
+    const C px = st.m.rho * st.m.ux * st.m.ux * st.m.ux;
+    const C py = st.m.rho * st.m.uy * st.m.uy * st.m.uy;
+    st.phix = solid ? C(0) : px;
+    st.phiy = solid ? C(0) : py;
 }
 
 // A lane's pair in a window: the columns ca (node A) and cb (node B, the
@@ -969,11 +1016,58 @@ template <> struct Tb2Word<_Float16> {
     }
 };
 
+// Walls that fill whole rows (InstDesc::rowwalls): a row is solid when
+// bit 0 of its first link-summary entry is set (scalar loads).
+struct RowWalls {
+    RowSum sum;
+    int ny;
+    __device__ __forceinline__ explicit RowWalls(const InstDesc &d)
+        : sum(d.rowsum, d.nsum), ny(d.ny) {}
+    __device__ __forceinline__ uint32_t solid(int y) const { return sum.one(y, 0) & 1u; }
+    // the pull flags of row y (0 <= y < ny): bit 0 the row is solid, bit 1
+    // the row below it (y - 1, wrapped), bit 2 the row above it (y + 1)
+    __device__ __forceinline__ uint32_t flags(int y) const {
+        const int ym = y == 0 ? ny - 1 : y - 1;
+        const int yp = y == ny - 1 ? 0 : y + 1;
+        return solid(y) | (solid(ym) << 1) | (solid(yp) << 2);
+    }
+};
+
 // One row of a lane's pair for the pull (as gather_pair_row), split lanes
-// element by element.
-template <class T>
+// element by element.  WALLS: wf holds the row's flags (RowWalls::flags,
+// kept in r.rs); next to a solid row below, populations 2, 5, 6 come back
+// from the node's own slots 4, 7, 8 (half-way bounce-back), next to one
+// above 4, 7, 8 from 2, 5, 6, so those loads read the row itself.
+template <class T, bool WALLS = false>
 __device__ __forceinline__ void tb2_gather(PairRow<T> &r, const PairCtx<T> &c, const Tb2Lane &ln,
-                                           bool odd, int y) {
+                                           bool odd, int y, uint32_t wf = 0u) {
+    if constexpr (WALLS) {
+        const int ym = (y == 0) ? c.ny - 1 : y - 1;
+        const int yp = (y == c.ny - 1) ? 0 : y + 1;
+        const int64_t e0 = (int64_t)y * c.pitch, em = (int64_t)ym * c.pitch,
+                      ep = (int64_t)yp * c.pitch;
+        const int64_t pl = c.plane;
+        const bool below = (wf & 2u) != 0, above = (wf & 4u) != 0;
+        const int64_t o[9] = {e0,
+                              pl + e0,
+                              below ? 4 * pl + e0 : 2 * pl + em,
+                              3 * pl + e0,
+                              above ? 2 * pl + e0 : 4 * pl + ep,
+                              below ? 7 * pl + e0 : 5 * pl + em,
+                              below ? 8 * pl + e0 : 6 * pl + em,
+                              above ? 5 * pl + e0 : 7 * pl + ep,
+                              above ? 6 * pl + e0 : 8 * pl + ep};
+        r.lk = 0u;
+        r.rs = wf;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r.w[i] = PairIO<T>::ld(c.in, o[i], c.opair);
+        r.edge[0] = r.edge[1] = r.edge[2] = T(0);
+        if (odd && ln.split) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) r.w[i] = Tb2Word<T>::get(c.in, o[i], ln);
+        }
+        return;
+    }
     gather_pair_row<T, false>(r, c, y, 0u);
     if (odd && ln.split) {
         const int ym = (y == 0) ? c.ny - 1 : y - 1;
@@ -993,6 +1087,24 @@ __device__ __forceinline__ void tb2_gather(PairRow<T> &r, const PairCtx<T> &c, c
     }
 }
 
+// The pull flags (pull_coeffs_pair) of the row at bit j of a pipeline's
+// wall bits sb (bit j + 1 the row behind it in the march, bit j - 1 the row
+// ahead).
+__device__ __forceinline__ uint32_t wall_flags(uint32_t sb, int j) {
+    return ((sb >> j) & 1u) | (((sb >> (j + 1)) & 1u) << 1) | (((sb >> (j - 1)) & 1u) << 2);
+}
+
+// A solid row keeps zeros (its slots are never read), as in the one-step
+// sweep.
+template <class C>
+__device__ __forceinline__ void solid_zero(C a[9], C b[9], uint32_t solid) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        a[i] = solid ? C(0) : a[i];
+        b[i] = solid ? C(0) : b[i];
+    }
+}
+
 template <class C> struct Tb2Carry {
     Coeffs<C> kA, kB;     // first step: coefficients of the next row to collide
     C pyA, pyB;           // ... its Phi_y
@@ -1000,6 +1112,7 @@ template <class C> struct Tb2Carry {
     MidWindow<C> wA, wB;  // first-step results in flight
     Coeffs<C> qA, qB;     // second step: coefficients of the next row to store
     C qyA, qyB, qbelA, qbelB;
+    uint32_t sb;          // whole-row walls: bit j, row y + (2 - j) dir solid
 };
 
 struct Tb2Params {
@@ -1011,11 +1124,13 @@ struct Tb2Params {
 // step's post-collision rows and that step's freshly collided row (oa, ob):
 // the pull (x neighbours by DPP lane shifts), the moments and the Phi_x
 // gradient, as the one-step sweep forms them.
-template <class C, bool SH, bool UP>
+// WALLS: wf bit 0 the row is solid, bit 1 the row behind it (in the
+// march's order), bit 2 the row ahead.
+template <class C, bool SH, bool UP, bool WALLS = false>
 __device__ __forceinline__ void pull_coeffs_pair(Coeffs<C> &ckA, Coeffs<C> &ckB, C &cyA, C &cyB,
                                                  const MidWindow<C> &wA, const MidWindow<C> &wB,
                                                  const C oa[9], const C ob[9],
-                                                 const Tb2Params &p) {
+                                                 const Tb2Params &p, uint32_t wf = 0u) {
     const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
     C fa[9], fb[9];
     MidWindow<C> lw, rw;
@@ -1030,7 +1145,8 @@ __device__ __forceinline__ void pull_coeffs_pair(Coeffs<C> &ckA, Coeffs<C> &ckB,
         lw.lo[2] = dpp_shr(C(0), wB.lo[2]);
         lf[5] = dpp_shr(C(0), ob[5]);
     }
-    mid_pull<C, UP>(fa, wA, oa, lw, lf, wB, ob);
+    const bool behind = (wf & 2u) != 0, ahead = (wf & 4u) != 0, solid = (wf & 1u) != 0;
+    mid_pull<C, UP, WALLS>(fa, wA, oa, lw, lf, wB, ob, behind, ahead);
     // node B: x + 2 is the next lane's node A (3, 6 and 7)
     rw.mid[2] = dpp_shl(C(0), wA.mid[2]);
     if (UP) {
@@ -1040,10 +1156,10 @@ __device__ __forceinline__ void pull_coeffs_pair(Coeffs<C> &ckA, Coeffs<C> &ckB,
         rw.lo[1] = dpp_shl(C(0), wA.lo[1]);
         rf[6] = dpp_shl(C(0), oa[6]);
     }
-    mid_pull<C, UP>(fb, wB, ob, wA, oa, rw, rf);
+    mid_pull<C, UP, WALLS>(fb, wB, ob, wA, oa, rw, rf, behind, ahead);
     RowState<C, SH> cA, cB;
-    node_state<C, SH>(cA, fa, gx, gy);
-    node_state<C, SH>(cB, fb, gx, gy);
+    node_state<C, SH>(cA, fa, gx, gy, WALLS && solid);
+    node_state<C, SH>(cB, fb, gx, gy, WALLS && solid);
     const C left = dpp_shr(C(0), cB.phix);
     const C right = dpp_shl(C(0), cA.phix);
     ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
@@ -1057,11 +1173,14 @@ __device__ __forceinline__ void pull_coeffs_pair(Coeffs<C> &ckA, Coeffs<C> &ckB,
 // (when `load`), (c) from STAGE 1 the first-step collision of row y + 2,
 // (d) from STAGE 2 the second-step pull of row y + 1 and its coefficients,
 // (e) at STAGE 3 the second-step collision and store of row y.
-template <int STAGE, class T, class C, bool SH, bool SYNC = true, bool UP = true>
+// WALLS: whole-row walls; lflags are the flags of row yload (RowWalls).
+template <int STAGE, class T, class C, bool SH, bool SYNC = true, bool UP = true,
+          bool WALLS = false>
 __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const PairCtx<T> &cx,
                                         const Tb2Lane &ln, bool odd, const Tb2Params &p,
                                         const BufAccess<T> &out, int y, bool load, int yload,
-                                        bool store, int pitch, int64_t plane, int stage = STAGE) {
+                                        bool store, int pitch, int64_t plane, int stage = STAGE,
+                                        uint32_t lflags = 0u) {
     const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
     OpenX<C> ox;
     ox.on = false;
@@ -1070,10 +1189,12 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     // (b) row y + 3, then (a) the next loads into the same registers
     C nyA, nyB;
     Coeffs<C> nkA, nkB;
+    // whole-row walls: bit j, row y + (3 - j) dir solid
+    const uint32_t sb = WALLS ? ((k.sb << 1) | (raw.rs & 1u)) : 0u;
     {
         RowState<C, SH> nA, nB;
-        widen_pair<T, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
-        if (load) tb2_gather<T>(raw, cx, ln, odd, yload);
+        widen_pair<T, C, SH, false, WALLS>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) tb2_gather<T, WALLS>(raw, cx, ln, odd, yload, lflags);
         const C left = dpp_shr(C(0), nB.phix);
         const C right = dpp_shl(C(0), nA.phix);
         nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
@@ -1096,20 +1217,22 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     C cyA = C(0), cyB = C(0);
     Coeffs<C> ckA, ckB;
     if (stage >= 2)
-        pull_coeffs_pair<C, SH, UP>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p);
+        pull_coeffs_pair<C, SH, UP, WALLS>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p,
+                                           wall_flags(sb, 2));
     // (e) collide row y of the second step and store the window's middle
     if (stage >= 3) {
         const C dya = C(0.5) * (UP ? cyA - k.qbelA : k.qbelA - cyA);
         const C dyb = C(0.5) * (UP ? cyB - k.qbelB : k.qbelB - cyB);
-        C sa[9], sb[9];
+        C sa[9], sb_[9];
         reconstruct<C>(sa, k.qA.base, k.qA.bx, k.qA.by, k.qA.bxx, k.qA.byy - ph * dya, k.qA.bxy,
                        k.qA.bxxy, k.qA.bxyy);
-        reconstruct<C>(sb, k.qB.base, k.qB.bx, k.qB.by, k.qB.bxx, k.qB.byy - ph * dyb, k.qB.bxy,
+        reconstruct<C>(sb_, k.qB.base, k.qB.bx, k.qB.by, k.qB.bxx, k.qB.byy - ph * dyb, k.qB.bxy,
                        k.qB.bxxy, k.qB.bxyy);
+        if (WALLS) solid_zero<C>(sa, sb_, (sb >> 3) & 1u);
         if (store) {
             const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, sa[i], sb[i]);
+            for (int i = 0; i < 9; ++i) PairIO<T>::st(out, i * plane + e0, cx.opair, sa[i], sb_[i]);
         }
     }
     // advance the pipeline by one row
@@ -1122,8 +1245,9 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
         k.qB = ckB;
     }
     if (stage >= 1) {
-        mid_shift<C, UP>(k.wA, oa);
-        mid_shift<C, UP>(k.wB, ob);
+        const bool smid = WALLS && ((sb >> 2) & 1u);
+        mid_shift<C, UP, WALLS>(k.wA, oa, smid);
+        mid_shift<C, UP, WALLS>(k.wB, ob, smid);
     }
     k.belA = k.pyA;
     k.belB = k.pyB;
@@ -1131,6 +1255,7 @@ __device__ __forceinline__ void tb2_row(Tb2Carry<C> &k, PairRow<T> &raw, const P
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
+    if (WALLS) k.sb = sb;
     if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
@@ -1275,26 +1400,28 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
 template <int ST> struct Tb2Rows;
 template <> struct Tb2Rows<ST_F32> {
     using Carry = Tb2Carry<float>;
-    template <int STAGE, bool SYNC, bool UP>
+    template <int STAGE, bool SYNC, bool UP, bool WALLS>
     __device__ static __forceinline__ void row(Carry &k, PairRow<float> &raw,
                                                const PairCtx<float> &cx, const Tb2Lane &ln,
                                                bool odd, const Tb2Params &p,
                                                const BufAccess<float> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
-                                               int stage = STAGE) {
-        tb2_row<STAGE, float, float, true, SYNC, UP>(k, raw, cx, ln, odd, p, out, y, load, yload,
-                                                     store, pitch, plane, stage);
+                                               int stage = STAGE, uint32_t lflags = 0u) {
+        tb2_row<STAGE, float, float, true, SYNC, UP, WALLS>(k, raw, cx, ln, odd, p, out, y, load,
+                                                            yload, store, pitch, plane, stage,
+                                                            lflags);
     }
 };
 template <> struct Tb2Rows<ST_F16> {
     using Carry = Tb2CarryH;
-    template <int STAGE, bool SYNC, bool UP>
+    template <int STAGE, bool SYNC, bool UP, bool WALLS>
     __device__ static __forceinline__ void row(Carry &k, PairRow<_Float16> &raw,
                                                const PairCtx<_Float16> &cx, const Tb2Lane &ln,
                                                bool odd, const Tb2Params &p,
                                                const BufAccess<_Float16> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
-                                               int stage = STAGE) {
+                                               int stage = STAGE, uint32_t = 0u) {
+        static_assert(!WALLS, "whole-row walls: FP32 storage only");
         tb2_row_h<STAGE, SYNC, UP>(k, raw, cx, ln, odd, p, out, y, load, yload, store, pitch,
                                    plane, stage);
     }
@@ -1307,7 +1434,8 @@ template <> struct Tb2Rows<ST_F16> {
 // per pipeline row (adjacent windows in step); batch work items run
 // without.  UP: the march goes up the row block (rows y0 - 6 ... y1 - 1 as
 // pipeline rows), else down it (y1 + 5 ... y0), every node computed alike.
-template <int ST, int DEPTH, bool SYNC = true, bool UP = true>
+// WALLS: the lattice's solid nodes fill whole rows (InstDesc::rowwalls).
+template <int ST, int DEPTH, bool SYNC = true, bool UP = true, bool WALLS = false>
 __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, int rb, int srcsel) {
     using T = typename Store<ST>::T;
     using R = Tb2Rows<ST>;
@@ -1348,40 +1476,49 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
         return UP ? y + 3 + DEPTH <= y1 + 2 : y - 3 - DEPTH >= y0 - 3;
     };
     const auto lrow = [&](int y) { return wrap_row(y + dir * (3 + DEPTH)); };
+    // the wall flags of a row to load (0 without walls)
+    const auto wfl = [&](int row) -> uint32_t {
+        if constexpr (WALLS) return RowWalls(d).flags(row);
+        return 0u;
+    };
+    const auto lfl = [&](int y) -> uint32_t { return ld(y) ? wfl(lrow(y)) : 0u; };
 
     typename R::Carry k{};
     PairRow<T> raw[DEPTH];
     const int ys = UP ? y0 - 6 : y1 + 5;  // the first pipeline row
-    tb2_gather<T>(raw[0], cx, ln, odd, wrap_row(ys + 3 * dir));
-    if (DEPTH == 2) tb2_gather<T>(raw[DEPTH - 1], cx, ln, odd, wrap_row(ys + 4 * dir));
+    tb2_gather<T, WALLS>(raw[0], cx, ln, odd, wrap_row(ys + 3 * dir), wfl(wrap_row(ys + 3 * dir)));
+    if (DEPTH == 2)
+        tb2_gather<T, WALLS>(raw[DEPTH - 1], cx, ln, odd, wrap_row(ys + 4 * dir),
+                             wfl(wrap_row(ys + 4 * dir)));
     constexpr int R1 = DEPTH - 1;
     int y = ys;
     for (int i = 0; i < 6; ++i, y += dir) {
         // both buffers named statically (a run-time index would move them
         // to scratch memory)
         if (DEPTH == 2 && (i & 1))
-            R::template row<-1, SYNC, UP>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
-                                          pitch, plane, i >> 1);
+            R::template row<-1, SYNC, UP, WALLS>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y),
+                                                 store, pitch, plane, i >> 1, lfl(y));
         else
-            R::template row<-1, SYNC, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
-                                          pitch, plane, i >> 1);
+            R::template row<-1, SYNC, UP, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y),
+                                                 store, pitch, plane, i >> 1, lfl(y));
     }
     // the rows of the block, y0 ... y1 - 1 in the march's order
     const auto inside = [&](int v) { return UP ? v < y1 : v >= y0; };
     if (DEPTH == 1) {
         for (; inside(y); y += dir)
-            R::template row<3, SYNC, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
-                                         pitch, plane);
+            R::template row<3, SYNC, UP, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y),
+                                                store, pitch, plane, 3, lfl(y));
     } else {
         for (; inside(y + dir); y += 2 * dir) {
-            R::template row<3, SYNC, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
-                                         pitch, plane);
-            R::template row<3, SYNC, UP>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir),
-                                         lrow(y + dir), store, pitch, plane);
+            R::template row<3, SYNC, UP, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y),
+                                                store, pitch, plane, 3, lfl(y));
+            R::template row<3, SYNC, UP, WALLS>(k, raw[R1], cx, ln, odd, p, out, y + dir,
+                                                ld(y + dir), lrow(y + dir), store, pitch, plane, 3,
+                                                lfl(y + dir));
         }
         if (inside(y))
-            R::template row<3, SYNC, UP>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
-                                         pitch, plane);
+            R::template row<3, SYNC, UP, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y),
+                                                store, pitch, plane, 3, lfl(y));
     }
 }
 
@@ -1439,6 +1576,7 @@ template <class C> struct Tb3Carry {
     MidWindow<C> vA, vB;  // second-step results in flight
     Coeffs<C> rA, rB;     // third step: the next row to collide and store
     C ryA, ryB, rbelA, rbelB;
+    uint32_t sb;          // whole-row walls: bit j, row y + (4 - j) dir solid
 };
 
 // Post-collision populations of a lane's pair from their coefficients and
@@ -1450,12 +1588,13 @@ __device__ __forceinline__ void collide_pair(C oa[9], C ob[9], const Coeffs<C> &
     reconstruct<C>(ob, b.base, b.bx, b.by, b.bxx, b.byy - ph * dyb, b.bxy, b.bxxy, b.bxyy);
 }
 
-template <int STAGE, bool UP = true, bool SYNC = true>
+// WALLS: whole-row walls; lflags are the flags of row yload (RowWalls).
+template <int STAGE, bool UP = true, bool SYNC = true, bool WALLS = false>
 __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
                                         const PairCtx<float> &cx, const Tb2Lane &ln, bool odd,
                                         const Tb2Params &p, const BufAccess<float> &out, int y,
                                         bool load, int yload, bool store, int pitch,
-                                        int64_t plane, int stage = STAGE) {
+                                        int64_t plane, int stage = STAGE, uint32_t lflags = 0u) {
     using C = float;
     constexpr bool SH = true;
     const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
@@ -1468,10 +1607,12 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
     // (b) row y + 5, then (a) the next loads into the same registers
     C nyA, nyB;
     Coeffs<C> nkA, nkB;
+    // whole-row walls: bit j, row y + (5 - j) dir solid
+    const uint32_t sb = WALLS ? ((k.sb << 1) | (raw.rs & 1u)) : 0u;
     {
         RowState<C, SH> nA, nB;
-        widen_pair<float, C, SH, false>(nA, nB, raw, cx, gx, gy, ox);
-        if (load) tb2_gather<float>(raw, cx, ln, odd, yload);
+        widen_pair<float, C, SH, false, WALLS>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) tb2_gather<float, WALLS>(raw, cx, ln, odd, yload, lflags);
         const C left = dpp_shr(C(0), nB.phix);
         const C right = dpp_shl(C(0), nA.phix);
         nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
@@ -1485,18 +1626,24 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
     // (d) second-step pull and coefficients of row y + 3
     C cyA = C(0), cyB = C(0);
     Coeffs<C> ckA, ckB;
-    if (stage >= 2) pull_coeffs_pair<C, SH, UP>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p);
+    if (stage >= 2)
+        pull_coeffs_pair<C, SH, UP, WALLS>(ckA, ckB, cyA, cyB, k.wA, k.wB, oa, ob, p,
+                                           wall_flags(sb, 2));
     // (e) second-step collision of row y + 2
-    C sa[9], sb[9];
-    if (stage >= 3) collide_pair<C>(sa, sb, k.qA, grad(cyA, k.qbelA), k.qB, grad(cyB, k.qbelB), ph);
+    C sa[9], sb_[9];
+    if (stage >= 3)
+        collide_pair<C>(sa, sb_, k.qA, grad(cyA, k.qbelA), k.qB, grad(cyB, k.qbelB), ph);
     // (f) third-step pull and coefficients of row y + 1
     C ryA = C(0), ryB = C(0);
     Coeffs<C> rkA, rkB;
-    if (stage >= 4) pull_coeffs_pair<C, SH, UP>(rkA, rkB, ryA, ryB, k.vA, k.vB, sa, sb, p);
+    if (stage >= 4)
+        pull_coeffs_pair<C, SH, UP, WALLS>(rkA, rkB, ryA, ryB, k.vA, k.vB, sa, sb_, p,
+                                           wall_flags(sb, 4));
     // (g) third-step collision of row y and the store of the window's middle
     if (stage >= 5) {
         C ta[9], tb[9];
         collide_pair<C>(ta, tb, k.rA, grad(ryA, k.rbelA), k.rB, grad(ryB, k.rbelB), ph);
+        if (WALLS) solid_zero<C>(ta, tb, (sb >> 5) & 1u);
         if (store) {
             const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
@@ -1514,8 +1661,9 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
         k.rB = rkB;
     }
     if (stage >= 3) {
-        mid_shift<C, UP>(k.vA, sa);
-        mid_shift<C, UP>(k.vB, sb);
+        const bool smid = WALLS && ((sb >> 4) & 1u);
+        mid_shift<C, UP, WALLS>(k.vA, sa, smid);
+        mid_shift<C, UP, WALLS>(k.vB, sb_, smid);
     }
     if (stage >= 2) {
         k.qbelA = k.qyA;
@@ -1526,8 +1674,9 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
         k.qB = ckB;
     }
     if (stage >= 1) {
-        mid_shift<C, UP>(k.wA, oa);
-        mid_shift<C, UP>(k.wB, ob);
+        const bool smid = WALLS && ((sb >> 2) & 1u);
+        mid_shift<C, UP, WALLS>(k.wA, oa, smid);
+        mid_shift<C, UP, WALLS>(k.wB, ob, smid);
     }
     k.belA = k.pyA;
     k.belB = k.pyB;
@@ -1535,6 +1684,7 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
+    if (WALLS) k.sb = sb;
     if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
@@ -1542,7 +1692,7 @@ __device__ __forceinline__ void tb3_row(Tb3Carry<float> &k, PairRow<float> &raw,
 // sweep_strip_tb2, with ten pipeline rows of fill and the block's rows
 // y0 - 5 ... y1 + 4 gathered.  SYNC: one workgroup barrier per pipeline
 // row; batch work items run without.
-template <int DEPTH, bool UP = true, bool SYNC = true>
+template <int DEPTH, bool UP = true, bool SYNC = true, bool WALLS = false>
 __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, int rb, int srcsel) {
     static_assert(DEPTH == 1 || DEPTH == 2, "loads one or two rows ahead");
     using T = float;
@@ -1580,36 +1730,47 @@ __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, in
         return UP ? y + 5 + DEPTH <= y1 + 4 : y - 5 - DEPTH >= y0 - 5;
     };
     const auto lrow = [&](int y) { return wrap_row(y + dir * (5 + DEPTH)); };
+    // the wall flags of a row to load (0 without walls)
+    const auto wfl = [&](int row) -> uint32_t {
+        if constexpr (WALLS) return RowWalls(d).flags(row);
+        return 0u;
+    };
+    const auto lfl = [&](int y) -> uint32_t { return ld(y) ? wfl(lrow(y)) : 0u; };
 
     Tb3Carry<float> k{};
     PairRow<T> raw[DEPTH];
     const int ys = UP ? y0 - 10 : y1 + 9;  // the first pipeline row
-    tb2_gather<T>(raw[0], cx, ln, odd, wrap_row(ys + 5 * dir));
-    if (DEPTH == 2) tb2_gather<T>(raw[DEPTH - 1], cx, ln, odd, wrap_row(ys + 6 * dir));
+    tb2_gather<T, WALLS>(raw[0], cx, ln, odd, wrap_row(ys + 5 * dir), wfl(wrap_row(ys + 5 * dir)));
+    if (DEPTH == 2)
+        tb2_gather<T, WALLS>(raw[DEPTH - 1], cx, ln, odd, wrap_row(ys + 6 * dir),
+                             wfl(wrap_row(ys + 6 * dir)));
     constexpr int R1 = DEPTH - 1;
     int y = ys;
     for (int i = 0; i < 10; ++i, y += dir) {
         // both buffers named statically (a run-time index would move them
         // to scratch memory)
         if (DEPTH == 2 && (i & 1))
-            tb3_row<-1, UP, SYNC>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
-                            plane, i >> 1);
+            tb3_row<-1, UP, SYNC, WALLS>(k, raw[R1], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
+                                         pitch, plane, i >> 1, lfl(y));
         else
-            tb3_row<-1, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch,
-                            plane, i >> 1);
+            tb3_row<-1, UP, SYNC, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
+                                         pitch, plane, i >> 1, lfl(y));
     }
     const auto inside = [&](int v) { return UP ? v < y1 : v >= y0; };
     if (DEPTH == 1) {
         for (; inside(y); y += dir)
-            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP, SYNC, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
+                                        pitch, plane, 5, lfl(y));
     } else {
         for (; inside(y + dir); y += 2 * dir) {
-            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
-            tb3_row<5, UP, SYNC>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir), lrow(y + dir),
-                           store, pitch, plane);
+            tb3_row<5, UP, SYNC, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
+                                        pitch, plane, 5, lfl(y));
+            tb3_row<5, UP, SYNC, WALLS>(k, raw[R1], cx, ln, odd, p, out, y + dir, ld(y + dir),
+                                        lrow(y + dir), store, pitch, plane, 5, lfl(y + dir));
         }
         if (inside(y))
-            tb3_row<5, UP, SYNC>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store, pitch, plane);
+            tb3_row<5, UP, SYNC, WALLS>(k, raw[0], cx, ln, odd, p, out, y, ld(y), lrow(y), store,
+                                        pitch, plane, 5, lfl(y));
     }
 }
 
@@ -1619,7 +1780,7 @@ __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, in
 // barriers of its row block.  FP32: DEPTH 1 fits 168 VGPRs (three
 // wavefronts per SIMD), DEPTH 2 210 (two); FP16: 133 (three) and 171 (two).
 constexpr int kTb2MaxWaves = 4;
-template <int ST, int DEPTH>
+template <int ST, int DEPTH, bool WALLS = false>
 __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d, int srcsel,
                                                                       int remap,
                                                                       int alternate) {
@@ -1636,9 +1797,9 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d
         // (both at the start or both at the end) and the second read can
         // hit in L2
         if (alternate && (rb & 1))
-            sweep_strip_tb2<ST, DEPTH, true, false>(d, strip, rb, srcsel);
+            sweep_strip_tb2<ST, DEPTH, true, false, WALLS>(d, strip, rb, srcsel);
         else
-            sweep_strip_tb2<ST, DEPTH, true, true>(d, strip, rb, srcsel);
+            sweep_strip_tb2<ST, DEPTH, true, true, WALLS>(d, strip, rb, srcsel);
     } else {
         const int y0 = rb * d.rows;
         const int y1 = min(y0 + d.rows, d.ny);
@@ -1648,7 +1809,8 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_kernel(InstDesc d
 
 // Three time steps per pass: workgroups as for two (sweep_tb2_kernel), R +
 // 10 barriers per row block; loads one row ahead (238 VGPRs, two wavefronts
-// per SIMD).
+// per SIMD).  WALLS: whole-row walls (InstDesc::rowwalls).
+template <bool WALLS>
 __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_kernel(InstDesc d, int srcsel,
                                                                       int remap,
                                                                       int alternate) {
@@ -1661,9 +1823,9 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_kernel(InstDesc d
     const int strip = (b - rb * groups) * wpb + w;
     if (strip < d.strips) {
         if (alternate && (rb & 1))
-            sweep_strip_tb3<1, false>(d, strip, rb, srcsel);
+            sweep_strip_tb3<1, false, true, WALLS>(d, strip, rb, srcsel);
         else
-            sweep_strip_tb3<1, true>(d, strip, rb, srcsel);
+            sweep_strip_tb3<1, true, true, WALLS>(d, strip, rb, srcsel);
     } else {
         const int y0 = rb * d.rows;
         const int y1 = min(y0 + d.rows, d.ny);
@@ -1672,7 +1834,8 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_kernel(InstDesc d
 }
 
 // Batched three-step pass (FP32): wavefront w takes item w = (member,
-// window, row block, -) of the three-step tables; no barriers.
+// window, row block, -) of the three-step tables; no barriers.  Members
+// with whole-row walls take the walled pipeline.
 __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_batch_kernel(
     const InstDesc *__restrict__ descs, int ndescs, const int4 *__restrict__ items, int nitems,
     int flip, int remap) {
@@ -1684,10 +1847,17 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb3_batch_kernel(
     const int4 it = items[wave];
     if ((unsigned)it.x >= (unsigned)ndescs) return;
     const InstDesc d = descs[it.x];
-    if (it.z & 1)
-        sweep_strip_tb3<1, false, false>(d, it.y, it.z, d.cur ^ flip);
-    else
-        sweep_strip_tb3<1, true, false>(d, it.y, it.z, d.cur ^ flip);
+    if (d.rowwalls) {
+        if (it.z & 1)
+            sweep_strip_tb3<1, false, false, true>(d, it.y, it.z, d.cur ^ flip);
+        else
+            sweep_strip_tb3<1, true, false, true>(d, it.y, it.z, d.cur ^ flip);
+    } else {
+        if (it.z & 1)
+            sweep_strip_tb3<1, false, false>(d, it.y, it.z, d.cur ^ flip);
+        else
+            sweep_strip_tb3<1, true, false>(d, it.y, it.z, d.cur ^ flip);
+    }
 }
 
 template <int ST, bool MASK, bool BUF>
@@ -1740,6 +1910,12 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_batch_kernel(
     const int4 it = items[wave];
     if ((unsigned)it.x >= (unsigned)ndescs) return;
     const InstDesc d = descs[it.x];
+    if constexpr (ST == ST_F32) {
+        if (d.rowwalls) {
+            sweep_strip_tb2<ST, DEPTH, false, true, true>(d, it.y, it.z, d.cur ^ flip);
+            return;
+        }
+    }
     sweep_strip_tb2<ST, DEPTH, false>(d, it.y, it.z, d.cur ^ flip);
 }
 
@@ -1819,9 +1995,13 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
     }
 }
 
+// Passes of several steps: FP32 or FP16 lattices, periodic, without a mask
+// -- or FP32 ones whose solid nodes fill whole rows (walls parallel to x).
 bool tb2_eligible(const InstDesc &d, int storage) {
-    return (storage == ST_F32 || storage == ST_F16) && d.links == nullptr && d.xbc == 0 &&
-           d.mask == nullptr && buffer_addressable(d, storage);
+    const bool open = d.links == nullptr && d.mask == nullptr;
+    const bool walls = storage == ST_F32 && d.rowwalls != 0 && d.links != nullptr;
+    return (storage == ST_F32 || storage == ST_F16) && (open || walls) && d.xbc == 0 &&
+           buffer_addressable(d, storage);
 }
 
 // Wavefronts from which the two-step pass uses four-wavefront workgroups
@@ -1917,6 +2097,11 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
             sweep_tb2_kernel<ST_F16, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
         else
             sweep_tb2_kernel<ST_F16, 1><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
+    } else if (t.rowwalls) {
+        if (deep)
+            sweep_tb2_kernel<ST_F32, 2, true><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
+        else
+            sweep_tb2_kernel<ST_F32, 1, true><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
     } else if (deep) {
         sweep_tb2_kernel<ST_F32, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
     } else {
@@ -2006,7 +2191,10 @@ hipError_t launch_sweep_tb3(const InstDesc &d, int storage, int src, const Launc
     // odd row blocks march down, as in the two-step pass: each block
     // boundary's ten shared rows are read by both blocks at the same end
     // of their runs
-    sweep_tb3_kernel<<<blocks, 64 * wpb, 0, stream>>>(t, src, tb3_xcd_remap(d, l), 1);
+    if (t.rowwalls)
+        sweep_tb3_kernel<true><<<blocks, 64 * wpb, 0, stream>>>(t, src, tb3_xcd_remap(d, l), 1);
+    else
+        sweep_tb3_kernel<false><<<blocks, 64 * wpb, 0, stream>>>(t, src, tb3_xcd_remap(d, l), 1);
     return hipGetLastError();
 }
 

@@ -18,6 +18,19 @@ def _torch():
     return torch
 
 
+_UPLOAD = {}
+
+
+def _upload_stream(device):
+    """A side stream per device (default priority) for uploads that must be
+    complete before a library call."""
+    torch = _torch()
+    key = str(device)
+    if key not in _UPLOAD:
+        _UPLOAD[key] = torch.cuda.Stream(device)
+    return _UPLOAD[key]
+
+
 def problem(nx, ny, tau_s, tau_s2, g=(0.0, 0.0), storage="f32", mask_ptr=None, inflow=None):
     """The C problem struct (no device memory touched).  inflow = (u_in,
     rho_in, rho_out) selects the open x boundaries (inflow wall, outlet)."""
@@ -64,8 +77,14 @@ class Lattice:
             m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
             if m.shape != (self.ny, self.nx):
                 raise ValueError("mask must have shape [ny, nx]")
-            with torch.cuda.stream(self.stream):
+            # trt_create reads the mask (on a stream of its own), so its copy
+            # must be complete by then: it goes up on a side stream, which is
+            # waited for alone (not the work queued on the lattice's stream)
+            up = _upload_stream(self.device)
+            with torch.cuda.stream(up):
                 self.mask = torch.from_numpy(m).pin_memory().to(self.device, non_blocking=True)
+            up.synchronize()
+            self.mask.record_stream(self.stream)
         self.inflow = None if inflow is None else tuple(float(v) for v in inflow)
         prob = problem(self.nx, self.ny, self.tau_s, self.tau_s2, self.g, storage,
                        self.mask.data_ptr() if self.mask is not None else None, self.inflow)

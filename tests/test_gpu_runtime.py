@@ -425,3 +425,26 @@ def test_pattern_probe_moves_the_pull_rows(L, storage):
         else:
             assert np.array_equal(got, want), i
     lat.close()
+
+
+def test_library_loaded_before_torch_uses_its_runtime():
+    """A process that loads the library (a footprint query) before it first
+    uses PyTorch still steps a lattice: the library binds to the HIP runtime
+    PyTorch ships, not to a second one that would find no GPU."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2312_10318_amd import lattice\n"
+            "assert lattice.footprint_bytes(64, 64, 'f32', has_mask=True) > 0\n"
+            "import numpy as np\n"
+            "m = np.zeros((16, 64), np.uint8); m[0] = 1\n"
+            "lat = lattice.Lattice(64, 16, 0.7, 1.0, storage='f32', mask=m)\n"
+            "lat.step(5)\n"
+            "print('steps', lat.state()[1], flush=True)\n"
+            "lat.close()\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=90)
+    say("case: library before torch: rc %d, %s" % (r.returncode, r.stdout.strip()))
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "steps 5" in r.stdout

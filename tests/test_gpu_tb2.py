@@ -92,8 +92,9 @@ def test_three_steps_per_launch_equal_one_step_sweeps(L, nx, ny, tiling):
 
 
 def test_three_steps_per_launch_apply_to_fp32_alone(L):
-    """FP16 lattices asked for three steps per launch take two, FP64 and
-    masked ones one; a batch of FP32 members takes three by default (two
+    """FP16 lattices asked for three steps per launch take two, FP64 ones
+    and masked ones whose solid nodes do not fill whole rows one (FP32 wall
+    rows take three); a batch of FP32 members takes three by default (two
     when asked), an FP16 batch two."""
     for storage, want in (("f32", 3), ("f16", 2), ("f64", 1)):
         lat = L.Lattice(256, 64, 0.7, 1.0, storage=storage)
@@ -102,10 +103,11 @@ def test_three_steps_per_launch_apply_to_fp32_alone(L):
         lat.close()
     mask = np.zeros((64, 256), np.uint8)
     mask[0] = mask[-1] = 1
-    lat = L.Lattice(256, 64, 0.7, 1.0, storage="f32", mask=mask)
-    lat.set_tuning(steps_per_sweep=3)
-    assert lat.tuning()[5] == 1
-    lat.close()
+    for m, want in ((mask, 3), (np.roll(mask, 1, axis=1) * (np.arange(256) > 3), 1)):
+        lat = L.Lattice(256, 64, 0.7, 1.0, storage="f32", mask=m)
+        lat.set_tuning(steps_per_sweep=3)
+        assert lat.tuning()[5] == want
+        lat.close()
     for storage, want in (("f32", 3), ("f16", 2)):
         lats = [L.Lattice(n, n, 0.7, 1.0, storage=storage) for n in (64, 130)]
         b = L.Batch(lats)
@@ -198,8 +200,8 @@ def test_two_steps_per_launch_fp16_one_launch_against_the_oracle(L):
 
 
 def test_two_steps_per_launch_applies_only_where_eligible(L):
-    """FP64 storage and masks keep one step per launch (and say so); every
-    width takes two."""
+    """FP64 storage and masks keep one step per launch (and say so) -- but
+    for FP32 wall rows, which take two; every width takes two."""
     cases = [dict(nx=256, ny=8, storage="f64"), dict(nx=201, ny=8, storage="f64")]
     for c in cases:
         lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
@@ -213,10 +215,13 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
             lat.close()
     mask = np.zeros((8, 256), np.uint8)
     mask[0] = 1
-    for storage in ("f32", "f16"):
-        lat = L.Lattice(256, 8, 0.7, 1.0, storage=storage, mask=mask)
+    part = mask.copy()
+    part[0, 200:] = 0
+    for m, storage, want in ((mask, "f32", 2), (mask, "f16", 1), (part, "f32", 1),
+                             (part, "f16", 1)):
+        lat = L.Lattice(256, 8, 0.7, 1.0, storage=storage, mask=m)
         lat.set_tuning(steps_per_sweep=2)
-        assert lat.tuning()[5] == 1
+        assert lat.tuning()[5] == want, storage
         lat.close()
 
 
@@ -267,7 +272,7 @@ def test_batch_two_step_members_equal_one_step_batches(L, storage, ksteps):
     them."""
     specs = [(64, 64), (200, 37), (97, 33), (128, 130), (131, 40), (250, 9), (66, 3)]
     mask = np.zeros((37, 200), np.uint8)
-    mask[0] = 1
+    mask[0, :150] = 1   # not a whole row: one step per launch
     runs = {}
     for sps in (1, ksteps):
         lats = []
@@ -298,7 +303,7 @@ def test_batch_two_step_members_equal_one_step_batches(L, storage, ksteps):
         assert ta == tc and np.array_equal(a, c), j
     # only one-step members: the batch takes one step per launch
     wall = np.zeros((8, 64), np.uint8)
-    wall[0] = 1
+    wall[0, :40] = 1
     lats = [L.Lattice(64, 8, 0.7, 1.0, storage=storage, mask=wall),
             L.Lattice(64, 8, 0.9, 1.0, storage=storage, mask=wall)]
     b = L.Batch(lats)

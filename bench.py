@@ -377,7 +377,8 @@ def run_serving(storage, rate=200.0, duration=2.0, budget_gb=64.0, seed=0):
 
 def run_extra(steps):
     """Companion measurements: the same lattice in FP16 and FP64 storage,
-    the batched workload (FP32 and FP16), the serving stream (FP16 and FP32), the
+    a force-driven channel of the same size (FP32, whole-row walls), the
+    batched workload (FP32 and FP16), the serving stream (FP16 and FP32), the
     double-shear-layer stability study, the Taylor-Green convergence study
     and the Poiseuille slip study."""
     out = {}
@@ -392,6 +393,8 @@ def run_extra(steps):
             "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5), "launch_shape": list(shape),
             "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / (HBM_PEAK_GBS * 1e9), 4)}
         log("extra %s: %.1f MLUPS" % (storage, mlups))
+    out["channel4096_f32"] = run_channel(steps)
+    log("extra channel: %s" % out["channel4096_f32"])
     out["batch256_f32"] = run_batch()
     log("extra batch: %s" % out["batch256_f32"])
     # the same batch in FP16 storage (set against single-instance FP64 above)
@@ -408,6 +411,26 @@ def run_extra(steps):
     out["poiseuille_slip_f64"] = run_poiseuille()
     log("extra Poiseuille slip study: %s" % out["poiseuille_slip_f64"])
     return out
+
+
+def run_channel(steps, n=4096):
+    """The force-driven channel (whole-row walls) at the benchmark's size in
+    FP32, the library's default launch shape; its error against the same
+    channel run alone in FP64 storage after the same steps."""
+    lat = channel_lattice(n, "f32")
+    ms = time_steps(lat, steps, 20)
+    shape = list(lat.tuning())
+    total = lat.state()[1]
+    u, v = velocity(lat)
+    lat.close()
+    tau1, tau2, g, mask, fields = channel_problem(n)
+    ur, vr = fp64_alone(n, n, tau1, tau2, total, fields, g=(g, 0.0), mask=mask)
+    emax, el2 = rel_errors(u, v, ur, vr)
+    mlups = n * n / (ms * 1e-3) / 1e6
+    return {"MLUPS": round(mlups, 1), "ms_per_step": round(ms, 5), "launch_shape": shape,
+            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU["f32"] / (HBM_PEAK_GBS * 1e9), 4),
+            "steps": total, "err_max": emax, "err_L2": el2,
+            "reference": "the same channel run alone in FP64 storage on the GPU"}
 
 
 def run_dsl_curve(n=1024, u0=0.04, checkpoints=(1000, 2000, 5000, 10000, 20000)):
@@ -496,6 +519,36 @@ def creeping_lattice(storage, tuning=None):
     return lat
 
 
+def channel_lattice(n, storage, tuning=None):
+    """A force-driven channel (the set-up of Sec. III.C) of n x n nodes:
+    walls on the first and last rows, g for a centre-line velocity of 0.01,
+    Lambda = 3/16, started from its steady parabola -- the multi-step passes
+    over whole-row walls."""
+    from paper_2312_10318_amd.lattice import Lattice
+    tau1, tau2, g, mask, fields = channel_problem(n)
+    lat = Lattice(n, n, tau1, tau2, g=(g, 0.0), mask=mask, storage=storage)
+    if tuning:
+        lat.set_tuning(*tuning)
+    lat.init_equilibrium(*fields)
+    return lat
+
+
+def channel_problem(n, uc=0.01):
+    """(tau1, tau2, g, mask, (rho, ux, uy)) of the n x n force-driven
+    channel: fluid rows 1 ... n - 2 between half-way walls, the steady
+    parabola of centre-line velocity uc as the initial velocity."""
+    import numpy as np
+    from paper_2312_10318_amd import inputs, params
+    tau1 = 0.8
+    tau2 = params.tau2_from_magic(tau1, 3 / 16)
+    g = 8 * params.nu_from_tau(tau1) * uc / (n - 2) ** 2
+    mask = inputs.channel_mask(n, n - 2)
+    rho, _, uy = inputs.rest_state(n, n)
+    y = (np.arange(n, dtype=np.float64) - (n - 1) / 2) / ((n - 2) / 2)
+    ux = np.where(mask != 0, 0.0, (uc * (1.0 - y * y))[:, None] * np.ones((1, n)))
+    return tau1, tau2, g, mask, (rho, ux, uy)
+
+
 def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
     """Kernels for rocprofv3: `steps` sweeps of the benchmark lattice (or of
     the creeping-flow lattice), then a plain copy of 1 GiB (known bytes) to
@@ -526,6 +579,8 @@ def profile_run(n, storage, steps, warmup, tuning, workload="tg"):
         if workload == "creeping":
             lat = creeping_lattice(storage, tuning)
             n = lat.nx
+        elif workload == "channel":
+            lat = channel_lattice(n, storage, tuning)
         else:
             lat = tg_lattice(n, storage, tuning=tuning)
             if tuning is None and workload == "tg":
@@ -574,9 +629,11 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler driver: run warmup + steps sweeps untimed, then a plain "
                          "1 GiB device copy (the counter calibration kernel), and exit")
-    ap.add_argument("--workload", default="tg", choices=["tg", "creeping", "batch", "stream"],
+    ap.add_argument("--workload", default="tg",
+                    choices=["tg", "creeping", "channel", "batch", "stream"],
                     help="lattice of --profile: the Taylor-Green benchmark (--n), the "
-                         "creeping-flow cylinder of Table 1 (1050^2, link map), the "
+                         "creeping-flow cylinder of Table 1 (1050^2, link map), a "
+                         "force-driven channel (--n, whole-row walls), the "
                          "256-member batch, or the access-pattern probe on the benchmark "
                          "lattice (the sweep's loads and stores without its arithmetic)")
     args = ap.parse_args()

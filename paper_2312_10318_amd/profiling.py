@@ -77,6 +77,17 @@ def _is_copy(name):
     return "copyBuffer" in name
 
 
+# `bench.py --profile` ends with this many plain copies of COPY_BYTES; only
+# those (the last copy dispatches) scale the counters -- a run may also
+# copy small buffers on the way (uploads)
+COPIES = 3
+
+
+def _last_copies(copies):
+    """Values of the run's closing copies from (dispatch id, value) pairs."""
+    return [v for _, v in sorted(copies)[-COPIES:]]
+
+
 def kernel_durations(trace_dir):
     """Durations (ns) of the run's sweep kernel -- the sweep kernel with the
     most dispatches (a run of two-step launches may end on a one-step
@@ -88,7 +99,8 @@ def kernel_durations(trace_dir):
         if _is_sweep(r["Kernel_Name"]):
             by_name.setdefault(r["Kernel_Name"], []).append(dt)
         elif _is_copy(r["Kernel_Name"]):
-            copy.append(dt)
+            copy.append((int(r["Dispatch_Id"]), dt))
+    copy = _last_copies(copy)
     if not by_name:
         return [], copy, None
     name = max(by_name, key=lambda k: len(by_name[k]))
@@ -107,8 +119,8 @@ def counter_values(pmc_dir, counter, kernel=None):
         if _is_sweep(r["Kernel_Name"]) and (kernel is None or r["Kernel_Name"] == kernel):
             sweep.append(v)
         elif _is_copy(r["Kernel_Name"]):
-            copy.append(v)
-    return sweep, copy
+            copy.append((int(r["Dispatch_Id"]), v))
+    return sweep, _last_copies(copy)
 
 
 def _run_record(log_path):
@@ -131,6 +143,8 @@ WORKLOADS = {
     "tg": ("Taylor-Green %dx%d", "taylor_green_%dx%d", 0),
     "creeping": ("creeping flow past a square cylinder (Sec. III.D), %dx%d, obstacle, "
                  "inflow wall and pressure outlet", "creeping_cylinder_%dx%d", 2),
+    "channel": ("force-driven channel (Sec. III.C), %dx%d, walls on the first and last rows "
+                "(whole-row walls: no link codes read)", "channel_%dx%d", 0),
     "batch": ("the 256-member batch (Taylor-Green and double-shear-layer members, sides "
               "64 to 1024, %d nodes in all, the library's default batch shape)", "batch256", 0),
     "stream": ("access-pattern probe (the sweep's loads, stores, launch shape and barriers "
@@ -211,9 +225,9 @@ def summarize(trace_dir, fetch_dir, write_dir, storage, n, steps, warmup, out_pr
     }
     if sq_dir:
         rec.update(sq_summary(sq_dir, kname, skip_first))
-    if workload in ("tg", "stream"):
+    if workload in ("tg", "stream", "channel"):
         cmd = ("python3 bench.py --profile%s --storage %s --n %d --steps %d --warmup %d"
-               % (" --workload stream" if workload == "stream" else "", storage, n, steps,
+               % ("" if workload == "tg" else " --workload " + workload, storage, n, steps,
                   warmup))
     else:
         cmd = ("python3 bench.py --profile --workload %s --storage %s --steps %d --warmup %d"

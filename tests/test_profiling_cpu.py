@@ -20,39 +20,41 @@ def _write(path, header, rows):
 
 
 def _fake_run(root, sweep_ns, copy_ns, fetch_kib, write_kib, copy_fetch, copy_write,
-              sweep=SWEEP, tail=()):
+              sweep=SWEEP, tail=(), upload=None):
     """Profiler output of `sweep` dispatches (then `tail`: (name, ns, fetch,
-    write) dispatches of another sweep kernel) and copies."""
+    write) dispatches of another sweep kernel) and copies; `upload`: (ns,
+    fetch, write) of a small copy dispatched before the sweeps."""
     t = os.path.join(root, "T", "host")
     rows, clock = [], 0
-    for dt in sweep_ns:
-        rows.append((sweep, clock, clock + dt))
-        clock += dt + 10
-    for name, dt, _, _ in tail:
-        rows.append((name, clock, clock + dt))
-        clock += dt + 10
-    for dt in copy_ns:
-        rows.append((COPY, clock, clock + dt))
+    first = [] if upload is None else [(COPY, upload[0])]
+    for k, (name, dt) in enumerate(first + [(sweep, dt) for dt in sweep_ns] +
+                                   [(x[0], x[1]) for x in tail] + [(COPY, dt) for dt in copy_ns]):
+        rows.append((name, clock, clock + dt, k + 1))
         clock += dt + 10
     _write(os.path.join(t, "run_kernel_trace.csv"),
-           ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+           ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Dispatch_Id"], rows)
     _write(os.path.join(t, "run_kernel_stats.csv"), ["Name", "Calls", "AverageNs", "MinNs", "MaxNs"],
            [(sweep, len(sweep_ns), sum(sweep_ns) / len(sweep_ns),
              min(sweep_ns), max(sweep_ns))])
     for sub, counter, sv, cv, k in (("F", "FETCH_SIZE", fetch_kib, copy_fetch, 2),
                                     ("W", "WRITE_SIZE", write_kib, copy_write, 3)):
-        rows = ([(sweep, counter, v) for v in sv] + [(x[0], counter, x[k]) for x in tail] +
-                [(COPY, counter, v) for v in cv])
+        pre = [] if upload is None else [(COPY, upload[k - 1])]
+        vals = (pre + [(sweep, v) for v in sv] + [(x[0], x[k]) for x in tail] +
+                [(COPY, v) for v in cv])
+        rows = [(name, counter, v, j + 1) for j, (name, v) in enumerate(vals)]
         _write(os.path.join(root, sub, "host", "run_counter_collection.csv"),
-               ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+               ["Kernel_Name", "Counter_Name", "Counter_Value", "Dispatch_Id"], rows)
     log = os.path.join(root, "run.log")
     with open(log, "w") as fh:
         fh.write("noise\n" + json.dumps({"profile": "done", "source_hash": "abc123"}) + "\n")
     return [os.path.join(root, d) for d in "TFW"], log
 
 
+@pytest.mark.parametrize("upload", [None, (300, 0.5, 0.03125)])
 @pytest.mark.parametrize("workload,link", [("tg", 0), ("creeping", 2)])
-def test_summary_scales_counters_by_the_copy_kernel(tmp_path, workload, link):
+def test_summary_scales_counters_by_the_copy_kernel(tmp_path, workload, link, upload):
+    """The counters are scaled by the run's three closing 1 GiB copies; a
+    small copy earlier in the run (an upload) does not enter the scale."""
     n = 64
     nodes = n * n
     alg = (72 + link) * nodes
@@ -66,9 +68,10 @@ def test_summary_scales_counters_by_the_copy_kernel(tmp_path, workload, link):
     fetch = [999.0, 999.0] + [rd / 2 / 1024.0] * 4
     write = [999.0, 999.0] + [wr / 1024.0] * 4
     (t, f, w), log = _fake_run(str(tmp_path), sweep_ns, [2000] * 3, fetch, write, copy_fetch,
-                               copy_write)
+                               copy_write, upload=upload)
     out = os.path.join(str(tmp_path), "summary")
     rec = profiling.summarize(t, f, w, "f32", n, 4, 2, out, run_log=log, workload=workload)
+    assert rec["copy_avg_duration_us"] == 2.0
     assert rec["dispatches"] == 4 and rec["avg_duration_us"] == 1.0
     assert rec["algorithmic_bytes_per_launch"] == alg
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0

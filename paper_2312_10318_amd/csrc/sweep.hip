@@ -1016,20 +1016,53 @@ template <> struct Tb2Word<_Float16> {
     }
 };
 
-// Walls that fill whole rows (InstDesc::rowwalls): a row is solid when
-// bit 0 of its first link-summary entry is set (scalar loads).
+// Walls that fill whole rows (InstDesc::rowwalls): every node of a row has
+// the same link code, so the first link-summary entry of row y holds its
+// state -- bit 0: the row is solid, bit 2: its pull source for direction 2,
+// row y - 1 (wrapped), is; bit 4: row y + 1 is (one scalar load).
 struct RowWalls {
     RowSum sum;
-    int ny;
-    __device__ __forceinline__ explicit RowWalls(const InstDesc &d)
-        : sum(d.rowsum, d.nsum), ny(d.ny) {}
-    __device__ __forceinline__ uint32_t solid(int y) const { return sum.one(y, 0) & 1u; }
+    __device__ __forceinline__ explicit RowWalls(const InstDesc &d) : sum(d.rowsum, d.nsum) {}
     // the pull flags of row y (0 <= y < ny): bit 0 the row is solid, bit 1
-    // the row below it (y - 1, wrapped), bit 2 the row above it (y + 1)
-    __device__ __forceinline__ uint32_t flags(int y) const {
-        const int ym = y == 0 ? ny - 1 : y - 1;
-        const int yp = y == ny - 1 ? 0 : y + 1;
-        return solid(y) | (solid(ym) << 1) | (solid(yp) << 2);
+    // the row below it, bit 2 the row above it
+    __device__ __forceinline__ uint32_t flags(int y) const { return of_entry(sum.one(y, 0)); }
+    // the same from the row's summary entry
+    __device__ static __forceinline__ uint32_t of_entry(uint32_t e) {
+        return (e & 1u) | (((e >> 2) & 1u) << 1) | (((e >> 4) & 1u) << 2);
+    }
+};
+
+// The wall flags (RowWalls::flags) of the rows a pass loads, which follow
+// one another in the march's order: the flags of the next row to load are
+// kept, and those of the row after it are read one load ahead, so the
+// scalar load's wait falls a pipeline row after its issue.
+template <bool UP, bool WALLS> struct LoadWalls {
+    int row = 0;        // the row after the next one to load
+    uint32_t next = 0;  // the next row to load's summary entry, as loaded
+    // first: the first row to load (any integer)
+    __device__ __forceinline__ LoadWalls(const InstDesc &d, int first) {
+        if constexpr (WALLS) {
+            int r = first < 0 ? first + d.ny : (first >= d.ny ? first - d.ny : first);
+            if (r < 0 || r >= d.ny) r = ((first % d.ny) + d.ny) % d.ny;
+            next = RowWalls(d).sum.one(r, 0);
+            row = step(r, d.ny);
+        }
+    }
+    // row + dir, wrapped
+    __device__ static __forceinline__ int step(int r, int ny) {
+        r += UP ? 1 : -1;
+        return r == ny ? 0 : (r < 0 ? ny - 1 : r);
+    }
+    // the flags of the next row to load; then moves on by one row
+    __device__ __forceinline__ uint32_t take(const InstDesc &d) {
+        if constexpr (!WALLS) {
+            return 0u;
+        } else {
+            const uint32_t f = RowWalls::of_entry(next);
+            next = RowWalls(d).sum.one(row, 0);
+            row = step(row, d.ny);
+            return f;
+        }
     }
 };
 
@@ -1476,9 +1509,13 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
         return UP ? y + 3 + DEPTH <= y1 + 2 : y - 3 - DEPTH >= y0 - 3;
     };
     const auto lrow = [&](int y) { return wrap_row(y + dir * (3 + DEPTH)); };
-    // the wall flags of a row to load (0 without walls)
+    // the wall flags of a row to load (0 without walls): rows are loaded in
+    // the march's order from the block's first gathered row on, which
+    // LoadWalls follows
+    LoadWalls<UP, WALLS> lw(d, UP ? y0 - 3 : y1 + 2);
     const auto wfl = [&](int row) -> uint32_t {
-        if constexpr (WALLS) return RowWalls(d).flags(row);
+        (void)row;
+        if constexpr (WALLS) return lw.take(d);
         return 0u;
     };
     const auto lfl = [&](int y) -> uint32_t { return ld(y) ? wfl(lrow(y)) : 0u; };
@@ -1730,9 +1767,13 @@ __device__ __forceinline__ void sweep_strip_tb3(const InstDesc &d, int strip, in
         return UP ? y + 5 + DEPTH <= y1 + 4 : y - 5 - DEPTH >= y0 - 5;
     };
     const auto lrow = [&](int y) { return wrap_row(y + dir * (5 + DEPTH)); };
-    // the wall flags of a row to load (0 without walls)
+    // the wall flags of a row to load (0 without walls): rows are loaded in
+    // the march's order from the block's first gathered row on, which
+    // LoadWalls follows
+    LoadWalls<UP, WALLS> lw(d, UP ? y0 - 5 : y1 + 4);
     const auto wfl = [&](int row) -> uint32_t {
-        if constexpr (WALLS) return RowWalls(d).flags(row);
+        (void)row;
+        if constexpr (WALLS) return lw.take(d);
         return 0u;
     };
     const auto lfl = [&](int y) -> uint32_t { return ld(y) ? wfl(lrow(y)) : 0u; };

@@ -1,12 +1,13 @@
 """Launch-shape autotuner for the fused sweep.
 
-For a lattice shape, storage type and mask presence it times the fused sweep
+For a lattice shape, storage type and mask kind (none; walls that fill
+whole rows; any other mask) it times the fused sweep
 over a grid of launch shapes (rows a wavefront marches, wavefronts per
 workgroup, XCD remap on/off, one or two columns per lane where two apply,
 one, two or three time steps per launch where they apply) on a scratch lattice of
 that shape, and keeps the fastest.  For a batch it times the batched step (rows, wavefronts per
 workgroup, XCD remap) on scratch copies of the members.  Results persist in
-a JSON cache keyed by GPU architecture, storage, mask presence and size
+a JSON cache keyed by GPU architecture, storage, mask kind and size
 buckets (for a batch: its member count and size mix); the cache path is
 $TRTLBM_TUNE_CACHE, else ~/.cache/trtlbm/tune.json.
 """
@@ -63,9 +64,23 @@ def _bucket(v: int) -> int:
     return 1 << max(6, min(15, int(round(math.log2(max(1, v))))))
 
 
-def key(nx: int, ny: int, storage: str, has_mask: bool, arch: str = "gfx950") -> str:
-    return "%s|%s|%s|%d|%d" % (arch, storage, "mask" if has_mask else "open", _bucket(nx),
-                               _bucket(ny))
+def key(nx: int, ny: int, storage: str, has_mask: bool, arch: str = "gfx950",
+        walls: bool = False) -> str:
+    """Cache key: storage, the lattice's kind (open; a mask whose solid
+    nodes fill whole rows, walls; any other mask or open x boundaries) and
+    the size buckets."""
+    kind = ("walls" if walls else "mask") if has_mask else "open"
+    return "%s|%s|%s|%d|%d" % (arch, storage, kind, _bucket(nx), _bucket(ny))
+
+
+def row_walls(mask, inflow=None) -> bool:
+    """Whether a host mask's solid nodes fill whole rows (and x is periodic):
+    such FP32 lattices take the multi-step passes as open ones do."""
+    if mask is None or inflow is not None:
+        return False
+    import numpy as np
+    m = np.asarray(mask) != 0
+    return bool(np.all(m == m[:, :1]))
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -92,14 +107,16 @@ def save_cache(cache: dict, path: str | None = None) -> bool:
     return True
 
 
-def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
+def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32",
+               walls: bool = False):
     """Launch shapes (rows, waves per workgroup, XCD remap, columns per
     lane, graph sweeps (0: default), time steps per launch, prefetch rows (0:
     automatic)) worth timing.  Two columns per lane apply to every width
     that is not 1 mod 128 (with or without a mask: masked lattices use the
     link map); two time steps per launch to FP32 and FP16 lattices without a
     mask, whose loads run one or two rows ahead; three to such FP32
-    lattices."""
+    lattices.  walls (with has_mask): the mask's solid nodes fill whole
+    rows, so FP32 lattices take two and three steps as open ones do."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -111,7 +128,8 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
             for w in waves:
                 for x in REMAP:
                     out.append((r, w, x, c, 0, 1, 0))
-    if storage in ("f32", "f16") and not has_mask:
+    multi = not has_mask or (walls and storage == "f32")
+    if storage in ("f32", "f16") and multi:
         for r in TB2_ROWS:
             if r > max(8, ny):
                 continue
@@ -128,7 +146,7 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32"):
                         continue
                     for x in REMAP:
                         out.append((r, w, x, 2, 0, 2, p))
-    if storage == "f32" and not has_mask:
+    if storage == "f32" and multi:
         for r in TB3_ROWS:
             if r > max(8, ny):
                 continue
@@ -172,7 +190,7 @@ def tune(nx: int, ny: int, storage: str = "f32", mask=None, steps: int | None = 
     if steps is None:
         steps = max(10, min(400, int(2e9 / max(1, nx * ny))))
     table = []
-    for shape in shapes or candidates(nx, ny, mask is not None, storage):
+    for shape in shapes or candidates(nx, ny, mask is not None, storage, row_walls(mask)):
         ms = time_shape(lat, shape, steps, max(2, steps // 10))
         table.append((list(shape), ms))
         if log:
@@ -184,11 +202,13 @@ def tune(nx: int, ny: int, storage: str = "f32", mask=None, steps: int | None = 
 
 
 def best_shape(nx: int, ny: int, storage: str = "f32", has_mask: bool = False,
-               autotune: bool = False, log=None):
+               autotune: bool = False, log=None, walls: bool = False):
     """Cached best launch shape, tuning (and caching) on a miss when
-    `autotune` is set; None when unknown (the library default applies)."""
+    `autotune` is set; None when unknown (the library default applies).
+    With a mask it is tuned on a channel (walls on the first and last rows),
+    plus, unless `walls`, a solid node off those rows."""
     cache = load_cache()
-    k = key(nx, ny, storage, has_mask)
+    k = key(nx, ny, storage, has_mask, walls=walls)
     if k in cache:
         return tuple(cache[k]["best"])
     if not autotune:
@@ -198,6 +218,8 @@ def best_shape(nx: int, ny: int, storage: str = "f32", has_mask: bool = False,
         import numpy as np
         mask = np.zeros((ny, nx), np.uint8)
         mask[0] = mask[-1] = 1
+        if not walls and ny > 2:
+            mask[ny // 2, nx // 2] = 1
     res = tune(nx, ny, storage, mask=mask, log=log)
     cache[k] = {"best": res["best"], "ms": res["ms"], "when": res["when"]}
     save_cache(cache)

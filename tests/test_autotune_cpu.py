@@ -55,6 +55,28 @@ def test_candidates_respect_width_and_storage_limits():
 def test_cache_key_buckets_sizes():
     assert autotune.key(4000, 4100, "f32", False) == autotune.key(4096, 4096, "f32", False)
     assert autotune.key(4096, 4096, "f32", True) != autotune.key(4096, 4096, "f32", False)
+    keys = {autotune.key(4096, 4096, "f32", m, walls=w) for m, w in
+            ((False, False), (True, False), (True, True))}
+    assert len(keys) == 3
+
+
+def test_whole_row_walls_get_multi_step_candidates_in_fp32():
+    """A mask whose solid nodes fill whole rows: FP32 lattices are offered
+    the two- and three-step shapes of open lattices; FP16 keeps one step."""
+    import numpy as np
+    walls = autotune.candidates(4096, 4096, True, "f32", walls=True)
+    open_ = autotune.candidates(4096, 4096, False, "f32")
+    assert sorted(walls) == sorted(open_)
+    assert all(s[5] == 1 for s in autotune.candidates(4096, 4096, True, "f16", walls=True))
+    m = np.zeros((10, 7), np.uint8)
+    assert autotune.row_walls(m)
+    m[[0, 9]] = 1
+    assert autotune.row_walls(m) and not autotune.row_walls(m, inflow=(0.01, 1.0, 1.0))
+    m[4, 3] = 1
+    assert not autotune.row_walls(m)
+    m = np.zeros((10, 7), np.uint8)
+    m[:, 0] = 1                       # a wall along y
+    assert not autotune.row_walls(m) and not autotune.row_walls(None)
 
 
 def test_build_reads_register_spills_from_compiler_remarks():

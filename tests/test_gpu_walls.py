@@ -7,7 +7,8 @@ wall row and wall rows keep zeros.  Every node's arithmetic is that of the
 one-step sweep over the link map, so the results are its bits: channels,
 adjacent wall rows, a single fluid row between walls, a wall whose
 neighbour lies across the periodic seam, an all-solid and an all-fluid
-mask, odd widths, lattices narrower than one window, every launch shape,
+mask, heights of one to three rows, odd widths, lattices narrower than
+one window, every launch shape,
 both march directions and the deep two-step pipeline; alone and in a
 batch; and a channel against the oracle.  A mask whose solid nodes do not
 fill whole rows keeps one step per launch, as does FP16 storage."""
@@ -53,7 +54,10 @@ WALLS = [(128, 37, (0, 36)),              # a channel
          (241, 20, (3, 19)),
          (3, 6, (0, 3)),                  # narrower than one window
          (121, 7, tuple(range(7))),       # every row solid
-         (250, 9, ())]                    # a mask without a solid node
+         (250, 9, ()),                    # a mask without a solid node
+         (200, 2, (1,)),                  # heights of one to three rows
+         (130, 1, ()),
+         (97, 3, (0, 2))]
 TILINGS = [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1)]
 
 

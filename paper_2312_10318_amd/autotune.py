@@ -75,7 +75,7 @@ def key(nx: int, ny: int, storage: str, has_mask: bool, arch: str = "gfx950",
 
 def row_walls(mask, inflow=None) -> bool:
     """Whether a host mask's solid nodes fill whole rows (and x is periodic):
-    such FP32 lattices take the multi-step passes as open ones do."""
+    such FP32 and FP16 lattices take the multi-step passes as open ones do."""
     if mask is None or inflow is not None:
         return False
     import numpy as np
@@ -116,7 +116,7 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32",
     link map); two time steps per launch to FP32 and FP16 lattices without a
     mask, whose loads run one or two rows ahead; three to such FP32
     lattices.  walls (with has_mask): the mask's solid nodes fill whole
-    rows, so FP32 lattices take two and three steps as open ones do."""
+    rows, so the lattice takes two and three steps as an open one does."""
     cols = COLS if nx % 128 != 1 else (1,)
     out = []
     for c in cols:
@@ -128,7 +128,7 @@ def candidates(nx: int, ny: int, has_mask: bool = False, storage: str = "f32",
             for w in waves:
                 for x in REMAP:
                     out.append((r, w, x, c, 0, 1, 0))
-    multi = not has_mask or (walls and storage == "f32")
+    multi = not has_mask or walls
     if storage in ("f32", "f16") and multi:
         for r in TB2_ROWS:
             if r > max(8, ny):

@@ -554,6 +554,50 @@ __device__ __forceinline__ void widen_pair(RowState<C, SHIFTED> &a, RowState<C, 
         // e_x = -1 (planes 3, 6, 7): node B pulls the next lane's node A
         const uint32_t w1 = dpp_shr(h0, r.w[1]), w5 = dpp_shr(h1, r.w[5]), w8 = dpp_shr(h2, r.w[8]);
         const uint32_t w3 = dpp_shl(h0, r.w[3]), w6 = dpp_shl(h1, r.w[6]), w7 = dpp_shl(h2, r.w[7]);
+        if constexpr (WALLS) {
+            // as below, but where a wall row below (5, 6) or above (7, 8)
+            // bounces a population, each node takes its own half of the
+            // own-slot word its load brought, moved to the half its sums read
+            uint32_t a5 = w5, a6 = c.tail ? h1 : r.w[6], a7 = c.tail ? h2 : r.w[7], a8 = w8;
+            uint32_t b5 = r.w[5], b6 = w6, b7 = w7, b8 = r.w[8];
+            if (r.rs & 2u) {
+                a5 = r.w[5] << 16;
+                a6 = r.w[6] << 16;
+                b5 = r.w[5] >> 16;
+                b6 = r.w[6] >> 16;
+            }
+            if (r.rs & 4u) {
+                a7 = r.w[7] << 16;
+                a8 = r.w[8] << 16;
+                b7 = r.w[7] >> 16;
+                b8 = r.w[8] >> 16;
+            }
+            {
+                const uint32_t o3 = c.tail ? h0 : r.w[3];
+                const float a13 = hsum<true, false>(w1, o3);
+                a.m.finish(hsum<true, false>(a5, a6), hsum<true, true>(a5, a6),
+                           hsum<true, false>(a7, a8), hsum<true, true>(a7, a8), a13,
+                           hsum<true, true>(w1, o3), hsum<false, false>(r.w[2], r.w[4]),
+                           hsum<false, true>(r.w[2], r.w[4]), hadd<false>(r.w[0], a13), gx, gy);
+            }
+            {
+                const float a13 = hsum<false, false>(r.w[1], w3);
+                b.m.finish(hsum<false, false>(b5, b6), hsum<false, true>(b5, b6),
+                           hsum<false, false>(b7, b8), hsum<false, true>(b7, b8), a13,
+                           hsum<false, true>(r.w[1], w3), hsum<true, false>(r.w[2], r.w[4]),
+                           hsum<true, true>(r.w[2], r.w[4]), hadd<true>(r.w[0], a13), gx, gy);
+            }
+            a.solid = b.solid = (r.rs & 1u) != 0;
+            const float pxa = a.m.rho * a.m.ux * a.m.ux * a.m.ux;
+            const float pya = a.m.rho * a.m.uy * a.m.uy * a.m.uy;
+            const float pxb = b.m.rho * b.m.ux * b.m.ux * b.m.ux;
+            const float pyb = b.m.rho * b.m.uy * b.m.uy * b.m.uy;
+            a.phix = a.solid ? 0.0f : pxa;
+            a.phiy = a.solid ? 0.0f : pya;
+            b.phix = b.solid ? 0.0f : pxb;
+            b.phiy = b.solid ? 0.0f : pyb;
+            return;
+        }
         // node A: f0 f2 f4 in the low halves of its own words; f1 f5 f8 in
         // the high halves of the shifted ones; f3 f6 f7 in the high halves of
         // its own (node B's column), or of the edge words for an odd width's
@@ -1305,6 +1349,10 @@ struct Tb2CarryH {
     Coeffs<float> qA, qB;
     float qyA, qyB, qbelA, qbelB;
 };
+// with whole-row walls, the wall bits of the pipeline's rows as well
+struct Tb2CarryHW : Tb2CarryH {
+    uint32_t sb;  // bit j: row y + (2 - j) dir solid
+};
 
 // The nine store words of a pair from its coefficients and Phi_y gradients,
 // as the one-step FP16 sweep forms them.
@@ -1324,14 +1372,16 @@ __device__ __forceinline__ void tb2_half_words(uint32_t wd[9], const Coeffs<floa
     wd[8] = half_out<8, true>(pb, half_out<8, false>(pa));
 }
 
-// One pipeline row with FP16 storage (stages as tb2_row).
-template <int STAGE, bool SYNC = true, bool UP = true>
-__device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
+// One pipeline row with FP16 storage (stages as tb2_row).  WALLS:
+// whole-row walls (as tb2_row; the second step's pull row carries the wall
+// flags of its neighbours to the widen, which bounces as for loaded rows).
+template <int STAGE, bool SYNC = true, bool UP = true, bool WALLS = false, class K>
+__device__ __forceinline__ void tb2_row_h(K &k, PairRow<_Float16> &raw,
                                           const PairCtx<_Float16> &cx, const Tb2Lane &ln,
                                           bool odd, const Tb2Params &p,
                                           const BufAccess<_Float16> &out, int y, bool load,
                                           int yload, bool store, int pitch, int64_t plane,
-                                          int stage = STAGE) {
+                                          int stage = STAGE, uint32_t lflags = 0u) {
     using C = float;
     constexpr bool SH = true;
     const C gx = p.gx, gy = p.gy, w1 = p.w1, w2 = p.w2, ph = p.ph;
@@ -1342,10 +1392,13 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
     // (b) row y + 3 from its stored halves, then (a) the next loads
     C nyA, nyB;
     Coeffs<C> nkA, nkB;
+    // whole-row walls: bit j, row y + (3 - j) dir solid
+    uint32_t sb = 0u;
+    if constexpr (WALLS) sb = (k.sb << 1) | (raw.rs & 1u);
     {
         RowState<C, SH> nA, nB;
-        widen_pair<_Float16, C, SH, true>(nA, nB, raw, cx, gx, gy, ox);
-        if (load) tb2_gather<_Float16>(raw, cx, ln, odd, yload);
+        widen_pair<_Float16, C, SH, true, WALLS>(nA, nB, raw, cx, gx, gy, ox);
+        if (load) tb2_gather<_Float16, WALLS>(raw, cx, ln, odd, yload, lflags);
         const C left = dpp_shr(C(0), nB.phix);
         const C right = dpp_shl(C(0), nA.phix);
         nkA = collide_coeffs<C, SH>(nA.m, C(0.5) * (nB.phix - left), w1, w2, ph, gx, gy);
@@ -1387,8 +1440,21 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
         }
         pr.edge[0] = pr.edge[1] = pr.edge[2] = _Float16(0);
         pr.lk = pr.rs = 0u;
+        if constexpr (WALLS) {
+            // row y + 1: the words bounced at a wall row ahead are its own
+            // words streaming forward (the window's middle); those bounced
+            // at a wall row behind are in lo (mid_shift); the widen takes
+            // them without shifts, by the row's geometric flags
+            const uint32_t behind = (sb >> 3) & 1u, ahead = (sb >> 1) & 1u;
+            if (ahead) {
+                pr.w[UP ? 4 : 2] = k.w.mid[3];
+                pr.w[UP ? 7 : 5] = k.w.mid[4];
+                pr.w[UP ? 8 : 6] = k.w.mid[5];
+            }
+            pr.rs = ((sb >> 2) & 1u) | ((UP ? behind : ahead) << 1) | ((UP ? ahead : behind) << 2);
+        }
         RowState<C, SH> cA, cB;
-        widen_pair<_Float16, C, SH, true>(cA, cB, pr, cx, gx, gy, ox);
+        widen_pair<_Float16, C, SH, true, WALLS>(cA, cB, pr, cx, gx, gy, ox);
         const C left = dpp_shr(C(0), cB.phix);
         const C right = dpp_shl(C(0), cA.phix);
         ckA = collide_coeffs<C, SH>(cA.m, C(0.5) * (cB.phix - left), w1, w2, ph, gx, gy);
@@ -1401,6 +1467,7 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
         uint32_t sw[9];
         tb2_half_words(sw, k.qA, C(0.5) * (UP ? cyA - k.qbelA : k.qbelA - cyA), k.qB,
                        C(0.5) * (UP ? cyB - k.qbelB : k.qbelB - cyB), ph);
+        if (WALLS) solid_zero<uint32_t>(sw, sw, (sb >> 3) & 1u);
         if (store) {
             const int64_t e0 = (int64_t)y * pitch;
 #pragma unroll
@@ -1419,22 +1486,23 @@ __device__ __forceinline__ void tb2_row_h(Tb2CarryH &k, PairRow<_Float16> &raw,
         k.qA = ckA;
         k.qB = ckB;
     }
-    if (stage >= 1) mid_shift<uint32_t, UP>(k.w, ow);
+    if (stage >= 1) mid_shift<uint32_t, UP, WALLS>(k.w, ow, WALLS && ((sb >> 2) & 1u));
     k.belA = k.pyA;
     k.belB = k.pyB;
     k.pyA = nyA;
     k.pyB = nyB;
     k.kA = nkA;
     k.kB = nkB;
+    if constexpr (WALLS) k.sb = sb;
     if (SYNC) __builtin_amdgcn_s_barrier();
 }
 
 // The pipeline row and carried state of each storage type.
 template <int ST> struct Tb2Rows;
 template <> struct Tb2Rows<ST_F32> {
-    using Carry = Tb2Carry<float>;
+    template <bool WALLS> using Carry = Tb2Carry<float>;
     template <int STAGE, bool SYNC, bool UP, bool WALLS>
-    __device__ static __forceinline__ void row(Carry &k, PairRow<float> &raw,
+    __device__ static __forceinline__ void row(Carry<WALLS> &k, PairRow<float> &raw,
                                                const PairCtx<float> &cx, const Tb2Lane &ln,
                                                bool odd, const Tb2Params &p,
                                                const BufAccess<float> &out, int y, bool load,
@@ -1446,17 +1514,16 @@ template <> struct Tb2Rows<ST_F32> {
     }
 };
 template <> struct Tb2Rows<ST_F16> {
-    using Carry = Tb2CarryH;
+    template <bool WALLS> using Carry = typename std::conditional<WALLS, Tb2CarryHW, Tb2CarryH>::type;
     template <int STAGE, bool SYNC, bool UP, bool WALLS>
-    __device__ static __forceinline__ void row(Carry &k, PairRow<_Float16> &raw,
+    __device__ static __forceinline__ void row(Carry<WALLS> &k, PairRow<_Float16> &raw,
                                                const PairCtx<_Float16> &cx, const Tb2Lane &ln,
                                                bool odd, const Tb2Params &p,
                                                const BufAccess<_Float16> &out, int y, bool load,
                                                int yload, bool store, int pitch, int64_t plane,
-                                               int stage = STAGE, uint32_t = 0u) {
-        static_assert(!WALLS, "whole-row walls: FP32 storage only");
-        tb2_row_h<STAGE, SYNC, UP>(k, raw, cx, ln, odd, p, out, y, load, yload, store, pitch,
-                                   plane, stage);
+                                               int stage = STAGE, uint32_t lflags = 0u) {
+        tb2_row_h<STAGE, SYNC, UP, WALLS>(k, raw, cx, ln, odd, p, out, y, load, yload, store,
+                                          pitch, plane, stage, lflags);
     }
 };
 
@@ -1520,7 +1587,7 @@ __device__ __forceinline__ void sweep_strip_tb2(const InstDesc &d, int strip, in
     };
     const auto lfl = [&](int y) -> uint32_t { return ld(y) ? wfl(lrow(y)) : 0u; };
 
-    typename R::Carry k{};
+    typename R::template Carry<WALLS> k{};
     PairRow<T> raw[DEPTH];
     const int ys = UP ? y0 - 6 : y1 + 5;  // the first pipeline row
     tb2_gather<T, WALLS>(raw[0], cx, ln, odd, wrap_row(ys + 3 * dir), wfl(wrap_row(ys + 3 * dir)));
@@ -1951,11 +2018,9 @@ __global__ __launch_bounds__(64 * kTb2MaxWaves) void sweep_tb2_batch_kernel(
     const int4 it = items[wave];
     if ((unsigned)it.x >= (unsigned)ndescs) return;
     const InstDesc d = descs[it.x];
-    if constexpr (ST == ST_F32) {
-        if (d.rowwalls) {
-            sweep_strip_tb2<ST, DEPTH, false, true, true>(d, it.y, it.z, d.cur ^ flip);
-            return;
-        }
+    if (d.rowwalls) {
+        sweep_strip_tb2<ST, DEPTH, false, true, true>(d, it.y, it.z, d.cur ^ flip);
+        return;
     }
     sweep_strip_tb2<ST, DEPTH, false>(d, it.y, it.z, d.cur ^ flip);
 }
@@ -2037,10 +2102,10 @@ hipError_t launch_sweep(const InstDesc &d, int storage, bool mask, int src, cons
 }
 
 // Passes of several steps: FP32 or FP16 lattices, periodic, without a mask
-// -- or FP32 ones whose solid nodes fill whole rows (walls parallel to x).
+// or with one whose solid nodes fill whole rows (walls parallel to x).
 bool tb2_eligible(const InstDesc &d, int storage) {
     const bool open = d.links == nullptr && d.mask == nullptr;
-    const bool walls = storage == ST_F32 && d.rowwalls != 0 && d.links != nullptr;
+    const bool walls = d.rowwalls != 0 && d.links != nullptr;
     return (storage == ST_F32 || storage == ST_F16) && (open || walls) && d.xbc == 0 &&
            buffer_addressable(d, storage);
 }
@@ -2133,7 +2198,12 @@ hipError_t launch_sweep_tb2(const InstDesc &d, int storage, int src, const Launc
     // 87.0, 2048^2 FP32 35.5 -> 36.4, 2048^2 FP16 26.3 -> 26.7), so only
     // deep FP32 launches alternate.
     const int alt = (deep && storage == ST_F32) ? 1 : 0;
-    if (storage == ST_F16) {
+    if (storage == ST_F16 && t.rowwalls) {
+        if (deep)
+            sweep_tb2_kernel<ST_F16, 2, true><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
+        else
+            sweep_tb2_kernel<ST_F16, 1, true><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
+    } else if (storage == ST_F16) {
         if (deep)
             sweep_tb2_kernel<ST_F16, 2><<<blocks, 64 * wpb, 0, stream>>>(t, src, l.xcd_remap, alt);
         else

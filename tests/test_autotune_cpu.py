@@ -60,14 +60,15 @@ def test_cache_key_buckets_sizes():
     assert len(keys) == 3
 
 
-def test_whole_row_walls_get_multi_step_candidates_in_fp32():
-    """A mask whose solid nodes fill whole rows: FP32 lattices are offered
-    the two- and three-step shapes of open lattices; FP16 keeps one step."""
+def test_whole_row_walls_get_multi_step_candidates():
+    """A mask whose solid nodes fill whole rows: FP32 and FP16 lattices are
+    offered the multi-step shapes of open lattices; FP64 keeps one step."""
     import numpy as np
-    walls = autotune.candidates(4096, 4096, True, "f32", walls=True)
-    open_ = autotune.candidates(4096, 4096, False, "f32")
-    assert sorted(walls) == sorted(open_)
-    assert all(s[5] == 1 for s in autotune.candidates(4096, 4096, True, "f16", walls=True))
+    for storage in ("f32", "f16", "f64"):
+        walls = autotune.candidates(4096, 4096, True, storage, walls=True)
+        open_ = autotune.candidates(4096, 4096, False, storage)
+        assert sorted(walls) == sorted(open_)
+    assert all(s[5] == 1 for s in autotune.candidates(4096, 4096, True, "f16"))
     m = np.zeros((10, 7), np.uint8)
     assert autotune.row_walls(m)
     m[[0, 9]] = 1

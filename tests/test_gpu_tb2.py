@@ -201,7 +201,7 @@ def test_two_steps_per_launch_fp16_one_launch_against_the_oracle(L):
 
 def test_two_steps_per_launch_applies_only_where_eligible(L):
     """FP64 storage and masks keep one step per launch (and say so) -- but
-    for FP32 wall rows, which take two; every width takes two."""
+    for wall rows, which take two; every width takes two."""
     cases = [dict(nx=256, ny=8, storage="f64"), dict(nx=201, ny=8, storage="f64")]
     for c in cases:
         lat = L.Lattice(c["nx"], c["ny"], 0.7, 1.0, storage=c["storage"])
@@ -217,7 +217,7 @@ def test_two_steps_per_launch_applies_only_where_eligible(L):
     mask[0] = 1
     part = mask.copy()
     part[0, 200:] = 0
-    for m, storage, want in ((mask, "f32", 2), (mask, "f16", 1), (part, "f32", 1),
+    for m, storage, want in ((mask, "f32", 2), (mask, "f16", 2), (part, "f32", 1),
                              (part, "f16", 1)):
         lat = L.Lattice(256, 8, 0.7, 1.0, storage=storage, mask=m)
         lat.set_tuning(steps_per_sweep=2)

@@ -1,5 +1,6 @@
-"""FP32 lattices whose solid nodes fill whole rows (walls parallel to x, the
-channels of Sec. III.C) take two and three time steps per launch.  Next to a
+"""Lattices whose solid nodes fill whole rows (walls parallel to x, the
+channels of Sec. III.C) take two time steps per launch (FP32 and FP16) and
+three (FP32).  Next to a
 wall row the first step's loads read the node's own slots of the bounced
 populations, and the later steps bounce them in registers from the node's
 own post-collision values (half-way bounce-back, Sec. II.D); Phi is 0 on a
@@ -11,7 +12,7 @@ mask, heights of one to three rows, odd widths, lattices narrower than
 one window, every launch shape,
 both march directions and the deep two-step pipeline; alone and in a
 batch; and a channel against the oracle.  A mask whose solid nodes do not
-fill whole rows keeps one step per launch, as does FP16 storage."""
+fill whole rows keeps one step per launch, as does FP64 storage."""
 import numpy as np
 import pytest
 
@@ -61,12 +62,12 @@ WALLS = [(128, 37, (0, 36)),              # a channel
 TILINGS = [(0, 0, -1), (1, 1, 0), (3, 2, 1), (8, 4, 1)]
 
 
-def _equal_runs(L, nx, ny, walls, tiling, ksteps, seed):
+def _equal_runs(L, nx, ny, walls, tiling, ksteps, seed, storage="f32"):
     f, mask, g, tau1, tau2 = _case(seed, nx, ny, walls)
-    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32", mask=mask).set_populations(f)
+    one = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage, mask=mask).set_populations(f)
     one.set_tuning(steps_per_sweep=1)
     assert one.tuning()[5] == 1
-    many = L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32", mask=mask).set_populations(f)
+    many = L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage, mask=mask).set_populations(f)
     many.set_tuning(*tiling, 2, 8, ksteps)
     assert many.tuning()[5] == ksteps and many.tuning()[1] <= 4
     for k in (1, 2, 5, 4, 11, 3, 6, 13):   # 45 steps: every remainder, graphs
@@ -82,27 +83,31 @@ def _equal_runs(L, nx, ny, walls, tiling, ksteps, seed):
 
 @pytest.mark.parametrize("nx,ny,walls", WALLS)
 @pytest.mark.parametrize("tiling", TILINGS)
-@pytest.mark.parametrize("ksteps", [2, 3])
-def test_wall_rows_multi_step_launches_equal_one_step_sweeps(L, nx, ny, walls, tiling, ksteps):
-    say("case: wall rows %s in %dx%d, %d steps per launch, tiling=%s"
-        % (walls, nx, ny, ksteps, tiling))
-    _equal_runs(L, nx, ny, walls, tiling, ksteps, nx + 3 * ny + len(walls))
+@pytest.mark.parametrize("storage,ksteps", [("f32", 2), ("f32", 3), ("f16", 2)])
+def test_wall_rows_multi_step_launches_equal_one_step_sweeps(L, nx, ny, walls, tiling, storage,
+                                                            ksteps):
+    say("case: wall rows %s in %dx%d %s, %d steps per launch, tiling=%s"
+        % (walls, nx, ny, storage, ksteps, tiling))
+    _equal_runs(L, nx, ny, walls, tiling, ksteps, nx + 3 * ny + len(walls), storage)
 
 
-@pytest.mark.parametrize("ksteps,tiling", [(2, (1, 4, 1)), (3, (1, 4, 1)), (3, (2, 1, 1))])
-def test_wall_rows_deep_pipeline_and_down_march(L, ksteps, tiling):
-    """At least 4096 wavefronts: the two-step pass loads two rows ahead, and
-    odd row blocks march down (as do the three-step pass's)."""
+@pytest.mark.parametrize("storage,ksteps,tiling", [("f32", 2, (1, 4, 1)), ("f32", 3, (1, 4, 1)),
+                                                   ("f32", 3, (2, 1, 1)), ("f16", 2, (1, 4, 1))])
+def test_wall_rows_deep_pipeline_and_down_march(L, storage, ksteps, tiling):
+    """At least 4096 wavefronts: the two-step pass loads two rows ahead in
+    FP32 (and marches odd row blocks down), as the three-step pass does."""
     nx, ny, walls = 1000, 520, (0, 100, 101, 257, 519)
     assert -(-nx // 120) * ny >= 4096
-    say("case: wall rows deep %dx%d, %d steps per launch, tiling=%s" % (nx, ny, ksteps, tiling))
-    _equal_runs(L, nx, ny, walls, tiling, ksteps, 7)
+    say("case: wall rows deep %dx%d %s, %d steps per launch, tiling=%s"
+        % (nx, ny, storage, ksteps, tiling))
+    _equal_runs(L, nx, ny, walls, tiling, ksteps, 7, storage)
 
 
 def test_wall_rows_eligibility(L):
-    """Whole solid rows allow FP32 launches of two and three steps (and the
-    defaults take them); a solid node outside a whole row, a wall along y,
-    FP16 and FP64 storage and open x boundaries keep one step."""
+    """Whole solid rows allow FP32 launches of two and three steps and FP16
+    launches of two (and the defaults take them); a solid node outside a
+    whole row, a wall along y, FP64 storage and open x boundaries keep one
+    step."""
     ny, nx = 40, 256
     rows = np.zeros((ny, nx), np.uint8)
     rows[[0, ny - 1]] = 1
@@ -111,14 +116,17 @@ def test_wall_rows_eligibility(L):
         lat.set_tuning(steps_per_sweep=want)
         assert lat.tuning()[5] == want
         lat.close()
-    lat = L.Lattice(nx, ny, 0.7, 1.0, storage="f32", mask=rows)
-    assert lat.tuning()[5] == 2                     # the default below 2048^2
-    lat.close()
+    for storage in ("f32", "f16"):
+        lat = L.Lattice(nx, ny, 0.7, 1.0, storage=storage, mask=rows)
+        assert lat.tuning()[5] == 2                 # the default below 2048^2
+        lat.set_tuning(steps_per_sweep=3)
+        assert lat.tuning()[5] == (3 if storage == "f32" else 2)
+        lat.close()
     part = rows.copy()
     part[0, 5] = 0
     cols = np.zeros((ny, nx), np.uint8)
     cols[:, 0] = 1
-    for mask, storage in ((part, "f32"), (cols, "f32"), (rows, "f16"), (rows, "f64")):
+    for mask, storage in ((part, "f32"), (cols, "f32"), (part, "f16"), (rows, "f64")):
         lat = L.Lattice(nx, ny, 0.7, 1.0, storage=storage, mask=mask)
         lat.set_tuning(steps_per_sweep=3)
         assert lat.tuning()[5] == 1, storage
@@ -129,8 +137,8 @@ def test_wall_rows_eligibility(L):
     lat.close()
 
 
-@pytest.mark.parametrize("ksteps", [2, 3])
-def test_wall_row_members_in_a_batch(L, ksteps):
+@pytest.mark.parametrize("storage,ksteps", [("f32", 2), ("f32", 3), ("f16", 2)])
+def test_wall_row_members_in_a_batch(L, storage, ksteps):
     """A batch of channels (odd and even widths), a mask that is not whole
     rows and an open lattice advances every member to the bits of a one-step
     batch; the channels take the multi-step launches."""
@@ -149,7 +157,7 @@ def test_wall_row_members_in_a_batch(L, ksteps):
                 f[:, mask.astype(bool)] = 0.0
             else:
                 f, mask, g, tau1, tau2 = _case(50 + k, nx, ny, walls)
-            lats.append(L.Lattice(nx, ny, tau1, tau2, g=g, storage="f32",
+            lats.append(L.Lattice(nx, ny, tau1, tau2, g=g, storage=storage,
                                   mask=mask).set_populations(f))
         b = L.Batch(lats)
         b.set_tuning(steps_per_sweep=sps, graph_steps=8)
@@ -165,8 +173,8 @@ def test_wall_row_members_in_a_batch(L, ksteps):
         for m in lats:
             m.close()
     for j, ((a, ta), (c, tc)) in enumerate(zip(runs[1], runs[ksteps])):
-        say("case: batch member %d, %d steps per launch: time %d/%d, differs at %d entries"
-            % (j, ksteps, ta, tc, int(np.sum(a != c))))
+        say("case: batch member %d %s, %d steps per launch: time %d/%d, differs at %d entries"
+            % (j, storage, ksteps, ta, tc, int(np.sum(a != c))))
         assert ta == tc and np.array_equal(a, c), j
 
 

@@ -47,7 +47,8 @@
  *    a solid node.  Solid nodes are never collided; their rho, u and f read
  *    back as 0 and they contribute nothing to diagnostics.  A mask whose
  *    solid nodes fill whole rows (walls parallel to x, as the channels of
- *    Sec. III.C) lets FP32 simulations take several steps per launch.
+ *    Sec. III.C) lets FP32 and FP16 simulations take several steps per
+ *    launch.
  */
 #ifndef TRTLBM_H
 #define TRTLBM_H
@@ -146,10 +147,10 @@ typedef struct {
                                 FP16).  k steps per launch move each
                                 population through HBM once per k steps and give the bits of
                                 k one-step sweeps.  Two apply to FP32 and FP16 simulations,
-                                alone or in a batch, without a mask or open boundaries, and
-                                to FP32 ones whose mask's solid nodes fill whole rows (x
-                                periodic); three to such FP32 simulations, alone or in an FP32
-                                batch; elsewhere sweeps take fewer steps.  With
+                                alone or in a batch, without a mask or open boundaries, or
+                                with a mask whose solid nodes fill whole rows (x periodic);
+                                three to such FP32 simulations, alone or in an FP32 batch;
+                                elsewhere sweeps take fewer steps.  With
                                 two or three steps per launch, rows_per_wave and
                                 waves_per_block shape that pass (cols_per_lane the one-step
                                 sweeps of leftover steps). */
@@ -347,7 +348,7 @@ trt_status trt_batch_update(trt_batch *b, int32_t n, trt_sim *const *sims);
 /* Advance every member nsteps steps (replays of captured graphs of batched
  * launches as for trt_step, plus at most a few plain launches).  With
  * the default steps_per_sweep, members that allow it (FP32 or FP16 without
- * a mask or open boundaries; FP32 with walls that fill whole rows) advance
+ * a mask or open boundaries, or with walls that fill whole rows) advance
  * three (FP32) or two (FP16) steps per launch and the others by one-step
  * sweeps in the same graphs; every member gets the bits it gets alone. */
 trt_status trt_batch_step(trt_batch *b, int64_t nsteps);

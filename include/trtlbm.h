@@ -122,7 +122,8 @@ typedef struct {
                                 one-column and batched sweeps and the two-step pass use at
                                 most 4, the two-column sweep at most 16 (FP64: 8) */
     int32_t xcd_remap;       /* 1: give each XCD a contiguous band of rows; 0: off; -1: default
-                                (on for one simulation -- except three-step launches of at
+                                (on for one simulation -- except three-step launches in
+                                their automatic rows from about 1500^2 nodes on, or of at
                                 least 3072 wavefronts, which run off -- and off for a
                                 batch) */
     int32_t cols_per_lane;   /* 1 or 2 columns per lane (0: 2 where it applies and nx >= 128) */

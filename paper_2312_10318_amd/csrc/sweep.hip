@@ -2235,13 +2235,37 @@ bool tb3_eligible(const InstDesc &d, int storage) {
     return storage == ST_F32 && tb2_eligible(d, storage);
 }
 
+// Rows that make the pass's four-wavefront workgroups (row blocks x groups
+// of four windows) just fit k whole rounds of the workgroups resident at
+// once (1024 SIMDs x two wavefronts / four per workgroup = 512), for the
+// smallest k = 1, 2, 3 that gives 8 to 192 rows; 0 if none does.  Same-run
+// measurements (us per step, such rows in the hardware's XCD order against
+// the rule below): 2048^2 21 rows 28.2 against 29.3, 3000^2 42 rows 54.4
+// against 61.3, 4096^2 74 rows 88.0 against 89.3, 6144^2 171 rows 201.9
+// against 202.5, 8192^2 147 rows 326.6 against 336.5.
+static int tb3_round_rows(const InstDesc &d) {
+    const int windows = (d.nx + kTb3Valid - 1) / kTb3Valid;
+    const int groups = (windows + 3) / 4;
+    const int slots = 1024 * 2 / 4;
+    for (int k = 1; k <= 3; ++k) {
+        const int blocks = k * slots / groups;
+        if (blocks < 1) continue;
+        const int r = (d.ny + blocks - 1) / blocks;
+        if (r >= 8 && r <= 192) return r;
+    }
+    return 0;
+}
+
 InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
     InstDesc t = d;
     t.strips = (d.nx + kTb3Valid - 1) / kTb3Valid;
     if (l.rows_per_wave > 0) {
         t.rows = l.rows_per_wave;
+    } else if (tb3_round_rows(d) > 0) {
+        t.rows = tb3_round_rows(d);
     } else {
-        // the longest of 48, 40, 32, 24 or 16 rows that gives 3072
+        // lattices too small for whole rounds (below about 1500^2): the
+        // longest of 48, 40, 32, 24 or 16 rows that gives 3072
         // wavefronts (four-wavefront workgroups), else the longest of those
         // and 12, 8 that gives 1536 (one-wavefront workgroups), else 8 (2048^2
         // at 8 rows, 4608 wavefronts: 35.6 us per step against 29.0 at 24
@@ -2274,15 +2298,22 @@ InstDesc tb3_desc(const InstDesc &d, const Launch &l) {
     return t;
 }
 
+// whether the rows in effect are the whole-round rows (none asked for):
+// those shapes take four-wavefront workgroups in the hardware's XCD order
+static bool tb3_rounds(const InstDesc &d, const Launch &l) {
+    return l.rows_per_wave <= 0 && tb3_round_rows(d) > 0;
+}
+
 int tb3_xcd_remap(const InstDesc &d, const Launch &l) {
     if (l.remap_asked) return l.xcd_remap;
+    if (tb3_rounds(d, l)) return 0;
     const InstDesc t = tb3_desc(d, l);
     return (long long)t.strips * t.rowblocks >= kTb3ManyWaves ? 0 : 1;
 }
 
 int tb3_waves_per_block(const InstDesc &d, const Launch &l) {
     const InstDesc t = tb3_desc(d, l);
-    const bool many = (long long)t.strips * t.rowblocks >= kTb3ManyWaves;
+    const bool many = tb3_rounds(d, l) || (long long)t.strips * t.rowblocks >= kTb3ManyWaves;
     int w = l.waves_per_block > 0 ? l.waves_per_block : (many ? 4 : 1);
     if (w > kTb2MaxWaves) w = kTb2MaxWaves;
     while (w > 1 && w / 2 >= t.strips) w /= 2;

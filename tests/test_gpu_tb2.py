@@ -232,14 +232,16 @@ def test_steps_per_launch_default_and_reported_shape(L):
     -- 120-column windows, the longest rows of 32 down to 8 that give 6144
     wavefronts (else 2048), four-wavefront workgroups from 4096 wavefronts
     on, loads two rows ahead in FP32 from 4096 wavefronts on; three steps --
-    116-column windows, rows of 48 down to 16 for 3072 wavefronts (four per
+    116-column windows, the rows that make four-wavefront workgroups fill
+    the machine in the fewest whole rounds with 8 to 192 rows (XCD
+    round-robin), else rows of 48 down to 16 for 3072 wavefronts (four per
     workgroup, XCD round-robin; else rows down to 8 for 1536, one per
     workgroup, XCD bands), loads one row ahead; an
     explicit request is kept (at most four wavefronts, no more than the
     windows need)."""
-    cases = [((4096, 4096), (), "f32", (48, 4, 1, 3)), ((4096, 4096), (), "f16", (16, 4, 1, 2)),
-             ((8192, 8192), (), "f32", (48, 4, 1, 3)), ((2048, 2048), (), "f32", (24, 1, 1, 3)),
-             ((3000, 3000), (), "f32", (24, 4, 1, 3)),
+    cases = [((4096, 4096), (), "f32", (74, 4, 1, 3)), ((4096, 4096), (), "f16", (16, 4, 1, 2)),
+             ((8192, 8192), (), "f32", (147, 4, 1, 3)), ((2048, 2048), (), "f32", (21, 4, 1, 3)),
+             ((3000, 3000), (), "f32", (42, 4, 1, 3)),
              ((1024, 1024), (), "f32", (8, 1, 1, 2)), ((256, 8), (), "f32", (8, 1, 1, 2)),
              ((4096, 64), (5, 16), "f32", (5, 4, 1, 2)), ((240, 64), (16, 4), "f32", (16, 2, 1, 2)),
              ((4096, 4096), (0, 0, 1, 0, 0, 2), "f32", (16, 4, 2, 2)),
